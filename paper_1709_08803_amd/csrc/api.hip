@@ -1,0 +1,107 @@
+// C ABI entry points for the residual and the Jacobian-vector product.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "bim_common.h"
+#include "vec.h"
+
+namespace bim {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return BIM_OK;
+    if (e == hipErrorOutOfMemory) return fail(BIM_ENOMEM, std::string(what) + ": out of device memory");
+    return fail(BIM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int validate(const bim_problem *p) {
+    if (!p) return fail(BIM_EINVAL, "problem is NULL");
+    if (p->N < 3 || p->M < 3) return fail(BIM_EINVAL, "mesh needs N >= 3 and M >= 3");
+    if ((long)p->N * p->M > (1L << 26)) return fail(BIM_EINVAL, "mesh too large");
+    if (!(p->dx > 0.0) || !(p->dy > 0.0)) return fail(BIM_EINVAL, "dx and dy must be positive");
+    if (!(p->froude > 0.0) || !std::isfinite(p->froude)) return fail(BIM_EINVAL, "Froude number must be positive");
+    if (!std::isfinite(p->x1) || !std::isfinite(p->y1) || !std::isfinite(p->n_decay))
+        return fail(BIM_EINVAL, "non-finite mesh origin or decay rate");
+    if (p->half_domain && p->y1 != 0.0) return fail(BIM_EINVAL, "a half domain must start at y1 = 0");
+    if (!p->beta || !p->beta_x || !p->beta_y) return fail(BIM_EINVAL, "bottom arrays must be device pointers");
+    return BIM_OK;
+}
+
+// Stream-ordered scratch allocation that is released when it goes out of scope.
+struct Scratch {
+    void *ptr = nullptr;
+    hipStream_t s;
+    explicit Scratch(hipStream_t st) : s(st) {}
+    int alloc(size_t bytes) { return hip_check(hipMallocAsync(&ptr, bytes, s), "hipMallocAsync"); }
+    ~Scratch() {
+        if (ptr) (void)hipFreeAsync(ptr, s);
+    }
+};
+
+}  // namespace bim
+
+using namespace bim;
+
+extern "C" {
+
+const char *bim_last_error(void) { return g_last_error.c_str(); }
+
+const char *bim_version(void) { return "bim-mi355x 0.1"; }
+
+int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, void *stream) {
+    g_last_error.clear();
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!u || !F) return fail(BIM_EINVAL, "u and F must be device pointers");
+    if (u == F) return fail(BIM_EINVAL, "F must not alias u");
+    if (prec != BIM_FP64 && prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
+    hipStream_t s = (hipStream_t)stream;
+    const Dims d(prob);
+    const PairLaunch pl = pair_launch(d, 0);
+    Scratch sc(s);
+    if ((rc = sc.alloc(residual_work_bytes(d, pl)))) return rc;
+    ResidualWork w;
+    residual_work_carve(sc.ptr, d, pl, &w);
+    return residual_enqueue(prob, u, F, prec, pl, w, s);
+}
+
+int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const double *v, double h, double *Jv,
+           int prec, void *stream) {
+    g_last_error.clear();
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!u || !Fu || !v || !Jv) return fail(BIM_EINVAL, "u, Fu, v and Jv must be device pointers");
+    if (Jv == u || Jv == Fu || Jv == v) return fail(BIM_EINVAL, "Jv must not alias an input");
+    if (prec != BIM_FP64 && prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
+    if (!std::isfinite(h)) return fail(BIM_EINVAL, "h must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    const Dims d(prob);
+    const PairLaunch pl = pair_launch(d, 0);
+    const size_t vec_bytes = ((sizeof(double) * d.nvec) + 255) & ~(size_t)255;
+    const size_t red_bytes = ((sizeof(double) * reduce_parts()) + 255) & ~(size_t)255;
+    Scratch sc(s);
+    if ((rc = sc.alloc(residual_work_bytes(d, pl) + 2 * vec_bytes + red_bytes))) return rc;
+    ResidualWork w;
+    residual_work_carve(sc.ptr, d, pl, &w);
+    double *uw = (double *)((char *)sc.ptr + w.bytes);
+    double *Fw = (double *)((char *)uw + vec_bytes);
+    double *part = (double *)((char *)Fw + vec_bytes);
+    const double eps = (prec == BIM_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+    if ((rc = fd_shift_enqueue(u, v, d.nvec, h, eps, part, w.scal, s))) return rc;
+    if ((rc = axpy_dev_enqueue(u, v, w.scal + 2, uw, d.nvec, s))) return rc;
+    if ((rc = residual_enqueue(prob, uw, Fw, prec, pl, w, s))) return rc;
+    return quotient_enqueue(Fw, Fu, w.scal + 2, Jv, d.nvec, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal declarations shared by the libbim translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "bim.h"
+
+namespace bim {
+
+// Records the message for bim_last_error() and returns `code`.
+int fail(int code, const std::string &msg);
+// Wraps a HIP call: on failure records "<what>: <hip error string>" and returns BIM_EHIP.
+int hip_check(hipError_t e, const char *what);
+
+#define BIM_HIP(call)                                        \
+    do {                                                     \
+        int _rc = ::bim::hip_check((call), #call);           \
+        if (_rc != BIM_OK) return _rc;                       \
+    } while (0)
+
+// Validates a problem description; returns BIM_OK or BIM_EINVAL with a message.
+int validate(const bim_problem *p);
+
+// Sizes derived from (N, M).
+struct Dims {
+    int N, M, nimg;
+    int nblk;      // (N+1) M: one block of u or F
+    int nvec;      // 3 (N+1) M
+    int ntg;       // (N-1) M collocation points per boundary
+    int nnode;     // N M nodes per boundary
+    explicit Dims(const bim_problem *p)
+        : N(p->N), M(p->M), nimg(p->half_domain ? 2 : 1), nblk((p->N + 1) * p->M),
+          nvec(3 * (p->N + 1) * p->M), ntg((p->N - 1) * p->M), nnode(p->N * p->M) {}
+};
+
+// Source-node record streamed by the all-pairs kernel: position x, elevation z,
+// slopes zx, zy, and the trapezoid weight w folded into the layer densities.
+// Bottom records carry the outward-normal sign of Green's identity (w < 0).
+template <typename T>
+struct alignas(8 * sizeof(T)) SrcRec {
+    T x, z, zx, zy, wD, ws, w, pad;
+};
+
+// Launch shape of the all-pairs kernel: target tiles of 64 collocation points
+// on one mesh row, source rows split into chunks (split-K over sources).
+struct PairLaunch {
+    int tiles_per_row;   // ceil((N-1) / 64)
+    int target_tiles;    // 2 M tiles_per_row
+    int src_rows;        // 2 nimg M
+    int rows_per_chunk;
+    int chunks;
+    int blocks;          // workgroups of 4 waves
+};
+PairLaunch pair_launch(const Dims &d, int rows_per_chunk_override);
+
+// Device workspace of one residual evaluation.
+struct ResidualWork {
+    double *nodes;   // [3][M][N]  zeta, phi, psi at the nodes
+    double *ydiv;    // [2][M][N]  zeta_y, phi_y at the nodes
+    double *tg;      // [8][2 ntg] x*, y*, d, D*, A, B, C, sigma* (FP64)
+    float *tg32;     // [7][2 ntg] FP32 copies for the FP32C kernel
+    void *srcS;      // SrcRec<T>[nnode]
+    void *srcB;      // SrcRec<T>[nnode]
+    double *part;    // [chunks][2 ntg][2]
+    double *scal;    // [4] device scalars (h, norms)
+    size_t bytes;
+};
+size_t residual_work_bytes(const Dims &d, const PairLaunch &pl);
+void residual_work_carve(void *base, const Dims &d, const PairLaunch &pl, ResidualWork *w);
+
+// Enqueues F = F(u) using a caller-provided workspace (no allocation).
+int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
+                     const PairLaunch &pl, const ResidualWork &w, hipStream_t s);
+
+}  // namespace bim

@@ -1,0 +1,410 @@
+// Residual F(u) of the discretised boundary-integral system (Section 3.1) on gfx950.
+//
+// Four kernels, stream-ordered:
+//   k_integrate   unpack u and integrate f_x along each slice (trapezoidal rule)
+//   k_nodes       y-derivatives at the nodes; source-node records for S and B
+//   k_targets     collocation-point records at (x_{k+1/2}, y_l)
+//   k_allpairs    the dense sums of eq. (new_finite_boundary_integral): every
+//                 collocation point against every node of both boundaries and
+//                 both y-images (hot loop)
+//   k_finalize    closed-form S2 integral, 2 pi term, dynamic condition,
+//                 radiation rows, and the row order of Appendix B
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "bim_common.h"
+
+namespace bim {
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// ------------------------------------------------------------------ rsqrt
+// FP32: the hardware reciprocal square root (about 1 ulp).
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// FP64: the hardware estimate (relative error ~5e-8) refined by one step of the
+// second-order Newton-Raphson/Householder correction y (1 + e/2 + 3e^2/8),
+// e = 1 - x y^2, whose truncation error 5e^3/16 lies below FP64 rounding.
+__device__ __forceinline__ double rsq(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = x * y;
+    double e = fma(-h, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
+// ------------------------------------------------------------------ A1: unpack + x-integration
+// f_{1,j} + trapezoidal integral of f_x along slice j (Section 3.1).
+__global__ void k_integrate(const double *__restrict__ u, double *__restrict__ nodes, int N, int M,
+                            double dx) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 3 * M) return;
+    const int f = idx / M, j = idx - f * M;
+    const double *s = u + (size_t)f * (N + 1) * M + (size_t)j * (N + 1);
+    double *o = nodes + ((size_t)f * M + j) * N;
+    const double hdx = 0.5 * dx;
+    double acc = s[0];
+    o[0] = acc;
+    for (int i = 1; i < N; ++i) {
+        acc += hdx * (s[i] + s[i + 1]);
+        o[i] = acc;
+    }
+}
+
+// y-derivative of node field g at (j, i): central differences inside, the
+// three-point one-sided stencil on the outer edge, zero on the symmetry line of
+// a half domain (mirror of the outer stencil on a full domain).
+__device__ __forceinline__ double ddy(const double *g, int j, int i, int N, int M, double dy, int half) {
+    const double inv2 = 0.5 / dy;
+    if (j > 0 && j < M - 1) return (g[(size_t)(j + 1) * N + i] - g[(size_t)(j - 1) * N + i]) * inv2;
+    if (j == M - 1)
+        return (3.0 * g[(size_t)j * N + i] - 4.0 * g[(size_t)(j - 1) * N + i] + g[(size_t)(j - 2) * N + i]) * inv2;
+    if (half) return 0.0;
+    return (-3.0 * g[i] + 4.0 * g[(size_t)N + i] - g[(size_t)2 * N + i]) * inv2;
+}
+
+// ------------------------------------------------------------------ node records
+template <typename T>
+__global__ void k_nodes(const double *__restrict__ u, const double *__restrict__ nodes,
+                        const double *__restrict__ beta, const double *__restrict__ beta_x,
+                        const double *__restrict__ beta_y, double *__restrict__ ydiv,
+                        SrcRec<T> *__restrict__ srcS, SrcRec<T> *__restrict__ srcB, int N, int M,
+                        double x1, double dx, double dy, int half) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N * M) return;
+    const int j = n / N, i = n - j * N;
+    const size_t nb = (size_t)(N + 1) * M;
+    const double *zeta = nodes, *phi = nodes + (size_t)N * M, *psi = nodes + (size_t)2 * N * M;
+    const double zy = ddy(zeta, j, i, N, M, dy, half);
+    const double py = ddy(phi, j, i, N, M, dy, half);
+    ydiv[n] = zy;
+    ydiv[(size_t)N * M + n] = py;
+    const double zx = u[(size_t)j * (N + 1) + 1 + i];
+    const double x = x1 + i * dx;
+    const double ci = (i == 0 || i == N - 1) ? 0.5 : 1.0;
+    const double cj = (j == 0 || j == M - 1) ? 0.5 : 1.0;
+    const double w = dx * dy * ci * cj;
+    SrcRec<T> a;
+    a.x = (T)x;
+    a.z = (T)zeta[n];
+    a.zx = (T)zx;
+    a.zy = (T)zy;
+    a.wD = (T)(w * (phi[n] - x));
+    a.ws = (T)(w * zx);
+    a.w = (T)w;
+    a.pad = (T)0;
+    srcS[n] = a;
+    // bottom: outward normal points down, so both layers enter with -w
+    SrcRec<T> b;
+    b.x = (T)x;
+    b.z = (T)beta[n];
+    b.zx = (T)beta_x[n];
+    b.zy = (T)beta_y[n];
+    b.wD = (T)(-w * (psi[n] - x));
+    b.ws = (T)(-w * beta_x[n]);
+    b.w = (T)(-w);
+    b.pad = (T)0;
+    srcB[n] = b;
+    (void)nb;
+}
+
+// ------------------------------------------------------------------ collocation-point records
+// tg layout: 8 arrays of 2 ntg entries: x*, y*, d, D*, A, B, C, sigma*; target
+// t = st ntg + l (N-1) + k, st = 0 on the free surface, 1 on the bottom.
+__global__ void k_targets(const double *__restrict__ nodes, const double *__restrict__ ydiv,
+                          const double *__restrict__ u, const double *__restrict__ beta,
+                          const double *__restrict__ beta_x, const double *__restrict__ beta_y,
+                          double *__restrict__ tg, float *__restrict__ tg32, int N, int M, double x1,
+                          double dx, double y1, double dy) {
+    const int ntg = (N - 1) * M;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * ntg) return;
+    const int st = t / ntg, r = t - st * ntg;
+    const int l = r / (N - 1), k = r - l * (N - 1);
+    const size_t n0 = (size_t)l * N + k, n1 = n0 + 1;
+    const double xs = x1 + (k + 0.5) * dx, ys = y1 + l * dy;
+    double d, D, ax, ay, sig;
+    if (st == 0) {
+        const double *zeta = nodes, *phi = nodes + (size_t)N * M;
+        const double *zy = ydiv;
+        const double zx0 = u[(size_t)l * (N + 1) + 1 + k], zx1 = u[(size_t)l * (N + 1) + 2 + k];
+        d = 0.5 * (zeta[n0] + zeta[n1]);
+        D = 0.5 * (phi[n0] + phi[n1]) - xs;
+        ax = 0.5 * (zx0 + zx1);
+        ay = 0.5 * (zy[n0] + zy[n1]);
+        sig = ax;
+    } else {
+        const double *psi = nodes + (size_t)2 * N * M;
+        d = 0.5 * (beta[n0] + beta[n1]);
+        D = 0.5 * (psi[n0] + psi[n1]) - xs;
+        ax = 0.5 * (beta_x[n0] + beta_x[n1]);
+        ay = 0.5 * (beta_y[n0] + beta_y[n1]);
+        sig = -ax;
+    }
+    const size_t T2 = (size_t)2 * ntg;
+    const double v[8] = {xs, ys, d, D, 1.0 + ax * ax, 2.0 * ax * ay, 1.0 + ay * ay, sig};
+    for (int q = 0; q < 8; ++q) tg[q * T2 + t] = v[q];
+    for (int q = 0; q < 7; ++q) tg32[q * T2 + t] = (float)v[q];
+}
+
+// ------------------------------------------------------------------ A2: all-pairs sums (hot loop)
+// One wave = 64 collocation points on one mesh row of one boundary; it walks a
+// chunk of source rows (boundary, image, y-row) and, for each, all N nodes of
+// that row.  Source records are read with wave-uniform addresses (scalar
+// loads); y-dependent terms are hoisted per source row.  Per pair:
+//   own boundary:   w (D - D*) K1 + w sigma K2  and  w S2   (two rsqrt)
+//   other boundary: w D K1 + w sigma K2                      (one rsqrt)
+// written as  ri (coef num ri^2 + w sigma)  with ri = 1/R.
+// FP32C: FP32 sums over one source row, combined across rows with Neumaier's
+// compensated summation; the chunk result is written in FP64.
+template <typename T, bool COMP>
+__global__ __launch_bounds__(256) void k_allpairs(
+    const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB, const T *__restrict__ tg,
+    int N, int M, int nimg, double y1, double dy, int tiles_per_row, int target_tiles, int chunks,
+    int rows_per_chunk, double *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    // the wave index is uniform: keep it (and everything derived) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = blockIdx.x * 4 + wave;
+    const int tt = g % target_tiles, c = g / target_tiles;
+    if (c >= chunks) return;
+    const int ntg = (N - 1) * M;
+    const size_t T2 = (size_t)2 * ntg;
+    const int st = tt / (M * tiles_per_row);
+    const int rem = tt - st * M * tiles_per_row;
+    const int l = rem / tiles_per_row;
+    const int k = (rem - l * tiles_per_row) * 64 + lane;
+    const bool valid = k < N - 1;
+    const int tid = st * ntg + l * (N - 1) + (valid ? k : N - 2);
+    const T xs = tg[0 * T2 + tid], ys = tg[1 * T2 + tid], d = tg[2 * T2 + tid], Dst = tg[3 * T2 + tid];
+    const T A = tg[4 * T2 + tid], B = tg[5 * T2 + tid], C = tg[6 * T2 + tid];
+
+    const int nrows = 2 * nimg * M;
+    const int r0 = c * rows_per_chunk;
+    const int r1 = min(nrows, r0 + rows_per_chunk);
+
+    T sum = 0, comp = 0;     // running (compensated) sum of the layer terms
+    T s2sum = 0, s2comp = 0; // running sum of w S2 over the own boundary
+    for (int r = r0; r < r1; ++r) {
+        const int ss = r & 1;  // interleave boundaries so every chunk mixes both
+        const int rr = r >> 1;
+        const int img = rr / M;
+        const int j = rr - img * M;
+        const T iota = img ? T(-1) : T(1);
+        const T t = T(iota * (y1 + j * dy)) - ys;
+        const T ti = t * iota;      // multiplies the source's a_y (mirrored on the image)
+        const T t2 = t * t;
+        const SrcRec<T> *__restrict__ src = (ss ? srcB : srcS) + (size_t)j * N;
+        T acc = 0, acc2 = 0;
+        if (ss == st) {
+            const T Bt = B * t, Ct2 = C * t2;
+#pragma unroll 4
+            for (int i = 0; i < N; ++i) {
+                const SrcRec<T> q = src[i];
+                const T s = q.x - xs;
+                const T dz = q.z - d;
+                const T r2 = fma(dz, dz, fma(s, s, t2));
+                const T ri = rsq(r2);
+                const T num = fma(-s, q.zx, fma(-ti, q.zy, dz));
+                const T ri2 = ri * ri;
+                const T coef = fma(-Dst, q.w, q.wD);
+                const T bsum = fma(coef * num, ri2, q.ws);
+                acc = fma(bsum, ri, acc);
+                const T Q = fma(s, fma(A, s, Bt), Ct2);
+                acc2 = fma(q.w, rsq(Q), acc2);
+            }
+        } else {
+#pragma unroll 4
+            for (int i = 0; i < N; ++i) {
+                const SrcRec<T> q = src[i];
+                const T s = q.x - xs;
+                const T dz = q.z - d;
+                const T r2 = fma(dz, dz, fma(s, s, t2));
+                const T ri = rsq(r2);
+                const T num = fma(-s, q.zx, fma(-ti, q.zy, dz));
+                const T ri2 = ri * ri;
+                const T bsum = fma(q.wD * num, ri2, q.ws);
+                acc = fma(bsum, ri, acc);
+            }
+        }
+        if (COMP) {
+            // Neumaier: exact error of each addition kept in comp
+            T tsum = sum + acc;
+            comp += (fabs(sum) >= fabs(acc)) ? ((sum - tsum) + acc) : ((acc - tsum) + sum);
+            sum = tsum;
+            T tq = s2sum + acc2;
+            s2comp += (fabs(s2sum) >= fabs(acc2)) ? ((s2sum - tq) + acc2) : ((acc2 - tq) + s2sum);
+            s2sum = tq;
+        } else {
+            sum += acc;
+            s2sum += acc2;
+        }
+    }
+    if (valid) {
+        double *o = part + ((size_t)c * T2 + tid) * 2;
+        o[0] = (double)sum + (double)comp;
+        o[1] = (double)s2sum + (double)s2comp;
+    }
+}
+
+// ------------------------------------------------------------------ A3 + A4: finalize
+// Closed form of the integral of (A s^2 + B s t + C t^2)^(-1/2) over a rectangle
+// from the antiderivative of Section 3.1; a term with a zero prefactor is its
+// limit, zero.
+__device__ double s2_antideriv(double A, double B, double C, double s, double t) {
+    const double Q = A * s * s + B * s * t + C * t * t;
+    double g = 0.0;
+    if (t != 0.0) g += t / sqrt(A) * log(2.0 * A * s + B * t + 2.0 * sqrt(A * Q));
+    if (s != 0.0) g += s / sqrt(C) * log(2.0 * C * t + B * s + 2.0 * sqrt(C * Q));
+    return g;
+}
+
+__global__ void k_finalize(const double *__restrict__ u, const double *__restrict__ nodes,
+                           const double *__restrict__ ydiv, const double *__restrict__ tg,
+                           const double *__restrict__ part, double *__restrict__ F, int N, int M,
+                           int chunks, double x1, double dx, double xlo, double xhi, double ylo,
+                           double yhi, double n_decay, double froude) {
+    const int nblk = (N + 1) * M;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= 3 * nblk) return;
+    const int blk = row / nblk;
+    const int rem = row - blk * nblk;
+    const int l = rem / (N + 1), col = rem - l * (N + 1);
+    const double *fx = u + (size_t)blk * nblk + (size_t)l * (N + 1) + 1;  // (f_x)_{., l}
+    const double *fv = nodes + ((size_t)blk * M + l) * N;                  // f_{., l}
+    if (col < 2) {
+        // radiation rows (eqs. scullen1-6 as discretised in Appendix B)
+        const double fxx = (fx[1] - fx[0]) / dx;
+        double v;
+        if (blk == 0) {
+            v = (col == 0) ? x1 * fx[0] + n_decay * fv[0] : x1 * fxx + n_decay * fx[0];
+        } else {
+            v = (col == 0) ? x1 * (fx[0] - 1.0) + n_decay * (fv[0] - x1) : x1 * fxx + n_decay * (fx[0] - 1.0);
+        }
+        F[row] = v;
+        return;
+    }
+    const int k = col - 2;
+    if (blk == 0) {
+        // dynamic condition, eq. (new_finite_dynamic), at (x_{k+1/2}, y_l)
+        const size_t n0 = (size_t)l * N + k, n1 = n0 + 1;
+        const double *zx = u + (size_t)l * (N + 1) + 1;
+        const double *px = u + (size_t)nblk + (size_t)l * (N + 1) + 1;
+        const double z = 0.5 * (nodes[n0] + nodes[n1]);
+        const double a = 0.5 * (zx[k] + zx[k + 1]);
+        const double b = 0.5 * (ydiv[n0] + ydiv[n1]);
+        const double p = 0.5 * (px[k] + px[k + 1]);
+        const double q = 0.5 * (ydiv[(size_t)N * M + n0] + ydiv[(size_t)N * M + n1]);
+        const double kin = 0.5 * ((1.0 + a * a) * q * q + (1.0 + b * b) * p * p - 2.0 * a * b * p * q) /
+                           (1.0 + a * a + b * b);
+        F[row] = kin + z / (froude * froude) - 0.5;
+        return;
+    }
+    // boundary-integral rows: F2 (blk 1, free surface), F7 (blk 2, bottom)
+    const int ntg = (N - 1) * M;
+    const size_t T2 = (size_t)2 * ntg;
+    const int tid = (blk - 1) * ntg + l * (N - 1) + k;
+    double acc = 0.0, acc2 = 0.0;
+    for (int c = 0; c < chunks; ++c) {  // fixed order: deterministic
+        const double *o = part + ((size_t)c * T2 + tid) * 2;
+        acc += o[0];
+        acc2 += o[1];
+    }
+    const double s2 = (blk == 2) ? -acc2 : acc2;  // bottom records carry -w
+    const double xs = tg[0 * T2 + tid], ys = tg[1 * T2 + tid], D = tg[3 * T2 + tid];
+    const double A = tg[4 * T2 + tid], B = tg[5 * T2 + tid], C = tg[6 * T2 + tid], sig = tg[7 * T2 + tid];
+    const double s1 = xlo - xs, s2e = xhi - xs, t1 = ylo - ys, t2 = yhi - ys;
+    const double I2 = s2_antideriv(A, B, C, s2e, t2) - s2_antideriv(A, B, C, s1, t2) -
+                      s2_antideriv(A, B, C, s2e, t1) + s2_antideriv(A, B, C, s1, t1);
+    F[row] = acc - sig * s2 + sig * I2 - kTwoPi * D;
+}
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+PairLaunch pair_launch(const Dims &d, int rows_per_chunk_override) {
+    PairLaunch pl;
+    pl.tiles_per_row = cdiv(d.N - 1, 64);
+    pl.target_tiles = 2 * d.M * pl.tiles_per_row;
+    pl.src_rows = 2 * d.nimg * d.M;
+    int rpc = rows_per_chunk_override;
+    if (rpc <= 0) {
+        // aim at ~16 resident-wave slots' worth of waves per SIMD (1024 SIMDs)
+        const long want_waves = 16384;
+        int chunks = std::max(1, std::min(pl.src_rows, cdiv(want_waves, pl.target_tiles)));
+        rpc = cdiv(pl.src_rows, chunks);
+    }
+    rpc = std::max(1, std::min(rpc, pl.src_rows));
+    pl.rows_per_chunk = rpc;
+    pl.chunks = cdiv(pl.src_rows, rpc);
+    pl.blocks = cdiv((long)pl.target_tiles * pl.chunks, 4);
+    return pl;
+}
+
+size_t residual_work_bytes(const Dims &d, const PairLaunch &pl) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t b = 0;
+    b += al(sizeof(double) * 3 * d.nnode);
+    b += al(sizeof(double) * 2 * d.nnode);
+    b += al(sizeof(double) * 8 * 2 * d.ntg);
+    b += al(sizeof(float) * 7 * 2 * d.ntg);
+    b += 2 * al(sizeof(SrcRec<double>) * d.nnode);
+    b += al(sizeof(double) * 2 * 2 * (size_t)d.ntg * pl.chunks);
+    b += al(sizeof(double) * 4);
+    return b;
+}
+
+void residual_work_carve(void *base, const Dims &d, const PairLaunch &pl, ResidualWork *w) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *p = (char *)base;
+    w->nodes = (double *)p; p += al(sizeof(double) * 3 * d.nnode);
+    w->ydiv = (double *)p; p += al(sizeof(double) * 2 * d.nnode);
+    w->tg = (double *)p; p += al(sizeof(double) * 8 * 2 * d.ntg);
+    w->tg32 = (float *)p; p += al(sizeof(float) * 7 * 2 * d.ntg);
+    w->srcS = p; p += al(sizeof(SrcRec<double>) * d.nnode);
+    w->srcB = p; p += al(sizeof(SrcRec<double>) * d.nnode);
+    w->part = (double *)p; p += al(sizeof(double) * 2 * 2 * (size_t)d.ntg * pl.chunks);
+    w->scal = (double *)p; p += al(sizeof(double) * 4);
+    w->bytes = (size_t)(p - (char *)base);
+}
+
+int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec, const PairLaunch &pl,
+                     const ResidualWork &w, hipStream_t s) {
+    const Dims d(p);
+    const int N = d.N, M = d.M;
+    const double xN = p->x1 + (N - 1) * p->dx, yM = p->y1 + (M - 1) * p->dy;
+    const double ylo = p->half_domain ? -yM : p->y1;
+    hipLaunchKernelGGL(k_integrate, dim3(cdiv(3 * M, 64)), dim3(64), 0, s, u, w.nodes, N, M, p->dx);
+    const int nb = cdiv(d.nnode, 256);
+    if (prec == BIM_FP64) {
+        hipLaunchKernelGGL(k_nodes<double>, dim3(nb), dim3(256), 0, s, u, w.nodes, p->beta, p->beta_x,
+                           p->beta_y, w.ydiv, (SrcRec<double> *)w.srcS, (SrcRec<double> *)w.srcB, N, M,
+                           p->x1, p->dx, p->dy, p->half_domain);
+    } else {
+        hipLaunchKernelGGL(k_nodes<float>, dim3(nb), dim3(256), 0, s, u, w.nodes, p->beta, p->beta_x,
+                           p->beta_y, w.ydiv, (SrcRec<float> *)w.srcS, (SrcRec<float> *)w.srcB, N, M,
+                           p->x1, p->dx, p->dy, p->half_domain);
+    }
+    hipLaunchKernelGGL(k_targets, dim3(cdiv(2 * d.ntg, 256)), dim3(256), 0, s, w.nodes, w.ydiv, u, p->beta,
+                       p->beta_x, p->beta_y, w.tg, w.tg32, N, M, p->x1, p->dx, p->y1, p->dy);
+    if (prec == BIM_FP64) {
+        hipLaunchKernelGGL((k_allpairs<double, false>), dim3(pl.blocks), dim3(256), 0, s,
+                           (const SrcRec<double> *)w.srcS, (const SrcRec<double> *)w.srcB, w.tg, N, M,
+                           d.nimg, p->y1, p->dy, pl.tiles_per_row, pl.target_tiles, pl.chunks,
+                           pl.rows_per_chunk, w.part);
+    } else {
+        hipLaunchKernelGGL((k_allpairs<float, true>), dim3(pl.blocks), dim3(256), 0, s,
+                           (const SrcRec<float> *)w.srcS, (const SrcRec<float> *)w.srcB, w.tg32, N, M,
+                           d.nimg, p->y1, p->dy, pl.tiles_per_row, pl.target_tiles, pl.chunks,
+                           pl.rows_per_chunk, w.part);
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(cdiv(d.nvec, 256)), dim3(256), 0, s, u, w.nodes, w.ydiv, w.tg,
+                       w.part, F, N, M, pl.chunks, p->x1, p->dx, p->x1, xN, ylo, yM, p->n_decay,
+                       p->froude);
+    return hip_check(hipGetLastError(), "residual kernel launch");
+}
+
+}  // namespace bim

@@ -1,0 +1,140 @@
+"""GPU residual and Jv (through the C ABI) against the FP64 CPU oracle."""
+import numpy as np
+import pytest
+
+from paper_1709_08803_amd import workloads as W
+from oracle import residual as R
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bim():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_1709_08803_amd import bim as B
+    B.lib()
+    return B
+
+
+def _gpu_F(B, p, u, prec):
+    dp = B.DeviceProblem(p)
+    ud = torch.as_tensor(u, device="cuda")
+    F = B.residual(dp, ud, prec=prec)
+    torch.cuda.synchronize()
+    return F.cpu().numpy()
+
+
+CASES = [
+    ("tiny-31x11", lambda: W.tiny(0.7), 1),
+    ("61x21-F1.4", lambda: W.working(1.4, N=61, M=21), 2),
+    ("ragged-45x9", lambda: W.make_problem(45, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 3),
+    ("full-31x13", lambda: W.make_problem(31, 13, -10, 10, -6, 6, 1.2, [W.Bump(0.2, 1.0, 1.0, cy=1.5)],
+                                          half_domain=False), 4),
+    ("min-3x3", lambda: W.make_problem(3, 3, -1, 1, 0, 1, 0.8, [W.Bump(0.1, 1.0, 1.0)]), 5),
+]
+
+
+@pytest.mark.parametrize("name,mk,seed", CASES, ids=[c[0] for c in CASES])
+def test_residual_fp64_matches_oracle(bim, name, mk, seed):
+    p = mk()
+    u = W.perturbed_state(p, seed)
+    F_ref = R.residual(p, u)
+    scale = R.term_magnitude_rows(p, u)
+    F = _gpu_F(bim, p, u, "fp64")
+    err = np.abs(F - F_ref) / scale
+    print(name, "max rel err", err.max())
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("name,mk,seed", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_residual_fp32c_matches_oracle(bim, name, mk, seed):
+    p = mk()
+    u = W.perturbed_state(p, seed)
+    F_ref = R.residual(p, u)
+    scale = R.term_magnitude_rows(p, u)
+    F = _gpu_F(bim, p, u, "fp32c")
+    err = np.abs(F - F_ref) / scale
+    print(name, "fp32c max rel err", err.max())
+    assert err.max() <= 1e-5
+
+
+@pytest.mark.parametrize("F_num", [0.7, 1.4])
+def test_residual_full_size_sampled_rows(bim, F_num):
+    # 181 x 61 at the benchmark's launch configuration; the oracle computes a
+    # seeded sample of rows one by one (all row kinds, edges included).
+    p = W.working(F_num)
+    u = W.perturbed_state(p, 11)
+    rng = np.random.default_rng(7)
+    nb = (p.N + 1) * p.M
+    rows = set(rng.choice(3 * nb, 150, replace=False).tolist())
+    for blk in range(3):  # corners and edges of every block
+        for l in (0, p.M - 1):
+            rows.update({blk * nb + l * (p.N + 1) + c for c in (0, 1, 2, p.N)})
+    rows = np.array(sorted(rows))
+    ref = R.residual_rows(p, u, rows)
+    F = _gpu_F(bim, p, u, "fp64")
+    F32 = _gpu_F(bim, p, u, "fp32c")
+    scale = R.term_magnitude_rows(p, u)[rows]
+    e64 = (np.abs(F[rows] - ref) / scale).max()
+    e32 = (np.abs(F32[rows] - ref) / scale).max()
+    print("181x61 F", F_num, "fp64", e64, "fp32c", e32)
+    assert e64 <= 1e-12
+    assert e32 <= 1e-5
+
+
+def test_residual_is_deterministic(bim):
+    p = W.working(0.7, N=61, M=21)
+    u = W.perturbed_state(p, 1)
+    a = _gpu_F(bim, p, u, "fp64")
+    b = _gpu_F(bim, p, u, "fp64")
+    assert np.array_equal(a, b)
+    c = _gpu_F(bim, p, u, "fp32c")
+    d = _gpu_F(bim, p, u, "fp32c")
+    assert np.array_equal(c, d)
+
+
+def test_uniform_stream_flat_bottom_is_zero_on_gpu(bim):
+    p = W.make_problem(61, 21, -20, 20, 0, 10, 0.7, [])
+    F = _gpu_F(bim, p, W.uniform_stream(p), "fp64")
+    assert np.abs(F).max() < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-6), ("fp32c", 2e-2)])
+def test_jv_matches_oracle_difference_quotient(bim, prec, tol):
+    p = W.tiny(0.7)
+    u = W.perturbed_state(p, 2)
+    v = W.random_direction(p, 3) * 1e-2
+    h = 1e-3 if prec == "fp64" else 1e-1
+    ref = (R.residual(p, u + h * v) - R.residual(p, u)) / h
+    dp = bim.DeviceProblem(p)
+    ud, vd = torch.as_tensor(u, device="cuda"), torch.as_tensor(v, device="cuda")
+    Fu = bim.residual(dp, ud, prec=prec)
+    J = bim.jv(dp, ud, Fu, vd, h=h, prec=prec)
+    torch.cuda.synchronize()
+    J = J.cpu().numpy()
+    err = np.abs(J - ref).max() / np.abs(ref).max()
+    print(prec, "jv rel err", err)
+    assert err <= tol
+
+
+def test_jv_default_shift_and_zero_direction(bim):
+    p = W.tiny(0.7)
+    u = W.perturbed_state(p, 2)
+    dp = bim.DeviceProblem(p)
+    ud = torch.as_tensor(u, device="cuda")
+    Fu = bim.residual(dp, ud)
+    z = torch.zeros_like(ud)
+    J = bim.jv(dp, ud, Fu, z)  # |v| = 0 -> Jv = 0
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(J).item() == 0
+    v = W.random_direction(p, 3)
+    J = bim.jv(dp, ud, Fu, torch.as_tensor(v, device="cuda"))  # default h rule
+    eps = 2.0 ** -52
+    h = np.sqrt(eps) * (1 + np.linalg.norm(u)) / np.linalg.norm(v)
+    ref = (R.residual(p, u + h * v) - R.residual(p, u)) / h
+    torch.cuda.synchronize()
+    err = np.abs(J.cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err < 1e-4
