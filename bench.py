@@ -1,0 +1,129 @@
+#!/usr/bin/env python3
+"""Benchmark of the boundary-integral JFNK hot path on one MI355X.
+
+Workload: the 181 x 61 half-domain mesh over x in [-30, 30], y in [0, 20] with
+the Gaussian bump 0.2 exp(-(x^2 + y^2)) and F = 0.7 (synthetic, seeded).
+A timed step is one evaluation of the dense residual F(u) in FP64 through the
+C ABI (unpack and x-integration, node and collocation records, all-pairs sums,
+closed-form singular term, dynamic and radiation rows, assembly).  `value` is
+pair-interactions per second (collocation point x source node x y-image).
+
+Also reported: the FP32-compensated evaluation, the all-pairs kernel's
+roofline fraction from HIP events on the launch stream, and the CPU oracle
+timed on a bounded sample of the same workload on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+FLOP_PER_PAIR = 25.5       # algorithmic FLOP per pair (mean over the four boundary pairings)
+PEAK_FP64_VECTOR = 78.6    # TFLOP/s, MI355X
+PEAK_FP32_VECTOR = 157.3   # TFLOP/s, MI355X
+
+
+def cpu_baseline(p, u, budget_s=15.0):
+    """Time the plain CPU oracle's all-pairs sums on a growing sample of collocation rows."""
+    import numpy as np
+    from oracle import residual as R
+    nf = R.reconstruct(p, u)
+    gS, DS, sigS, gB, DB, sigB = R.surface_and_bottom(p, nf)
+    tg = R.targets_from_fields(p, nf, "S")
+    tb = R.targets_from_fields(p, nf, "B")
+    pairs_per_target = 2 * p.N * p.M * (2 if p.half_domain else 1)
+    rng = np.random.default_rng(0)
+    n = 64
+    spent, pairs = 0.0, 0
+    while spent < budget_s:
+        idx = rng.choice(tg.x.size, n, replace=False)
+        t0 = time.perf_counter()
+        R.bie_rows(p, gS, DS, sigS, gB, DB, sigB, R.subset(tg, idx))
+        R.bie_rows(p, gS, DS, sigS, gB, DB, sigB, R.subset(tb, idx))
+        dt = time.perf_counter() - t0
+        spent += dt
+        pairs += 2 * n * pairs_per_target
+        n = min(tg.x.size, n * 2)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pairs / spent, "unit": "pair-interactions/s", "cores": cores, "kind": "oracle",
+            "sample": f"{pairs} pairs: random collocation rows of the 181x61 FP64 residual "
+                      f"(surface and bottom), {spent:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the method's sharding "
+              f"across GPUs is described in DESIGN.md, not run).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1709_08803_amd import bim as B
+    from paper_1709_08803_amd import workloads as W
+
+    p = W.working(0.7)
+    dp = B.DeviceProblem(p)
+    u_host = W.perturbed_state(p, 11)
+    u = torch.as_tensor(u_host, device="cuda")
+    F = torch.empty_like(u)
+    pairs = p.pairs_per_eval()
+
+    for _ in range(args.warmup):
+        B.residual(dp, u, "fp64", out=F)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        B.residual(dp, u, "fp64", out=F)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / args.steps * 1e3
+    value = pairs * args.steps / dt
+
+    # dominant kernel: all-pairs sums, HIP events on the launch stream
+    k64, t64 = B.residual_timed(dp, u, "fp64", iters=max(5, args.steps // 2))
+    k32, t32 = B.residual_timed(dp, u, "fp32c", iters=max(5, args.steps // 2))
+    ach64 = pairs * FLOP_PER_PAIR / (k64 * 1e-3) / 1e12
+    ach32 = pairs * FLOP_PER_PAIR / (k32 * 1e-3) / 1e12
+
+    out = {
+        "metric": "pair-interactions/s + time-to-converged-solve, 181x61 grid: FP64 vs mixed/learned",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "residual F(u), 181x61 half domain, x in [-30,30], y in [0,20], "
+                               "bump 0.2 exp(-(x^2+y^2)), F=0.7, FP64",
+                   "pairs_per_eval": pairs},
+        "roofline": {"bound": "alu", "achieved": ach64, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
+                     "frac": ach64 / PEAK_FP64_VECTOR, "traffic": None,
+                     "kernel": "k_allpairs<double>", "kernel_ms": k64,
+                     "flop_per_pair": FLOP_PER_PAIR},
+        "fp32c": {"eval_ms": t32, "kernel_ms": k32, "pairs_per_s": pairs / (t32 * 1e-3),
+                  "roofline": {"bound": "alu", "achieved": ach32, "peak": PEAK_FP32_VECTOR,
+                               "unit": "TFLOP/s", "frac": ach32 / PEAK_FP32_VECTOR}},
+        "fp64_eval_ms_events": t64,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, u_host)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

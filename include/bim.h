@@ -92,6 +92,136 @@ int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, 
 int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const double *v,
            double h, double *Jv, int prec, void *stream);
 
+/*
+ * Launch shape of the all-pairs kernel (the sums of the boundary-integral rows):
+ *   targets_per_lane: collocation rows handled by one lane (1 or 2);
+ *   unroll:           unroll depth of the loop over source nodes (2, 4 or 8);
+ *   rows_per_chunk:   source rows per workgroup chunk (split of the source
+ *                     dimension across workgroups); <= 0 picks a default.
+ */
+typedef struct bim_pair_config {
+    int32_t targets_per_lane;
+    int32_t unroll;
+    int32_t rows_per_chunk;
+} bim_pair_config;
+
+/*
+ * Measurement aid for benchmarks: enqueues `iters` evaluations of F(u) (as
+ * bim_residual) on `stream` with HIP events recorded on that stream around
+ * every launch of the all-pairs kernel and around every whole evaluation,
+ * waits for them, and returns the average durations in *kernel_ms and
+ * *total_ms (host pointers).  cfg (host, may be NULL) forces a launch shape;
+ * NULL uses the one bim_residual would use.
+ */
+int bim_residual_timed(const bim_problem *prob, const double *u, double *F, int prec, int iters,
+                       const bim_pair_config *cfg, void *stream, double *kernel_ms, double *total_ms);
+
+/*
+ * Autotuner: times the all-pairs kernel for every supported launch shape on
+ * this mesh and precision (with u as the evaluation point), remembers the
+ * fastest for all later calls in this process with the same (N, M,
+ * half_domain, prec), and returns it in *best (host, may be NULL) with its
+ * kernel time in *best_ms (host, may be NULL).  Synchronises the stream.
+ */
+int bim_tune_residual(const bim_problem *prob, const double *u, int prec, void *stream,
+                      bim_pair_config *best, double *best_ms);
+
+/*
+ * Preconditioner P (Section 4.2; Appendix A): the Jacobian J~ of the
+ * linearised discrete problem (Appendix B, with the bottom single layer
+ * entering with density -beta_x as in the residual), with its four dense
+ * blocks kept only within a band of slices |m - l| <= band_halfwidth
+ * ("b blocks of size (N+1) x (N+1) in each row", b = 2 band_halfwidth + 1).
+ * P depends only on the mesh and F (not on u or the bottom).
+ *   band_halfwidth < 0 selects max(1, round(M / 20)) (b ~ M/10 as in Table 1).
+ * precond_setup factors P on the device and returns a library-owned handle
+ * (free with precond_destroy).  It synchronises `stream`.  Device memory used:
+ * precond_bytes().  Requires N + 1 <= 1024.  Returns BIM_EDOMAIN if a block
+ * that must be inverted is singular.
+ * precond_apply enqueues z = P^-1 r (device vectors of 3(N+1)M, z must not
+ * alias r).  Applies on one handle share its scratch: do not overlap them.
+ */
+typedef struct bim_precond bim_precond;
+int precond_setup(const bim_problem *prob, int band_halfwidth, bim_precond **out, void *stream);
+int precond_apply(const bim_precond *P, const double *r, double *z, void *stream);
+void precond_destroy(bim_precond *P);
+int64_t precond_bytes(const bim_precond *P);
+int precond_band(const bim_precond *P);
+
+/*
+ * Options of the Jacobian-free Newton-Krylov solver (Section 3.2).
+ *   ftol:           stop when ||F(u)||_inf <= ftol (FP64 residual);
+ *   gmres_rtol:     relative residual tolerance of each linear solve;
+ *   restart:        GMRES restart length m (Krylov basis of m + 1 vectors);
+ *   max_restarts:   restarts per linear solve;
+ *   max_newton:     Newton steps;
+ *   max_backtracks: halvings of the step length mu in the line search
+ *                   (accept when ||F(u + mu du)||_2 <= (1 - 1e-4 mu) ||F(u)||_2);
+ *   inner_prec:     precision of the all-pairs sums inside the Jacobian-vector
+ *                   products (BIM_FP64 or BIM_FP32C); the Newton residual,
+ *                   the line search and the update are always FP64;
+ *   band_halfwidth: band of the preconditioner built when none is passed;
+ *   use_precond:    0 runs GMRES without preconditioning.
+ * jfnk_default_opts fills 1e-10, 1e-8, 30, 10, 30, 20, BIM_FP64, -1, 1.
+ */
+typedef struct bim_jfnk_opts {
+    double ftol;
+    double gmres_rtol;
+    int32_t restart;
+    int32_t max_restarts;
+    int32_t max_newton;
+    int32_t max_backtracks;
+    int32_t inner_prec;
+    int32_t band_halfwidth;
+    int32_t use_precond;
+} bim_jfnk_opts;
+
+/* Outcome of a solve (host struct).  history[k] = ||F||_inf after k Newton steps. */
+typedef struct bim_jfnk_report {
+    int32_t status;               /* return code of the solve */
+    int32_t newton_iters;
+    int32_t gmres_iters;          /* total Krylov iterations */
+    int32_t residual_evals;       /* FP64 residual evaluations (Newton + line search) */
+    int32_t inner_residual_evals; /* base evaluations F(u) in the inner precision */
+    int32_t jv_evals;             /* Jacobian-vector products (one residual each) */
+    int32_t backtracks;
+    double fnorm_inf;             /* final ||F||_inf */
+    double fnorm0_inf;            /* initial ||F||_inf */
+    double gmres_relres_last;     /* relative residual estimate of the last linear solve */
+    double time_ms;               /* wall time of the call, preconditioner setup included */
+    double precond_ms;            /* preconditioner setup time (0 if one was passed) */
+    double history[64];
+} bim_jfnk_report;
+
+void jfnk_default_opts(bim_jfnk_opts *opts);
+
+/*
+ * Solves F(u) = 0 by damped inexact Newton (Section 3.2): each step solves
+ * J(u) du = -F(u) by restarted GMRES with right preconditioning by P, where
+ * J(u) v is the difference quotient of bim_jv (shift sqrt(eps)(1+||u||)/||v||,
+ * eps of the inner precision), then backtracks on the step length.
+ *   P: a preconditioner from precond_setup for this problem, or NULL to build
+ *      one internally (timed in rep->precond_ms).
+ *   u: device [3(N+1)M], the start on entry, the last iterate on exit.
+ *   opts: NULL for the defaults.  rep: host, may be NULL.
+ * Synchronises `stream` repeatedly (the host takes the Newton and Krylov
+ * decisions).  Returns BIM_OK when ||F||_inf <= ftol, BIM_NOT_CONVERGED after
+ * max_newton steps, BIM_LINESEARCH_FAIL when no step length decreases ||F||,
+ * BIM_EDOMAIN on a non-finite residual.
+ */
+int jfnk_solve(const bim_problem *prob, const bim_precond *P, double *u, const bim_jfnk_opts *opts,
+               bim_jfnk_report *rep, void *stream);
+
+/*
+ * The discrete linear solution used as the Newton start: u_lin = u0 -
+ * J~^-1 F_lin(u0), where u0 is the uniform stream (zeta = 0, phi = psi = x) and
+ * F_lin the linearised residual (Section 4.2, Appendix B): the same
+ * discretisation on the planes z = 0 and z = -1, forced by beta_x.  Solved by
+ * GMRES preconditioned with P (NULL: built internally) to relative tolerance
+ * rtol (<= 0: 1e-12).  u_out: device [3(N+1)M].
+ */
+int bim_linear_start(const bim_problem *prob, const bim_precond *P, double *u_out, double rtol, void *stream);
+
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char *bim_last_error(void);
 

@@ -213,3 +213,59 @@ class Preconditioner:
 
     def matvec(self, z: np.ndarray) -> np.ndarray:
         return self.P @ z
+
+
+def banded_matvec(p, z: np.ndarray, hb: int) -> np.ndarray:
+    """P z without forming P (any mesh size): the linear rows of Appendix B
+    applied to z with the kernel sums restricted to source slices |m - l| <= hb
+    (the singular-subtraction term of the K5 row uses the full row sum, as in J~)."""
+    N, M, F, n, x1, dx = p.N, p.M, p.froude, p.n_decay, p.x1, p.dx
+    nf = R.reconstruct(p, z)  # linear in z: node values and x-derivatives of each block
+    nb = (N + 1) * M
+    out = np.zeros(3 * nb)
+    X, Y = R.collocation_points(p)
+    xs, ys = X.reshape(M, N - 1), Y.reshape(M, N - 1)
+    ci = np.full(N, 1.0)
+    ci[[0, -1]] = 0.5
+    xn = p.x()
+    xlo, xhi, ylo, yhi = R.integration_rectangle(p)
+    zeta_s = R.half_mesh(nf.zeta)
+    zx_s = R.half_mesh(nf.zeta_x)
+    phi_s = R.half_mesh(nf.phi)
+    phx_s = R.half_mesh(nf.phi_x)
+    psi_s = R.half_mesh(nf.psi)
+    F1 = phx_s + zeta_s / (F * F)
+    F2 = -TWO_PI * phi_s
+    F7 = -TWO_PI * psi_s
+    images = (1.0, -1.0) if p.half_domain else (1.0,)
+    for l in range(M):
+        s = xn[None, :] - xs[l][:, None]  # [N-1][N]
+        rowsum = np.zeros(N - 1)
+        for m in range(M):
+            cm = 0.5 if m in (0, M - 1) else 1.0
+            w = p.dx * p.dy * ci * cm
+            k5 = np.zeros((N - 1, N))
+            k6 = np.zeros_like(k5)
+            k7 = np.zeros_like(k5)
+            for iota in images:
+                t = iota * p.y()[m] - ys[l][0]
+                r2 = s * s + t * t
+                k5 += w / np.sqrt(r2)
+                k6 += w / (r2 + 1.0) ** 1.5
+                k7 += w / np.sqrt(r2 + 1.0)
+            rowsum += k5.sum(axis=1)
+            if abs(m - l) <= hb:
+                F2[l] += k5 @ nf.zeta_x[m] + k6 @ nf.psi[m]
+                F7[l] += k7 @ nf.zeta_x[m] + k6 @ nf.phi[m]
+        one = np.ones(N - 1)
+        I5 = R.s2_integral(one, 0 * one, one, xlo - xs[l], xhi - xs[l], ylo - ys[l], yhi - ys[l])
+        F2[l] -= zx_s[l] * (rowsum - I5)
+    rad = {
+        "F5": x1 * nf.zeta_x[:, 0] + n * nf.zeta[:, 0],
+        "F6": x1 / dx * (nf.zeta_x[:, 1] - nf.zeta_x[:, 0]) + n * nf.zeta_x[:, 0],
+        "F3": x1 * nf.phi_x[:, 0] + n * nf.phi[:, 0],
+        "F4": x1 / dx * (nf.phi_x[:, 1] - nf.phi_x[:, 0]) + n * nf.phi_x[:, 0],
+        "F8": x1 * nf.psi_x[:, 0] + n * nf.psi[:, 0],
+        "F9": x1 / dx * (nf.psi_x[:, 1] - nf.psi_x[:, 0]) + n * nf.psi_x[:, 0],
+    }
+    return R.assemble(p, F1, F2, F7, rad)

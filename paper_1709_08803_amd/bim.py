@@ -49,7 +49,22 @@ def lib():
         pp = ctypes.POINTER(_Problem)
         L.bim_residual.argtypes = [pp, vp, vp, i32, vp]
         L.bim_jv.argtypes = [pp, vp, vp, vp, dbl, vp, i32, vp]
-        for name in ("bim_residual", "bim_jv"):
+        L.bim_residual_timed.argtypes = [pp, vp, vp, i32, i32, ctypes.POINTER(PairConfig), vp,
+                                         ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+        L.bim_tune_residual.argtypes = [pp, vp, i32, vp, ctypes.POINTER(PairConfig), ctypes.POINTER(dbl)]
+        L.precond_setup.argtypes = [pp, i32, ctypes.POINTER(vp), vp]
+        L.precond_apply.argtypes = [vp, vp, vp, vp]
+        L.precond_destroy.argtypes = [vp]
+        L.precond_destroy.restype = None
+        L.precond_bytes.argtypes = [vp]
+        L.precond_bytes.restype = ctypes.c_int64
+        L.precond_band.argtypes = [vp]
+        L.jfnk_default_opts.argtypes = [ctypes.POINTER(JfnkOpts)]
+        L.jfnk_default_opts.restype = None
+        L.jfnk_solve.argtypes = [pp, vp, vp, ctypes.POINTER(JfnkOpts), ctypes.POINTER(JfnkReport), vp]
+        L.bim_linear_start.argtypes = [pp, vp, vp, dbl, vp]
+        for name in ("bim_residual", "bim_jv", "bim_residual_timed", "bim_tune_residual", "precond_setup",
+                     "precond_apply", "precond_band", "jfnk_solve", "bim_linear_start"):
             getattr(L, name).restype = i32
         L.bim_last_error.restype = ctypes.c_char_p
         L.bim_version.restype = ctypes.c_char_p
@@ -71,6 +86,33 @@ def _stream(stream: Optional[torch.cuda.Stream]) -> int:
 def _dptr(t: torch.Tensor) -> int:
     assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
     return t.data_ptr()
+
+
+class PairConfig(ctypes.Structure):
+    _fields_ = [("targets_per_lane", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("rows_per_chunk", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.targets_per_lane, self.unroll, self.rows_per_chunk)
+
+
+class JfnkOpts(ctypes.Structure):
+    _fields_ = [("ftol", ctypes.c_double), ("gmres_rtol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("max_restarts", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("max_backtracks", ctypes.c_int32),
+                ("inner_prec", ctypes.c_int32), ("band_halfwidth", ctypes.c_int32), ("use_precond", ctypes.c_int32)]
+
+
+class JfnkReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("newton_iters", ctypes.c_int32), ("gmres_iters", ctypes.c_int32),
+                ("residual_evals", ctypes.c_int32), ("inner_residual_evals", ctypes.c_int32),
+                ("jv_evals", ctypes.c_int32), ("backtracks", ctypes.c_int32), ("fnorm_inf", ctypes.c_double),
+                ("fnorm0_inf", ctypes.c_double), ("gmres_relres_last", ctypes.c_double), ("time_ms", ctypes.c_double),
+                ("precond_ms", ctypes.c_double), ("history", ctypes.c_double * 64)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "history"}
+        d["history"] = [self.history[i] for i in range(min(64, self.newton_iters + 1))]
+        return d
 
 
 class DeviceProblem:
@@ -106,6 +148,98 @@ def jv(dp: DeviceProblem, u: torch.Tensor, Fu: torch.Tensor, v: torch.Tensor, h:
     _check(lib().bim_jv(dp.ref(), _dptr(u), _dptr(Fu), _dptr(v), float(h), _dptr(J), _PREC[prec],
                         _stream(stream)))
     return J
+
+
+def residual_timed(dp: DeviceProblem, u: torch.Tensor, prec="fp64", iters: int = 10, config=None,
+                   stream=None):
+    """(all-pairs kernel ms, whole evaluation ms), averaged over `iters` evaluations (HIP events).
+
+    config: (targets_per_lane, unroll, rows_per_chunk) or None for the current choice.
+    """
+    F = torch.empty_like(u)
+    k, t = ctypes.c_double(), ctypes.c_double()
+    cfg = ctypes.byref(PairConfig(*config)) if config is not None else None
+    _check(lib().bim_residual_timed(dp.ref(), _dptr(u), _dptr(F), _PREC[prec], int(iters), cfg,
+                                    _stream(stream), ctypes.byref(k), ctypes.byref(t)))
+    return k.value, t.value
+
+
+def tune_residual(dp: DeviceProblem, u: torch.Tensor, prec="fp64", stream=None):
+    """Run the in-library autotuner; returns ((tpl, unroll, rows_per_chunk), kernel ms)."""
+    best, ms = PairConfig(), ctypes.c_double()
+    _check(lib().bim_tune_residual(dp.ref(), _dptr(u), _PREC[prec], _stream(stream), ctypes.byref(best),
+                                   ctypes.byref(ms)))
+    return best.as_tuple(), ms.value
+
+
+class Preconditioner:
+    """Library-owned block-banded preconditioner P (freed with close() or on deletion)."""
+
+    def __init__(self, dp: DeviceProblem, band_halfwidth: int = -1, stream=None):
+        self._h = ctypes.c_void_p()
+        self.dp = dp
+        _check(lib().precond_setup(dp.ref(), int(band_halfwidth), ctypes.byref(self._h), _stream(stream)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def band(self) -> int:
+        return lib().precond_band(self._h)
+
+    @property
+    def nbytes(self) -> int:
+        return lib().precond_bytes(self._h)
+
+    def apply(self, r: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        z = out if out is not None else torch.empty_like(r)
+        _check(lib().precond_apply(self._h, _dptr(r), _dptr(z), _stream(stream)))
+        return z
+
+    def close(self):
+        if self._h:
+            lib().precond_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_opts(**kw) -> JfnkOpts:
+    o = JfnkOpts()
+    lib().jfnk_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "inner_prec":
+            v = _PREC[v]
+        setattr(o, k, v)
+    return o
+
+
+def solve(dp: DeviceProblem, u: torch.Tensor, P: Optional[Preconditioner] = None, stream=None,
+          check: bool = True, **opts) -> dict:
+    """jfnk_solve in place on u; returns the report as a dict (status included)."""
+    o = default_opts(**opts)
+    rep = JfnkReport()
+    rc = lib().jfnk_solve(dp.ref(), P.handle if P is not None else None, _dptr(u), ctypes.byref(o),
+                          ctypes.byref(rep), _stream(stream))
+    if rc < 0 and check:
+        _check(rc)
+    d = rep.as_dict()
+    d["status"] = rc
+    return d
+
+
+def linear_start(dp: DeviceProblem, P: Optional[Preconditioner] = None, rtol: float = 0.0,
+                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    u = out if out is not None else torch.empty(dp.n, dtype=torch.float64, device=dp.device)
+    rc = lib().bim_linear_start(dp.ref(), P.handle if P is not None else None, _dptr(u), float(rtol),
+                                _stream(stream))
+    _check(rc)
+    return u
 
 
 def version() -> str:

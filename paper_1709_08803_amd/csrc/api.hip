@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "bim_common.h"
 #include "vec.h"
@@ -68,12 +69,55 @@ int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, 
     if (prec != BIM_FP64 && prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
     hipStream_t s = (hipStream_t)stream;
     const Dims d(prob);
-    const PairLaunch pl = pair_launch(d, 0);
+    const PairLaunch pl = pair_launch_for(prob, prec);
     Scratch sc(s);
     if ((rc = sc.alloc(residual_work_bytes(d, pl)))) return rc;
     ResidualWork w;
     residual_work_carve(sc.ptr, d, pl, &w);
     return residual_enqueue(prob, u, F, prec, pl, w, s);
+}
+
+int bim_residual_timed(const bim_problem *prob, const double *u, double *F, int prec, int iters,
+                       const bim_pair_config *cfg, void *stream, double *kernel_ms, double *total_ms) {
+    g_last_error.clear();
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!u || !F || u == F) return fail(BIM_EINVAL, "u and F must be distinct device pointers");
+    if (prec != BIM_FP64 && prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
+    if (iters < 1 || !kernel_ms || !total_ms) return fail(BIM_EINVAL, "iters >= 1 and result pointers required");
+    hipStream_t s = (hipStream_t)stream;
+    const Dims d(prob);
+    const PairLaunch pl = cfg ? pair_launch(d, cfg->targets_per_lane, cfg->unroll, cfg->rows_per_chunk)
+                              : pair_launch_for(prob, prec);
+    Scratch sc(s);
+    if ((rc = sc.alloc(residual_work_bytes(d, pl)))) return rc;
+    ResidualWork w;
+    residual_work_carve(sc.ptr, d, pl, &w);
+    std::vector<hipEvent_t> ev(4 * (size_t)iters, nullptr);
+    for (auto &e : ev)
+        if ((rc = hip_check(hipEventCreate(&e), "hipEventCreate"))) break;
+    for (int it = 0; rc == BIM_OK && it < iters; ++it) {
+        hipEvent_t *e = &ev[4 * (size_t)it];
+        if ((rc = hip_check(hipEventRecord(e[0], s), "hipEventRecord"))) break;
+        if ((rc = residual_enqueue(prob, u, F, prec, pl, w, s, e + 1))) break;
+        rc = hip_check(hipEventRecord(e[3], s), "hipEventRecord");
+    }
+    if (rc == BIM_OK) rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    double ksum = 0.0, tsum = 0.0;
+    for (int it = 0; rc == BIM_OK && it < iters; ++it) {
+        float a = 0.f, b = 0.f;
+        hipEvent_t *e = &ev[4 * (size_t)it];
+        if ((rc = hip_check(hipEventElapsedTime(&a, e[1], e[2]), "hipEventElapsedTime"))) break;
+        if ((rc = hip_check(hipEventElapsedTime(&b, e[0], e[3]), "hipEventElapsedTime"))) break;
+        ksum += a;
+        tsum += b;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc) return rc;
+    *kernel_ms = ksum / iters;
+    *total_ms = tsum / iters;
+    return BIM_OK;
 }
 
 int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const double *v, double h, double *Jv,
@@ -87,7 +131,7 @@ int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const dou
     if (!std::isfinite(h)) return fail(BIM_EINVAL, "h must be finite");
     hipStream_t s = (hipStream_t)stream;
     const Dims d(prob);
-    const PairLaunch pl = pair_launch(d, 0);
+    const PairLaunch pl = pair_launch_for(prob, prec);
     const size_t vec_bytes = ((sizeof(double) * d.nvec) + 255) & ~(size_t)255;
     const size_t red_bytes = ((sizeof(double) * reduce_parts()) + 255) & ~(size_t)255;
     Scratch sc(s);

@@ -48,14 +48,21 @@ struct alignas(8 * sizeof(T)) SrcRec {
 // Launch shape of the all-pairs kernel: target tiles of 64 collocation points
 // on one mesh row, source rows split into chunks (split-K over sources).
 struct PairLaunch {
+    int tpl;             // collocation rows per lane (1 or 2)
+    int unroll;          // inner-loop unroll over source nodes (2, 4 or 8)
     int tiles_per_row;   // ceil((N-1) / 64)
-    int target_tiles;    // 2 M tiles_per_row
+    int row_groups;      // ceil(M / tpl)
+    int target_tiles;    // 2 row_groups tiles_per_row
     int src_rows;        // 2 nimg M
     int rows_per_chunk;
     int chunks;
     int blocks;          // workgroups of 4 waves
 };
-PairLaunch pair_launch(const Dims &d, int rows_per_chunk_override);
+// tpl/unroll outside the supported set fall back to 1/4; rows_per_chunk <= 0 picks a default.
+PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk);
+// The launch used by the public entry points: the autotuned choice for this
+// (mesh, precision) if bim_tune_residual has run, else the default.
+PairLaunch pair_launch_for(const bim_problem *p, int prec);
 
 // Device workspace of one residual evaluation.
 struct ResidualWork {
@@ -73,7 +80,10 @@ size_t residual_work_bytes(const Dims &d, const PairLaunch &pl);
 void residual_work_carve(void *base, const Dims &d, const PairLaunch &pl, ResidualWork *w);
 
 // Enqueues F = F(u) using a caller-provided workspace (no allocation).
+// ev_pair (optional): two events recorded right before and after the all-pairs launch.
+// linear = 1 evaluates the linearised residual F_lin of Section 4.2 instead.
 int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
-                     const PairLaunch &pl, const ResidualWork &w, hipStream_t s);
+                     const PairLaunch &pl, const ResidualWork &w, hipStream_t s,
+                     hipEvent_t *ev_pair = nullptr, int linear = 0);
 
 }  // namespace bim

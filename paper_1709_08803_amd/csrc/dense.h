@@ -1,0 +1,36 @@
+// FP64 dense kernels used by the preconditioner (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace bim {
+
+// One product of a batched GEMM: C = alpha A B + beta C (row-major).
+struct GemmItem {
+    const double *A;
+    const double *B;
+    double *C;
+};
+// One matrix of a batched inversion: Ainv = A^-1 (s x s, row-major).
+struct InvItem {
+    const double *A;
+    long lda;
+    double *Ainv;
+    long ldinv;
+};
+
+// items_dev: device array of `batch` items; all share m, n, k and leading dims.
+int gemm_enqueue(const GemmItem *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
+                 double alpha, double beta, hipStream_t s);
+// work: device scratch of batch * s * 2s doubles; info[b] = 0 or (1 + column of a zero pivot).
+int invert_enqueue(const InvItem *items_dev, int batch, int s_dim, double *work, int *info, hipStream_t s);
+// y = alpha A x + beta c (dense, rows x cols, row-major with leading dim lda); c may equal y.
+int gemv_enqueue(const double *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
+                 double alpha, double beta, hipStream_t s);
+// y = alpha B x + beta c for a slice-block-banded B stored [M][2w+1][s][s]; c may equal y.
+int bandmv_enqueue(const double *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
+                   double alpha, double beta, hipStream_t s);
+int copy2d_enqueue(const double *src, long lds, double *dst, long ldd, int rows, int cols, hipStream_t s);
+int identity_enqueue(double *A, long n, hipStream_t s);
+
+}  // namespace bim

@@ -1,0 +1,391 @@
+// Jacobian-free Newton-Krylov driver (Section 3.2): damped inexact Newton with a
+// backtracking line search on ||F||_2, each step solved by restarted GMRES with
+// right preconditioning, the Jacobian action replaced by the first-order
+// difference quotient of the residual.  All vectors stay on the device; the
+// host reads back one short column of the Hessenberg matrix per GMRES
+// iteration and a few norms per Newton step to take its decisions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "bim_common.h"
+#include "precond.h"
+#include "vec.h"
+
+namespace bim {
+
+namespace {
+
+inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Workspace {
+    void *mem = nullptr;
+    hipStream_t s = nullptr;
+    ~Workspace() {
+        if (mem) (void)hipFreeAsync(mem, s);
+    }
+};
+
+struct Krylov {
+    const bim_problem *p;
+    Dims d;
+    hipStream_t s;
+    const Precond *pc;
+    int m;                    // restart length
+    PairLaunch pl;            // launch used for both precisions (chunks sized for the larger)
+    ResidualWork rw;
+    double *V, *Z, *w, *ut, *Ft, *r, *part, *hdev, *scal, *ydev;
+    double *hhost;            // pinned: h column + norm
+    long n;
+    int jv_evals = 0, res_evals = 0;
+    // Jacobian action of the current Newton point
+    const double *u = nullptr, *Fin = nullptr;
+    int prec = BIM_FP64, linear = 0;
+    double eps = 0;
+
+    int jv(const double *z, double *out) {
+        int rc;
+        if (linear) {
+            // F_lin is affine: F_lin(u + z) - F_lin(u) = J~ z exactly
+            if ((rc = fd_shift_enqueue(u, z, n, 1.0, eps, part, scal, s))) return rc;
+        } else if ((rc = fd_shift_enqueue(u, z, n, 0.0, eps, part, scal, s))) {
+            return rc;
+        }
+        if ((rc = axpy_dev_enqueue(u, z, scal + 2, ut, n, s))) return rc;
+        if ((rc = residual_enqueue(p, ut, Ft, prec, pl, rw, s, nullptr, linear))) return rc;
+        ++jv_evals;
+        return quotient_enqueue(Ft, Fin, scal + 2, out, n, s);
+    }
+    int apply_prec(const double *v, double *z) {
+        if (pc) return precond_apply_enqueue(pc, v, z, s);
+        return hip_check(hipMemcpyAsync(z, v, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy");
+    }
+    int norm_to_host(const double *v, double *out) {
+        int rc;
+        if ((rc = dot_enqueue(v, v, n, part, scal + 3, true, s))) return rc;
+        if ((rc = hip_check(hipMemcpyAsync(hhost, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s), "copy")))
+            return rc;
+        if ((rc = hip_check(hipStreamSynchronize(s), "sync"))) return rc;
+        *out = hhost[0];
+        return BIM_OK;
+    }
+
+    // Solves J x = b approximately (x zero-initialised here); returns iterations used.
+    int gmres(const double *b, double *x, double rtol, int max_restarts, int *iters, double *relres) {
+        int rc;
+        *iters = 0;
+        if ((rc = hip_check(hipMemsetAsync(x, 0, sizeof(double) * n, s), "memset"))) return rc;
+        if ((rc = hip_check(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy")))
+            return rc;
+        double beta;
+        if ((rc = norm_to_host(r, &beta))) return rc;
+        const double beta0 = beta;
+        *relres = 1.0;
+        if (!(beta0 > 0.0)) {
+            *relres = 0.0;
+            return std::isfinite(beta0) ? BIM_OK : fail(BIM_EDOMAIN, "non-finite right-hand side");
+        }
+        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+        for (int cyc = 0; cyc <= max_restarts; ++cyc) {
+            // v0 = r / beta
+            hhost[0] = beta;
+            if ((rc = hip_check(hipMemcpyAsync(scal + 3, hhost, sizeof(double), hipMemcpyHostToDevice, s), "copy")))
+                return rc;
+            if ((rc = scale_inv_enqueue(r, scal + 3, V, n, s))) return rc;
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int jend = 0;
+            bool done = false;
+            for (int j = 0; j < m; ++j) {
+                double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
+                if ((rc = apply_prec(vj, zj))) return rc;
+                if ((rc = jv(zj, w))) return rc;
+                // classical Gram-Schmidt, twice
+                if ((rc = multidot_enqueue(V, n, j + 1, w, n, part, hdev, false, s))) return rc;
+                if ((rc = orth_update_enqueue(V, n, j + 1, hdev, w, n, s))) return rc;
+                if ((rc = multidot_enqueue(V, n, j + 1, w, n, part, hdev + m + 1, false, s))) return rc;
+                if ((rc = orth_update_enqueue(V, n, j + 1, hdev + m + 1, w, n, s))) return rc;
+                if ((rc = dot_enqueue(w, w, n, part, hdev + 2 * (m + 1), true, s))) return rc;
+                if ((rc = scale_inv_enqueue(w, hdev + 2 * (m + 1), vn, n, s))) return rc;
+                if ((rc = hip_check(hipMemcpyAsync(hhost, hdev, sizeof(double) * (3 * (m + 1)),
+                                                   hipMemcpyDeviceToHost, s), "copy")))
+                    return rc;
+                if ((rc = hip_check(hipStreamSynchronize(s), "sync"))) return rc;
+                ++*iters;
+                double *col = &H[(size_t)j];  // column j: H[i * m + j]
+                for (int i = 0; i <= j; ++i) col[(size_t)i * m] = hhost[i] + hhost[m + 1 + i];
+                const double hn = hhost[2 * (m + 1)];
+                col[(size_t)(j + 1) * m] = hn;
+                if (!std::isfinite(hn)) return fail(BIM_EDOMAIN, "non-finite Krylov vector");
+                for (int i = 0; i < j; ++i) {  // previous rotations
+                    const double a = col[(size_t)i * m], bb = col[(size_t)(i + 1) * m];
+                    col[(size_t)i * m] = cs[i] * a + sn[i] * bb;
+                    col[(size_t)(i + 1) * m] = -sn[i] * a + cs[i] * bb;
+                }
+                const double a = col[(size_t)j * m], bb = col[(size_t)(j + 1) * m];
+                const double rr = std::hypot(a, bb);
+                cs[j] = rr > 0 ? a / rr : 1.0;
+                sn[j] = rr > 0 ? bb / rr : 0.0;
+                col[(size_t)j * m] = rr;
+                col[(size_t)(j + 1) * m] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                jend = j + 1;
+                *relres = std::fabs(g[j + 1]) / beta0;
+                if (*relres <= rtol || hn == 0.0) {
+                    done = true;
+                    break;
+                }
+            }
+            // y = H^-1 g (upper triangular), x += Z y
+            for (int i = jend - 1; i >= 0; --i) {
+                double v = g[i];
+                for (int k = i + 1; k < jend; ++k) v -= H[(size_t)i * m + k] * y[k];
+                y[i] = v / H[(size_t)i * m + i];
+            }
+            if ((rc = hip_check(hipMemcpyAsync(ydev, y.data(), sizeof(double) * jend, hipMemcpyHostToDevice, s),
+                                "copy")))
+                return rc;
+            if ((rc = combine_enqueue(Z, n, jend, ydev, x, n, s))) return rc;
+            if ((rc = hip_check(hipStreamSynchronize(s), "sync"))) return rc;  // y host buffer reuse
+            if (done || cyc == max_restarts) break;
+            // true residual r = b - J x
+            if ((rc = jv(x, w))) return rc;
+            if ((rc = axpby_enqueue(1.0, b, -1.0, w, r, n, s))) return rc;
+            if ((rc = norm_to_host(r, &beta))) return rc;
+            *relres = beta / beta0;
+            if (*relres <= rtol) break;
+        }
+        return BIM_OK;
+    }
+};
+
+int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const bim_jfnk_opts *o,
+               bim_jfnk_report *rep, hipStream_t s, bool linear_start_only) {
+    auto t0 = std::chrono::steady_clock::now();
+    const Dims d(p);
+    const long n = d.nvec;
+    const int m = std::max(1, o->restart);
+    Krylov K{p, d, s};
+    K.n = n;
+    K.m = m;
+    // one workspace sized for the larger chunk count of the two precisions
+    const PairLaunch pl64 = pair_launch_for(p, BIM_FP64), pl32 = pair_launch_for(p, BIM_FP32C);
+    PairLaunch plw = pl64.chunks >= pl32.chunks ? pl64 : pl32;
+    size_t bytes = residual_work_bytes(d, plw);
+    const size_t vb = al256(sizeof(double) * n);
+    bytes += vb * ((size_t)(m + 1) + m + 8);                        // V, Z, w, ut, Ft, r, x, F, Fin, delta
+    bytes += al256(sizeof(double) * (size_t)reduce_parts() * (m + 1));  // part
+    bytes += al256(sizeof(double) * 3 * (m + 1)) + al256(sizeof(double) * 8) + al256(sizeof(double) * (m + 1));
+    Workspace ws;
+    ws.s = s;
+    int rc = hip_check(hipMallocAsync(&ws.mem, bytes, s), "hipMallocAsync(jfnk)");
+    if (rc) return rc;
+    double *hhost = nullptr;
+    rc = hip_check(hipHostMalloc((void **)&hhost, sizeof(double) * 3 * (m + 2)), "hipHostMalloc");
+    if (rc) return rc;
+    struct HostFree {
+        double *p;
+        ~HostFree() {
+            if (p) (void)hipHostFree(p);
+        }
+    } hf{hhost};
+    residual_work_carve(ws.mem, d, plw, &K.rw);
+    char *c = (char *)ws.mem + K.rw.bytes;
+    auto take = [&](size_t b) {
+        char *q = c;
+        c += al256(b);
+        return (double *)q;
+    };
+    K.V = take(sizeof(double) * n * (m + 1));
+    K.Z = take(sizeof(double) * n * m);
+    K.w = take(sizeof(double) * n);
+    K.ut = take(sizeof(double) * n);
+    K.Ft = take(sizeof(double) * n);
+    K.r = take(sizeof(double) * n);
+    double *F = take(sizeof(double) * n);
+    double *Fin = take(sizeof(double) * n);
+    double *delta = take(sizeof(double) * n);
+    double *rhs = take(sizeof(double) * n);
+    K.part = take(sizeof(double) * (size_t)reduce_parts() * (m + 1));
+    K.hdev = take(sizeof(double) * 3 * (m + 1));
+    K.scal = take(sizeof(double) * 8);
+    K.ydev = take(sizeof(double) * (m + 1));
+    K.hhost = hhost;
+    K.pl = plw;
+
+    // preconditioner: caller's, or built here
+    bim_precond *own = nullptr;
+    double precond_ms = 0.0;
+    if (!P && o->use_precond) {
+        auto tp = std::chrono::steady_clock::now();
+        if ((rc = precond_setup(p, o->band_halfwidth, &own, s))) return rc;
+        precond_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
+        P = own;
+    }
+    struct OwnFree {
+        bim_precond *p;
+        ~OwnFree() {
+            if (p) precond_destroy(p);
+        }
+    } of{own};
+    K.pc = o->use_precond ? precond_impl(P) : nullptr;
+
+    bim_jfnk_report R{};
+    R.precond_ms = precond_ms;
+    auto finish = [&](int status) {
+        R.status = status;
+        R.jv_evals = K.jv_evals;
+        R.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (rep) *rep = R;
+        return status;
+    };
+
+    if (linear_start_only) {
+        // u_lin = u0 - J~^-1 F_lin(u0): one linear solve with the exact linear operator
+        if ((rc = uniform_stream_enqueue(u_io, d.N, d.M, p->x1, s))) return rc;
+        if ((rc = residual_enqueue(p, u_io, F, BIM_FP64, plw, K.rw, s, nullptr, 1))) return rc;
+        if ((rc = axpby_enqueue(-1.0, F, 0.0, nullptr, rhs, n, s))) return rc;
+        K.u = u_io;
+        K.Fin = F;
+        K.prec = BIM_FP64;
+        K.linear = 1;
+        K.eps = std::ldexp(1.0, -52);
+        int it = 0;
+        double rr = 1.0;
+        if ((rc = K.gmres(rhs, delta, o->gmres_rtol, o->max_restarts, &it, &rr))) return rc;
+        if ((rc = axpby_enqueue(1.0, u_io, 1.0, delta, u_io, n, s))) return rc;
+        if ((rc = hip_check(hipStreamSynchronize(s), "sync"))) return rc;
+        R.gmres_iters = it;
+        R.gmres_relres_last = rr;
+        return finish(rr <= o->gmres_rtol * 10 ? BIM_OK : BIM_NOT_CONVERGED);
+    }
+
+    auto norms = [&](const double *v, double *n2, double *ninf) -> int {
+        int q;
+        if ((q = dot_enqueue(v, v, n, K.part, K.scal + 4, true, s))) return q;
+        if ((q = maxabs_enqueue(v, n, K.part, K.scal + 5, s))) return q;
+        if ((q = hip_check(hipMemcpyAsync(hhost, K.scal + 4, sizeof(double) * 2, hipMemcpyDeviceToHost, s), "copy")))
+            return q;
+        if ((q = hip_check(hipStreamSynchronize(s), "sync"))) return q;
+        *n2 = hhost[0];
+        *ninf = hhost[1];
+        return BIM_OK;
+    };
+
+    if ((rc = residual_enqueue(p, u_io, F, BIM_FP64, plw, K.rw, s))) return rc;
+    R.residual_evals = 1;
+    double fn2, finf;
+    if ((rc = norms(F, &fn2, &finf))) return rc;
+    R.fnorm0_inf = finf;
+    const int maxh = (int)(sizeof(R.history) / sizeof(R.history[0]));
+    for (int k = 0;; ++k) {
+        if (k < maxh) R.history[k] = finf;
+        R.fnorm_inf = finf;
+        R.newton_iters = k;
+        if (!std::isfinite(fn2)) return finish(fail(BIM_EDOMAIN, "non-finite residual"));
+        if (finf <= o->ftol) return finish(BIM_OK);
+        if (k >= o->max_newton) return finish(BIM_NOT_CONVERGED);
+        // inner Jacobian action around u in the requested precision
+        K.u = u_io;
+        K.prec = o->inner_prec;
+        K.linear = 0;
+        K.eps = (o->inner_prec == BIM_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+        if (o->inner_prec == BIM_FP64) {
+            K.Fin = F;
+        } else {
+            if ((rc = residual_enqueue(p, u_io, Fin, o->inner_prec, plw, K.rw, s))) return rc;
+            ++R.inner_residual_evals;
+            K.Fin = Fin;
+        }
+        if ((rc = axpby_enqueue(-1.0, F, 0.0, nullptr, rhs, n, s))) return rc;
+        int it = 0;
+        double rr = 1.0;
+        if ((rc = K.gmres(rhs, delta, o->gmres_rtol, o->max_restarts, &it, &rr))) return rc;
+        R.gmres_iters += it;
+        R.gmres_relres_last = rr;
+        // backtracking line search on ||F||_2 (sufficient decrease)
+        double mu = 1.0;
+        bool ok = false;
+        for (int bt = 0; bt <= o->max_backtracks; ++bt) {
+            if ((rc = axpby_enqueue(1.0, u_io, mu, delta, K.ut, n, s))) return rc;
+            if ((rc = residual_enqueue(p, K.ut, K.Ft, BIM_FP64, plw, K.rw, s))) return rc;
+            ++R.residual_evals;
+            double tn2, tinf;
+            if ((rc = norms(K.Ft, &tn2, &tinf))) return rc;
+            if (std::isfinite(tn2) && tn2 <= (1.0 - 1e-4 * mu) * fn2) {
+                ok = true;
+                fn2 = tn2;
+                finf = tinf;
+                break;
+            }
+            ++R.backtracks;
+            mu *= 0.5;
+        }
+        if (!ok) return finish(BIM_LINESEARCH_FAIL);
+        if ((rc = hip_check(hipMemcpyAsync(u_io, K.ut, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy")))
+            return rc;
+        if ((rc = hip_check(hipMemcpyAsync(F, K.Ft, sizeof(double) * n, hipMemcpyDeviceToDevice, s), "copy")))
+            return rc;
+    }
+}
+
+}  // namespace
+
+}  // namespace bim
+
+using namespace bim;
+
+extern "C" {
+
+void jfnk_default_opts(bim_jfnk_opts *o) {
+    if (!o) return;
+    o->ftol = 1e-10;
+    o->gmres_rtol = 1e-8;
+    o->restart = 30;
+    o->max_restarts = 10;
+    o->max_newton = 30;
+    o->max_backtracks = 20;
+    o->inner_prec = BIM_FP64;
+    o->band_halfwidth = -1;
+    o->use_precond = 1;
+}
+
+static int check_opts(const bim_jfnk_opts *o) {
+    if (!o) return fail(BIM_EINVAL, "options are NULL");
+    if (!(o->ftol > 0) || !(o->gmres_rtol > 0) || o->restart < 1 || o->restart > 200 || o->max_restarts < 0 ||
+        o->max_newton < 0 || o->max_backtracks < 0)
+        return fail(BIM_EINVAL, "invalid solver options");
+    if (o->inner_prec != BIM_FP64 && o->inner_prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
+    return BIM_OK;
+}
+
+int jfnk_solve(const bim_problem *prob, const bim_precond *P, double *u, const bim_jfnk_opts *opts,
+               bim_jfnk_report *rep, void *stream) {
+    int rc = validate(prob);
+    if (rc) return rc;
+    bim_jfnk_opts o;
+    jfnk_default_opts(&o);
+    if (opts) o = *opts;
+    if ((rc = check_opts(&o))) return rc;
+    if (!u) return fail(BIM_EINVAL, "u must be a device pointer");
+    return solve_impl(prob, P, u, &o, rep, (hipStream_t)stream, false);
+}
+
+int bim_linear_start(const bim_problem *prob, const bim_precond *P, double *u_out, double rtol, void *stream) {
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!u_out) return fail(BIM_EINVAL, "u_out must be a device pointer");
+    bim_jfnk_opts o;
+    jfnk_default_opts(&o);
+    o.gmres_rtol = rtol > 0 ? rtol : 1e-12;
+    o.max_restarts = 20;
+    bim_jfnk_report r{};
+    return solve_impl(prob, P, u_out, &o, &r, (hipStream_t)stream, true);
+}
+
+}  // extern "C"

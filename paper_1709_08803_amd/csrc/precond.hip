@@ -1,0 +1,552 @@
+// Block-banded preconditioner P (Section 4.2 and Appendix A) on gfx950.
+//
+// P is the Jacobian J~ of the linearised discrete system (Appendix B) with its
+// four dense blocks (2,1), (2,3), (3,1), (3,2) kept only for slice pairs
+// |m - l| <= h (slice-block band).  With the unknowns and rows grouped in three
+// blocks of n = (N+1) M (zeta | phi | psi; F1 | F2 | F7) and each block in M
+// slices of s = N+1:
+//      [ P11 P12  0  ]   P11, P12, P22 = P33: the same s x s block on every slice
+//  P = [ P21 P22 P23 ]   P21, P23 = P32, P31: slice-block-banded, half-width h
+//      [ P31 P32 P33 ]
+// The paper factors P as a 3 x 3 block LU in the order 1, 2, 3, which leaves
+// two dense n x n factor blocks (L32, U33).  Here the block-diagonal blocks
+// 1 and 3 are eliminated first:
+//      E = P11^-1 P12,  G = P33^-1 (P32 - P31 E)                 (band h)
+//      S = P22 - P21 E - P23 G                                    (band 2h)
+// so that P z = r is solved exactly by
+//      a1 = P11^-1 r1,  a3 = P33^-1 (r3 - P31 a1)
+//      z2 = S^-1 (r2 - P21 a1 - P23 a3),  z3 = a3 - G z2,  z1 = a1 - E z2.
+// S is factored by a block LU without inter-block pivoting (its diagonal
+// blocks are inverted with partial pivoting) and its inverse is formed
+// explicitly, so that the apply is one dense GEMV plus banded products, all
+// bound by HBM bandwidth.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "bim_common.h"
+#include "dense.h"
+#include "precond.h"
+
+namespace bim {
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Coefficient of dx (f_x)_i in the trapezoidal node value f_k (0-based).
+__device__ __forceinline__ double trap(int k, int i) {
+    if (k == 0 || i > k) return 0.0;
+    if (i == 0 || i == k) return 0.5;
+    return 1.0;
+}
+// Coefficient of dx (f_x)_i in the half-mesh value f*_k = (f_k + f_{k+1}) / 2.
+__device__ __forceinline__ double tau(int k, int i) { return 0.5 * (trap(k, i) + trap(k + 1, i)); }
+
+// The three slice-diagonal blocks (identical on every slice):
+//   D11: F5, F6, F1 on zeta;  D12: F1 on phi;  D22 (= D33): F3, F4, F2 on phi.
+__global__ void k_diag_blocks(double *D11, double *D12, double *D22, int N, double x1, double dx, double n_decay,
+                              double froude) {
+    const int s = N + 1;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)s * s) return;
+    const int r = (int)(e / s), c = (int)(e % s);
+    double d11 = 0.0, d12 = 0.0, d22 = 0.0;
+    if (r == 0) {  // F5 / F3: x1 f_x,1 + n f_1
+        if (c == 0) d11 = d22 = n_decay;
+        if (c == 1) d11 = d22 = x1;
+    } else if (r == 1) {  // F6 / F4: (x1/dx) f_x,2 + (n - x1/dx) f_x,1
+        if (c == 1) d11 = d22 = n_decay - x1 / dx;
+        if (c == 2) d11 = d22 = x1 / dx;
+    } else {
+        const int k = r - 2;
+        const double pt = (c == 0) ? 1.0 : dx * tau(k, c - 1);  // d f*_k / d u-slice
+        d11 = pt / (froude * froude);
+        d22 = -kTwoPi * pt;
+        if (c == 1 + k || c == 2 + k) d12 = 0.5;
+    }
+    D11[e] = d11;
+    D12[e] = d12;
+    D22[e] = d22;
+}
+
+// Per collocation point (k, l): sum over every node and image of w K5, and the
+// exact integral of K5 over the truncated (mirrored) rectangle.
+__global__ __launch_bounds__(64) void k_k5_rowsum(double *rowsum, double *I5, int N, int M, double x1, double dx,
+                                                  double y1, double dy, int nimg, double xlo, double xhi,
+                                                  double ylo, double yhi) {
+    const int t = blockIdx.x;  // l (N-1) + k
+    const int l = t / (N - 1), k = t - l * (N - 1);
+    const int lane = threadIdx.x;
+    const double xs = x1 + (k + 0.5) * dx, ys = y1 + l * dy;
+    double v = 0.0;
+    for (int img = 0; img < nimg; ++img) {
+        const double iota = img ? -1.0 : 1.0;
+        for (int n = lane; n < N * M; n += 64) {
+            const int m = n / N, i = n - m * N;
+            const double ci = (i == 0 || i == N - 1) ? 0.5 : 1.0, cm = (m == 0 || m == M - 1) ? 0.5 : 1.0;
+            const double s = x1 + i * dx - xs, tt = iota * (y1 + m * dy) - ys;
+            v += dx * dy * ci * cm / sqrt(s * s + tt * tt);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) {
+        rowsum[t] = v;
+        auto G = [](double s, double tt) {
+            double g = 0.0;
+            const double q = sqrt(s * s + tt * tt);
+            if (tt != 0.0) g += tt * log(2.0 * s + 2.0 * q);
+            if (s != 0.0) g += s * log(2.0 * tt + 2.0 * q);
+            return g;
+        };
+        const double s1 = xlo - xs, s2 = xhi - xs, t1 = ylo - ys, t2 = yhi - ys;
+        I5[t] = G(s2, t2) - G(s1, t2) - G(s2, t1) + G(s1, t1);
+    }
+}
+
+// Band blocks of P21 (K5 on zeta_x, with the singular subtraction on slice l),
+// P31 (K7 on zeta_x) and P23 = P32 (K6 on the node values of a potential).
+// One wave per (l, band offset, k) row; zero rows 0, 1 (radiation) are left
+// from the initial clear.
+__global__ __launch_bounds__(64) void k_band_rows(double *B21, double *B23, double *B31, const double *rowsum,
+                                                  const double *I5, int N, int M, int h, double x1, double dx,
+                                                  double y1, double dy, int nimg) {
+    const int s = N + 1;
+    const int idx = blockIdx.x;  // (l (2h+1) + off) (N-1) + k
+    const int k = idx % (N - 1);
+    const int lo = idx / (N - 1);
+    const int off = lo % (2 * h + 1), l = lo / (2 * h + 1);
+    const int m = l + off - h;
+    if (m < 0 || m >= M) return;
+    const int lane = threadIdx.x;
+    const size_t blk = ((size_t)l * (2 * h + 1) + off) * s * s;
+    double *r21 = B21 + blk + (size_t)(2 + k) * s;
+    double *r23 = B23 + blk + (size_t)(2 + k) * s;
+    double *r31 = B31 + blk + (size_t)(2 + k) * s;
+    const double xs = x1 + (k + 0.5) * dx, ys = y1 + l * dy;
+    const double cm = (m == 0 || m == M - 1) ? 0.5 : 1.0;
+    // singular subtraction of the K5 row sum on the target's own slice (d/d zeta*_x)
+    const double corr = (m == l) ? 0.5 * (rowsum[l * (N - 1) + k] - I5[l * (N - 1) + k]) : 0.0;
+    // suffix sums of w K6 from the right end of the slice
+    double carry = 0.0;
+    const int nseg = (N + 63) / 64;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int i = seg * 64 + lane;
+        double k5 = 0.0, k6 = 0.0, k7 = 0.0;
+        if (i < N) {
+            const double ci = (i == 0 || i == N - 1) ? 0.5 : 1.0;
+            const double w = dx * dy * ci * cm;
+            const double sx = x1 + i * dx - xs;
+            for (int img = 0; img < nimg; ++img) {
+                const double tt = (img ? -1.0 : 1.0) * (y1 + m * dy) - ys;
+                const double r2 = sx * sx + tt * tt;
+                k5 += w / sqrt(r2);
+                const double q = 1.0 / sqrt(r2 + 1.0);
+                k7 += w * q;
+                k6 += w * q * q * q;
+            }
+            r21[1 + i] = k5 - ((i == k || i == k + 1) ? corr : 0.0);
+            r31[1 + i] = k7;
+        }
+        // inclusive suffix scan of k6 within the segment (lane i gets sum over lanes >= i)
+        double v = k6;
+        for (int o = 1; o < 64; o <<= 1) {
+            const double y = __shfl_down(v, o, 64);
+            if (lane + o < 64) v += y;
+        }
+        const double strict_after = v - k6 + carry;  // sum over nodes > i
+        if (i < N && i >= 1) r23[1 + i] = dx * (0.5 * k6 + strict_after);
+        if (i == 0) {
+            // column of f_1: sum of all; column of (f_x)_1: dx/2 sum over i >= 1
+            const double total = v + carry;
+            r23[0] = total;
+            r23[1] = 0.5 * dx * (total - k6);
+        }
+        carry += __shfl(v, 0, 64);
+    }
+}
+
+// Replicate one s x s block into every diagonal slot of a band-0 array.
+__global__ void k_replicate(const double *src, double *dst, int M, long ss) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)M * ss) return;
+    dst[e] = src[e % ss];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host orchestration
+struct DevArena {
+    char *base = nullptr;
+    size_t used = 0, cap = 0;
+    template <typename T>
+    T *take(size_t count) {
+        size_t bytes = (sizeof(T) * count + 255) & ~(size_t)255;
+        T *p = (T *)(base + used);
+        used += bytes;
+        return p;
+    }
+};
+
+static size_t band_elems(int M, int w, int s) { return (size_t)M * (2 * w + 1) * s * s; }
+
+static double *band_blk(double *band, int w, int s, int l, int m) {
+    return band + ((size_t)l * (2 * w + 1) + (m - l + w)) * s * s;
+}
+
+int precond_build(const bim_problem *p, int hb, Precond **out, hipStream_t st) {
+    const Dims d(p);
+    const int N = d.N, M = d.M, s = N + 1;
+    const int h = hb;
+    const long n = (long)s * M;
+    const int w2 = 2 * h;
+    Precond *pc = new Precond();
+    pc->N = N;
+    pc->M = M;
+    pc->s = s;
+    pc->h = h;
+    pc->n = n;
+    // layout of the persistent part
+    size_t pers = 0;
+    auto add = [&](size_t elems) { pers += (sizeof(double) * elems + 255) & ~(size_t)255; };
+    add(band_elems(M, 0, s));  // Dinv11 replicated
+    add(band_elems(M, 0, s));  // Dinv22 replicated
+    add(band_elems(M, 0, s));  // E replicated
+    add(band_elems(M, h, s));  // B21
+    add(band_elems(M, h, s));  // B23
+    add(band_elems(M, h, s));  // B31
+    add(band_elems(M, h, s));  // G
+    add((size_t)n * n);        // S^-1
+    add((size_t)4 * n);        // apply scratch
+    pc->bytes = pers;
+    int rc = hip_check(hipMalloc(&pc->mem, pers), "hipMalloc(preconditioner)");
+    if (rc) {
+        delete pc;
+        return rc;
+    }
+    DevArena ar{(char *)pc->mem, 0, pers};
+    pc->Dinv11 = ar.take<double>(band_elems(M, 0, s));
+    pc->Dinv22 = ar.take<double>(band_elems(M, 0, s));
+    pc->E = ar.take<double>(band_elems(M, 0, s));
+    pc->B21 = ar.take<double>(band_elems(M, h, s));
+    pc->B23 = ar.take<double>(band_elems(M, h, s));
+    pc->B31 = ar.take<double>(band_elems(M, h, s));
+    pc->G = ar.take<double>(band_elems(M, h, s));
+    pc->Sinv = ar.take<double>((size_t)n * n);
+    pc->scratch = ar.take<double>((size_t)4 * n);
+
+    // setup-only scratch
+    size_t tmp = 0;
+    auto addt = [&](size_t bytes) { tmp += (bytes + 255) & ~(size_t)255; };
+    addt(sizeof(double) * 3 * s * s);               // D11, D12, D22
+    addt(sizeof(double) * 2 * s * s);               // single inverses
+    addt(sizeof(double) * 2 * d.ntg);               // rowsum5, I5
+    addt(sizeof(double) * band_elems(M, h, s));     // T (band h)
+    addt(sizeof(double) * band_elems(M, w2, s));    // S band 2h
+    addt(sizeof(double) * (size_t)M * s * s);       // Uinv
+    addt(sizeof(double) * (size_t)M * s * w2 * s);  // L rows
+    addt(sizeof(double) * (size_t)M * s * w2 * s);  // U rows
+    addt(sizeof(double) * (size_t)s * n);           // one block row of S^-1 (temp)
+    addt(sizeof(double) * (size_t)4 * s * 2 * s);   // inversion work
+    addt(sizeof(int) * (M + 2));                    // info
+    const size_t nitems = 64 + (size_t)M * (2 * h + 1) * 4 + (size_t)M * (2 * w2 + 1) * (2 * h + 3) +
+                          (size_t)M * (w2 * w2 + w2 + 2) + 16;
+    addt(sizeof(GemmItem) * nitems);
+    addt(sizeof(InvItem) * (M + 4));
+    void *tbase = nullptr;
+    rc = hip_check(hipMallocAsync(&tbase, tmp, st), "hipMallocAsync(preconditioner setup)");
+    if (rc) {
+        (void)hipFree(pc->mem);
+        delete pc;
+        return rc;
+    }
+    DevArena ta{(char *)tbase, 0, tmp};
+    double *D11 = ta.take<double>((size_t)3 * s * s);
+    double *D12 = D11 + (size_t)s * s;
+    double *D22 = D12 + (size_t)s * s;
+    double *Dinv11 = ta.take<double>((size_t)2 * s * s);
+    double *Dinv22 = Dinv11 + (size_t)s * s;
+    double *rowsum = ta.take<double>((size_t)2 * d.ntg);
+    double *I5 = rowsum + d.ntg;
+    double *T = ta.take<double>(band_elems(M, h, s));
+    double *S = ta.take<double>(band_elems(M, w2, s));
+    double *Uinv = ta.take<double>((size_t)M * s * s);
+    double *Lrow = ta.take<double>((size_t)M * s * w2 * s);
+    double *Urow = ta.take<double>((size_t)M * s * w2 * s);
+    double *rowtmp = ta.take<double>((size_t)s * n);
+    double *invwork = ta.take<double>((size_t)4 * s * 2 * s);
+    int *info = ta.take<int>(M + 2);
+    GemmItem *items_dev = ta.take<GemmItem>(nitems);
+    InvItem *inv_dev = ta.take<InvItem>(M + 4);
+
+    std::vector<GemmItem> items;
+    items.reserve(nitems);
+    std::vector<InvItem> invs;
+    struct Op {
+        int kind;  // 0 gemm, 1 invert, 2 copy rows
+        size_t first;
+        int count, m, nn, k, lda, ldb, ldc;
+        double alpha, beta;
+    };
+    std::vector<Op> ops;
+    auto gemm = [&](std::vector<GemmItem> batch, int m_, int n_, int k_, int lda, int ldb, int ldc, double al,
+                    double be) {
+        if (batch.empty()) return;
+        ops.push_back({0, items.size(), (int)batch.size(), m_, n_, k_, lda, ldb, ldc, al, be});
+        items.insert(items.end(), batch.begin(), batch.end());
+    };
+    const double xN = p->x1 + (N - 1) * p->dx, yM = p->y1 + (M - 1) * p->dy;
+    const double ylo = p->half_domain ? -yM : p->y1;
+
+#define RUN(x)                   \
+    do {                         \
+        const int rc_ = (x);     \
+        if (rc_) return rc_;     \
+    } while (0)
+
+    rc = [&]() -> int {
+    // 1. diagonal blocks and their inverses, E = D11^-1 D12
+    hipLaunchKernelGGL(k_diag_blocks, dim3(cdiv((long)s * s, 256)), dim3(256), 0, st, D11, D12, D22, N, p->x1,
+                       p->dx, p->n_decay, p->froude);
+    invs.push_back({D11, s, Dinv11, s});
+    invs.push_back({D22, s, Dinv22, s});
+    RUN(hip_check(hipMemcpyAsync(inv_dev, invs.data(), sizeof(InvItem) * 2, hipMemcpyHostToDevice, st), "copy"));
+    RUN(invert_enqueue(inv_dev, 2, s, invwork, info, st));
+    hipLaunchKernelGGL(k_replicate, dim3(cdiv((long)M * s * s, 256)), dim3(256), 0, st, Dinv11, pc->Dinv11, M,
+                       (long)s * s);
+    hipLaunchKernelGGL(k_replicate, dim3(cdiv((long)M * s * s, 256)), dim3(256), 0, st, Dinv22, pc->Dinv22, M,
+                       (long)s * s);
+
+    // 2. band blocks of P21, P23 (= P32), P31
+    for (double *b : {pc->B21, pc->B23, pc->B31})
+        RUN(hip_check(hipMemsetAsync(b, 0, sizeof(double) * band_elems(M, h, s), st), "memset"));
+    hipLaunchKernelGGL(k_k5_rowsum, dim3(d.ntg), dim3(64), 0, st, rowsum, I5, N, M, p->x1, p->dx, p->y1, p->dy,
+                       d.nimg, p->x1, xN, ylo, yM);
+    hipLaunchKernelGGL(k_band_rows, dim3(M * (2 * h + 1) * (N - 1)), dim3(64), 0, st, pc->B21, pc->B23, pc->B31,
+                       rowsum, I5, N, M, h, p->x1, p->dx, p->y1, p->dy, d.nimg);
+    RUN(hip_check(hipGetLastError(), "band assembly launch"));
+
+    {
+        // E (one block) then replicated
+        gemm({{Dinv11, D12, rowtmp}}, s, s, s, s, s, s, 1.0, 0.0);
+        // T[l][m] = B23[l][m] - B31[l][m] E ; G[l][m] = Dinv22 T[l][m]
+        std::vector<GemmItem> b1, b2, b3;
+        for (int l = 0; l < M; ++l)
+            for (int m = std::max(0, l - h); m <= std::min(M - 1, l + h); ++m) {
+                b1.push_back({band_blk(pc->B31, h, s, l, m), rowtmp, band_blk(T, h, s, l, m)});
+                b2.push_back({Dinv22, band_blk(T, h, s, l, m), band_blk(pc->G, h, s, l, m)});
+            }
+        // S = D22 on the diagonal, - B21 E within band h, - sum_q B23[l][q] G[q][m]
+        std::vector<GemmItem> bS1;
+        for (int l = 0; l < M; ++l)
+            for (int m = std::max(0, l - h); m <= std::min(M - 1, l + h); ++m)
+                bS1.push_back({band_blk(pc->B21, h, s, l, m), rowtmp, band_blk(S, w2, s, l, m)});
+        // enqueue in dependency order
+        size_t op0 = ops.size();
+        (void)op0;
+        // E first (needs Dinv11)
+        // T = B23 copy is done before the -B31 E accumulation (copy via GEMM with beta)
+        gemm(b1, s, s, s, s, s, s, -1.0, 1.0);  // T := T - B31 E   (T pre-filled with B23)
+        gemm(b2, s, s, s, s, s, s, 1.0, 0.0);   // G := Dinv22 T
+        gemm(bS1, s, s, s, s, s, s, -1.0, 1.0); // S := S - B21 E   (S pre-filled with D22 on the diagonal)
+        for (int dq = -h; dq <= h; ++dq) {
+            std::vector<GemmItem> bq;
+            for (int l = 0; l < M; ++l) {
+                const int q = l + dq;
+                if (q < 0 || q >= M) continue;
+                for (int m = std::max(0, q - h); m <= std::min(M - 1, q + h); ++m)
+                    bq.push_back({band_blk(pc->B23, h, s, l, q), band_blk(pc->G, h, s, q, m),
+                                  band_blk(S, w2, s, l, m)});
+            }
+            gemm(bq, s, s, s, s, s, s, -1.0, 1.0);
+        }
+    }
+    // block LU of S (band 2h): per step l, L[q][l] = S[q][l] Uinv[l] (into Lrow), then
+    // S[q][m] -= L[q][l] S[l][m] for q, m in l+1..l+2h
+    std::vector<size_t> lu_ops_first(M), lu_ops_count(M);
+    for (int l = 0; l < M; ++l) {
+        lu_ops_first[l] = ops.size();
+        std::vector<GemmItem> bl, bu;
+        for (int q = l + 1; q <= std::min(M - 1, l + w2); ++q) {
+            double *Lql = Lrow + ((size_t)q * s) * (w2 * s) + (size_t)(l - (q - w2)) * s;  // ld = w2 s
+            bl.push_back({band_blk(S, w2, s, q, l), Uinv + (size_t)l * s * s, Lql});
+        }
+        gemm(bl, s, s, s, s, s, w2 * s, 1.0, 0.0);
+        for (int q = l + 1; q <= std::min(M - 1, l + w2); ++q)
+            for (int m = l + 1; m <= std::min(M - 1, l + w2); ++m) {
+                const double *Lql = Lrow + ((size_t)q * s) * (w2 * s) + (size_t)(l - (q - w2)) * s;
+                bu.push_back({Lql, band_blk(S, w2, s, l, m), band_blk(S, w2, s, q, m)});
+            }
+        // lda of L blocks is w2 s; other operands s: handled by a dedicated op (A stride differs)
+        gemm(bu, s, s, s, w2 * s, s, s, -1.0, 1.0);
+        lu_ops_count[l] = ops.size() - lu_ops_first[l];
+    }
+    for (int l = 0; l < M; ++l) invs.push_back({band_blk(S, w2, s, l, l), s, Uinv + (size_t)l * s * s, s});
+
+    // upload all item arrays once
+    RUN(hip_check(hipMemcpyAsync(items_dev, items.data(), sizeof(GemmItem) * items.size(), hipMemcpyHostToDevice,
+                                 st),
+                  "copy"));
+    RUN(hip_check(hipMemcpyAsync(inv_dev, invs.data(), sizeof(InvItem) * invs.size(), hipMemcpyHostToDevice, st),
+                  "copy"));
+    {
+        auto run_op = [&](const Op &o) {
+            return gemm_enqueue(items_dev + o.first, o.count, o.m, o.nn, o.k, o.lda, o.ldb, o.ldc, o.alpha, o.beta,
+                                st);
+        };
+        // E, replicated
+        RUN(run_op(ops[0]));
+        hipLaunchKernelGGL(k_replicate, dim3(cdiv((long)M * s * s, 256)), dim3(256), 0, st, rowtmp, pc->E, M,
+                           (long)s * s);
+        // T := B23 ; S := 0 with D22 on the diagonal
+        RUN(copy2d_enqueue(pc->B23, 1, T, 1, 1, (int)band_elems(M, h, s), st));
+        RUN(hip_check(hipMemsetAsync(S, 0, sizeof(double) * band_elems(M, w2, s), st), "memset"));
+        for (int l = 0; l < M; ++l) RUN(copy2d_enqueue(D22, s, band_blk(S, w2, s, l, l), s, s, s, st));
+        for (size_t q = 1; q < lu_ops_first[0]; ++q) RUN(run_op(ops[q]));
+        // zero L/U row buffers (short rows at the ends stay zero)
+        RUN(hip_check(hipMemsetAsync(Lrow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));
+        RUN(hip_check(hipMemsetAsync(Urow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));
+        for (int l = 0; l < M; ++l) {
+            RUN(invert_enqueue(inv_dev + 2 + l, 1, s, invwork, info + 2 + l, st));
+            for (size_t q = 0; q < lu_ops_count[l]; ++q) RUN(run_op(ops[lu_ops_first[l] + q]));
+        }
+        // U rows: U[l][m] for m = l+1..l+2h packed as [l][s][2h s]
+        for (int l = 0; l < M; ++l)
+            for (int m = l + 1; m <= std::min(M - 1, l + w2); ++m)
+                RUN(copy2d_enqueue(band_blk(S, w2, s, l, m), s, Urow + ((size_t)l * s) * (w2 * s) + (size_t)(m - l - 1) * s,
+                                   w2 * s, s, s, st));
+        // S^-1: forward with L (unit lower), backward with U
+        RUN(identity_enqueue(pc->Sinv, n, st));
+        std::vector<GemmItem> fw, bw1, bw2;
+        for (int l = 1; l < M; ++l) {
+            const int q0 = std::max(0, l - w2);
+            fw.push_back({Lrow + ((size_t)l * s) * (w2 * s) + (size_t)(q0 - (l - w2)) * s, pc->Sinv + (size_t)q0 * s * n,
+                          pc->Sinv + (size_t)l * s * n});
+        }
+        for (int l = M - 1; l >= 0; --l) {
+            bw1.push_back({Urow + ((size_t)l * s) * (w2 * s), pc->Sinv + (size_t)(l + 1) * s * n,
+                           pc->Sinv + (size_t)l * s * n});
+            bw2.push_back({Uinv + (size_t)l * s * s, pc->Sinv + (size_t)l * s * n, rowtmp});
+        }
+        const size_t base = items.size();
+        std::vector<GemmItem> all;
+        all.insert(all.end(), fw.begin(), fw.end());
+        all.insert(all.end(), bw1.begin(), bw1.end());
+        all.insert(all.end(), bw2.begin(), bw2.end());
+        (void)base;
+        GemmItem *sv_dev = items_dev + items.size();
+        if (items.size() + all.size() > nitems)
+            return fail(BIM_EINVAL, "internal: preconditioner item buffer too small");
+        RUN(hip_check(hipMemcpyAsync(sv_dev, all.data(), sizeof(GemmItem) * all.size(), hipMemcpyHostToDevice, st),
+                      "copy"));
+        for (int l = 1; l < M; ++l) {
+            const int q0 = std::max(0, l - w2);
+            // only columns of block rows < l can be nonzero in rows q < l of L^-1
+            RUN(gemm_enqueue(sv_dev + (l - 1), 1, s, l * s, (l - q0) * s, w2 * s, (int)n, (int)n, -1.0, 1.0, st));
+        }
+        for (int t = 0; t < M; ++t) {
+            const int l = M - 1 - t;
+            const int kk = std::min(M - 1, l + w2) - l;  // number of blocks to the right
+            if (kk > 0)
+                RUN(gemm_enqueue(sv_dev + (M - 1) + t, 1, s, (int)n, kk * s, w2 * s, (int)n, (int)n, -1.0, 1.0, st));
+            RUN(gemm_enqueue(sv_dev + (M - 1) + M + t, 1, s, (int)n, s, s, (int)n, (int)n, 1.0, 0.0, st));
+            RUN(copy2d_enqueue(rowtmp, n, pc->Sinv + (size_t)l * s * n, n, s, (int)n, st));
+        }
+        // a zero pivot in any inverted block makes P singular in this factorisation
+        std::vector<int> hinfo(2 + M, 0);
+        RUN(hip_check(hipMemcpyAsync(hinfo.data(), info, sizeof(int) * (2 + M), hipMemcpyDeviceToHost, st),
+                      "copy"));
+        RUN(hip_check(hipStreamSynchronize(st), "hipStreamSynchronize"));
+        for (int q = 0; q < 2 + M; ++q)
+            if (hinfo[q]) return fail(BIM_EDOMAIN, "preconditioner: singular diagonal block " + std::to_string(q));
+    }
+    return BIM_OK;
+    }();
+#undef RUN
+    (void)hipFreeAsync(tbase, st);
+    if (rc) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(pc->mem);
+        delete pc;
+        return rc;
+    }
+    *out = pc;
+    return BIM_OK;
+}
+
+int precond_apply_enqueue(const Precond *pc, const double *r, double *z, hipStream_t st) {
+    const int M = pc->M, s = pc->s, h = pc->h;
+    const long n = pc->n;
+    const double *r1 = r, *r2 = r + n, *r3 = r + 2 * n;
+    double *z1 = z, *z2 = z + n, *z3 = z + 2 * n;
+    double *a1 = pc->scratch, *a3 = a1 + n, *t2 = a3 + n, *t3 = t2 + n;
+    int rc;
+    if ((rc = bandmv_enqueue(pc->Dinv11, M, 0, s, r1, nullptr, a1, 1.0, 0.0, st))) return rc;       // a1
+    if ((rc = bandmv_enqueue(pc->B31, M, h, s, a1, r3, t3, -1.0, 1.0, st))) return rc;              // r3 - P31 a1
+    if ((rc = bandmv_enqueue(pc->Dinv22, M, 0, s, t3, nullptr, a3, 1.0, 0.0, st))) return rc;       // a3
+    if ((rc = bandmv_enqueue(pc->B21, M, h, s, a1, r2, t2, -1.0, 1.0, st))) return rc;              // r2 - P21 a1
+    if ((rc = bandmv_enqueue(pc->B23, M, h, s, a3, t2, t2, -1.0, 1.0, st))) return rc;              // - P23 a3
+    if ((rc = gemv_enqueue(pc->Sinv, n, t2, nullptr, z2, (int)n, (int)n, 1.0, 0.0, st))) return rc; // z2
+    if ((rc = bandmv_enqueue(pc->G, M, h, s, z2, a3, z3, -1.0, 1.0, st))) return rc;                // z3
+    return bandmv_enqueue(pc->E, M, 0, s, z2, a1, z1, -1.0, 1.0, st);                               // z1
+}
+
+void precond_free(Precond *pc) {
+    if (!pc) return;
+    if (pc->mem) (void)hipFree(pc->mem);
+    delete pc;
+}
+
+}  // namespace bim
+
+// ------------------------------------------------------------------ C ABI
+struct bim_precond {
+    bim::Precond *pc;
+};
+
+using namespace bim;
+
+extern "C" {
+
+int precond_setup(const bim_problem *prob, int band_halfwidth, bim_precond **out, void *stream) {
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!out) return fail(BIM_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    const int hb = band_halfwidth < 0 ? std::max(1, (int)std::lround(prob->M / 20.0)) : band_halfwidth;
+    if (hb < 1 || hb >= prob->M) return fail(BIM_EINVAL, "band half-width must be in [1, M-1]");
+    if (prob->N + 1 > 1024) return fail(BIM_EINVAL, "N + 1 must not exceed 1024");
+    Precond *pc = nullptr;
+    rc = precond_build(prob, hb, &pc, (hipStream_t)stream);
+    if (rc) return rc;
+    *out = new bim_precond{pc};
+    return BIM_OK;
+}
+
+int precond_apply(const bim_precond *P, const double *r, double *z, void *stream) {
+    if (!P || !P->pc) return fail(BIM_EINVAL, "preconditioner handle is NULL");
+    if (!r || !z) return fail(BIM_EINVAL, "r and z must be device pointers");
+    if (r == z) return fail(BIM_EINVAL, "z must not alias r");
+    return precond_apply_enqueue(P->pc, r, z, (hipStream_t)stream);
+}
+
+void precond_destroy(bim_precond *P) {
+    if (!P) return;
+    precond_free(P->pc);
+    delete P;
+}
+
+int64_t precond_bytes(const bim_precond *P) { return (P && P->pc) ? (int64_t)P->pc->bytes : 0; }
+
+int precond_band(const bim_precond *P) { return (P && P->pc) ? P->pc->h : 0; }
+
+}  // extern "C"
+
+namespace bim {
+Precond *precond_impl(const bim_precond *P) { return P ? P->pc : nullptr; }
+}  // namespace bim

@@ -36,20 +36,28 @@ __device__ __forceinline__ double rsq(double x) {
 }
 
 // ------------------------------------------------------------------ A1: unpack + x-integration
-// f_{1,j} + trapezoidal integral of f_x along slice j (Section 3.1).
-__global__ void k_integrate(const double *__restrict__ u, double *__restrict__ nodes, int N, int M,
-                            double dx) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 3 * M) return;
+// f_{1,j} + trapezoidal integral of f_x along slice j (Section 3.1).  One wave
+// per (field, slice): 64-wide inclusive scans of the trapezoid increments with
+// the running total carried from one 64-node segment to the next.
+__global__ __launch_bounds__(64) void k_integrate(const double *__restrict__ u, double *__restrict__ nodes,
+                                                  int N, int M, double dx) {
+    const int idx = blockIdx.x;  // field * M + slice
     const int f = idx / M, j = idx - f * M;
+    const int lane = threadIdx.x;
     const double *s = u + (size_t)f * (N + 1) * M + (size_t)j * (N + 1);
     double *o = nodes + ((size_t)f * M + j) * N;
     const double hdx = 0.5 * dx;
-    double acc = s[0];
-    o[0] = acc;
-    for (int i = 1; i < N; ++i) {
-        acc += hdx * (s[i] + s[i + 1]);
-        o[i] = acc;
+    double carry = s[0];
+    for (int base = 0; base < N; base += 64) {
+        const int i = base + lane;
+        // increment into node i: (dx/2)(f_x,i-1 + f_x,i), zero for the first node
+        double v = (i > 0 && i < N) ? hdx * (s[i] + s[i + 1]) : 0.0;
+        for (int o2 = 1; o2 < 64; o2 <<= 1) {
+            const double y = __shfl_up(v, o2, 64);
+            if (lane >= o2) v += y;
+        }
+        if (i < N) o[i] = carry + v;
+        carry += __shfl(v, 63, 64);
     }
 }
 
@@ -71,7 +79,7 @@ __global__ void k_nodes(const double *__restrict__ u, const double *__restrict__
                         const double *__restrict__ beta, const double *__restrict__ beta_x,
                         const double *__restrict__ beta_y, double *__restrict__ ydiv,
                         SrcRec<T> *__restrict__ srcS, SrcRec<T> *__restrict__ srcB, int N, int M,
-                        double x1, double dx, double dy, int half) {
+                        double x1, double dx, double dy, int half, int linear) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N * M) return;
     const int j = n / N, i = n - j * N;
@@ -86,11 +94,13 @@ __global__ void k_nodes(const double *__restrict__ u, const double *__restrict__
     const double ci = (i == 0 || i == N - 1) ? 0.5 : 1.0;
     const double cj = (j == 0 || j == M - 1) ? 0.5 : 1.0;
     const double w = dx * dy * ci * cj;
+    // linear mode: the boundaries are the planes z = 0 and z = -1 (Section 4.2);
+    // the layer densities are unchanged
     SrcRec<T> a;
     a.x = (T)x;
-    a.z = (T)zeta[n];
-    a.zx = (T)zx;
-    a.zy = (T)zy;
+    a.z = linear ? (T)0 : (T)zeta[n];
+    a.zx = linear ? (T)0 : (T)zx;
+    a.zy = linear ? (T)0 : (T)zy;
     a.wD = (T)(w * (phi[n] - x));
     a.ws = (T)(w * zx);
     a.w = (T)w;
@@ -99,9 +109,9 @@ __global__ void k_nodes(const double *__restrict__ u, const double *__restrict__
     // bottom: outward normal points down, so both layers enter with -w
     SrcRec<T> b;
     b.x = (T)x;
-    b.z = (T)beta[n];
-    b.zx = (T)beta_x[n];
-    b.zy = (T)beta_y[n];
+    b.z = linear ? (T)-1 : (T)beta[n];
+    b.zx = linear ? (T)0 : (T)beta_x[n];
+    b.zy = linear ? (T)0 : (T)beta_y[n];
     b.wD = (T)(-w * (psi[n] - x));
     b.ws = (T)(-w * beta_x[n]);
     b.w = (T)(-w);
@@ -117,7 +127,7 @@ __global__ void k_targets(const double *__restrict__ nodes, const double *__rest
                           const double *__restrict__ u, const double *__restrict__ beta,
                           const double *__restrict__ beta_x, const double *__restrict__ beta_y,
                           double *__restrict__ tg, float *__restrict__ tg32, int N, int M, double x1,
-                          double dx, double y1, double dy) {
+                          double dx, double y1, double dy, int linear) {
     const int ntg = (N - 1) * M;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * ntg) return;
@@ -143,6 +153,10 @@ __global__ void k_targets(const double *__restrict__ nodes, const double *__rest
         ay = 0.5 * (beta_y[n0] + beta_y[n1]);
         sig = -ax;
     }
+    if (linear) {  // flat boundaries: elevation 0 or -1, S2 = 1/r
+        d = st ? -1.0 : 0.0;
+        ax = ay = 0.0;
+    }
     const size_t T2 = (size_t)2 * ntg;
     const double v[8] = {xs, ys, d, D, 1.0 + ax * ax, 2.0 * ax * ay, 1.0 + ay * ay, sig};
     for (int q = 0; q < 8; ++q) tg[q * T2 + t] = v[q];
@@ -150,20 +164,45 @@ __global__ void k_targets(const double *__restrict__ nodes, const double *__rest
 }
 
 // ------------------------------------------------------------------ A2: all-pairs sums (hot loop)
-// One wave = 64 collocation points on one mesh row of one boundary; it walks a
-// chunk of source rows (boundary, image, y-row) and, for each, all N nodes of
-// that row.  Source records are read with wave-uniform addresses (scalar
-// loads); y-dependent terms are hoisted per source row.  Per pair:
+// One wave = 64 consecutive collocation points x*_k on TPL mesh rows of one
+// boundary.  It walks a chunk of source rows (boundary, image, y-row) and, for
+// each, all N nodes of that row.  Source records are read with wave-uniform
+// addresses (scalar loads) and shared by the TPL targets of a lane; every
+// y-dependent term is hoisted per source row because y* is uniform in the wave.
+// Per pair:
 //   own boundary:   w (D - D*) K1 + w sigma K2  and  w S2   (two rsqrt)
 //   other boundary: w D K1 + w sigma K2                      (one rsqrt)
 // written as  ri (coef num ri^2 + w sigma)  with ri = 1/R.
 // FP32C: FP32 sums over one source row, combined across rows with Neumaier's
 // compensated summation; the chunk result is written in FP64.
+template <typename T>
+struct TargetState {
+    T ys, d, Dst, A, B, C;        // collocation data
+    T t, ti, t2, Bt, Ct2;         // per source row
+    T acc, acc2;                  // per source row sums
+    T sum, comp, s2sum, s2comp;   // across rows
+};
+
 template <typename T, bool COMP>
+__device__ __forceinline__ void row_end(TargetState<T> &g) {
+    if (COMP) {
+        T tsum = g.sum + g.acc;
+        g.comp += (fabs(g.sum) >= fabs(g.acc)) ? ((g.sum - tsum) + g.acc) : ((g.acc - tsum) + g.sum);
+        g.sum = tsum;
+        T tq = g.s2sum + g.acc2;
+        g.s2comp += (fabs(g.s2sum) >= fabs(g.acc2)) ? ((g.s2sum - tq) + g.acc2) : ((g.acc2 - tq) + g.s2sum);
+        g.s2sum = tq;
+    } else {
+        g.sum += g.acc;
+        g.s2sum += g.acc2;
+    }
+}
+
+template <typename T, bool COMP, int TPL, int UNROLL>
 __global__ __launch_bounds__(256) void k_allpairs(
     const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB, const T *__restrict__ tg,
-    int N, int M, int nimg, double y1, double dy, int tiles_per_row, int target_tiles, int chunks,
-    int rows_per_chunk, double *__restrict__ part) {
+    int N, int M, int nimg, double y1, double dy, int tiles_per_row, int row_groups, int target_tiles,
+    int chunks, int rows_per_chunk, double *__restrict__ part) {
     const int lane = threadIdx.x & 63;
     // the wave index is uniform: keep it (and everything derived) in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -172,80 +211,98 @@ __global__ __launch_bounds__(256) void k_allpairs(
     if (c >= chunks) return;
     const int ntg = (N - 1) * M;
     const size_t T2 = (size_t)2 * ntg;
-    const int st = tt / (M * tiles_per_row);
-    const int rem = tt - st * M * tiles_per_row;
-    const int l = rem / tiles_per_row;
-    const int k = (rem - l * tiles_per_row) * 64 + lane;
-    const bool valid = k < N - 1;
-    const int tid = st * ntg + l * (N - 1) + (valid ? k : N - 2);
-    const T xs = tg[0 * T2 + tid], ys = tg[1 * T2 + tid], d = tg[2 * T2 + tid], Dst = tg[3 * T2 + tid];
-    const T A = tg[4 * T2 + tid], B = tg[5 * T2 + tid], C = tg[6 * T2 + tid];
-
+    const int st = tt / (row_groups * tiles_per_row);
+    const int rem = tt - st * row_groups * tiles_per_row;
+    const int lg = rem / tiles_per_row;
+    const int k = (rem - lg * tiles_per_row) * 64 + lane;
+    const bool kvalid = k < N - 1;
+    const int kk = kvalid ? k : N - 2;
+    TargetState<T> ts[TPL];
+    T xs = 0;
+#pragma unroll
+    for (int q = 0; q < TPL; ++q) {
+        const int l = min(lg * TPL + q, M - 1);
+        const int tid = st * ntg + l * (N - 1) + kk;
+        xs = tg[0 * T2 + tid];
+        ts[q].ys = tg[1 * T2 + tid];
+        ts[q].d = tg[2 * T2 + tid];
+        ts[q].Dst = tg[3 * T2 + tid];
+        ts[q].A = tg[4 * T2 + tid];
+        ts[q].B = tg[5 * T2 + tid];
+        ts[q].C = tg[6 * T2 + tid];
+        ts[q].sum = ts[q].comp = ts[q].s2sum = ts[q].s2comp = 0;
+    }
     const int nrows = 2 * nimg * M;
     const int r0 = c * rows_per_chunk;
     const int r1 = min(nrows, r0 + rows_per_chunk);
-
-    T sum = 0, comp = 0;     // running (compensated) sum of the layer terms
-    T s2sum = 0, s2comp = 0; // running sum of w S2 over the own boundary
     for (int r = r0; r < r1; ++r) {
         const int ss = r & 1;  // interleave boundaries so every chunk mixes both
         const int rr = r >> 1;
         const int img = rr / M;
         const int j = rr - img * M;
         const T iota = img ? T(-1) : T(1);
-        const T t = T(iota * (y1 + j * dy)) - ys;
-        const T ti = t * iota;      // multiplies the source's a_y (mirrored on the image)
-        const T t2 = t * t;
+        const T yj = T(iota * (y1 + j * dy));
+#pragma unroll
+        for (int q = 0; q < TPL; ++q) {
+            ts[q].t = yj - ts[q].ys;
+            ts[q].ti = ts[q].t * iota;  // multiplies the source's a_y (mirrored on the image)
+            ts[q].t2 = ts[q].t * ts[q].t;
+            ts[q].Bt = ts[q].B * ts[q].t;
+            ts[q].Ct2 = ts[q].C * ts[q].t2;
+            ts[q].acc = 0;
+            ts[q].acc2 = 0;
+        }
         const SrcRec<T> *__restrict__ src = (ss ? srcB : srcS) + (size_t)j * N;
-        T acc = 0, acc2 = 0;
         if (ss == st) {
-            const T Bt = B * t, Ct2 = C * t2;
-#pragma unroll 4
+#pragma unroll UNROLL
             for (int i = 0; i < N; ++i) {
-                const SrcRec<T> q = src[i];
-                const T s = q.x - xs;
-                const T dz = q.z - d;
-                const T r2 = fma(dz, dz, fma(s, s, t2));
-                const T ri = rsq(r2);
-                const T num = fma(-s, q.zx, fma(-ti, q.zy, dz));
-                const T ri2 = ri * ri;
-                const T coef = fma(-Dst, q.w, q.wD);
-                const T bsum = fma(coef * num, ri2, q.ws);
-                acc = fma(bsum, ri, acc);
-                const T Q = fma(s, fma(A, s, Bt), Ct2);
-                acc2 = fma(q.w, rsq(Q), acc2);
+                const SrcRec<T> p = src[i];
+                const T s = p.x - xs;
+#pragma unroll
+                for (int q = 0; q < TPL; ++q) {
+                    TargetState<T> &e = ts[q];
+                    const T dz = p.z - e.d;
+                    const T r2 = fma(dz, dz, fma(s, s, e.t2));
+                    const T ri = rsq(r2);
+                    const T num = fma(-s, p.zx, fma(-e.ti, p.zy, dz));
+                    const T ri2 = ri * ri;
+                    const T coef = fma(-e.Dst, p.w, p.wD);
+                    const T bsum = fma(coef * num, ri2, p.ws);
+                    e.acc = fma(bsum, ri, e.acc);
+                    const T Q = fma(s, fma(e.A, s, e.Bt), e.Ct2);
+                    e.acc2 = fma(p.w, rsq(Q), e.acc2);
+                }
             }
         } else {
-#pragma unroll 4
+#pragma unroll UNROLL
             for (int i = 0; i < N; ++i) {
-                const SrcRec<T> q = src[i];
-                const T s = q.x - xs;
-                const T dz = q.z - d;
-                const T r2 = fma(dz, dz, fma(s, s, t2));
-                const T ri = rsq(r2);
-                const T num = fma(-s, q.zx, fma(-ti, q.zy, dz));
-                const T ri2 = ri * ri;
-                const T bsum = fma(q.wD * num, ri2, q.ws);
-                acc = fma(bsum, ri, acc);
+                const SrcRec<T> p = src[i];
+                const T s = p.x - xs;
+#pragma unroll
+                for (int q = 0; q < TPL; ++q) {
+                    TargetState<T> &e = ts[q];
+                    const T dz = p.z - e.d;
+                    const T r2 = fma(dz, dz, fma(s, s, e.t2));
+                    const T ri = rsq(r2);
+                    const T num = fma(-s, p.zx, fma(-e.ti, p.zy, dz));
+                    const T ri2 = ri * ri;
+                    const T bsum = fma(p.wD * num, ri2, p.ws);
+                    e.acc = fma(bsum, ri, e.acc);
+                }
             }
         }
-        if (COMP) {
-            // Neumaier: exact error of each addition kept in comp
-            T tsum = sum + acc;
-            comp += (fabs(sum) >= fabs(acc)) ? ((sum - tsum) + acc) : ((acc - tsum) + sum);
-            sum = tsum;
-            T tq = s2sum + acc2;
-            s2comp += (fabs(s2sum) >= fabs(acc2)) ? ((s2sum - tq) + acc2) : ((acc2 - tq) + s2sum);
-            s2sum = tq;
-        } else {
-            sum += acc;
-            s2sum += acc2;
-        }
+#pragma unroll
+        for (int q = 0; q < TPL; ++q) row_end<T, COMP>(ts[q]);
     }
-    if (valid) {
-        double *o = part + ((size_t)c * T2 + tid) * 2;
-        o[0] = (double)sum + (double)comp;
-        o[1] = (double)s2sum + (double)s2comp;
+#pragma unroll
+    for (int q = 0; q < TPL; ++q) {
+        const int l = lg * TPL + q;
+        if (kvalid && l < M) {
+            const int tid = st * ntg + l * (N - 1) + k;
+            double *o = part + ((size_t)c * T2 + tid) * 2;
+            o[0] = (double)ts[q].sum + (double)ts[q].comp;
+            o[1] = (double)ts[q].s2sum + (double)ts[q].s2comp;
+        }
     }
 }
 
@@ -265,7 +322,7 @@ __global__ void k_finalize(const double *__restrict__ u, const double *__restric
                            const double *__restrict__ ydiv, const double *__restrict__ tg,
                            const double *__restrict__ part, double *__restrict__ F, int N, int M,
                            int chunks, double x1, double dx, double xlo, double xhi, double ylo,
-                           double yhi, double n_decay, double froude) {
+                           double yhi, double n_decay, double froude, int linear) {
     const int nblk = (N + 1) * M;
     const int row = blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= 3 * nblk) return;
@@ -299,7 +356,8 @@ __global__ void k_finalize(const double *__restrict__ u, const double *__restric
         const double q = 0.5 * (ydiv[(size_t)N * M + n0] + ydiv[(size_t)N * M + n1]);
         const double kin = 0.5 * ((1.0 + a * a) * q * q + (1.0 + b * b) * p * p - 2.0 * a * b * p * q) /
                            (1.0 + a * a + b * b);
-        F[row] = kin + z / (froude * froude) - 0.5;
+        // linear mode: eq. (linear_dynamic2), phi*_x + zeta*/F^2 - 1
+        F[row] = linear ? p + z / (froude * froude) - 1.0 : kin + z / (froude * froude) - 0.5;
         return;
     }
     // boundary-integral rows: F2 (blk 1, free surface), F7 (blk 2, bottom)
@@ -325,14 +383,17 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
-PairLaunch pair_launch(const Dims &d, int rows_per_chunk_override) {
+PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk) {
     PairLaunch pl;
+    pl.tpl = (tpl == 2) ? 2 : 1;
+    pl.unroll = (unroll == 2 || unroll == 8) ? unroll : 4;
     pl.tiles_per_row = cdiv(d.N - 1, 64);
-    pl.target_tiles = 2 * d.M * pl.tiles_per_row;
+    pl.row_groups = cdiv(d.M, pl.tpl);
+    pl.target_tiles = 2 * pl.row_groups * pl.tiles_per_row;
     pl.src_rows = 2 * d.nimg * d.M;
-    int rpc = rows_per_chunk_override;
+    int rpc = rows_per_chunk;
     if (rpc <= 0) {
-        // aim at ~16 resident-wave slots' worth of waves per SIMD (1024 SIMDs)
+        // aim at ~16 waves per SIMD (1024 SIMDs) so the last wave of waves is a small tail
         const long want_waves = 16384;
         int chunks = std::max(1, std::min(pl.src_rows, cdiv(want_waves, pl.target_tiles)));
         rpc = cdiv(pl.src_rows, chunks);
@@ -372,38 +433,55 @@ void residual_work_carve(void *base, const Dims &d, const PairLaunch &pl, Residu
 }
 
 int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec, const PairLaunch &pl,
-                     const ResidualWork &w, hipStream_t s) {
+                     const ResidualWork &w, hipStream_t s, hipEvent_t *ev_pair, int linear) {
     const Dims d(p);
     const int N = d.N, M = d.M;
     const double xN = p->x1 + (N - 1) * p->dx, yM = p->y1 + (M - 1) * p->dy;
     const double ylo = p->half_domain ? -yM : p->y1;
-    hipLaunchKernelGGL(k_integrate, dim3(cdiv(3 * M, 64)), dim3(64), 0, s, u, w.nodes, N, M, p->dx);
+    hipLaunchKernelGGL(k_integrate, dim3(3 * M), dim3(64), 0, s, u, w.nodes, N, M, p->dx);
     const int nb = cdiv(d.nnode, 256);
     if (prec == BIM_FP64) {
         hipLaunchKernelGGL(k_nodes<double>, dim3(nb), dim3(256), 0, s, u, w.nodes, p->beta, p->beta_x,
                            p->beta_y, w.ydiv, (SrcRec<double> *)w.srcS, (SrcRec<double> *)w.srcB, N, M,
-                           p->x1, p->dx, p->dy, p->half_domain);
+                           p->x1, p->dx, p->dy, p->half_domain, linear);
     } else {
         hipLaunchKernelGGL(k_nodes<float>, dim3(nb), dim3(256), 0, s, u, w.nodes, p->beta, p->beta_x,
                            p->beta_y, w.ydiv, (SrcRec<float> *)w.srcS, (SrcRec<float> *)w.srcB, N, M,
-                           p->x1, p->dx, p->dy, p->half_domain);
+                           p->x1, p->dx, p->dy, p->half_domain, linear);
     }
     hipLaunchKernelGGL(k_targets, dim3(cdiv(2 * d.ntg, 256)), dim3(256), 0, s, w.nodes, w.ydiv, u, p->beta,
-                       p->beta_x, p->beta_y, w.tg, w.tg32, N, M, p->x1, p->dx, p->y1, p->dy);
+                       p->beta_x, p->beta_y, w.tg, w.tg32, N, M, p->x1, p->dx, p->y1, p->dy, linear);
+    if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[0], s));
+#define BIM_LAUNCH_PAIRS(T, COMP, TPL, UNR, TG)                                                         \
+    hipLaunchKernelGGL((k_allpairs<T, COMP, TPL, UNR>), dim3(pl.blocks), dim3(256), 0, s,               \
+                       (const SrcRec<T> *)w.srcS, (const SrcRec<T> *)w.srcB, TG, N, M, d.nimg, p->y1,   \
+                       p->dy, pl.tiles_per_row, pl.row_groups, pl.target_tiles, pl.chunks,              \
+                       pl.rows_per_chunk, w.part)
+    const int vsel = (pl.tpl == 2 ? 3 : 0) + (pl.unroll == 2 ? 0 : pl.unroll == 4 ? 1 : 2);
     if (prec == BIM_FP64) {
-        hipLaunchKernelGGL((k_allpairs<double, false>), dim3(pl.blocks), dim3(256), 0, s,
-                           (const SrcRec<double> *)w.srcS, (const SrcRec<double> *)w.srcB, w.tg, N, M,
-                           d.nimg, p->y1, p->dy, pl.tiles_per_row, pl.target_tiles, pl.chunks,
-                           pl.rows_per_chunk, w.part);
+        switch (vsel) {
+            case 0: BIM_LAUNCH_PAIRS(double, false, 1, 2, w.tg); break;
+            case 1: BIM_LAUNCH_PAIRS(double, false, 1, 4, w.tg); break;
+            case 2: BIM_LAUNCH_PAIRS(double, false, 1, 8, w.tg); break;
+            case 3: BIM_LAUNCH_PAIRS(double, false, 2, 2, w.tg); break;
+            case 4: BIM_LAUNCH_PAIRS(double, false, 2, 4, w.tg); break;
+            default: BIM_LAUNCH_PAIRS(double, false, 2, 8, w.tg); break;
+        }
     } else {
-        hipLaunchKernelGGL((k_allpairs<float, true>), dim3(pl.blocks), dim3(256), 0, s,
-                           (const SrcRec<float> *)w.srcS, (const SrcRec<float> *)w.srcB, w.tg32, N, M,
-                           d.nimg, p->y1, p->dy, pl.tiles_per_row, pl.target_tiles, pl.chunks,
-                           pl.rows_per_chunk, w.part);
+        switch (vsel) {
+            case 0: BIM_LAUNCH_PAIRS(float, true, 1, 2, w.tg32); break;
+            case 1: BIM_LAUNCH_PAIRS(float, true, 1, 4, w.tg32); break;
+            case 2: BIM_LAUNCH_PAIRS(float, true, 1, 8, w.tg32); break;
+            case 3: BIM_LAUNCH_PAIRS(float, true, 2, 2, w.tg32); break;
+            case 4: BIM_LAUNCH_PAIRS(float, true, 2, 4, w.tg32); break;
+            default: BIM_LAUNCH_PAIRS(float, true, 2, 8, w.tg32); break;
+        }
     }
+#undef BIM_LAUNCH_PAIRS
+    if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[1], s));
     hipLaunchKernelGGL(k_finalize, dim3(cdiv(d.nvec, 256)), dim3(256), 0, s, u, w.nodes, w.ydiv, w.tg,
                        w.part, F, N, M, pl.chunks, p->x1, p->dx, p->x1, xN, ylo, yM, p->n_decay,
-                       p->froude);
+                       p->froude, linear);
     return hip_check(hipGetLastError(), "residual kernel launch");
 }
 

@@ -1,0 +1,90 @@
+"""GPU linear start and JFNK solves (through the C ABI) against the oracle's solutions."""
+import numpy as np
+import pytest
+
+from paper_1709_08803_amd import workloads as W
+from oracle import jfnk as OJ
+from oracle import linear as Lin
+from oracle import residual as R
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bim():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_1709_08803_amd import bim as B
+    B.lib()
+    return B
+
+
+@pytest.mark.parametrize("F", [0.7, 1.4])
+def test_linear_start_matches_oracle(bim, F):
+    p = W.tiny(F)
+    ref = Lin.linear_start(p)
+    dp = bim.DeviceProblem(p)
+    u = bim.linear_start(dp).cpu().numpy()
+    err = np.abs(u - ref).max() / np.abs(ref).max()
+    print("linear start rel err", err)
+    assert err < 1e-9
+
+
+ORACLE_CACHE = {}
+
+
+def oracle_solution(p, key):
+    if key not in ORACLE_CACHE:
+        pc = Lin.Preconditioner(p)
+        res = OJ.newton_krylov(p, Lin.linear_start(p, pc.J), pc, ftol=1e-12)
+        assert res.converged
+        ORACLE_CACHE[key] = res.u
+    return ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("F,inner,tol", [(0.7, "fp64", 1e-9), (1.4, "fp64", 1e-9), (0.7, "fp32c", 1e-8),
+                                         (1.4, "fp32c", 1e-8)])
+def test_converged_solution_matches_oracle(bim, F, inner, tol):
+    p = W.tiny(F)
+    ref = oracle_solution(p, ("tiny", F))
+    dp = bim.DeviceProblem(p)
+    P = bim.Preconditioner(dp)
+    u = bim.linear_start(dp, P)
+    rep = bim.solve(dp, u, P, ftol=1e-12, inner_prec=inner)
+    print(F, inner, rep)
+    assert rep["status"] == 0
+    uh = u.cpu().numpy()
+    z_gpu = R.reconstruct(p, uh)
+    z_ref = R.reconstruct(p, ref)
+    dz = np.abs(z_gpu.zeta - z_ref.zeta).max()
+    dphi = np.abs(z_gpu.phi - z_ref.phi).max()
+    print("max |dzeta|", dz, "max |dphi|", dphi)
+    assert dz <= tol and dphi <= 10 * tol
+    # the oracle agrees that the GPU solution solves the discrete system
+    assert np.abs(R.residual(p, uh)).max() < 1e-10
+
+
+def test_solver_reports_nonconvergence_and_bad_input(bim):
+    p = W.tiny(0.7)
+    dp = bim.DeviceProblem(p)
+    u = bim.linear_start(dp)
+    rep = bim.solve(dp, u.clone(), max_newton=0)
+    assert rep["status"] == 1  # BIM_NOT_CONVERGED
+    bad = u.clone()
+    bad[5] = float("nan")
+    rep = bim.solve(dp, bad, check=False)
+    assert rep["status"] == -4  # BIM_EDOMAIN
+
+
+def test_unpreconditioned_gmres_needs_more_iterations(bim):
+    # the preconditioner's purpose (Section 4.2): fewer Krylov iterations for the same Newton steps
+    p = W.tiny(0.7)
+    dp = bim.DeviceProblem(p)
+    P = bim.Preconditioner(dp)
+    u0 = bim.linear_start(dp, P)
+    a = bim.solve(dp, u0.clone(), P, ftol=1e-9)
+    b = bim.solve(dp, u0.clone(), None, ftol=1e-9, use_precond=0, max_restarts=40, check=False)
+    print("with P", a["gmres_iters"], "without", b["gmres_iters"])
+    assert a["status"] == 0
+    assert b["gmres_iters"] > 3 * a["gmres_iters"]

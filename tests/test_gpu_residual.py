@@ -138,3 +138,45 @@ def test_jv_default_shift_and_zero_direction(bim):
     torch.cuda.synchronize()
     err = np.abs(J.cpu().numpy() - ref).max() / np.abs(ref).max()
     assert err < 1e-4
+
+
+VARIANTS = [(tpl, unr, rpc) for tpl in (1, 2) for unr in (2, 4, 8) for rpc in (1, 3)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+def test_every_launch_variant_matches_oracle(bim, prec, tol):
+    # the autotuner may pick any of these; all must meet the same bar
+    p = W.make_problem(45, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)])  # M odd: a lone last row pair
+    u = W.perturbed_state(p, 3)
+    F_ref = R.residual(p, u)
+    scale = R.term_magnitude_rows(p, u)
+    dp = bim.DeviceProblem(p)
+    ud = torch.as_tensor(u, device="cuda")
+    for cfg in VARIANTS:
+        F = torch.empty_like(ud)
+        bim.lib()  # loaded
+        k, t = bim.residual_timed(dp, ud, prec, iters=1, config=cfg)
+        # residual_timed writes into a scratch F; evaluate through the public path with the same shape
+        import ctypes
+        Fd = torch.empty_like(ud)
+        kk, tt = ctypes.c_double(), ctypes.c_double()
+        rc = bim.lib().bim_residual_timed(dp.ref(), ud.data_ptr(), Fd.data_ptr(), bim._PREC[prec], 1,
+                                          ctypes.byref(bim.PairConfig(*cfg)), torch.cuda.current_stream().cuda_stream,
+                                          ctypes.byref(kk), ctypes.byref(tt))
+        assert rc == 0
+        err = (np.abs(Fd.cpu().numpy() - F_ref) / scale).max()
+        assert err <= tol, (cfg, err)
+
+
+def test_autotuner_choice_is_used_and_correct(bim):
+    p = W.working(0.7, N=61, M=21)
+    u = W.perturbed_state(p, 4)
+    dp = bim.DeviceProblem(p)
+    ud = torch.as_tensor(u, device="cuda")
+    best, ms = bim.tune_residual(dp, ud, "fp64")
+    assert best[0] in (1, 2) and best[1] in (2, 4, 8) and ms > 0
+    F = bim.residual(dp, ud, "fp64")
+    torch.cuda.synchronize()
+    F_ref = R.residual(p, u)
+    scale = R.term_magnitude_rows(p, u)
+    assert (np.abs(F.cpu().numpy() - F_ref) / scale).max() <= 1e-12

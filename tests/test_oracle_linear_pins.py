@@ -124,3 +124,12 @@ def test_linear_start_solves_linear_system_and_is_second_order_accurate():
         res.append(np.abs(R.residual(p, ul)).max())
     # the nonlinear residual of the linear solution is O(eps^2)
     assert 3.3 < res[0] / res[1] < 4.7
+
+
+@pytest.mark.parametrize("N,M,hb", [(31, 11, 1), (21, 9, 2), (13, 7, 3)])
+def test_banded_matvec_equals_dense_banded_jacobian(N, M, hb):
+    p = W.make_problem(N, M, -10, 10, 0, 6, 0.8, [W.Bump(0.1, 1, 1)])
+    pc = Lin.Preconditioner(p, hb=hb)
+    z = np.random.default_rng(1).standard_normal(p.n_unknowns)
+    a, b = pc.matvec(z), Lin.banded_matvec(p, z, hb)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
