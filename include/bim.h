@@ -162,7 +162,7 @@ int precond_band(const bim_precond *P);
  *                   the line search and the update are always FP64;
  *   band_halfwidth: band of the preconditioner built when none is passed;
  *   use_precond:    0 runs GMRES without preconditioning.
- * jfnk_default_opts fills 1e-10, 1e-8, 30, 10, 30, 20, BIM_FP64, -1, 1.
+ * jfnk_default_opts fills 1e-10, 1e-8, 30, 10, 30, 20, BIM_FP64, -1, 1, 1.
  */
 typedef struct bim_jfnk_opts {
     double ftol;
@@ -174,6 +174,7 @@ typedef struct bim_jfnk_opts {
     int32_t inner_prec;
     int32_t band_halfwidth;
     int32_t use_precond;
+    int32_t use_graphs;  /* 1: replay each Arnoldi step's device work from a HIP graph */
 } bim_jfnk_opts;
 
 /* Outcome of a solve (host struct).  history[k] = ||F||_inf after k Newton steps. */
@@ -221,6 +222,70 @@ int jfnk_solve(const bim_problem *prob, const bim_precond *P, double *u, const b
  * rtol (<= 0: 1e-12).  u_out: device [3(N+1)M].
  */
 int bim_linear_start(const bim_problem *prob, const bim_precond *P, double *u_out, double rtol, void *stream);
+
+/*
+ * F_i = F(u_i) for `count` problems (possibly of different mesh sizes) whose
+ * all-pairs sums run in one persistent launch: the work items of all problems
+ * form one list that every wave walks with a fixed stride, so each F_i is
+ * deterministic and independent of the other problems in the batch.
+ *   probs: host array of `count` problems; u, F: host arrays of device pointers.
+ */
+int bim_residual_batched(const bim_problem *probs, int count, const double *const *u, double *const *F,
+                         int prec, void *stream);
+
+/*
+ * Solves `count` problems of possibly different mesh sizes together (a
+ * parameter sweep).  Each problem follows the algorithm of jfnk_solve; the
+ * problems advance in lockstep rounds in which every unfinished problem needs
+ * one residual evaluation, and the all-pairs sums of all of them run in one
+ * persistent launch (bim_residual_batched).  A problem that fails does not stop
+ * the others.
+ *   probs: host array; Ps: host array of preconditioners (or NULL entries /
+ *   a NULL array to build them internally); us: host array of device vectors
+ *   (start in, last iterate out); opts: NULL for defaults (restart <= 30);
+ *   reps: host array of `count` reports (may be NULL).
+ * Returns the most negative status among the problems, else the largest soft
+ * status, else BIM_OK.
+ */
+int jfnk_solve_batched(const bim_problem *probs, int count, bim_precond *const *Ps, double *const *us,
+                       const bim_jfnk_opts *opts, bim_jfnk_report *reps, void *stream);
+
+/*
+ * Learned initial guess.  A small network -- two 3x3 stride-2 convolutions
+ * with ReLU, a fully connected ReLU layer that also sees F, and a linear fully
+ * connected output -- maps (F, the bottom beta on the N x M mesh) to a
+ * correction (dzeta_x, dphi_x) of the discrete linear start; the upstream
+ * values zeta_1, phi_1 follow from the radiation rows, psi is the linear
+ * start's.  Weights are FP32 masters with bf16 copies; every contraction runs
+ * on bf16 matrix cores with FP32 accumulation.
+ *   Input X0: device bf16 [B][M][N][2] (channels (beta+1)/0.3, (F-1.25)/0.75),
+ *   ffeat: device FP32 [B] ((F-1.25)/0.75), targets T / outputs Y: device
+ *   FP32 [B][2][M][N] (correction / out_scale).  Layer l's weights are
+ *   [fan_in][fan_out] FP32 (conv fan_in ordered (ky, kx, c_in)).
+ */
+typedef struct lg_arch {
+    int32_t W, H;      /* mesh N (x) and M (y) */
+    int32_t C1, C2;    /* convolution channels */
+    int32_t D3;        /* hidden width */
+    double out_scale;  /* output units */
+} lg_arch;
+typedef struct lg_net lg_net;
+void lg_default_arch(lg_arch *arch, int N, int M);
+int lg_create(const lg_arch *arch, uint64_t seed, int max_batch, lg_net **out);
+void lg_destroy(lg_net *net);
+int lg_num_params(const lg_net *net, int layer, int64_t *weights, int64_t *biases);
+int lg_set_params(lg_net *net, int layer, const float *w_host, const float *b_host);
+/* host copies of layer parameters and of the last backward pass's gradients (any may be NULL) */
+int lg_get_params(const lg_net *net, int layer, float *w_host, float *b_host, float *gw_host, float *gb_host);
+int lg_forward(lg_net *net, const uint16_t *X0, const float *ffeat, int B, float *Y_out, void *stream);
+/* forward, mean-squared-error loss against T, backward, and (update != 0) one Adam step (lr);
+   *loss_out (host, may be NULL) receives the loss (synchronises). */
+int lg_train_step(lg_net *net, const uint16_t *X0, const float *ffeat, const float *T, int B, float lr, int update,
+                  float *loss_out, void *stream);
+/* network input of one problem (X0 [M][N][2] bf16, ffeat [1]) */
+int lg_make_input(const bim_problem *prob, uint16_t *X0, float *ffeat, void *stream);
+/* Newton start: the linear start (bim_linear_start with P) plus the network's correction. */
+int lg_infer_start(lg_net *net, const bim_problem *prob, const bim_precond *P, double *u_out, void *stream);
 
 /* Message describing the calling thread's most recent failure ("" if none). */
 const char *bim_last_error(void);

@@ -59,12 +59,32 @@ def lib():
         L.precond_bytes.argtypes = [vp]
         L.precond_bytes.restype = ctypes.c_int64
         L.precond_band.argtypes = [vp]
+        L.bim_residual_batched.argtypes = [pp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, vp]
+        L.bim_residual_batched.restype = i32
         L.jfnk_default_opts.argtypes = [ctypes.POINTER(JfnkOpts)]
         L.jfnk_default_opts.restype = None
         L.jfnk_solve.argtypes = [pp, vp, vp, ctypes.POINTER(JfnkOpts), ctypes.POINTER(JfnkReport), vp]
         L.bim_linear_start.argtypes = [pp, vp, vp, dbl, vp]
+        L.jfnk_solve_batched.argtypes = [pp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(JfnkOpts),
+                                         ctypes.POINTER(JfnkReport), vp]
+        L.jfnk_solve_batched.restype = i32
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.lg_default_arch.argtypes = [ctypes.POINTER(LgArch), i32, i32]
+        L.lg_default_arch.restype = None
+        L.lg_create.argtypes = [ctypes.POINTER(LgArch), ctypes.c_uint64, i32, ctypes.POINTER(vp)]
+        L.lg_destroy.argtypes = [vp]
+        L.lg_destroy.restype = None
+        L.lg_num_params.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.lg_set_params.argtypes = [vp, i32, fp, fp]
+        L.lg_get_params.argtypes = [vp, i32, fp, fp, fp, fp]
+        L.lg_forward.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.lg_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, i32, fp, vp]
+        L.lg_make_input.argtypes = [pp, vp, vp, vp]
+        L.lg_infer_start.argtypes = [vp, pp, vp, vp, vp]
         for name in ("bim_residual", "bim_jv", "bim_residual_timed", "bim_tune_residual", "precond_setup",
-                     "precond_apply", "precond_band", "jfnk_solve", "bim_linear_start"):
+                     "precond_apply", "precond_band", "jfnk_solve", "bim_linear_start", "lg_create",
+                     "lg_num_params", "lg_set_params", "lg_get_params", "lg_forward", "lg_train_step",
+                     "lg_make_input", "lg_infer_start"):
             getattr(L, name).restype = i32
         L.bim_last_error.restype = ctypes.c_char_p
         L.bim_version.restype = ctypes.c_char_p
@@ -99,7 +119,8 @@ class PairConfig(ctypes.Structure):
 class JfnkOpts(ctypes.Structure):
     _fields_ = [("ftol", ctypes.c_double), ("gmres_rtol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("max_backtracks", ctypes.c_int32),
-                ("inner_prec", ctypes.c_int32), ("band_halfwidth", ctypes.c_int32), ("use_precond", ctypes.c_int32)]
+                ("inner_prec", ctypes.c_int32), ("band_halfwidth", ctypes.c_int32), ("use_precond", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32)]
 
 
 class JfnkReport(ctypes.Structure):
@@ -113,6 +134,11 @@ class JfnkReport(ctypes.Structure):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "history"}
         d["history"] = [self.history[i] for i in range(min(64, self.newton_iters + 1))]
         return d
+
+
+class LgArch(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int32), ("H", ctypes.c_int32), ("C1", ctypes.c_int32), ("C2", ctypes.c_int32),
+                ("D3", ctypes.c_int32), ("out_scale", ctypes.c_double)]
 
 
 class DeviceProblem:
@@ -140,6 +166,17 @@ def residual(dp: DeviceProblem, u: torch.Tensor, prec="fp64", out: Optional[torc
     F = out if out is not None else torch.empty_like(u)
     _check(lib().bim_residual(dp.ref(), _dptr(u), _dptr(F), _PREC[prec], _stream(stream)))
     return F
+
+
+def residual_batched(dps, us, prec="fp64", outs=None, stream=None):
+    """F_i = F(u_i) for a list of problems in one persistent all-pairs launch."""
+    n = len(dps)
+    outs = outs if outs is not None else [torch.empty_like(u) for u in us]
+    arr = (_Problem * n)(*[d.struct for d in dps])
+    up = (ctypes.c_void_p * n)(*[_dptr(u) for u in us])
+    fp = (ctypes.c_void_p * n)(*[_dptr(f) for f in outs])
+    _check(lib().bim_residual_batched(arr, n, up, fp, _PREC[prec], _stream(stream)))
+    return outs
 
 
 def jv(dp: DeviceProblem, u: torch.Tensor, Fu: torch.Tensor, v: torch.Tensor, h: float = 0.0,
@@ -233,6 +270,20 @@ def solve(dp: DeviceProblem, u: torch.Tensor, P: Optional[Preconditioner] = None
     return d
 
 
+def solve_batched(dps, us, Ps=None, stream=None, check: bool = True, **opts):
+    """jfnk_solve_batched in place on every u; returns (status, [report dicts])."""
+    n = len(dps)
+    o = default_opts(**opts)
+    arr = (_Problem * n)(*[d.struct for d in dps])
+    up = (ctypes.c_void_p * n)(*[_dptr(u) for u in us])
+    pp = (ctypes.c_void_p * n)(*[(P.handle.value if P is not None else None) for P in Ps]) if Ps else None
+    reps = (JfnkReport * n)()
+    rc = lib().jfnk_solve_batched(arr, n, pp, up, ctypes.byref(o), reps, _stream(stream))
+    if rc < 0 and check:
+        _check(rc)
+    return rc, [r.as_dict() for r in reps]
+
+
 def linear_start(dp: DeviceProblem, P: Optional[Preconditioner] = None, rtol: float = 0.0,
                  out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     u = out if out is not None else torch.empty(dp.n, dtype=torch.float64, device=dp.device)
@@ -240,6 +291,79 @@ def linear_start(dp: DeviceProblem, P: Optional[Preconditioner] = None, rtol: fl
                                 _stream(stream))
     _check(rc)
     return u
+
+
+class LearnedNet:
+    """The learned-start network (library-owned; bf16 kernels with FP32 accumulation)."""
+
+    def __init__(self, N: int, M: int, seed: int = 0, max_batch: int = 64, **arch):
+        a = LgArch()
+        lib().lg_default_arch(ctypes.byref(a), int(N), int(M))
+        for k, v in arch.items():
+            setattr(a, k, v)
+        self.arch = a
+        self.max_batch = max_batch
+        self._h = ctypes.c_void_p()
+        _check(lib().lg_create(ctypes.byref(a), ctypes.c_uint64(seed), int(max_batch), ctypes.byref(self._h)))
+
+    @property
+    def n_out(self) -> int:
+        return 2 * self.arch.H * self.arch.W
+
+    def shapes(self, layer: int):
+        w, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().lg_num_params(self._h, layer, ctypes.byref(w), ctypes.byref(b)))
+        return w.value, b.value
+
+    def get(self, layer: int):
+        """(W, b, gW, gb) as float32 numpy arrays (W flattened [fan_in * fan_out])."""
+        nw, nb = self.shapes(layer)
+        arrs = [np.empty(nw, np.float32), np.empty(nb, np.float32), np.empty(nw, np.float32), np.empty(nb, np.float32)]
+        fptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        _check(lib().lg_get_params(self._h, layer, *[fptr(a) for a in arrs]))
+        return arrs
+
+    def set(self, layer: int, W=None, b=None):
+        fptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if a is not None else None
+        W = np.ascontiguousarray(W, dtype=np.float32) if W is not None else None
+        b = np.ascontiguousarray(b, dtype=np.float32) if b is not None else None
+        _check(lib().lg_set_params(self._h, layer, fptr(W), fptr(b)))
+
+    def forward(self, X0: torch.Tensor, ffeat: torch.Tensor, stream=None) -> torch.Tensor:
+        B = ffeat.shape[0]
+        Y = torch.empty((B, self.n_out), dtype=torch.float32, device=ffeat.device)
+        _check(lib().lg_forward(self._h, X0.data_ptr(), ffeat.data_ptr(), B, Y.data_ptr(), _stream(stream)))
+        return Y
+
+    def train_step(self, X0: torch.Tensor, ffeat: torch.Tensor, T: torch.Tensor, lr: float, update: bool = True,
+                   stream=None) -> float:
+        loss = ctypes.c_float()
+        _check(lib().lg_train_step(self._h, X0.data_ptr(), ffeat.data_ptr(), T.data_ptr(), ffeat.shape[0],
+                                   ctypes.c_float(lr), 1 if update else 0, ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def make_input(self, dp: DeviceProblem, stream=None):
+        X0 = torch.empty((dp.host.M, dp.host.N, 2), dtype=torch.int16, device=dp.device)
+        f = torch.empty(1, dtype=torch.float32, device=dp.device)
+        _check(lib().lg_make_input(dp.ref(), X0.data_ptr(), f.data_ptr(), _stream(stream)))
+        return X0, f
+
+    def infer_start(self, dp: DeviceProblem, P: Optional[Preconditioner] = None, out=None, stream=None):
+        u = out if out is not None else torch.empty(dp.n, dtype=torch.float64, device=dp.device)
+        _check(lib().lg_infer_start(self._h, dp.ref(), P.handle if P is not None else None, _dptr(u),
+                                    _stream(stream)))
+        return u
+
+    def close(self):
+        if self._h:
+            lib().lg_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

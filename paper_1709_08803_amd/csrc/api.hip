@@ -1,6 +1,7 @@
 // C ABI entry points for the residual and the Jacobian-vector product.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -149,3 +150,50 @@ int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const dou
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ batched residual
+namespace bim {
+
+// Rows per chunk that give every work item about the same number of pairs
+// (~`pairs_target` source nodes per lane) across problems of different sizes.
+int balanced_rows_per_chunk(const Dims &d, int pairs_target) {
+    return std::max(1, std::min(2 * d.nimg * d.M, (pairs_target + d.N - 1) / d.N));
+}
+
+}  // namespace bim
+
+extern "C" int bim_residual_batched(const bim_problem *probs, int count, const double *const *u, double *const *F,
+                                    int prec, void *stream) {
+    g_last_error.clear();
+    if (count < 0 || (count > 0 && (!probs || !u || !F))) return fail(BIM_EINVAL, "bad batch arguments");
+    if (count == 0) return BIM_OK;
+    if (prec != BIM_FP64 && prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
+    int rc;
+    for (int i = 0; i < count; ++i) {
+        if ((rc = validate(&probs[i]))) return rc;
+        if (!u[i] || !F[i] || u[i] == F[i]) return fail(BIM_EINVAL, "u[i], F[i] must be distinct device pointers");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // one kernel variant for the batch: the tuned one of the largest problem
+    int big = 0;
+    for (int i = 1; i < count; ++i)
+        if ((long)probs[i].N * probs[i].M > (long)probs[big].N * probs[big].M) big = i;
+    const PairLaunch ref = pair_launch_for(&probs[big], prec);
+    std::vector<PairLaunch> pls(count);
+    std::vector<ResidualWork> ws(count);
+    size_t total = 0;
+    std::vector<size_t> offs(count);
+    for (int i = 0; i < count; ++i) {
+        const Dims d(&probs[i]);
+        pls[i] = pair_launch(d, ref.tpl, ref.unroll, balanced_rows_per_chunk(d, 6 * 181));
+        offs[i] = total;
+        total += (residual_work_bytes(d, pls[i]) + 255) & ~(size_t)255;
+    }
+    const size_t desc_off = total;
+    total += sizeof(PairDesc) * count;
+    Scratch sc(s);
+    if ((rc = sc.alloc(total))) return rc;
+    for (int i = 0; i < count; ++i) residual_work_carve((char *)sc.ptr + offs[i], Dims(&probs[i]), pls[i], &ws[i]);
+    return residual_batched_enqueue(probs, count, u, F, prec, pls.data(), ws.data(),
+                                    (PairDesc *)((char *)sc.ptr + desc_off), 0, s);
+}

@@ -1,0 +1,226 @@
+// Batched FP64 vector and preconditioner kernels: one launch per operation for
+// all problems of a lockstep round (blockIdx.y = problem).  Reductions are
+// two-pass with fixed order, so every problem's result is deterministic.
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "bim_common.h"
+
+namespace bim {
+
+namespace {
+
+constexpr int kT = 256;
+
+__device__ double bsum256(double v) {
+    __shared__ double sh[kT / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kT / 64; ++q) r += sh[q];
+    __syncthreads();
+    return r;
+}
+
+// part[row * kBRedBlocks + bx]; row = blockIdx.z (multidot) or 0 (dot)
+__global__ __launch_bounds__(kT) void k_bdot_part(const BOp *__restrict__ ops, int multi) {
+    const BOp o = ops[blockIdx.y];
+    const int row = multi ? (int)blockIdx.z : 0;
+    if (row >= (multi ? o.nv : 1)) return;
+    const double *a = multi ? o.a + (size_t)row * o.ld : o.a;
+    double v = 0.0;
+    for (long e = (long)blockIdx.x * kT + threadIdx.x; e < o.n; e += (long)kBRedBlocks * kT) v = fma(a[e], o.b[e], v);
+    v = bsum256(v);
+    if (threadIdx.x == 0) o.part[(size_t)row * kBRedBlocks + blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kT) void k_bdot_sum(const BOp *__restrict__ ops, int multi, int take_sqrt) {
+    const BOp o = ops[blockIdx.y];
+    const int row = blockIdx.x;
+    if (row >= (multi ? o.nv : 1)) return;
+    double v = (threadIdx.x < kBRedBlocks) ? o.part[(size_t)row * kBRedBlocks + threadIdx.x] : 0.0;
+    v = bsum256(v);
+    if (threadIdx.x == 0) o.sc[row] = take_sqrt ? sqrt(v) : v;
+}
+
+__global__ __launch_bounds__(kT) void k_borth(const BOp *__restrict__ ops, double sign) {
+    const BOp o = ops[blockIdx.y];
+    for (long e = (long)blockIdx.x * kT + threadIdx.x; e < o.n; e += (long)gridDim.x * kT) {
+        double acc = o.c[e];
+        for (int r = 0; r < o.nv; ++r) acc = fma(sign * o.a[(size_t)r * o.ld + e], o.sa[r], acc);
+        o.c[e] = acc;
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_belem(const BOp *__restrict__ ops, int kind) {
+    const BOp o = ops[blockIdx.y];
+    for (long e = (long)blockIdx.x * kT + threadIdx.x; e < o.n; e += (long)gridDim.x * kT) {
+        switch (kind) {
+            case 0: o.c[e] = o.a[e] / o.sa[0]; break;                     // scale_inv
+            case 1: o.c[e] = fma(o.sa[0], o.b[e], o.a[e]); break;         // axpy_dev
+            case 2: {                                                     // quotient
+                const double h = o.sa[0];
+                o.c[e] = (h != 0.0) ? (o.a[e] - o.b[e]) / h : 0.0;
+                break;
+            }
+            default:                                                      // axpby
+                o.c[e] = (o.beta == 0.0) ? o.alpha * o.a[e] : fma(o.alpha, o.a[e], o.beta * o.b[e]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_bmax_part(const BOp *__restrict__ ops) {
+    __shared__ double sh[kT];
+    const BOp o = ops[blockIdx.y];
+    double v = 0.0;
+    for (long e = (long)blockIdx.x * kT + threadIdx.x; e < o.n; e += (long)kBRedBlocks * kT) {
+        const double x = fabs(o.a[e]);
+        v = (x > v || x != x) ? x : v;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int q = kT / 2; q > 0; q >>= 1) {
+        if (threadIdx.x < q) {
+            const double y = sh[threadIdx.x + q];
+            if (y > sh[threadIdx.x] || y != y) sh[threadIdx.x] = y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) o.part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_bmax_sum(const BOp *__restrict__ ops, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const BOp o = ops[i];
+    double v = 0.0;
+    for (int b = 0; b < kBRedBlocks; ++b) {
+        const double y = o.part[b];
+        if (y > v || y != y) v = y;
+    }
+    o.sc[0] = v;
+}
+
+__global__ void k_bshift(const BOp *__restrict__ ops, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const BOp o = ops[i];
+    if (o.alpha > 0.0) {
+        o.sc[2] = o.alpha;
+    } else {
+        const double nu = o.sc[0], nv = o.sc[1];
+        o.sc[2] = (nv > 0.0) ? sqrt(o.beta) * (1.0 + nu) / nv : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bbandmv(const BBand *__restrict__ ops) {
+    const BBand o = ops[blockIdx.y];
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= o.M * o.s) return;
+    const int l = row / o.s, r = row - l * o.s;
+    double v = 0.0;
+    const int m0 = max(0, l - o.w), m1 = min(o.M - 1, l + o.w);
+    for (int m = m0; m <= m1; ++m) {
+        const double *b = o.band + (((size_t)l * (2 * o.w + 1) + (m - l + o.w)) * o.s + r) * o.s;
+        const double *xm = o.x + (size_t)m * o.s;
+        for (int j = lane; j < o.s; j += 64) v = fma(b[j], xm[j], v);
+    }
+    for (int q = 32; q > 0; q >>= 1) v += __shfl_xor(v, q, 64);
+    if (lane == 0) o.y[row] = (o.beta == 0.0) ? o.alpha * v : fma(o.alpha, v, o.beta * o.c[row]);
+}
+
+__global__ __launch_bounds__(256) void k_bgemv(const BGemv *__restrict__ ops) {
+    const BGemv o = ops[blockIdx.y];
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= o.rows) return;
+    const double *a = o.A + (size_t)row * o.lda;
+    double v = 0.0;
+    for (int j = lane; j < o.cols; j += 64) v = fma(a[j], o.x[j], v);
+    for (int q = 32; q > 0; q >>= 1) v += __shfl_xor(v, q, 64);
+    if (lane == 0) o.y[row] = (o.beta == 0.0) ? o.alpha * v : fma(o.alpha, v, o.beta * o.c[row]);
+}
+
+__global__ void k_bgather(const BOp *__restrict__ ops) {
+    const BOp o = ops[blockIdx.x];
+    for (int t = threadIdx.x; t < 8 + o.nv; t += blockDim.x) o.c[t] = (t < 8) ? o.a[t] : o.b[t - 8];
+}
+
+constexpr int kElemBlocks = 128;  // grid-stride blocks per problem for elementwise ops
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+int b_dot(const BOp *ops, int count, bool take_sqrt, hipStream_t s) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_bdot_part, dim3(kBRedBlocks, count, 1), dim3(kT), 0, s, ops, 0);
+    hipLaunchKernelGGL(k_bdot_sum, dim3(1, count), dim3(kT), 0, s, ops, 0, take_sqrt ? 1 : 0);
+    return hip_check(hipGetLastError(), "batched dot launch");
+}
+
+int b_multidot(const BOp *ops, int count, int max_nv, hipStream_t s) {
+    if (count <= 0 || max_nv <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_bdot_part, dim3(kBRedBlocks, count, max_nv), dim3(kT), 0, s, ops, 1);
+    hipLaunchKernelGGL(k_bdot_sum, dim3(max_nv, count), dim3(kT), 0, s, ops, 1, 0);
+    return hip_check(hipGetLastError(), "batched multidot launch");
+}
+
+int b_orth(const BOp *ops, int count, hipStream_t s) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_borth, dim3(kElemBlocks, count), dim3(kT), 0, s, ops, -1.0);
+    return hip_check(hipGetLastError(), "batched orth launch");
+}
+
+int b_combine(const BOp *ops, int count, hipStream_t s) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_borth, dim3(kElemBlocks, count), dim3(kT), 0, s, ops, 1.0);
+    return hip_check(hipGetLastError(), "batched combine launch");
+}
+
+static int elem(const BOp *ops, int count, int kind, hipStream_t s) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_belem, dim3(kElemBlocks, count), dim3(kT), 0, s, ops, kind);
+    return hip_check(hipGetLastError(), "batched elementwise launch");
+}
+int b_scale_inv(const BOp *ops, int count, hipStream_t s) { return elem(ops, count, 0, s); }
+int b_axpy_dev(const BOp *ops, int count, hipStream_t s) { return elem(ops, count, 1, s); }
+int b_quotient(const BOp *ops, int count, hipStream_t s) { return elem(ops, count, 2, s); }
+int b_axpby(const BOp *ops, int count, hipStream_t s) { return elem(ops, count, 3, s); }
+
+int b_maxabs(const BOp *ops, int count, hipStream_t s) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_bmax_part, dim3(kBRedBlocks, count), dim3(kT), 0, s, ops);
+    hipLaunchKernelGGL(k_bmax_sum, dim3(cdiv(count, 64)), dim3(64), 0, s, ops, count);
+    return hip_check(hipGetLastError(), "batched max launch");
+}
+
+int b_shift(const BOp *ops, int count, hipStream_t s) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_bshift, dim3(cdiv(count, 64)), dim3(64), 0, s, ops, count);
+    return hip_check(hipGetLastError(), "batched shift launch");
+}
+
+int b_gather(const BOp *ops, int count, hipStream_t s) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_bgather, dim3(count), dim3(128), 0, s, ops);
+    return hip_check(hipGetLastError(), "batched gather launch");
+}
+
+int b_bandmv(const BBand *ops, int count, int max_rows, hipStream_t s) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_bbandmv, dim3(cdiv(max_rows, 4), count), dim3(256), 0, s, ops);
+    return hip_check(hipGetLastError(), "batched bandmv launch");
+}
+
+int b_gemv(const BGemv *ops, int count, int max_rows, hipStream_t s) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_bgemv, dim3(cdiv(max_rows, 4), count), dim3(256), 0, s, ops);
+    return hip_check(hipGetLastError(), "batched gemv launch");
+}
+
+}  // namespace bim

@@ -64,6 +64,19 @@ PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk);
 // (mesh, precision) if bim_tune_residual has run, else the default.
 PairLaunch pair_launch_for(const bim_problem *p, int prec);
 
+// One problem of a batched all-pairs launch (device array entry).  srcS, srcB
+// and tg point at SrcRec<T> / T data of the batch's precision.
+struct PairDesc {
+    const void *srcS;
+    const void *srcB;
+    const void *tg;
+    double *part;
+    int N, M, nimg;
+    double y1, dy;
+    int tiles_per_row, row_groups, target_tiles, chunks, rows_per_chunk;
+    long item0;  // index of this problem's first work item in the batch
+};
+
 // Device workspace of one residual evaluation.
 struct ResidualWork {
     double *nodes;   // [3][M][N]  zeta, phi, psi at the nodes
@@ -85,5 +98,13 @@ void residual_work_carve(void *base, const Dims &d, const PairLaunch &pl, Residu
 int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
                      const PairLaunch &pl, const ResidualWork &w, hipStream_t s,
                      hipEvent_t *ev_pair = nullptr, int linear = 0);
+
+// Enqueues F_i = F(u_i) for `count` problems whose all-pairs sums share one
+// persistent launch.  pls[i] must have the same tpl/unroll for every i; ws[i]
+// is problem i's workspace; descs_dev: device array of `count` PairDesc.
+// max_blocks caps the persistent grid (<= 0: 2048 workgroups).
+int residual_batched_enqueue(const bim_problem *probs, int count, const double *const *u, double *const *F,
+                             int prec, const PairLaunch *pls, const ResidualWork *ws, PairDesc *descs_dev,
+                             int max_blocks, hipStream_t s, hipEvent_t *ev_pair = nullptr);
 
 }  // namespace bim

@@ -57,7 +57,6 @@ struct Krylov {
         }
         if ((rc = axpy_dev_enqueue(u, z, scal + 2, ut, n, s))) return rc;
         if ((rc = residual_enqueue(p, ut, Ft, prec, pl, rw, s, nullptr, linear))) return rc;
-        ++jv_evals;
         return quotient_enqueue(Ft, Fin, scal + 2, out, n, s);
     }
     int apply_prec(const double *v, double *z) {
@@ -72,6 +71,55 @@ struct Krylov {
         if ((rc = hip_check(hipStreamSynchronize(s), "sync"))) return rc;
         *out = hhost[0];
         return BIM_OK;
+    }
+
+    // Device work of Arnoldi step j: z_j = P^-1 v_j, w = J z_j, two passes of
+    // classical Gram-Schmidt against v_0..v_j, v_{j+1} = w / |w|, and the
+    // Hessenberg column copied to the host.
+    int arnoldi_enqueue(int j) {
+        int rc;
+        double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
+        if ((rc = apply_prec(vj, zj))) return rc;
+        if ((rc = jv(zj, w))) return rc;
+        if ((rc = multidot_enqueue(V, n, j + 1, w, n, part, hdev, false, s))) return rc;
+        if ((rc = orth_update_enqueue(V, n, j + 1, hdev, w, n, s))) return rc;
+        if ((rc = multidot_enqueue(V, n, j + 1, w, n, part, hdev + m + 1, false, s))) return rc;
+        if ((rc = orth_update_enqueue(V, n, j + 1, hdev + m + 1, w, n, s))) return rc;
+        if ((rc = dot_enqueue(w, w, n, part, hdev + 2 * (m + 1), true, s))) return rc;
+        if ((rc = scale_inv_enqueue(w, hdev + 2 * (m + 1), vn, n, s))) return rc;
+        return hip_check(hipMemcpyAsync(hhost, hdev, sizeof(double) * (3 * (m + 1)), hipMemcpyDeviceToHost, s),
+                         "copy");
+    }
+    // Arnoldi step j, replayed from a HIP graph captured on first use (the
+    // buffers of step j do not move during a solve).
+    std::vector<hipGraphExec_t> graphs;
+    bool use_graphs = false;
+    int arnoldi(int j) {
+        ++jv_evals;
+        if (!use_graphs) return arnoldi_enqueue(j);
+        if (graphs.size() < (size_t)m) graphs.assign(m, nullptr);
+        if (!graphs[j]) {
+            int rc = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            if (rc) return rc;
+            const int rc_work = arnoldi_enqueue(j);
+            hipGraph_t g = nullptr;
+            rc = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
+            if (rc_work) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc_work;
+            }
+            if (rc) return rc;
+            hipGraphExec_t ex = nullptr;
+            rc = hip_check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+            (void)hipGraphDestroy(g);
+            if (rc) return rc;
+            graphs[j] = ex;
+        }
+        return hip_check(hipGraphLaunch(graphs[j], s), "hipGraphLaunch");
+    }
+    ~Krylov() {
+        for (auto g : graphs)
+            if (g) (void)hipGraphExecDestroy(g);
     }
 
     // Solves J x = b approximately (x zero-initialised here); returns iterations used.
@@ -101,19 +149,7 @@ struct Krylov {
             int jend = 0;
             bool done = false;
             for (int j = 0; j < m; ++j) {
-                double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
-                if ((rc = apply_prec(vj, zj))) return rc;
-                if ((rc = jv(zj, w))) return rc;
-                // classical Gram-Schmidt, twice
-                if ((rc = multidot_enqueue(V, n, j + 1, w, n, part, hdev, false, s))) return rc;
-                if ((rc = orth_update_enqueue(V, n, j + 1, hdev, w, n, s))) return rc;
-                if ((rc = multidot_enqueue(V, n, j + 1, w, n, part, hdev + m + 1, false, s))) return rc;
-                if ((rc = orth_update_enqueue(V, n, j + 1, hdev + m + 1, w, n, s))) return rc;
-                if ((rc = dot_enqueue(w, w, n, part, hdev + 2 * (m + 1), true, s))) return rc;
-                if ((rc = scale_inv_enqueue(w, hdev + 2 * (m + 1), vn, n, s))) return rc;
-                if ((rc = hip_check(hipMemcpyAsync(hhost, hdev, sizeof(double) * (3 * (m + 1)),
-                                                   hipMemcpyDeviceToHost, s), "copy")))
-                    return rc;
+                if ((rc = arnoldi(j))) return rc;
                 if ((rc = hip_check(hipStreamSynchronize(s), "sync"))) return rc;
                 ++*iters;
                 double *col = &H[(size_t)j];  // column j: H[i * m + j]
@@ -155,6 +191,7 @@ struct Krylov {
             if (done || cyc == max_restarts) break;
             // true residual r = b - J x
             if ((rc = jv(x, w))) return rc;
+            ++jv_evals;
             if ((rc = axpby_enqueue(1.0, b, -1.0, w, r, n, s))) return rc;
             if ((rc = norm_to_host(r, &beta))) return rc;
             *relres = beta / beta0;
@@ -164,9 +201,36 @@ struct Krylov {
     }
 };
 
+// Private non-blocking stream for a solve (HIP graphs cannot be captured on the
+// null stream): ordered after the caller's stream on entry, and the caller's
+// stream is ordered after it on exit.
+struct SolveStream {
+    hipStream_t caller = nullptr, own = nullptr;
+    hipEvent_t ev = nullptr;
+    int open(hipStream_t c) {
+        caller = c;
+        int rc = hip_check(hipStreamCreateWithFlags(&own, hipStreamNonBlocking), "hipStreamCreate");
+        if (rc) return rc;
+        if ((rc = hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate"))) return rc;
+        if ((rc = hip_check(hipEventRecord(ev, caller), "hipEventRecord"))) return rc;
+        return hip_check(hipStreamWaitEvent(own, ev, 0), "hipStreamWaitEvent");
+    }
+    ~SolveStream() {
+        if (own) {
+            if (ev && hipEventRecord(ev, own) == hipSuccess) (void)hipStreamWaitEvent(caller, ev, 0);
+            (void)hipStreamSynchronize(own);
+            (void)hipStreamDestroy(own);
+        }
+        if (ev) (void)hipEventDestroy(ev);
+    }
+};
+
 int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const bim_jfnk_opts *o,
-               bim_jfnk_report *rep, hipStream_t s, bool linear_start_only) {
+               bim_jfnk_report *rep, hipStream_t caller, bool linear_start_only) {
     auto t0 = std::chrono::steady_clock::now();
+    SolveStream ss;
+    if (int rc0 = ss.open(caller)) return rc0;
+    hipStream_t s = ss.own;
     const Dims d(p);
     const long n = d.nvec;
     const int m = std::max(1, o->restart);
@@ -217,6 +281,7 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
     K.ydev = take(sizeof(double) * (m + 1));
     K.hhost = hhost;
     K.pl = plw;
+    K.use_graphs = o->use_graphs != 0;
 
     // preconditioner: caller's, or built here
     bim_precond *own = nullptr;
@@ -353,6 +418,7 @@ void jfnk_default_opts(bim_jfnk_opts *o) {
     o->inner_prec = BIM_FP64;
     o->band_halfwidth = -1;
     o->use_precond = 1;
+    o->use_graphs = 1;
 }
 
 static int check_opts(const bim_jfnk_opts *o) {

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "bim_common.h"
 
@@ -164,6 +165,32 @@ __global__ void k_targets(const double *__restrict__ nodes, const double *__rest
 }
 
 // ------------------------------------------------------------------ A2: all-pairs sums (hot loop)
+// One source record as a single 8-wide vector load (one scalar load per node).
+template <typename T>
+struct RecVec;
+template <>
+struct RecVec<float> {
+    typedef float type __attribute__((ext_vector_type(8)));
+};
+template <>
+struct RecVec<double> {
+    typedef double type __attribute__((ext_vector_type(8)));
+};
+template <typename T>
+__device__ __forceinline__ SrcRec<T> load_rec(const SrcRec<T> *__restrict__ p) {
+    const typename RecVec<T>::type v = *reinterpret_cast<const typename RecVec<T>::type *>(p);
+    SrcRec<T> r;
+    r.x = v[0];
+    r.z = v[1];
+    r.zx = v[2];
+    r.zy = v[3];
+    r.wD = v[4];
+    r.ws = v[5];
+    r.w = v[6];
+    r.pad = v[7];
+    return r;
+}
+
 // One wave = 64 consecutive collocation points x*_k on TPL mesh rows of one
 // boundary.  It walks a chunk of source rows (boundary, image, y-row) and, for
 // each, all N nodes of that row.  Source records are read with wave-uniform
@@ -199,16 +226,10 @@ __device__ __forceinline__ void row_end(TargetState<T> &g) {
 }
 
 template <typename T, bool COMP, int TPL, int UNROLL>
-__global__ __launch_bounds__(256) void k_allpairs(
-    const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB, const T *__restrict__ tg,
-    int N, int M, int nimg, double y1, double dy, int tiles_per_row, int row_groups, int target_tiles,
-    int chunks, int rows_per_chunk, double *__restrict__ part) {
-    const int lane = threadIdx.x & 63;
-    // the wave index is uniform: keep it (and everything derived) in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int g = blockIdx.x * 4 + wave;
-    const int tt = g % target_tiles, c = g / target_tiles;
-    if (c >= chunks) return;
+__device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
+                                          const T *__restrict__ tg, int N, int M, int nimg, double y1, double dy,
+                                          int tiles_per_row, int row_groups, int rows_per_chunk,
+                                          double *__restrict__ part, int tt, int c, int lane) {
     const int ntg = (N - 1) * M;
     const size_t T2 = (size_t)2 * ntg;
     const int st = tt / (row_groups * tiles_per_row);
@@ -256,7 +277,7 @@ __global__ __launch_bounds__(256) void k_allpairs(
         if (ss == st) {
 #pragma unroll UNROLL
             for (int i = 0; i < N; ++i) {
-                const SrcRec<T> p = src[i];
+                const SrcRec<T> p = load_rec(src + i);
                 const T s = p.x - xs;
 #pragma unroll
                 for (int q = 0; q < TPL; ++q) {
@@ -276,7 +297,7 @@ __global__ __launch_bounds__(256) void k_allpairs(
         } else {
 #pragma unroll UNROLL
             for (int i = 0; i < N; ++i) {
-                const SrcRec<T> p = src[i];
+                const SrcRec<T> p = load_rec(src + i);
                 const T s = p.x - xs;
 #pragma unroll
                 for (int q = 0; q < TPL; ++q) {
@@ -303,6 +324,44 @@ __global__ __launch_bounds__(256) void k_allpairs(
             o[0] = (double)ts[q].sum + (double)ts[q].comp;
             o[1] = (double)ts[q].s2sum + (double)ts[q].s2comp;
         }
+    }
+}
+
+
+// Single problem: one wave per (target tile, source chunk).
+template <typename T, bool COMP, int TPL, int UNROLL>
+__global__ __launch_bounds__(256) void k_allpairs(
+    const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB, const T *__restrict__ tg,
+    int N, int M, int nimg, double y1, double dy, int tiles_per_row, int row_groups, int target_tiles,
+    int chunks, int rows_per_chunk, double *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    // the wave index is uniform: keep it (and everything derived) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = blockIdx.x * 4 + wave;
+    const int tt = g % target_tiles, c = g / target_tiles;
+    if (c >= chunks) return;
+    pair_item<T, COMP, TPL, UNROLL>(srcS, srcB, tg, N, M, nimg, y1, dy, tiles_per_row, row_groups, rows_per_chunk,
+                                    part, tt, c, lane);
+}
+
+// Many problems in one persistent launch: the work items (target tile, source
+// chunk) of all problems form one list; every wave walks it with a fixed stride,
+// so the schedule (and each problem's fixed-order reduction) is deterministic.
+template <typename T, bool COMP, int TPL, int UNROLL>
+__global__ __launch_bounds__(256) void k_allpairs_batched(const PairDesc *__restrict__ descs, int count,
+                                                          long total_items) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long nwaves = (long)gridDim.x * 4;
+    int inst = 0;
+    for (long item = (long)blockIdx.x * 4 + wave; item < total_items; item += nwaves) {
+        while (inst + 1 < count && descs[inst + 1].item0 <= item) ++inst;  // items grow monotonically
+        const PairDesc &D = descs[inst];
+        const int local = (int)(item - D.item0);
+        const int tt = local % D.target_tiles, c = local / D.target_tiles;
+        pair_item<T, COMP, TPL, UNROLL>((const SrcRec<T> *)D.srcS, (const SrcRec<T> *)D.srcB, (const T *)D.tg,
+                                        D.N, D.M, D.nimg, D.y1, D.dy, D.tiles_per_row, D.row_groups,
+                                        D.rows_per_chunk, D.part, tt, c, lane);
     }
 }
 
@@ -483,6 +542,93 @@ int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
                        w.part, F, N, M, pl.chunks, p->x1, p->dx, p->x1, xN, ylo, yM, p->n_decay,
                        p->froude, linear);
     return hip_check(hipGetLastError(), "residual kernel launch");
+}
+
+
+int residual_batched_enqueue(const bim_problem *probs, int count, const double *const *u, double *const *F,
+                             int prec, const PairLaunch *pls, const ResidualWork *ws, PairDesc *descs_dev,
+                             int max_blocks, hipStream_t s, hipEvent_t *ev_pair) {
+    if (count <= 0) return BIM_OK;
+    const int tpl = pls[0].tpl, unroll = pls[0].unroll;
+    std::vector<PairDesc> descs(count);
+    long total = 0;
+    for (int i = 0; i < count; ++i) {
+        const bim_problem *p = &probs[i];
+        const Dims d(p);
+        const PairLaunch &pl = pls[i];
+        if (pl.tpl != tpl || pl.unroll != unroll) return fail(BIM_EINVAL, "batched launch needs one kernel variant");
+        const ResidualWork &w = ws[i];
+        const int N = d.N, M = d.M;
+        hipLaunchKernelGGL(k_integrate, dim3(3 * M), dim3(64), 0, s, u[i], w.nodes, N, M, p->dx);
+        const int nb = cdiv(d.nnode, 256);
+        if (prec == BIM_FP64)
+            hipLaunchKernelGGL(k_nodes<double>, dim3(nb), dim3(256), 0, s, u[i], w.nodes, p->beta, p->beta_x,
+                               p->beta_y, w.ydiv, (SrcRec<double> *)w.srcS, (SrcRec<double> *)w.srcB, N, M, p->x1,
+                               p->dx, p->dy, p->half_domain, 0);
+        else
+            hipLaunchKernelGGL(k_nodes<float>, dim3(nb), dim3(256), 0, s, u[i], w.nodes, p->beta, p->beta_x,
+                               p->beta_y, w.ydiv, (SrcRec<float> *)w.srcS, (SrcRec<float> *)w.srcB, N, M, p->x1,
+                               p->dx, p->dy, p->half_domain, 0);
+        hipLaunchKernelGGL(k_targets, dim3(cdiv(2 * d.ntg, 256)), dim3(256), 0, s, w.nodes, w.ydiv, u[i], p->beta,
+                           p->beta_x, p->beta_y, w.tg, w.tg32, N, M, p->x1, p->dx, p->y1, p->dy, 0);
+        PairDesc &D = descs[i];
+        D.srcS = w.srcS;
+        D.srcB = w.srcB;
+        D.tg = (prec == BIM_FP64) ? (const void *)w.tg : (const void *)w.tg32;
+        D.part = w.part;
+        D.N = N;
+        D.M = M;
+        D.nimg = d.nimg;
+        D.y1 = p->y1;
+        D.dy = p->dy;
+        D.tiles_per_row = pl.tiles_per_row;
+        D.row_groups = pl.row_groups;
+        D.target_tiles = pl.target_tiles;
+        D.chunks = pl.chunks;
+        D.rows_per_chunk = pl.rows_per_chunk;
+        D.item0 = total;
+        total += (long)pl.target_tiles * pl.chunks;
+    }
+    BIM_HIP(hipMemcpyAsync(descs_dev, descs.data(), sizeof(PairDesc) * count, hipMemcpyHostToDevice, s));
+    const long want = (total + 3) / 4;
+    const int blocks = (int)std::max(1L, std::min(want, (long)(max_blocks > 0 ? max_blocks : 2048)));
+    if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[0], s));
+#define BIM_LAUNCH_BATCH(T, COMP, TPL, UNR)                                                                   \
+    hipLaunchKernelGGL((k_allpairs_batched<T, COMP, TPL, UNR>), dim3(blocks), dim3(256), 0, s, descs_dev, count, \
+                       total)
+    const int vsel = (tpl == 2 ? 3 : 0) + (unroll == 2 ? 0 : unroll == 4 ? 1 : 2);
+    if (prec == BIM_FP64) {
+        switch (vsel) {
+            case 0: BIM_LAUNCH_BATCH(double, false, 1, 2); break;
+            case 1: BIM_LAUNCH_BATCH(double, false, 1, 4); break;
+            case 2: BIM_LAUNCH_BATCH(double, false, 1, 8); break;
+            case 3: BIM_LAUNCH_BATCH(double, false, 2, 2); break;
+            case 4: BIM_LAUNCH_BATCH(double, false, 2, 4); break;
+            default: BIM_LAUNCH_BATCH(double, false, 2, 8); break;
+        }
+    } else {
+        switch (vsel) {
+            case 0: BIM_LAUNCH_BATCH(float, true, 1, 2); break;
+            case 1: BIM_LAUNCH_BATCH(float, true, 1, 4); break;
+            case 2: BIM_LAUNCH_BATCH(float, true, 1, 8); break;
+            case 3: BIM_LAUNCH_BATCH(float, true, 2, 2); break;
+            case 4: BIM_LAUNCH_BATCH(float, true, 2, 4); break;
+            default: BIM_LAUNCH_BATCH(float, true, 2, 8); break;
+        }
+    }
+#undef BIM_LAUNCH_BATCH
+    if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[1], s));
+    for (int i = 0; i < count; ++i) {
+        const bim_problem *p = &probs[i];
+        const Dims d(p);
+        const int N = d.N, M = d.M;
+        const double xN = p->x1 + (N - 1) * p->dx, yM = p->y1 + (M - 1) * p->dy;
+        const double ylo = p->half_domain ? -yM : p->y1;
+        hipLaunchKernelGGL(k_finalize, dim3(cdiv(d.nvec, 256)), dim3(256), 0, s, u[i], ws[i].nodes, ws[i].ydiv,
+                           ws[i].tg, ws[i].part, F[i], N, M, pls[i].chunks, p->x1, p->dx, p->x1, xN, ylo, yM,
+                           p->n_decay, p->froude, 0);
+    }
+    return hip_check(hipGetLastError(), "batched residual launch");
 }
 
 }  // namespace bim

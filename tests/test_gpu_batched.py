@@ -1,0 +1,82 @@
+"""Batched residual: one persistent launch over problems of uneven size."""
+import numpy as np
+import pytest
+
+from paper_1709_08803_amd import workloads as W
+from oracle import residual as R
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bim():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_1709_08803_amd import bim as B
+    B.lib()
+    return B
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+def test_batched_residual_matches_oracle_per_instance(bim, prec, tol):
+    probs = W.sweep_instances(6, seed=0, n_choices=[31, 34, 46, 61])
+    probs.append(W.tiny(0.9))
+    dps = [bim.DeviceProblem(p) for p in probs]
+    us_h = [W.perturbed_state(p, 20 + i) for i, p in enumerate(probs)]
+    us = [torch.as_tensor(u, device="cuda") for u in us_h]
+    Fs = bim.residual_batched(dps, us, prec)
+    torch.cuda.synchronize()
+    for p, u, F in zip(probs, us_h, Fs):
+        ref = R.residual(p, u)
+        scale = R.term_magnitude_rows(p, u)
+        err = (np.abs(F.cpu().numpy() - ref) / scale).max()
+        print(p.name, prec, err)
+        assert err <= tol
+
+
+def test_batched_equals_single_with_same_split(bim):
+    # with the same kernel variant and source split a problem's result does not
+    # depend on the batch it runs in
+    probs = W.sweep_instances(4, seed=3, n_choices=[31, 46])
+    dps = [bim.DeviceProblem(p) for p in probs]
+    us = [torch.as_tensor(W.perturbed_state(p, 5), device="cuda") for p in probs]
+    a = bim.residual_batched(dps, us, "fp64")
+    b = bim.residual_batched(dps[1:2], us[1:2], "fp64")
+    c = bim.residual_batched(dps[::-1], us[::-1], "fp64")
+    torch.cuda.synchronize()
+    assert torch.equal(a[1], b[0])
+    assert torch.equal(a[0], c[-1])
+
+
+def test_batched_solve_matches_single_solves_and_oracle(bim):
+    from oracle import jfnk as OJ
+    from oracle import linear as Lin
+    probs = W.sweep_instances(5, seed=1, n_choices=[31, 34, 37])
+    dps = [bim.DeviceProblem(p) for p in probs]
+    starts = [bim.linear_start(dp) for dp in dps]
+    ub = [u.clone() for u in starts]
+    rc, reps = bim.solve_batched(dps, ub, ftol=1e-11, check=False)
+    for i, (p, dp) in enumerate(zip(probs, dps)):
+        us = starts[i].clone()
+        rep = bim.solve(dp, us, ftol=1e-11, check=False)
+        print(p.name, "batched", reps[i]["status"], reps[i]["newton_iters"], reps[i]["gmres_iters"],
+              "single", rep["status"], rep["newton_iters"], rep["gmres_iters"])
+        if rep["status"] != 0:
+            continue  # a failed instance must fail in both
+        assert reps[i]["status"] == 0
+        a, b = ub[i].cpu().numpy(), us.cpu().numpy()
+        za, zb = R.reconstruct(p, a).zeta, R.reconstruct(p, b).zeta
+        assert np.abs(za - zb).max() <= 1e-9
+        assert np.abs(R.residual(p, a)).max() < 1e-9
+
+
+def test_batched_solve_mixed_precision(bim):
+    probs = W.sweep_instances(3, seed=2, n_choices=[31, 46])
+    dps = [bim.DeviceProblem(p) for p in probs]
+    us = [bim.linear_start(dp) for dp in dps]
+    rc, reps = bim.solve_batched(dps, us, ftol=1e-10, inner_prec="fp32c", check=False)
+    for p, u, r in zip(probs, us, reps):
+        print(p.name, r["status"], r["newton_iters"], r["gmres_iters"])
+        if r["status"] == 0:
+            assert np.abs(R.residual(p, u.cpu().numpy())).max() < 1e-9

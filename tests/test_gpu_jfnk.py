@@ -88,3 +88,18 @@ def test_unpreconditioned_gmres_needs_more_iterations(bim):
     print("with P", a["gmres_iters"], "without", b["gmres_iters"])
     assert a["status"] == 0
     assert b["gmres_iters"] > 3 * a["gmres_iters"]
+
+
+def test_graph_replay_matches_eager_solve(bim):
+    # every Arnoldi step is captured once and replayed across restarts and
+    # Newton steps; the replays must reproduce the eager path bit for bit
+    p = W.tiny(1.4)
+    dp = bim.DeviceProblem(p)
+    P = bim.Preconditioner(dp)
+    u0 = bim.linear_start(dp, P)
+    ua, ub = u0.clone(), u0.clone()
+    ra = bim.solve(dp, ua, P, ftol=1e-12, restart=10, use_graphs=1)
+    rb = bim.solve(dp, ub, P, ftol=1e-12, restart=10, use_graphs=0)
+    assert ra["status"] == 0 and rb["status"] == 0
+    assert ra["gmres_iters"] == rb["gmres_iters"] and ra["gmres_iters"] > 10  # restarts replayed graphs
+    assert torch.equal(ua, ub)

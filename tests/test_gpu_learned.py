@@ -1,0 +1,108 @@
+"""Learned-start network: bf16 GPU kernels against the FP64 CPU oracle of the same network."""
+import numpy as np
+import pytest
+
+from paper_1709_08803_amd import workloads as W
+from oracle import learned as OL
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def bim():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_1709_08803_amd import bim as B
+    B.lib()
+    return B
+
+
+def _bf16_tensor(x):
+    """float array -> int16 tensor of bf16 bits (round to nearest even, as the kernels do)."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return torch.as_tensor(u.view(np.int16).copy(), device="cuda")
+
+
+def _net_and_params(bim, N, M, B, seed):
+    net = bim.LearnedNet(N, M, seed=seed, max_batch=B, C1=8, C2=16, D3=64)
+    params = []
+    for l in range(4):
+        Wf, b, _, _ = net.get(l)
+        a = net.arch
+        fan_out = [a.C1, a.C2, a.D3, 2 * M * N][l]
+        b = np.random.default_rng(seed + l).normal(0, 0.05, b.shape).astype(np.float32)
+        net.set(l, None, b)
+        params.append((Wf.reshape(-1, fan_out).astype(np.float64), b.astype(np.float64)))
+    return net, params
+
+
+def _inputs(N, M, B, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(0, 1, (B, M, N, 2)).astype(np.float32)
+    f = rng.normal(0, 1, B).astype(np.float32)
+    T = rng.normal(0, 1, (B, 2 * M * N)).astype(np.float32)
+    return X, f, T
+
+
+@pytest.mark.parametrize("N,M,B", [(21, 9, 3), (33, 15, 5)])
+def test_forward_matches_fp64_oracle(bim, N, M, B):
+    net, params = _net_and_params(bim, N, M, B, 1)
+    X, f, _ = _inputs(N, M, B, 2)
+    Y = net.forward(_bf16_tensor(X), torch.as_tensor(f, device="cuda")).cpu().numpy()
+    Yref, _ = OL.forward(params, X, f)
+    err = np.abs(Y - Yref).max() / np.abs(Yref).max()
+    print("forward rel err", err)
+    assert err < 2e-3
+
+
+@pytest.mark.parametrize("N,M,B", [(21, 9, 3), (33, 15, 5)])
+def test_gradients_match_fp64_oracle(bim, N, M, B):
+    net, params = _net_and_params(bim, N, M, B, 3)
+    X, f, T = _inputs(N, M, B, 4)
+    loss = net.train_step(_bf16_tensor(X), torch.as_tensor(f, device="cuda"), torch.as_tensor(T, device="cuda"),
+                          lr=0.0, update=False)
+    Y, cache = OL.forward(params, X, f)
+    lref, dY = OL.loss_and_grad_out(Y, T)
+    grads = OL.backward(params, cache, dY)
+    assert abs(loss - lref) < 1e-3 * lref
+    for l in range(4):
+        _, _, gw, gb = net.get(l)
+        rw = grads[l][0].reshape(-1)
+        rb = grads[l][1]
+        ew = np.abs(gw - rw).max() / (np.abs(rw).max() + 1e-30)
+        eb = np.abs(gb - rb).max() / (np.abs(rb).max() + 1e-30)
+        print("layer", l, "grad rel err", ew, eb)
+        assert ew < 2e-2 and eb < 2e-2
+
+
+def test_training_reduces_loss(bim):
+    N, M, B = 21, 9, 8
+    net = bim.LearnedNet(N, M, seed=5, max_batch=B, C1=8, C2=16, D3=64)
+    X, f, T = _inputs(N, M, B, 6)
+    T = 0.1 * np.tanh(T).astype(np.float32)
+    Xd, fd, Td = _bf16_tensor(X), torch.as_tensor(f, device="cuda"), torch.as_tensor(T, device="cuda")
+    first = net.train_step(Xd, fd, Td, lr=1e-3)
+    for _ in range(200):
+        last = net.train_step(Xd, fd, Td, lr=1e-3)
+    print("loss", first, "->", last)
+    assert last < 0.2 * first
+
+
+def test_learned_start_is_linear_start_plus_correction(bim):
+    p = W.tiny(0.8)
+    dp = bim.DeviceProblem(p)
+    net = bim.LearnedNet(p.N, p.M, seed=7, max_batch=1, C1=8, C2=16, D3=32)
+    ul = bim.linear_start(dp).cpu().numpy()
+    u = net.infer_start(dp).cpu().numpy()
+    X0, f = net.make_input(dp)
+    Y = net.forward(X0, f).cpu().numpy()[0] * net.arch.out_scale
+    nb = (p.N + 1) * p.M
+    for fld in range(2):
+        blk = (u - ul)[fld * nb:(fld + 1) * nb].reshape(p.M, p.N + 1)
+        assert np.allclose(blk[:, 1:], Y[fld * p.N * p.M:(fld + 1) * p.N * p.M].reshape(p.M, p.N), atol=1e-12)
+        # upstream value keeps the radiation row x1 f_x,1 + n f_1 unchanged
+        assert np.allclose(p.x1 * blk[:, 1] + p.n_decay * blk[:, 0], 0.0, atol=1e-12)
+    assert np.array_equal(u[2 * nb:], ul[2 * nb:])
