@@ -9,8 +9,11 @@ closed-form singular term, dynamic and radiation rows, assembly).  `value` is
 pair-interactions per second (collocation point x source node x y-image).
 
 Also reported: the FP32-compensated evaluation, the all-pairs kernel's
-roofline fraction from HIP events on the launch stream, and the CPU oracle
-timed on a bounded sample of the same workload on this host's cores.
+roofline fraction from HIP events on the launch stream, the time to a converged
+solve (preconditioner setup, linear start and JFNK with FP64 or FP32-compensated
+inner sums, with the distance between the two solutions and, where a stored
+oracle solution of the same problem exists, to it), and the CPU oracle timed on
+a bounded sample of the same workload on this host's cores.
 """
 import argparse
 import json
@@ -54,12 +57,68 @@ def cpu_baseline(p, u, budget_s=15.0):
                       f"(surface and bottom), {spent:.1f} s"}
 
 
+def time_to_solution(B, W, np, torch, froude, ftol=1e-10):
+    """Wall time from the mesh to ||F||_inf <= ftol on the 181 x 61 problem at one F."""
+    p = W.working(froude)
+    dp = B.DeviceProblem(p)
+    nb = (p.N + 1) * p.M
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = B.Preconditioner(dp)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ulin = B.linear_start(dp, P)
+    torch.cuda.synchronize()
+    t_lin = time.perf_counter() - t0
+    res = {"froude": froude, "band_halfwidth": P.band, "precond_setup_ms": t_setup * 1e3,
+           "linear_start_ms": t_lin * 1e3}
+    sols = {}
+    for prec in ("fp64", "fp32c"):
+        u = ulin.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = B.solve(dp, u, P, ftol=ftol, inner_prec=prec, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sols[prec] = u.cpu().numpy()
+        res[prec] = {"status": rep["status"], "solve_ms": dt * 1e3,
+                     "total_ms": (dt + t_setup + t_lin) * 1e3, "newton": rep["newton_iters"],
+                     "gmres": rep["gmres_iters"], "jv_evals": rep["jv_evals"],
+                     "residual_evals": rep["residual_evals"], "fnorm_inf": rep["fnorm_inf"]}
+    P.close()
+    d = sols["fp32c"] - sols["fp64"]
+    res["fp32c_vs_fp64"] = {"max_dzeta_x": float(np.abs(d[:nb]).max()),
+                            "max_dphi_x": float(np.abs(d[nb:2 * nb]).max())}
+    if res["fp64"]["status"] == 0 and res["fp32c"]["status"] == 0:
+        res["speedup_fp32c"] = res["fp64"]["solve_ms"] / res["fp32c"]["solve_ms"]
+    gold = os.path.join(HERE, "tests", "golden", f"working_181x61_F{froude}.npz")
+    if os.path.exists(gold):
+        ref = np.load(gold)["u"]
+        zr, pr = node_values(p, ref, 0), node_values(p, ref, 1)
+        for prec, u in sols.items():
+            res[prec]["max_dzeta_vs_oracle"] = float(np.abs(node_values(p, u, 0) - zr).max())
+            res[prec]["max_dphi_vs_oracle"] = float(np.abs(node_values(p, u, 1) - pr).max())
+    return res
+
+
+def node_values(p, u, f):
+    """f-th field at the nodes from u (trapezoidal x-integration of f_x from f_1)."""
+    import numpy as np
+    nb = (p.N + 1) * p.M
+    blk = u[f * nb:(f + 1) * nb].reshape(p.M, p.N + 1)
+    fx = blk[:, 1:]
+    steps = 0.5 * p.dx * (fx[:, 1:] + fx[:, :-1])
+    return blk[:, :1] + np.concatenate([np.zeros((p.M, 1)), np.cumsum(steps, axis=1)], axis=1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the method's sharding "
@@ -119,7 +178,10 @@ def main():
                   "roofline": {"bound": "alu", "achieved": ach32, "peak": PEAK_FP32_VECTOR,
                                "unit": "TFLOP/s", "frac": ach32 / PEAK_FP32_VECTOR}},
         "fp64_eval_ms_events": t64,
+        "residual_evals_per_s": 1e3 / ms_step,
     }
+    if not args.no_solve:
+        out["time_to_solution"] = [time_to_solution(B, W, np, torch, f) for f in (0.7, 1.4)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, u_host)
     print(json.dumps(out))

@@ -133,7 +133,9 @@ int bim_tune_residual(const bim_problem *prob, const double *u, int prec, void *
  * blocks kept only within a band of slices |m - l| <= band_halfwidth
  * ("b blocks of size (N+1) x (N+1) in each row", b = 2 band_halfwidth + 1).
  * P depends only on the mesh and F (not on u or the bottom).
- *   band_halfwidth < 0 selects max(1, round(M / 20)) (b ~ M/10 as in Table 1).
+ *   band_halfwidth < 0 selects max(1, round(M / 6)) (b ~ M/3 blocks: wider than
+ *   the b ~ M/10 of Table 1, because GMRES iterations per Newton step fall
+ *   several-fold for a modest rise in setup and apply cost).
  * precond_setup factors P on the device and returns a library-owned handle
  * (free with precond_destroy).  It synchronises `stream`.  Device memory used:
  * precond_bytes().  Requires N + 1 <= 1024.  Returns BIM_EDOMAIN if a block
@@ -175,6 +177,8 @@ typedef struct bim_jfnk_opts {
     int32_t band_halfwidth;
     int32_t use_precond;
     int32_t use_graphs;  /* 1: replay each Arnoldi step's device work from a HIP graph */
+    double fd_eps;       /* epsilon of the shift rule h = sqrt(eps)(1 + |u|)/|v|; <= 0: the
+                            unit roundoff of the inner precision (2^-52 or 2^-23) */
 } bim_jfnk_opts;
 
 /* Outcome of a solve (host struct).  history[k] = ||F||_inf after k Newton steps. */

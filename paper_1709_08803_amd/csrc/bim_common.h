@@ -64,6 +64,10 @@ PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk);
 // (mesh, precision) if bim_tune_residual has run, else the default.
 PairLaunch pair_launch_for(const bim_problem *p, int prec);
 
+// Spare source records after each record array (read, never used, by the
+// all-pairs prefetch at the end of a row).
+constexpr int kRecPad = 8;
+
 // One problem of a batched all-pairs launch (device array entry).  srcS, srcB
 // and tg point at SrcRec<T> / T data of the batch's precision.
 struct PairDesc {

@@ -359,7 +359,8 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
         K.u = u_io;
         K.prec = o->inner_prec;
         K.linear = 0;
-        K.eps = (o->inner_prec == BIM_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+        K.eps = (o->fd_eps > 0) ? o->fd_eps
+                : (o->inner_prec == BIM_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
         if (o->inner_prec == BIM_FP64) {
             K.Fin = F;
         } else {
@@ -419,12 +420,13 @@ void jfnk_default_opts(bim_jfnk_opts *o) {
     o->band_halfwidth = -1;
     o->use_precond = 1;
     o->use_graphs = 1;
+    o->fd_eps = 0.0;
 }
 
 static int check_opts(const bim_jfnk_opts *o) {
     if (!o) return fail(BIM_EINVAL, "options are NULL");
     if (!(o->ftol > 0) || !(o->gmres_rtol > 0) || o->restart < 1 || o->restart > 200 || o->max_restarts < 0 ||
-        o->max_newton < 0 || o->max_backtracks < 0)
+        o->max_newton < 0 || o->max_backtracks < 0 || !(o->fd_eps < 1.0))
         return fail(BIM_EINVAL, "invalid solver options");
     if (o->inner_prec != BIM_FP64 && o->inner_prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
     return BIM_OK;

@@ -190,7 +190,8 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         hops.insert(hops.end(), v.begin(), v.end());
         return (int)slices.size() - 1;
     };
-    const double eps_in = (o->inner_prec == BIM_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+    const double eps_in = (o->fd_eps > 0) ? o->fd_eps
+                          : (o->inner_prec == BIM_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
     const int maxh = (int)(sizeof(I[0].R.history) / sizeof(I[0].R.history[0]));
     int rounds = 0;
 
@@ -603,7 +604,8 @@ extern "C" int jfnk_solve_batched(const bim_problem *probs, int count, bim_preco
     jfnk_default_opts(&o);
     if (opts) o = *opts;
     if (!(o.ftol > 0) || !(o.gmres_rtol > 0) || o.restart < 1 || o.restart > 30 || o.max_restarts < 0 ||
-        o.max_newton < 0 || o.max_backtracks < 0 || (o.inner_prec != BIM_FP64 && o.inner_prec != BIM_FP32C))
+        o.max_newton < 0 || o.max_backtracks < 0 || !(o.fd_eps < 1.0) ||
+        (o.inner_prec != BIM_FP64 && o.inner_prec != BIM_FP32C))
         return fail(BIM_EINVAL, "invalid solver options (batched restart must be <= 30)");
     return solve_batched_impl(probs, count, Ps, us, &o, reps, (hipStream_t)stream);
 }

@@ -518,7 +518,7 @@ int precond_setup(const bim_problem *prob, int band_halfwidth, bim_precond **out
     if (rc) return rc;
     if (!out) return fail(BIM_EINVAL, "out must not be NULL");
     *out = nullptr;
-    const int hb = band_halfwidth < 0 ? std::max(1, (int)std::lround(prob->M / 20.0)) : band_halfwidth;
+    const int hb = band_halfwidth < 0 ? std::max(1, (int)std::lround(prob->M / 6.0)) : band_halfwidth;
     if (hb < 1 || hb >= prob->M) return fail(BIM_EINVAL, "band half-width must be in [1, M-1]");
     if (prob->N + 1 > 1024) return fail(BIM_EINVAL, "N + 1 must not exceed 1024");
     Precond *pc = nullptr;

@@ -191,6 +191,41 @@ __device__ __forceinline__ SrcRec<T> load_rec(const SrcRec<T> *__restrict__ p) {
     return r;
 }
 
+// Walk the N source records of one row in groups of UNROLL with the next
+// group's scalar loads in flight while the current group is computed.  Scalar
+// loads may return out of order, so a wait covers every load issued before
+// it: the next group is loaded into separate registers and handed over only
+// after the current group's arithmetic, which is where the single wait falls.
+// The prefetch reads up to UNROLL records past the end of a row; the record
+// arrays carry kRecPad spare records so that this stays inside them (the
+// values read there are never used).
+// FP64 records (two scalar loads of 16 dwords per pair of records) gain
+// nothing from it (measured), so they keep the plain loop.
+template <typename T, int UNROLL, typename Body>
+__device__ __forceinline__ void walk_row(const SrcRec<T> *__restrict__ src, int N, Body &&body) {
+    static_assert(UNROLL <= kRecPad, "prefetch beyond the record padding");
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll UNROLL
+        for (int i = 0; i < N; ++i) body(load_rec(src + i));
+        return;
+    }
+    const int full = N - N % UNROLL;
+    SrcRec<T> cur[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) cur[u] = load_rec(src + u);
+    for (int i0 = 0; i0 < full; i0 += UNROLL) {
+        SrcRec<T> nxt[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) nxt[u] = load_rec(src + i0 + UNROLL + u);
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) body(cur[u]);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) cur[u] = nxt[u];
+    }
+    for (int u = 0; u < N - full; ++u) body(cur[u]);
+}
+
 // One wave = 64 consecutive collocation points x*_k on TPL mesh rows of one
 // boundary.  It walks a chunk of source rows (boundary, image, y-row) and, for
 // each, all N nodes of that row.  Source records are read with wave-uniform
@@ -275,9 +310,7 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
         }
         const SrcRec<T> *__restrict__ src = (ss ? srcB : srcS) + (size_t)j * N;
         if (ss == st) {
-#pragma unroll UNROLL
-            for (int i = 0; i < N; ++i) {
-                const SrcRec<T> p = load_rec(src + i);
+            walk_row<T, UNROLL>(src, N, [&](const SrcRec<T> &p) {
                 const T s = p.x - xs;
 #pragma unroll
                 for (int q = 0; q < TPL; ++q) {
@@ -293,11 +326,9 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                     const T Q = fma(s, fma(e.A, s, e.Bt), e.Ct2);
                     e.acc2 = fma(p.w, rsq(Q), e.acc2);
                 }
-            }
+            });
         } else {
-#pragma unroll UNROLL
-            for (int i = 0; i < N; ++i) {
-                const SrcRec<T> p = load_rec(src + i);
+            walk_row<T, UNROLL>(src, N, [&](const SrcRec<T> &p) {
                 const T s = p.x - xs;
 #pragma unroll
                 for (int q = 0; q < TPL; ++q) {
@@ -310,7 +341,7 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                     const T bsum = fma(p.wD * num, ri2, p.ws);
                     e.acc = fma(bsum, ri, e.acc);
                 }
-            }
+            });
         }
 #pragma unroll
         for (int q = 0; q < TPL; ++q) row_end<T, COMP>(ts[q]);
@@ -471,7 +502,7 @@ size_t residual_work_bytes(const Dims &d, const PairLaunch &pl) {
     b += al(sizeof(double) * 2 * d.nnode);
     b += al(sizeof(double) * 8 * 2 * d.ntg);
     b += al(sizeof(float) * 7 * 2 * d.ntg);
-    b += 2 * al(sizeof(SrcRec<double>) * d.nnode);
+    b += 2 * al(sizeof(SrcRec<double>) * (d.nnode + kRecPad));
     b += al(sizeof(double) * 2 * 2 * (size_t)d.ntg * pl.chunks);
     b += al(sizeof(double) * 4);
     return b;
@@ -484,8 +515,8 @@ void residual_work_carve(void *base, const Dims &d, const PairLaunch &pl, Residu
     w->ydiv = (double *)p; p += al(sizeof(double) * 2 * d.nnode);
     w->tg = (double *)p; p += al(sizeof(double) * 8 * 2 * d.ntg);
     w->tg32 = (float *)p; p += al(sizeof(float) * 7 * 2 * d.ntg);
-    w->srcS = p; p += al(sizeof(SrcRec<double>) * d.nnode);
-    w->srcB = p; p += al(sizeof(SrcRec<double>) * d.nnode);
+    w->srcS = p; p += al(sizeof(SrcRec<double>) * (d.nnode + kRecPad));
+    w->srcB = p; p += al(sizeof(SrcRec<double>) * (d.nnode + kRecPad));
     w->part = (double *)p; p += al(sizeof(double) * 2 * 2 * (size_t)d.ntg * pl.chunks);
     w->scal = (double *)p; p += al(sizeof(double) * 4);
     w->bytes = (size_t)(p - (char *)base);

@@ -138,11 +138,13 @@ def working(froude: float = 0.7, N: int = 181, M: int = 61) -> Problem:
 
 
 def sweep_instances(count: int, seed: int, n_choices: Optional[Sequence[int]] = None,
-                    fixed_n: Optional[int] = None) -> List[Problem]:
+                    fixed_n: Optional[int] = None, domain: Tuple[float, float, float] = (-30.0, 30.0, 20.0),
+                    height: Tuple[float, float] = (0.05, 0.3)) -> List[Problem]:
     """Seeded parameter sweep: uneven grids, F ~ U[0.5, 2], three topography kinds.
 
     Grids: N drawn from {61, 64, ..., 181} (N = 1 mod 3), M = (N-1)/3 + 1 over
-    x in [-30, 30], y in [0, 20] (so dx = dy).  fixed_n forces one grid size.
+    x in [-30, 30], y in [0, 20] (so dx = dy).  fixed_n forces one grid size;
+    domain = (x_lo, x_hi, y_hi) and height = (h_lo, h_hi) override the defaults.
     Topography kinds: a single Gaussian h exp(-(x^2+y^2)/w^2); a transverse
     ridge h exp(-x^2/w^2); two inline bumps at (0, 0) and (d, 0); with
     h ~ U[0.05, 0.3], w ~ U[0.5, 2], d ~ U[4, 12].
@@ -156,7 +158,7 @@ def sweep_instances(count: int, seed: int, n_choices: Optional[Sequence[int]] = 
         M = (N - 1) // 3 + 1
         F = float(rng.uniform(0.5, 2.0))
         kind = int(rng.integers(0, 3))
-        h = float(rng.uniform(0.05, 0.3))
+        h = float(rng.uniform(*height))
         w = float(rng.uniform(0.5, 2.0))
         d = float(rng.uniform(4.0, 12.0))
         if kind == 0:
@@ -165,7 +167,7 @@ def sweep_instances(count: int, seed: int, n_choices: Optional[Sequence[int]] = 
             bumps = [Bump(h, w, math.inf)]
         else:
             bumps = [Bump(h, w, w), Bump(h, w, w, cx=d)]
-        out.append(make_problem(N, M, -30.0, 30.0, 0.0, 20.0, F, bumps,
+        out.append(make_problem(N, M, domain[0], domain[1], 0.0, domain[2], F, bumps,
                                 name=f"sweep{seed}-{c}-k{kind}-{N}x{M}"))
     return out
 

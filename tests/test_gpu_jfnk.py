@@ -103,3 +103,26 @@ def test_graph_replay_matches_eager_solve(bim):
     assert ra["status"] == 0 and rb["status"] == 0
     assert ra["gmres_iters"] == rb["gmres_iters"] and ra["gmres_iters"] > 10  # restarts replayed graphs
     assert torch.equal(ua, ub)
+
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("inner,tol", [("fp64", 1e-9), ("fp32c", 1e-8)])
+def test_full_size_solution_matches_stored_oracle_solution(bim, inner, tol):
+    # 181 x 61, F = 1.4: the oracle's converged solution (tests/golden/make_working_solutions.py)
+    p = W.working(1.4)
+    ref = np.load(f"{GOLDEN}/working_181x61_F1.4.npz")["u"]
+    dp = bim.DeviceProblem(p)
+    P = bim.Preconditioner(dp)
+    u = bim.linear_start(dp, P)
+    rep = bim.solve(dp, u, P, ftol=1e-11, inner_prec=inner)
+    print(inner, {k: rep[k] for k in ("status", "newton_iters", "gmres_iters", "fnorm_inf", "time_ms")})
+    assert rep["status"] == 0
+    uh = u.cpu().numpy()
+    z_gpu, z_ref = R.reconstruct(p, uh), R.reconstruct(p, ref)
+    dz = np.abs(z_gpu.zeta - z_ref.zeta).max()
+    dphi = np.abs(z_gpu.phi - z_ref.phi).max()
+    print("max |dzeta|", dz, "max |dphi|", dphi)
+    assert dz <= tol and dphi <= 10 * tol
+    P.close()

@@ -19,9 +19,11 @@ def bim():
 
 
 CASES = [
-    ("tiny-31x11-h1", lambda: W.tiny(0.7), -1),
+    ("tiny-31x11-default", lambda: W.tiny(0.7), -1),
+    ("tiny-31x11-h1", lambda: W.tiny(0.7), 1),
     ("31x11-h2", lambda: W.tiny(1.4), 2),
-    ("61x21-h1", lambda: W.working(0.7, N=61, M=21), -1),
+    ("61x21-h1", lambda: W.working(0.7, N=61, M=21), 1),
+    ("61x21-default", lambda: W.working(0.7, N=61, M=21), -1),
     ("ragged-45x9-h3", lambda: W.make_problem(45, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 3),
     ("full-31x13", lambda: W.make_problem(31, 13, -10, 10, -6, 6, 1.2, [], half_domain=False), 1),
 ]
@@ -30,10 +32,11 @@ CASES = [
 @pytest.mark.parametrize("name,mk,hb", CASES, ids=[c[0] for c in CASES])
 def test_precond_apply_matches_oracle_solve(bim, name, mk, hb):
     p = mk()
-    pc_ref = Lin.Preconditioner(p, hb=hb)
     dp = bim.DeviceProblem(p)
     P = bim.Preconditioner(dp, hb)
-    assert P.band == pc_ref.hb
+    if hb < 0:  # the library's default band: max(1, round(M / 6)) slices
+        assert P.band == max(1, round(p.M / 6))
+    pc_ref = Lin.Preconditioner(p, hb=P.band)
     rng = np.random.default_rng(5)
     for trial in range(2):
         r = rng.standard_normal(p.n_unknowns)
@@ -51,12 +54,12 @@ def test_precond_full_size_solves_banded_system(bim):
     p = W.working(0.7)
     dp = bim.DeviceProblem(p)
     P = bim.Preconditioner(dp)
-    assert P.band == 3
+    assert P.band == 10
     r = np.random.default_rng(6).standard_normal(p.n_unknowns)
     z = P.apply(torch.as_tensor(r, device="cuda"))
     torch.cuda.synchronize()
     z = z.cpu().numpy()
-    res = Lin.banded_matvec(p, z, 3) - r
+    res = Lin.banded_matvec(p, z, P.band) - r
     print("181x61 |Pz - r| / |r|", np.abs(res).max() / np.abs(r).max(), "bytes", P.nbytes)
     assert np.abs(res).max() <= 1e-9 * np.abs(r).max()
     P.close()
