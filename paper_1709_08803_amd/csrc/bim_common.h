@@ -50,10 +50,10 @@ struct alignas(8 * sizeof(T)) SrcRec {
 struct PairLaunch {
     int tpl;             // collocation rows per lane (1 or 2)
     int unroll;          // inner-loop unroll over source nodes (2, 4 or 8)
-    int tiles_per_row;   // ceil((N-1) / 64)
     int row_groups;      // ceil(M / tpl)
-    int target_tiles;    // 2 row_groups tiles_per_row
-    int src_rows;        // 2 nimg M
+    int tiles_per_bnd;   // ceil(row_groups (N-1) / 64): 64-lane tiles per boundary
+    int target_tiles;    // 2 tiles_per_bnd
+    int src_rows;        // 2 M source-row visits (both images of a row in one visit)
     int rows_per_chunk;
     int chunks;
     int blocks;          // workgroups of 4 waves
@@ -77,7 +77,7 @@ struct PairDesc {
     double *part;
     int N, M, nimg;
     double y1, dy;
-    int tiles_per_row, row_groups, target_tiles, chunks, rows_per_chunk;
+    int tiles_per_bnd, row_groups, target_tiles, chunks, rows_per_chunk;
     long item0;  // index of this problem's first work item in the batch
 };
 

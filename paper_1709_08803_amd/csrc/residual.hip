@@ -226,27 +226,31 @@ __device__ __forceinline__ void walk_row(const SrcRec<T> *__restrict__ src, int 
     for (int u = 0; u < N - full; ++u) body(cur[u]);
 }
 
-// One wave = 64 consecutive collocation points x*_k on TPL mesh rows of one
-// boundary.  It walks a chunk of source rows (boundary, image, y-row) and, for
-// each, all N nodes of that row.  Source records are read with wave-uniform
-// addresses (scalar loads) and shared by the TPL targets of a lane; every
-// y-dependent term is hoisted per source row because y* is uniform in the wave.
+// One wave = 64 collocation points of one boundary: consecutive entries of
+// the list of (row group, x*_k) points of that boundary, where a row group is
+// TPL mesh rows handled by the same lane (so rows need not fill whole waves).
+// The wave walks a chunk of source rows (boundary, y-row) and, for each, all N
+// nodes of that row.  Source records are read with wave-uniform addresses
+// (scalar loads) and shared by the TPL targets of a lane; every y-dependent
+// term is hoisted per source row.  On a half domain each record serves both
+// images (x, y_j) and (x, -y_j), which share s, dz, s^2 + dz^2 and the
+// x-part of the double-layer numerator.
 // Per pair:
 //   own boundary:   w (D - D*) K1 + w sigma K2  and  w S2   (two rsqrt)
 //   other boundary: w D K1 + w sigma K2                      (one rsqrt)
 // written as  ri (coef num ri^2 + w sigma)  with ri = 1/R.
 // FP32C: FP32 sums over one source row, combined across rows with Neumaier's
 // compensated summation; the chunk result is written in FP64.
-template <typename T>
+template <typename T, int NI>
 struct TargetState {
-    T ys, d, Dst, A, B, C;        // collocation data
-    T t, ti, t2, Bt, Ct2;         // per source row
-    T acc, acc2;                  // per source row sums
-    T sum, comp, s2sum, s2comp;   // across rows
+    T ys, d, Dst, A, B, C;                       // collocation data
+    T t[NI], ti[NI], t2[NI], Bt[NI], Ct2[NI];    // per source row and image
+    T acc, acc2;                                 // per source row sums
+    T sum, comp, s2sum, s2comp;                  // across rows
 };
 
-template <typename T, bool COMP>
-__device__ __forceinline__ void row_end(TargetState<T> &g) {
+template <typename T, bool COMP, int NI>
+__device__ __forceinline__ void row_end(TargetState<T, NI> &g) {
     if (COMP) {
         T tsum = g.sum + g.acc;
         g.comp += (fabs(g.sum) >= fabs(g.acc)) ? ((g.sum - tsum) + g.acc) : ((g.acc - tsum) + g.sum);
@@ -260,25 +264,27 @@ __device__ __forceinline__ void row_end(TargetState<T> &g) {
     }
 }
 
-template <typename T, bool COMP, int TPL, int UNROLL>
+// NI = 2: half domain (both images per source row); NI = 1: full domain.
+template <typename T, bool COMP, int TPL, int UNROLL, int NI>
 __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
-                                          const T *__restrict__ tg, int N, int M, int nimg, double y1, double dy,
-                                          int tiles_per_row, int row_groups, int rows_per_chunk,
+                                          const T *__restrict__ tg, int N, int M, double y1, double dy,
+                                          int tiles_per_bnd, int row_groups, int rows_per_chunk,
                                           double *__restrict__ part, int tt, int c, int lane) {
     const int ntg = (N - 1) * M;
     const size_t T2 = (size_t)2 * ntg;
-    const int st = tt / (row_groups * tiles_per_row);
-    const int rem = tt - st * row_groups * tiles_per_row;
-    const int lg = rem / tiles_per_row;
-    const int k = (rem - lg * tiles_per_row) * 64 + lane;
-    const bool kvalid = k < N - 1;
-    const int kk = kvalid ? k : N - 2;
-    TargetState<T> ts[TPL];
+    const int st = tt / tiles_per_bnd;
+    const int npts = row_groups * (N - 1);
+    const int idx = (tt - st * tiles_per_bnd) * 64 + lane;
+    const bool valid = idx < npts;
+    const int ic = valid ? idx : npts - 1;
+    const int lg = ic / (N - 1);
+    const int k = ic - lg * (N - 1);
+    TargetState<T, NI> ts[TPL];
     T xs = 0;
 #pragma unroll
     for (int q = 0; q < TPL; ++q) {
         const int l = min(lg * TPL + q, M - 1);
-        const int tid = st * ntg + l * (N - 1) + kk;
+        const int tid = st * ntg + l * (N - 1) + k;
         xs = tg[0 * T2 + tid];
         ts[q].ys = tg[1 * T2 + tid];
         ts[q].d = tg[2 * T2 + tid];
@@ -288,23 +294,24 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
         ts[q].C = tg[6 * T2 + tid];
         ts[q].sum = ts[q].comp = ts[q].s2sum = ts[q].s2comp = 0;
     }
-    const int nrows = 2 * nimg * M;
     const int r0 = c * rows_per_chunk;
-    const int r1 = min(nrows, r0 + rows_per_chunk);
+    const int r1 = min(2 * M, r0 + rows_per_chunk);
     for (int r = r0; r < r1; ++r) {
         const int ss = r & 1;  // interleave boundaries so every chunk mixes both
-        const int rr = r >> 1;
-        const int img = rr / M;
-        const int j = rr - img * M;
-        const T iota = img ? T(-1) : T(1);
-        const T yj = T(iota * (y1 + j * dy));
+        const int j = r >> 1;
+        const T yj = T(y1 + j * dy);
 #pragma unroll
         for (int q = 0; q < TPL; ++q) {
-            ts[q].t = yj - ts[q].ys;
-            ts[q].ti = ts[q].t * iota;  // multiplies the source's a_y (mirrored on the image)
-            ts[q].t2 = ts[q].t * ts[q].t;
-            ts[q].Bt = ts[q].B * ts[q].t;
-            ts[q].Ct2 = ts[q].C * ts[q].t2;
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                // image i = 1 is (x, -y_j): a_y changes sign, which ti carries
+                const T t = (i == 0) ? yj - ts[q].ys : -yj - ts[q].ys;
+                ts[q].t[i] = t;
+                ts[q].ti[i] = (i == 0) ? t : -t;
+                ts[q].t2[i] = t * t;
+                ts[q].Bt[i] = ts[q].B * t;
+                ts[q].Ct2[i] = ts[q].C * (t * t);
+            }
             ts[q].acc = 0;
             ts[q].acc2 = 0;
         }
@@ -314,17 +321,20 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                 const T s = p.x - xs;
 #pragma unroll
                 for (int q = 0; q < TPL; ++q) {
-                    TargetState<T> &e = ts[q];
+                    TargetState<T, NI> &e = ts[q];
                     const T dz = p.z - e.d;
-                    const T r2 = fma(dz, dz, fma(s, s, e.t2));
-                    const T ri = rsq(r2);
-                    const T num = fma(-s, p.zx, fma(-e.ti, p.zy, dz));
-                    const T ri2 = ri * ri;
+                    const T base = (NI == 2) ? fma(s, s, dz * dz) : fma(s, s, e.t2[0]);
+                    const T nb0 = fma(-s, p.zx, dz);
                     const T coef = fma(-e.Dst, p.w, p.wD);
-                    const T bsum = fma(coef * num, ri2, p.ws);
-                    e.acc = fma(bsum, ri, e.acc);
-                    const T Q = fma(s, fma(e.A, s, e.Bt), e.Ct2);
-                    e.acc2 = fma(p.w, rsq(Q), e.acc2);
+#pragma unroll
+                    for (int i = 0; i < NI; ++i) {
+                        const T ri = rsq((NI == 2) ? base + e.t2[i] : fma(dz, dz, base));
+                        const T num = fma(-e.ti[i], p.zy, nb0);
+                        const T bsum = fma(coef * num, ri * ri, p.ws);
+                        e.acc = fma(bsum, ri, e.acc);
+                        const T Q = fma(s, fma(e.A, s, e.Bt[i]), e.Ct2[i]);
+                        e.acc2 = fma(p.w, rsq(Q), e.acc2);
+                    }
                 }
             });
         } else {
@@ -332,24 +342,27 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                 const T s = p.x - xs;
 #pragma unroll
                 for (int q = 0; q < TPL; ++q) {
-                    TargetState<T> &e = ts[q];
+                    TargetState<T, NI> &e = ts[q];
                     const T dz = p.z - e.d;
-                    const T r2 = fma(dz, dz, fma(s, s, e.t2));
-                    const T ri = rsq(r2);
-                    const T num = fma(-s, p.zx, fma(-e.ti, p.zy, dz));
-                    const T ri2 = ri * ri;
-                    const T bsum = fma(p.wD * num, ri2, p.ws);
-                    e.acc = fma(bsum, ri, e.acc);
+                    const T base = (NI == 2) ? fma(s, s, dz * dz) : fma(s, s, e.t2[0]);
+                    const T nb0 = fma(-s, p.zx, dz);
+#pragma unroll
+                    for (int i = 0; i < NI; ++i) {
+                        const T ri = rsq((NI == 2) ? base + e.t2[i] : fma(dz, dz, base));
+                        const T num = fma(-e.ti[i], p.zy, nb0);
+                        const T bsum = fma(p.wD * num, ri * ri, p.ws);
+                        e.acc = fma(bsum, ri, e.acc);
+                    }
                 }
             });
         }
 #pragma unroll
-        for (int q = 0; q < TPL; ++q) row_end<T, COMP>(ts[q]);
+        for (int q = 0; q < TPL; ++q) row_end<T, COMP, NI>(ts[q]);
     }
 #pragma unroll
     for (int q = 0; q < TPL; ++q) {
         const int l = lg * TPL + q;
-        if (kvalid && l < M) {
+        if (valid && l < M) {
             const int tid = st * ntg + l * (N - 1) + k;
             double *o = part + ((size_t)c * T2 + tid) * 2;
             o[0] = (double)ts[q].sum + (double)ts[q].comp;
@@ -358,12 +371,24 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
     }
 }
 
+template <typename T, bool COMP, int TPL, int UNROLL>
+__device__ __forceinline__ void pair_item_any(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
+                                              const T *__restrict__ tg, int N, int M, int nimg, double y1,
+                                              double dy, int tiles_per_bnd, int row_groups, int rows_per_chunk,
+                                              double *__restrict__ part, int tt, int c, int lane) {
+    if (nimg == 2)
+        pair_item<T, COMP, TPL, UNROLL, 2>(srcS, srcB, tg, N, M, y1, dy, tiles_per_bnd, row_groups, rows_per_chunk,
+                                           part, tt, c, lane);
+    else
+        pair_item<T, COMP, TPL, UNROLL, 1>(srcS, srcB, tg, N, M, y1, dy, tiles_per_bnd, row_groups, rows_per_chunk,
+                                           part, tt, c, lane);
+}
 
 // Single problem: one wave per (target tile, source chunk).
 template <typename T, bool COMP, int TPL, int UNROLL>
 __global__ __launch_bounds__(256) void k_allpairs(
     const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB, const T *__restrict__ tg,
-    int N, int M, int nimg, double y1, double dy, int tiles_per_row, int row_groups, int target_tiles,
+    int N, int M, int nimg, double y1, double dy, int tiles_per_bnd, int row_groups, int target_tiles,
     int chunks, int rows_per_chunk, double *__restrict__ part) {
     const int lane = threadIdx.x & 63;
     // the wave index is uniform: keep it (and everything derived) in scalar registers
@@ -371,8 +396,8 @@ __global__ __launch_bounds__(256) void k_allpairs(
     const int g = blockIdx.x * 4 + wave;
     const int tt = g % target_tiles, c = g / target_tiles;
     if (c >= chunks) return;
-    pair_item<T, COMP, TPL, UNROLL>(srcS, srcB, tg, N, M, nimg, y1, dy, tiles_per_row, row_groups, rows_per_chunk,
-                                    part, tt, c, lane);
+    pair_item_any<T, COMP, TPL, UNROLL>(srcS, srcB, tg, N, M, nimg, y1, dy, tiles_per_bnd, row_groups,
+                                        rows_per_chunk, part, tt, c, lane);
 }
 
 // Many problems in one persistent launch: the work items (target tile, source
@@ -390,9 +415,9 @@ __global__ __launch_bounds__(256) void k_allpairs_batched(const PairDesc *__rest
         const PairDesc &D = descs[inst];
         const int local = (int)(item - D.item0);
         const int tt = local % D.target_tiles, c = local / D.target_tiles;
-        pair_item<T, COMP, TPL, UNROLL>((const SrcRec<T> *)D.srcS, (const SrcRec<T> *)D.srcB, (const T *)D.tg,
-                                        D.N, D.M, D.nimg, D.y1, D.dy, D.tiles_per_row, D.row_groups,
-                                        D.rows_per_chunk, D.part, tt, c, lane);
+        pair_item_any<T, COMP, TPL, UNROLL>((const SrcRec<T> *)D.srcS, (const SrcRec<T> *)D.srcB,
+                                            (const T *)D.tg, D.N, D.M, D.nimg, D.y1, D.dy, D.tiles_per_bnd,
+                                            D.row_groups, D.rows_per_chunk, D.part, tt, c, lane);
     }
 }
 
@@ -477,10 +502,10 @@ PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk) {
     PairLaunch pl;
     pl.tpl = (tpl == 2) ? 2 : 1;
     pl.unroll = (unroll == 2 || unroll == 8) ? unroll : 4;
-    pl.tiles_per_row = cdiv(d.N - 1, 64);
     pl.row_groups = cdiv(d.M, pl.tpl);
-    pl.target_tiles = 2 * pl.row_groups * pl.tiles_per_row;
-    pl.src_rows = 2 * d.nimg * d.M;
+    pl.tiles_per_bnd = cdiv(pl.row_groups * (d.N - 1), 64);
+    pl.target_tiles = 2 * pl.tiles_per_bnd;
+    pl.src_rows = 2 * d.M;
     int rpc = rows_per_chunk;
     if (rpc <= 0) {
         // aim at ~16 waves per SIMD (1024 SIMDs) so the last wave of waves is a small tail
@@ -545,7 +570,7 @@ int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
 #define BIM_LAUNCH_PAIRS(T, COMP, TPL, UNR, TG)                                                         \
     hipLaunchKernelGGL((k_allpairs<T, COMP, TPL, UNR>), dim3(pl.blocks), dim3(256), 0, s,               \
                        (const SrcRec<T> *)w.srcS, (const SrcRec<T> *)w.srcB, TG, N, M, d.nimg, p->y1,   \
-                       p->dy, pl.tiles_per_row, pl.row_groups, pl.target_tiles, pl.chunks,              \
+                       p->dy, pl.tiles_per_bnd, pl.row_groups, pl.target_tiles, pl.chunks,              \
                        pl.rows_per_chunk, w.part)
     const int vsel = (pl.tpl == 2 ? 3 : 0) + (pl.unroll == 2 ? 0 : pl.unroll == 4 ? 1 : 2);
     if (prec == BIM_FP64) {
@@ -612,7 +637,7 @@ int residual_batched_enqueue(const bim_problem *probs, int count, const double *
         D.nimg = d.nimg;
         D.y1 = p->y1;
         D.dy = p->dy;
-        D.tiles_per_row = pl.tiles_per_row;
+        D.tiles_per_bnd = pl.tiles_per_bnd;
         D.row_groups = pl.row_groups;
         D.target_tiles = pl.target_tiles;
         D.chunks = pl.chunks;

@@ -43,7 +43,7 @@ extern "C" int bim_tune_residual(const bim_problem *prob, const double *u, int p
     double *F = nullptr;
     if ((rc = hip_check(hipMallocAsync((void **)&F, sizeof(double) * d.nvec, s), "hipMallocAsync"))) return rc;
     std::vector<bim_pair_config> cands;
-    const int src_rows = 2 * d.nimg * d.M;
+    const int src_rows = 2 * d.M;
     for (int tpl : {1, 2})
         for (int unr : {2, 4, 8})
             for (long want : {8192L, 16384L, 32768L}) {
