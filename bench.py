@@ -57,6 +57,22 @@ def cpu_baseline(p, u, budget_s=15.0):
                       f"(surface and bottom), {spent:.1f} s"}
 
 
+def measured_traffic():
+    """HBM bytes per FP64 all-pairs launch from the committed counter runs, or None
+    if the kernel source has changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "k_allpairs_181x61_hbm_traffic.md")
+    src = os.path.join(HERE, "paper_1709_08803_amd", "csrc", "residual.hip")
+    try:
+        fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if fields.get("source_sha256_prefix", "").strip() != sha:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15):
     """Wall time from the mesh to ||F||_inf <= ftol on the 181 x 61 problem at one F."""
     p = W.working(froude)
@@ -119,6 +135,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="first run a plain elementwise copy of MB megabytes (reads MB, writes MB), "
+                         "the reference for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the method's sharding "
@@ -129,6 +148,15 @@ def main():
     import torch
     from paper_1709_08803_amd import bim as B
     from paper_1709_08803_amd import workloads as W
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     p = W.working(0.7)
     dp = B.DeviceProblem(p)
@@ -171,7 +199,7 @@ def main():
                                "bump 0.2 exp(-(x^2+y^2)), F=0.7, FP64",
                    "pairs_per_eval": pairs},
         "roofline": {"bound": "alu", "achieved": ach64, "peak": PEAK_FP64_VECTOR, "unit": "TFLOP/s",
-                     "frac": ach64 / PEAK_FP64_VECTOR, "traffic": None,
+                     "frac": ach64 / PEAK_FP64_VECTOR, "traffic": measured_traffic(),
                      "kernel": "k_allpairs<double>", "kernel_ms": k64,
                      "flop_per_pair": FLOP_PER_PAIR},
         "fp32c": {"eval_ms": t32, "kernel_ms": k32, "pairs_per_s": pairs / (t32 * 1e-3),

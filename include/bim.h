@@ -255,22 +255,27 @@ int jfnk_solve_batched(const bim_problem *probs, int count, bim_precond *const *
                        const bim_jfnk_opts *opts, bim_jfnk_report *reps, void *stream);
 
 /*
- * Learned initial guess.  A small network -- two 3x3 stride-2 convolutions
- * with ReLU, a fully connected ReLU layer that also sees F, and a linear fully
- * connected output -- maps (F, the bottom beta on the N x M mesh) to a
- * correction (dzeta_x, dphi_x) of the discrete linear start; the upstream
- * values zeta_1, phi_1 follow from the radiation rows, psi is the linear
- * start's.  Weights are FP32 masters with bf16 copies; every contraction runs
- * on bf16 matrix cores with FP32 accumulation.
- *   Input X0: device bf16 [B][M][N][2] (channels (beta+1)/0.3, (F-1.25)/0.75),
- *   ffeat: device FP32 [B] ((F-1.25)/0.75), targets T / outputs Y: device
- *   FP32 [B][2][M][N] (correction / out_scale).  Layer l's weights are
- *   [fan_in][fan_out] FP32 (conv fan_in ordered (ky, kx, c_in)).
+ * Learned initial guess (the network of the learned-start extension; not in
+ * the paper).  A small network -- two 3x3 stride-2 convolutions with ReLU, a
+ * fully connected ReLU layer that also sees F, and a linear fully connected
+ * output -- maps (F, the bottom beta on the N x M mesh) and, with in_linear,
+ * the discrete linear start's (zeta_x, phi_x) to a correction (dzeta_x,
+ * dphi_x) of the linear start.  The upstream values f_1 and the psi block are
+ * the linear start's.  Weights are FP32 masters with bf16 copies; every
+ * contraction runs on bf16 matrix cores with FP32 accumulation.
+ *   Input X0: device bf16 [B][M][N][C0], C0 = 2 + 2 in_linear (channels
+ *   (beta+1)/0.3, (F-1.25)/0.75 and, with in_linear, zeta_x/0.2,
+ *   (phi_x-1)/0.2 of the linear start); ffeat: device FP32 [B] ((F-1.25)/0.75);
+ *   targets T / outputs Y: device FP32 [B][2][M][N] (correction / out_scale).
+ *   Layer l's weights are [fan_in][fan_out] FP32 (conv fan_in ordered
+ *   (ky, kx, c_in)).  Errors: BIM_EINVAL for sizes that do not match the
+ *   network or batches above max_batch.
  */
 typedef struct lg_arch {
     int32_t W, H;      /* mesh N (x) and M (y) */
     int32_t C1, C2;    /* convolution channels */
     int32_t D3;        /* hidden width */
+    int32_t in_linear; /* 1: the linear start's (zeta_x, phi_x) are input channels */
     double out_scale;  /* output units */
 } lg_arch;
 typedef struct lg_net lg_net;
@@ -286,8 +291,10 @@ int lg_forward(lg_net *net, const uint16_t *X0, const float *ffeat, int B, float
    *loss_out (host, may be NULL) receives the loss (synchronises). */
 int lg_train_step(lg_net *net, const uint16_t *X0, const float *ffeat, const float *T, int B, float lr, int update,
                   float *loss_out, void *stream);
-/* network input of one problem (X0 [M][N][2] bf16, ffeat [1]) */
-int lg_make_input(const bim_problem *prob, uint16_t *X0, float *ffeat, void *stream);
+/* network input of one problem (X0 [M][N][2 + 2 in_linear] bf16, ffeat [1]); u_lin
+   (device, the linear start in the unknown vector's order) is read when in_linear = 1 */
+int lg_make_input(const bim_problem *prob, const double *u_lin, int in_linear, uint16_t *X0, float *ffeat,
+                  void *stream);
 /* Newton start: the linear start (bim_linear_start with P) plus the network's correction. */
 int lg_infer_start(lg_net *net, const bim_problem *prob, const bim_precond *P, double *u_out, void *stream);
 

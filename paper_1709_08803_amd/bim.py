@@ -79,7 +79,7 @@ def lib():
         L.lg_get_params.argtypes = [vp, i32, fp, fp, fp, fp]
         L.lg_forward.argtypes = [vp, vp, vp, i32, vp, vp]
         L.lg_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, i32, fp, vp]
-        L.lg_make_input.argtypes = [pp, vp, vp, vp]
+        L.lg_make_input.argtypes = [pp, vp, i32, vp, vp, vp]
         L.lg_infer_start.argtypes = [vp, pp, vp, vp, vp]
         for name in ("bim_residual", "bim_jv", "bim_residual_timed", "bim_tune_residual", "precond_setup",
                      "precond_apply", "precond_band", "jfnk_solve", "bim_linear_start", "lg_create",
@@ -138,7 +138,7 @@ class JfnkReport(ctypes.Structure):
 
 class LgArch(ctypes.Structure):
     _fields_ = [("W", ctypes.c_int32), ("H", ctypes.c_int32), ("C1", ctypes.c_int32), ("C2", ctypes.c_int32),
-                ("D3", ctypes.c_int32), ("out_scale", ctypes.c_double)]
+                ("D3", ctypes.c_int32), ("in_linear", ctypes.c_int32), ("out_scale", ctypes.c_double)]
 
 
 class DeviceProblem:
@@ -342,10 +342,16 @@ class LearnedNet:
                                    ctypes.c_float(lr), 1 if update else 0, ctypes.byref(loss), _stream(stream)))
         return loss.value
 
-    def make_input(self, dp: DeviceProblem, stream=None):
-        X0 = torch.empty((dp.host.M, dp.host.N, 2), dtype=torch.int16, device=dp.device)
+    @property
+    def in_channels(self) -> int:
+        return 4 if self.arch.in_linear else 2
+
+    def make_input(self, dp: DeviceProblem, u_lin: Optional[torch.Tensor] = None, stream=None):
+        """Network input of one problem; u_lin (the linear start) is needed when the net reads it."""
+        X0 = torch.empty((dp.host.M, dp.host.N, self.in_channels), dtype=torch.int16, device=dp.device)
         f = torch.empty(1, dtype=torch.float32, device=dp.device)
-        _check(lib().lg_make_input(dp.ref(), X0.data_ptr(), f.data_ptr(), _stream(stream)))
+        _check(lib().lg_make_input(dp.ref(), _dptr(u_lin) if u_lin is not None else None, int(self.arch.in_linear),
+                                   X0.data_ptr(), f.data_ptr(), _stream(stream)))
         return X0, f
 
     def infer_start(self, dp: DeviceProblem, P: Optional[Preconditioner] = None, out=None, stream=None):

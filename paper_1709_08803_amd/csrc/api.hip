@@ -157,7 +157,9 @@ namespace bim {
 // Rows per chunk that give every work item about the same number of pairs
 // (~`pairs_target` source nodes per lane) across problems of different sizes.
 int balanced_rows_per_chunk(const Dims &d, int pairs_target) {
-    return std::max(1, std::min(2 * d.nimg * d.M, (pairs_target + d.N - 1) / d.N));
+    // one source-row visit covers nimg images of N nodes
+    const int per_row = d.nimg * d.N;
+    return std::max(1, std::min(2 * d.M, (pairs_target + per_row - 1) / per_row));
 }
 
 }  // namespace bim

@@ -58,11 +58,15 @@ struct PairLaunch {
     int chunks;
     int blocks;          // workgroups of 4 waves
 };
-// tpl/unroll outside the supported set fall back to 1/4; rows_per_chunk <= 0 picks a default.
-PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk);
+// tpl/unroll outside the supported set fall back to 1/4; rows_per_chunk <= 0
+// splits the source rows so that the launch has about want_waves waves.
+PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk, long want_waves = 16384);
 // The launch used by the public entry points: the autotuned choice for this
 // (mesh, precision) if bim_tune_residual has run, else the default.
 PairLaunch pair_launch_for(const bim_problem *p, int prec);
+// Source rows per chunk giving about pairs_target pairs per (collocation point,
+// chunk) work item; used to even out work items across the meshes of a batch.
+int balanced_rows_per_chunk(const Dims &d, int pairs_target);
 
 // Spare source records after each record array (read, never used, by the
 // all-pairs prefetch at the end of a row).

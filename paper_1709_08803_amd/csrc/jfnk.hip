@@ -36,7 +36,7 @@ struct Krylov {
     hipStream_t s;
     const Precond *pc;
     int m;                    // restart length
-    PairLaunch pl;            // launch used for both precisions (chunks sized for the larger)
+    PairLaunch pl64, pl32;    // launch shape per precision (workspace sized for the larger chunk count)
     ResidualWork rw;
     double *V, *Z, *w, *ut, *Ft, *r, *part, *hdev, *scal, *ydev;
     double *hhost;            // pinned: h column + norm
@@ -56,7 +56,8 @@ struct Krylov {
             return rc;
         }
         if ((rc = axpy_dev_enqueue(u, z, scal + 2, ut, n, s))) return rc;
-        if ((rc = residual_enqueue(p, ut, Ft, prec, pl, rw, s, nullptr, linear))) return rc;
+        if ((rc = residual_enqueue(p, ut, Ft, prec, prec == BIM_FP64 ? pl64 : pl32, rw, s, nullptr, linear)))
+            return rc;
         return quotient_enqueue(Ft, Fin, scal + 2, out, n, s);
     }
     int apply_prec(const double *v, double *z) {
@@ -280,7 +281,8 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
     K.scal = take(sizeof(double) * 8);
     K.ydev = take(sizeof(double) * (m + 1));
     K.hhost = hhost;
-    K.pl = plw;
+    K.pl64 = pl64;
+    K.pl32 = pl32;
     K.use_graphs = o->use_graphs != 0;
 
     // preconditioner: caller's, or built here
@@ -313,7 +315,7 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
     if (linear_start_only) {
         // u_lin = u0 - J~^-1 F_lin(u0): one linear solve with the exact linear operator
         if ((rc = uniform_stream_enqueue(u_io, d.N, d.M, p->x1, s))) return rc;
-        if ((rc = residual_enqueue(p, u_io, F, BIM_FP64, plw, K.rw, s, nullptr, 1))) return rc;
+        if ((rc = residual_enqueue(p, u_io, F, BIM_FP64, pl64, K.rw, s, nullptr, 1))) return rc;
         if ((rc = axpby_enqueue(-1.0, F, 0.0, nullptr, rhs, n, s))) return rc;
         K.u = u_io;
         K.Fin = F;
@@ -342,7 +344,7 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
         return BIM_OK;
     };
 
-    if ((rc = residual_enqueue(p, u_io, F, BIM_FP64, plw, K.rw, s))) return rc;
+    if ((rc = residual_enqueue(p, u_io, F, BIM_FP64, pl64, K.rw, s))) return rc;
     R.residual_evals = 1;
     double fn2, finf;
     if ((rc = norms(F, &fn2, &finf))) return rc;
@@ -364,7 +366,9 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
         if (o->inner_prec == BIM_FP64) {
             K.Fin = F;
         } else {
-            if ((rc = residual_enqueue(p, u_io, Fin, o->inner_prec, plw, K.rw, s))) return rc;
+            if ((rc = residual_enqueue(p, u_io, Fin, o->inner_prec, o->inner_prec == BIM_FP64 ? pl64 : pl32, K.rw,
+                                       s)))
+                return rc;
             ++R.inner_residual_evals;
             K.Fin = Fin;
         }
@@ -379,7 +383,7 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
         bool ok = false;
         for (int bt = 0; bt <= o->max_backtracks; ++bt) {
             if ((rc = axpby_enqueue(1.0, u_io, mu, delta, K.ut, n, s))) return rc;
-            if ((rc = residual_enqueue(p, K.ut, K.Ft, BIM_FP64, plw, K.rw, s))) return rc;
+            if ((rc = residual_enqueue(p, K.ut, K.Ft, BIM_FP64, pl64, K.rw, s))) return rc;
             ++R.residual_evals;
             double tn2, tinf;
             if ((rc = norms(K.Ft, &tn2, &tinf))) return rc;

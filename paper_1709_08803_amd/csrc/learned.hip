@@ -1,12 +1,13 @@
 // Learned initial guess: a small convolutional encoder + MLP that maps
-// (F, bottom topography on the mesh) to a correction of the linear start
-// (zeta_x, phi_x) on the same mesh.  Hand-written bf16 kernels with FP32
+// (F, bottom topography on the mesh), and optionally the linear start itself,
+// to a correction of the linear start's (zeta_x, phi_x) on the same mesh.  Hand-written bf16 kernels with FP32
 // accumulation: matrix-core (MFMA 16x16x16 bf16) GEMMs for the dense
 // contractions (convolutions through im2col, fully connected layers), and
 // elementwise kernels for bias, ReLU, loss and Adam.  FP32 master weights.
 //
 // Layout (NHWC, row-major):
-//   X0  [B][H][W][2]      channels: (beta + 1) / 0.3, (F - 1.25) / 0.75
+//   X0  [B][H][W][C0]     channels: (beta + 1) / 0.3, (F - 1.25) / 0.75 and, with
+//                         in_linear, the linear start's zeta_x / 0.2, (phi_x - 1) / 0.2
 //   Y1  [B][H1][W1][C1]   conv 3x3 stride 2 pad 1, ReLU      H1 = ceil(H/2), W1 = ceil(W/2)
 //   Y2  [B][H2][W2][C2]   conv 3x3 stride 2 pad 1, ReLU      H2 = ceil(H1/2), W2 = ceil(W1/2)
 //   Y3  [B][D3]           fully connected on [Y2, F], ReLU
@@ -216,12 +217,20 @@ __global__ void k_to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y,
     if (e < n) y[e] = f2bf(x[e]);
 }
 
-// network input from a problem: NHWC [H = M][W = N][2]
-__global__ void k_make_input(const double *__restrict__ beta, double froude, uint16_t *__restrict__ X, int N, int M) {
+// network input from a problem: NHWC [H = M][W = N][C0]; C0 = 4 adds the
+// linear start's x-derivative planes (u_lin in the unknown vector's order)
+__global__ void k_make_input(const double *__restrict__ beta, double froude, const double *__restrict__ ulin,
+                             uint16_t *__restrict__ X, int N, int M, int C0) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= N * M) return;
-    X[2 * e] = f2bf((float)((beta[e] + 1.0) / 0.3));
-    X[2 * e + 1] = f2bf((float)((froude - 1.25) / 0.75));
+    X[C0 * e] = f2bf((float)((beta[e] + 1.0) / 0.3));
+    X[C0 * e + 1] = f2bf((float)((froude - 1.25) / 0.75));
+    if (C0 == 4) {
+        const int j = e / N, i = e - j * N;
+        const size_t nb = (size_t)(N + 1) * M, at = (size_t)j * (N + 1) + 1 + i;
+        X[C0 * e + 2] = f2bf((float)(ulin[at] / 0.2));
+        X[C0 * e + 3] = f2bf((float)((ulin[nb + at] - 1.0) / 0.2));
+    }
 }
 
 // A2' = [A2 | F-feature | 0 pad]: copies rows of A2 into a wider buffer and sets the F column
@@ -233,21 +242,19 @@ __global__ void k_append_feature(const uint16_t *__restrict__ A2, uint16_t *__re
     A2p[e] = (c < d2) ? A2[(size_t)b * d2 + c] : (c == d2 ? f2bf(f[b]) : (uint16_t)0);
 }
 
-// u = u_lin + correction: zeta_x, phi_x blocks get out_scale * Y; the upstream values
-// follow from the radiation rows F5, F3 (x1 f_x + n f_1 = const), which stay satisfied.
+// u = u_lin + correction: the zeta_x, phi_x entries get out_scale * Y; the upstream
+// values f_1 and the psi block stay those of the linear start (an error in the
+// predicted f_x at the first node would enter f_1 amplified by |x1| / n through
+// the radiation rows).
 __global__ void k_apply_correction(const double *__restrict__ ulin, const float *__restrict__ Y, double *__restrict__ u,
-                                   int N, int M, double x1, double n_decay, double scale) {
+                                   int N, int M, double scale) {
     const long nb = (long)(N + 1) * M;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 3 * nb) return;
     const int f = (int)(e / nb);
     const int j = (int)((e % nb) / (N + 1)), c = (int)((e % nb) % (N + 1));
     double v = ulin[e];
-    if (f < 2) {
-        const size_t plane = (size_t)f * N * M;
-        if (c >= 1) v += scale * (double)Y[plane + (size_t)j * N + (c - 1)];
-        else v += -x1 * scale * (double)Y[plane + (size_t)j * N] / n_decay;  // keeps x1 df_x,1 + n df_1 = 0
-    }
+    if (f < 2 && c >= 1) v += scale * (double)Y[(size_t)f * N * M + (size_t)j * N + (c - 1)];
     u[e] = v;
 }
 
@@ -256,6 +263,7 @@ __global__ void k_apply_correction(const double *__restrict__ ulin, const float 
 // ------------------------------------------------------------------ network object
 struct LgNet {
     lg_arch a;
+    int C0;  // input channels
     int H1, W1, H2, W2, D2, D2p, Dout;
     long nparam[4], nbias[4];
     // FP32 master parameters, gradients, Adam moments; bf16 weight copies
@@ -289,8 +297,8 @@ static int lg_alloc(LgNet *net, int maxB) {
     }
     const size_t B = maxB;
     const size_t r1 = B * net->H1 * net->W1, r2 = B * net->H2 * net->W2;
-    want((void **)&net->X0, 2 * B * a.H * a.W * 2);
-    want((void **)&net->cols1, 2 * r1 * 18);
+    want((void **)&net->X0, 2 * B * a.H * a.W * net->C0);
+    want((void **)&net->cols1, 2 * r1 * 9 * net->C0);
     want((void **)&net->A1, 2 * r1 * a.C1);
     want((void **)&net->cols2, 2 * r2 * 9 * a.C1);
     want((void **)&net->A2, 2 * B * net->D2);
@@ -335,9 +343,10 @@ static int forward_impl(LgNet *net, const uint16_t *X0, const float *ffeat, int 
     int rc;
     const long r1 = (long)B * net->H1 * net->W1, r2 = (long)B * net->H2 * net->W2;
     // conv1
-    hipLaunchKernelGGL(k_im2col, dim3(cdiv(r1 * 18, 256)), dim3(256), 0, s, X0, net->cols1, B, a.H, a.W, 2, net->H1,
-                       net->W1);
-    if ((rc = gemm(net->cols1, 18, 1, net->wb[0], a.C1, 1, net->Y1, a.C1, (int)r1, a.C1, 18, 1.f, 0.f, s))) return rc;
+    const int K1 = 9 * net->C0;
+    hipLaunchKernelGGL(k_im2col, dim3(cdiv(r1 * K1, 256)), dim3(256), 0, s, X0, net->cols1, B, a.H, a.W, net->C0,
+                       net->H1, net->W1);
+    if ((rc = gemm(net->cols1, K1, 1, net->wb[0], a.C1, 1, net->Y1, a.C1, (int)r1, a.C1, K1, 1.f, 0.f, s))) return rc;
     hipLaunchKernelGGL(k_bias_act, dim3(cdiv(r1 * a.C1, 256)), dim3(256), 0, s, net->Y1, net->b[0], net->A1,
                        (long)a.C1, r1, a.C1, 1);
     // conv2
@@ -406,7 +415,8 @@ static int backward_impl(LgNet *net, int B, hipStream_t s) {
     hipLaunchKernelGGL(k_relu_back, dim3(cdiv(r1 * a.C1, 256)), dim3(256), 0, s, net->dA1, net->Y1, net->dY1b,
                        r1 * a.C1);
     // conv1: dW1 = cols1^T dY1, db1
-    if ((rc = gemm(net->cols1, 1, 18, net->dY1b, a.C1, 1, net->gw[0], a.C1, 18, a.C1, (int)r1, 1.f, 0.f, s))) return rc;
+    const int K1 = 9 * net->C0;
+    if ((rc = gemm(net->cols1, 1, K1, net->dY1b, a.C1, 1, net->gw[0], a.C1, K1, a.C1, (int)r1, 1.f, 0.f, s))) return rc;
     hipLaunchKernelGGL(k_colsum, dim3(cdiv(a.C1, 256)), dim3(256), 0, s, net->dA1, net->gb[0], r1, a.C1);
     return hip_check(hipGetLastError(), "learned backward launch");
 }
@@ -423,15 +433,18 @@ void lg_default_arch(lg_arch *a, int N, int M) {
     a->C1 = 16;
     a->C2 = 32;
     a->D3 = 256;
+    a->in_linear = 1;
     a->out_scale = 0.05;
 }
 
 int lg_create(const lg_arch *arch, uint64_t seed, int max_batch, lg_net **out) {
     if (!arch || !out || max_batch < 1) return fail(BIM_EINVAL, "bad learned-net arguments");
-    if (arch->H < 3 || arch->W < 3 || arch->C1 < 1 || arch->C2 < 1 || arch->D3 < 1)
+    if (arch->H < 3 || arch->W < 3 || arch->C1 < 1 || arch->C2 < 1 || arch->D3 < 1 ||
+        (arch->in_linear != 0 && arch->in_linear != 1))
         return fail(BIM_EINVAL, "bad learned-net architecture");
     LgNet *net = new LgNet();
     net->a = *arch;
+    net->C0 = arch->in_linear ? 4 : 2;
     net->H1 = (arch->H + 1) / 2;
     net->W1 = (arch->W + 1) / 2;
     net->H2 = (net->H1 + 1) / 2;
@@ -439,7 +452,7 @@ int lg_create(const lg_arch *arch, uint64_t seed, int max_batch, lg_net **out) {
     net->D2 = net->H2 * net->W2 * arch->C2;
     net->D2p = ((net->D2 + 1 + 15) / 16) * 16;
     net->Dout = 2 * arch->H * arch->W;
-    const long fan[4] = {18, 9L * arch->C1, (long)net->D2 + 1, arch->D3};
+    const long fan[4] = {9L * net->C0, 9L * arch->C1, (long)net->D2 + 1, arch->D3};
     const long outs[4] = {arch->C1, arch->C2, arch->D3, net->Dout};
     for (int l = 0; l < 4; ++l) {
         net->nparam[l] = fan[l] * outs[l];
@@ -559,13 +572,16 @@ int lg_train_step(lg_net *n, const uint16_t *X0, const float *ffeat, const float
     return hip_check(hipGetLastError(), "train step launch");
 }
 
-int lg_make_input(const bim_problem *prob, uint16_t *X0, float *ffeat, void *stream) {
+int lg_make_input(const bim_problem *prob, const double *u_lin, int in_linear, uint16_t *X0, float *ffeat,
+                  void *stream) {
     int rc = validate(prob);
     if (rc) return rc;
     if (!X0 || !ffeat) return fail(BIM_EINVAL, "X0 and ffeat must be device pointers");
+    if (in_linear != 0 && in_linear != 1) return fail(BIM_EINVAL, "in_linear must be 0 or 1");
+    if (in_linear && !u_lin) return fail(BIM_EINVAL, "the linear start is needed for in_linear inputs");
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_make_input, dim3(cdiv((long)prob->N * prob->M, 256)), dim3(256), 0, s, prob->beta,
-                       prob->froude, X0, prob->N, prob->M);
+                       prob->froude, u_lin, X0, prob->N, prob->M, in_linear ? 4 : 2);
     const float f = (float)((prob->froude - 1.25) / 0.75);
     if ((rc = hip_check(hipMemcpyAsync(ffeat, &f, sizeof(float), hipMemcpyHostToDevice, s), "copy"))) return rc;
     return hip_check(hipStreamSynchronize(s), "sync");
@@ -588,7 +604,7 @@ int lg_infer_start(lg_net *n, const bim_problem *prob, const bim_precond *P, dou
         return rc;
     }
     hipLaunchKernelGGL(k_make_input, dim3(cdiv((long)prob->N * prob->M, 256)), dim3(256), 0, s, prob->beta,
-                       prob->froude, net->X0, prob->N, prob->M);
+                       prob->froude, ulin, net->X0, prob->N, prob->M, net->C0);
     const float f = (float)((prob->froude - 1.25) / 0.75);
     if ((rc = hip_check(hipMemcpyAsync(net->ffeat, &f, sizeof(float), hipMemcpyHostToDevice, s), "copy"))) {
         (void)hipFreeAsync(ulin, s);
@@ -599,7 +615,7 @@ int lg_infer_start(lg_net *n, const bim_problem *prob, const bim_precond *P, dou
         return rc;
     }
     hipLaunchKernelGGL(k_apply_correction, dim3(cdiv(nvec, 256)), dim3(256), 0, s, ulin, net->Y4, u_out, prob->N,
-                       prob->M, prob->x1, prob->n_decay, net->a.out_scale);
+                       prob->M, net->a.out_scale);
     (void)hipFreeAsync(ulin, s);
     return hip_check(hipStreamSynchronize(s), "sync");
 }

@@ -498,7 +498,7 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
-PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk) {
+PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk, long want_waves) {
     PairLaunch pl;
     pl.tpl = (tpl == 2) ? 2 : 1;
     pl.unroll = (unroll == 2 || unroll == 8) ? unroll : 4;
@@ -508,8 +508,7 @@ PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk) {
     pl.src_rows = 2 * d.M;
     int rpc = rows_per_chunk;
     if (rpc <= 0) {
-        // aim at ~16 waves per SIMD (1024 SIMDs) so the last wave of waves is a small tail
-        const long want_waves = 16384;
+        // many waves per SIMD (1024 SIMDs) so the last round of waves is a small tail
         int chunks = std::max(1, std::min(pl.src_rows, cdiv(want_waves, pl.target_tiles)));
         rpc = cdiv(pl.src_rows, chunks);
     }

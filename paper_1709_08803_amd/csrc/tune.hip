@@ -25,7 +25,10 @@ PairLaunch pair_launch_for(const bim_problem *p, int prec) {
         if (it != g_best.end())
             return pair_launch(d, it->second.targets_per_lane, it->second.unroll, it->second.rows_per_chunk);
     }
-    return pair_launch(d, 1, 4, 0);
+    // untuned defaults: the fastest shapes measured at 181 x 61 (FP64: 4-way
+    // unroll, ~16 waves per SIMD; FP32C: 2-way unroll, ~24 waves per SIMD)
+    if (prec == BIM_FP32C) return pair_launch(d, 1, 2, 0, 24576);
+    return pair_launch(d, 1, 4, 0, 16384);
 }
 
 }  // namespace bim

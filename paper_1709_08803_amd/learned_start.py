@@ -53,7 +53,7 @@ def generate(problems: List[W.Problem], net: B.LearnedNet, batch: int = 32, ftol
             if rep["status"] != 0:
                 continue
             uh, lh = u.cpu().numpy(), ul.cpu().numpy()
-            X0, f = net.make_input(dp)
+            X0, f = net.make_input(dp, ul)
             tgt = ((_xblocks(p, uh) - _xblocks(p, lh)) / scale).astype(np.float32).reshape(-1)
             out.append(Sample(p, X0, f, torch.as_tensor(tgt, device=X0.device), uh, lh))
         log(f"  generated {len(out)}/{b0 + len(probs)} converged ({time.perf_counter() - t0:.1f} s)")

@@ -139,12 +139,14 @@ def working(froude: float = 0.7, N: int = 181, M: int = 61) -> Problem:
 
 def sweep_instances(count: int, seed: int, n_choices: Optional[Sequence[int]] = None,
                     fixed_n: Optional[int] = None, domain: Tuple[float, float, float] = (-30.0, 30.0, 20.0),
-                    height: Tuple[float, float] = (0.05, 0.3)) -> List[Problem]:
+                    height: Tuple[float, float] = (0.05, 0.3), froude: Tuple[float, float] = (0.5, 2.0),
+                    width: Tuple[float, float] = (0.5, 2.0), kinds: Sequence[int] = (0, 1, 2)) -> List[Problem]:
     """Seeded parameter sweep: uneven grids, F ~ U[0.5, 2], three topography kinds.
 
     Grids: N drawn from {61, 64, ..., 181} (N = 1 mod 3), M = (N-1)/3 + 1 over
     x in [-30, 30], y in [0, 20] (so dx = dy).  fixed_n forces one grid size;
-    domain = (x_lo, x_hi, y_hi) and height = (h_lo, h_hi) override the defaults.
+    domain = (x_lo, x_hi, y_hi), height, froude and width ranges and the set of
+    topography kinds override the defaults.
     Topography kinds: a single Gaussian h exp(-(x^2+y^2)/w^2); a transverse
     ridge h exp(-x^2/w^2); two inline bumps at (0, 0) and (d, 0); with
     h ~ U[0.05, 0.3], w ~ U[0.5, 2], d ~ U[4, 12].
@@ -156,10 +158,10 @@ def sweep_instances(count: int, seed: int, n_choices: Optional[Sequence[int]] = 
     for c in range(count):
         N = int(fixed_n) if fixed_n is not None else int(rng.choice(n_choices))
         M = (N - 1) // 3 + 1
-        F = float(rng.uniform(0.5, 2.0))
-        kind = int(rng.integers(0, 3))
+        F = float(rng.uniform(*froude))
+        kind = int(kinds[int(rng.integers(0, len(kinds)))])
         h = float(rng.uniform(*height))
-        w = float(rng.uniform(0.5, 2.0))
+        w = float(rng.uniform(*width))
         d = float(rng.uniform(4.0, 12.0))
         if kind == 0:
             bumps = [Bump(h, w, w)]

@@ -26,8 +26,8 @@ def _bf16_tensor(x):
     return torch.as_tensor(u.view(np.int16).copy(), device="cuda")
 
 
-def _net_and_params(bim, N, M, B, seed):
-    net = bim.LearnedNet(N, M, seed=seed, max_batch=B, C1=8, C2=16, D3=64)
+def _net_and_params(bim, N, M, B, seed, in_linear=1):
+    net = bim.LearnedNet(N, M, seed=seed, max_batch=B, C1=8, C2=16, D3=64, in_linear=in_linear)
     params = []
     for l in range(4):
         Wf, b, _, _ = net.get(l)
@@ -39,18 +39,18 @@ def _net_and_params(bim, N, M, B, seed):
     return net, params
 
 
-def _inputs(N, M, B, seed):
+def _inputs(N, M, B, seed, C=4):
     rng = np.random.default_rng(seed)
-    X = rng.normal(0, 1, (B, M, N, 2)).astype(np.float32)
+    X = rng.normal(0, 1, (B, M, N, C)).astype(np.float32)
     f = rng.normal(0, 1, B).astype(np.float32)
     T = rng.normal(0, 1, (B, 2 * M * N)).astype(np.float32)
     return X, f, T
 
 
-@pytest.mark.parametrize("N,M,B", [(21, 9, 3), (33, 15, 5)])
-def test_forward_matches_fp64_oracle(bim, N, M, B):
-    net, params = _net_and_params(bim, N, M, B, 1)
-    X, f, _ = _inputs(N, M, B, 2)
+@pytest.mark.parametrize("N,M,B,lin", [(21, 9, 3, 0), (33, 15, 5, 1)])
+def test_forward_matches_fp64_oracle(bim, N, M, B, lin):
+    net, params = _net_and_params(bim, N, M, B, 1, lin)
+    X, f, _ = _inputs(N, M, B, 2, net.in_channels)
     Y = net.forward(_bf16_tensor(X), torch.as_tensor(f, device="cuda")).cpu().numpy()
     Yref, _ = OL.forward(params, X, f)
     err = np.abs(Y - Yref).max() / np.abs(Yref).max()
@@ -58,10 +58,10 @@ def test_forward_matches_fp64_oracle(bim, N, M, B):
     assert err < 2e-3
 
 
-@pytest.mark.parametrize("N,M,B", [(21, 9, 3), (33, 15, 5)])
-def test_gradients_match_fp64_oracle(bim, N, M, B):
-    net, params = _net_and_params(bim, N, M, B, 3)
-    X, f, T = _inputs(N, M, B, 4)
+@pytest.mark.parametrize("N,M,B,lin", [(21, 9, 3, 0), (33, 15, 5, 1)])
+def test_gradients_match_fp64_oracle(bim, N, M, B, lin):
+    net, params = _net_and_params(bim, N, M, B, 3, lin)
+    X, f, T = _inputs(N, M, B, 4, net.in_channels)
     loss = net.train_step(_bf16_tensor(X), torch.as_tensor(f, device="cuda"), torch.as_tensor(T, device="cuda"),
                           lr=0.0, update=False)
     Y, cache = OL.forward(params, X, f)
@@ -81,7 +81,7 @@ def test_gradients_match_fp64_oracle(bim, N, M, B):
 def test_training_reduces_loss(bim):
     N, M, B = 21, 9, 8
     net = bim.LearnedNet(N, M, seed=5, max_batch=B, C1=8, C2=16, D3=64)
-    X, f, T = _inputs(N, M, B, 6)
+    X, f, T = _inputs(N, M, B, 6, net.in_channels)
     T = 0.1 * np.tanh(T).astype(np.float32)
     Xd, fd, Td = _bf16_tensor(X), torch.as_tensor(f, device="cuda"), torch.as_tensor(T, device="cuda")
     first = net.train_step(Xd, fd, Td, lr=1e-3)
@@ -95,16 +95,22 @@ def test_learned_start_is_linear_start_plus_correction(bim):
     p = W.tiny(0.8)
     dp = bim.DeviceProblem(p)
     net = bim.LearnedNet(p.N, p.M, seed=7, max_batch=1, C1=8, C2=16, D3=32)
-    ul = bim.linear_start(dp).cpu().numpy()
+    uld = bim.linear_start(dp)
+    ul = uld.cpu().numpy()
     u = net.infer_start(dp).cpu().numpy()
-    X0, f = net.make_input(dp)
-    Y = net.forward(X0, f).cpu().numpy()[0] * net.arch.out_scale
+    X0, f = net.make_input(dp, uld)
+    # the input holds the topography, F and the linear start's x-derivative planes
+    Xh = X0.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    Xh = Xh.view(np.float32).reshape(p.M, p.N, 4)
     nb = (p.N + 1) * p.M
+    zx = ul[:nb].reshape(p.M, p.N + 1)[:, 1:]
+    assert np.allclose(Xh[..., 0], (p.beta + 1) / 0.3, rtol=1e-2, atol=1e-3)
+    assert np.allclose(Xh[..., 2], zx / 0.2, rtol=1e-2, atol=1e-3)
+    Y = net.forward(X0, f).cpu().numpy()[0] * net.arch.out_scale
     for fld in range(2):
         blk = (u - ul)[fld * nb:(fld + 1) * nb].reshape(p.M, p.N + 1)
         assert np.allclose(blk[:, 1:], Y[fld * p.N * p.M:(fld + 1) * p.N * p.M].reshape(p.M, p.N), atol=1e-12)
-        # upstream value keeps the radiation row x1 f_x,1 + n f_1 unchanged
-        assert np.allclose(p.x1 * blk[:, 1] + p.n_decay * blk[:, 0], 0.0, atol=1e-12)
+        assert np.all(blk[:, 0] == 0.0)  # upstream values stay the linear start's
     assert np.array_equal(u[2 * nb:], ul[2 * nb:])
 
 
