@@ -179,6 +179,8 @@ typedef struct bim_jfnk_opts {
     int32_t use_graphs;  /* 1: replay each Arnoldi step's device work from a HIP graph */
     double fd_eps;       /* epsilon of the shift rule h = sqrt(eps)(1 + |u|)/|v|; <= 0: the
                             unit roundoff of the inner precision (2^-52 or 2^-23) */
+    int32_t stall_steps; /* s > 0: stop (BIM_NOT_CONVERGED) once ||F||_inf has not halved over
+                            the last s Newton steps; 0: no such stop */
 } bim_jfnk_opts;
 
 /* Outcome of a solve (host struct).  history[k] = ||F||_inf after k Newton steps. */

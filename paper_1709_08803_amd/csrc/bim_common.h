@@ -78,9 +78,10 @@ struct PairDesc {
     const void *srcS;
     const void *srcB;
     const void *tg;
+    const double *tg64;  // FP64 collocation records (y* for the per-row t)
     double *part;
     int N, M, nimg;
-    double y1, dy;
+    double y1, dx, dy;
     int tiles_per_bnd, row_groups, target_tiles, chunks, rows_per_chunk;
     long item0;  // index of this problem's first work item in the batch
 };

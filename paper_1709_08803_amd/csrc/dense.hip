@@ -2,6 +2,7 @@
 // Gauss-Jordan inversion with partial pivoting, matrix-vector products.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <vector>
 
 #include "bim_common.h"
@@ -68,6 +69,152 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
             *p = (beta == 0.0) ? alpha * acc[r][c] : fma(alpha, acc[r][c], beta * (*p));
         }
     }
+}
+
+// In-place Gauss-Jordan inversion with partial pivoting of one s x s block
+// (s <= 192) per 512-thread workgroup, with the matrix held in registers:
+// thread (ty, tx) = (tid / 64, tid % 64) owns rows ty + 8 i (i < 24) and
+// columns tx + 64 j (j < 3).  Step k: the owners of column k find the pivot
+// row p, rows k and p and column k are staged in LDS, and every thread updates
+// its elements (row k becomes the scaled pivot row with A[k][k] replaced by 1,
+// row r != k loses fac[r] times it, column k of those rows starting from 0).
+// The row interchanges are undone as column interchanges, in reverse order,
+// when the result is written.
+constexpr int kRegTy = 8, kRegRows = 24, kRegCols = 3;
+constexpr int kRegThreads = 64 * kRegTy;
+constexpr int kRegMaxS = kRegTy * kRegRows;  // = 64 kRegCols = 192
+
+__global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__restrict__ items, int s,
+                                                            int *__restrict__ info) {
+    const InvItem it = items[blockIdx.x];
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    __shared__ double rowk[kRegMaxS], rowp[kRegMaxS], fac[kRegMaxS];
+    __shared__ double redv[kRegTy];
+    __shared__ int redi[kRegTy];
+    __shared__ int ipiv[kRegMaxS], dst[kRegMaxS];
+    double a[kRegRows][kRegCols];
+#pragma unroll
+    for (int i = 0; i < kRegRows; ++i)
+#pragma unroll
+        for (int j = 0; j < kRegCols; ++j) {
+            const int r = ty + kRegTy * i, c = tx + 64 * j;
+            a[i][j] = (r < s && c < s) ? it.A[(size_t)r * it.lda + c] : 0.0;
+        }
+    for (int e = tid; e < kRegMaxS; e += kRegThreads) rowk[e] = rowp[e] = fac[e] = 0.0;
+    __syncthreads();
+    int bad = 0;
+    for (int k = 0; k < s; ++k) {
+        const int jk = k >> 6;
+        // pivot candidates of column k, one per thread row
+        if (tx == (k & 63)) {
+            double bv = -1.0;
+            int bi = k;
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i) {
+                const int r = ty + kRegTy * i;
+                const double v = fabs(jk == 0 ? a[i][0] : (jk == 1 ? a[i][1] : a[i][2]));
+                if (r >= k && r < s && v > bv) {
+                    bv = v;
+                    bi = r;
+                }
+            }
+            redv[ty] = bv;
+            redi[ty] = bi;
+        }
+        __syncthreads();
+        // every thread reduces the candidates in the same order (uniform result)
+        double pv = -1.0;
+        int p = k;
+        for (int t = 0; t < kRegTy; ++t) {
+            const double v = redv[t];
+            const int q = redi[t];
+            if (v > pv || (v == pv && q < p)) {
+                pv = v;
+                p = q;
+            }
+        }
+        if (!(pv > 0.0) || !isfinite(pv)) {
+            bad = k + 1;
+            break;
+        }
+        // stage rows k, p and column k
+        if (ty == k % kRegTy) {
+            const int ir = k / kRegTy;
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i)
+                if (i == ir) {
+#pragma unroll
+                    for (int j = 0; j < kRegCols; ++j) {
+                        const int c = tx + 64 * j;
+                        if (c < s) rowk[c] = a[i][j];
+                    }
+                }
+        }
+        if (ty == p % kRegTy) {
+            const int ir = p / kRegTy;
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i)
+                if (i == ir) {
+#pragma unroll
+                    for (int j = 0; j < kRegCols; ++j) {
+                        const int c = tx + 64 * j;
+                        if (c < s) rowp[c] = a[i][j];
+                    }
+                }
+        }
+        if (tx == (k & 63)) {
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i) {
+                const int r = ty + kRegTy * i;
+                if (r < s) fac[r] = (jk == 0 ? a[i][0] : (jk == 1 ? a[i][1] : a[i][2]));
+            }
+        }
+        if (tid == 0) ipiv[k] = p;
+        __syncthreads();
+        const double pivinv = 1.0 / rowp[k];
+        const double fk = fac[k];
+        double pc[kRegCols], rk[kRegCols];
+#pragma unroll
+        for (int j = 0; j < kRegCols; ++j) {
+            const int c = tx + 64 * j;
+            pc[j] = ((c == k) ? 1.0 : rowp[c]) * pivinv;
+            rk[j] = (c == k) ? 0.0 : rowk[c];
+        }
+#pragma unroll
+        for (int i = 0; i < kRegRows; ++i) {
+            const int r = ty + kRegTy * i;
+            const double f = (r == p) ? fk : fac[r];
+#pragma unroll
+            for (int j = 0; j < kRegCols; ++j) {
+                const int c = tx + 64 * j;
+                const double old = (r == p) ? rk[j] : ((c == k) ? 0.0 : a[i][j]);
+                a[i][j] = (r == k) ? pc[j] : fma(-f, pc[j], old);
+            }
+        }
+        __syncthreads();  // LDS rows are rewritten by the next step
+    }
+    if (tid == 0 && info) info[blockIdx.x] = bad;
+    if (bad) return;
+    // column interchanges in reverse order: output column dst[c] holds column c
+    if (tid == 0) {
+        for (int c = 0; c < s; ++c) dst[c] = c;  // src[c]: which column lands in output column c
+        for (int k = s - 1; k >= 0; --k) {
+            const int q = ipiv[k];
+            const int t = dst[k];
+            dst[k] = dst[q];
+            dst[q] = t;
+        }
+        for (int c = 0; c < s; ++c) rowk[dst[c]] = (double)c;  // inverse permutation
+        for (int c = 0; c < s; ++c) dst[c] = (int)rowk[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRegRows; ++i)
+#pragma unroll
+        for (int j = 0; j < kRegCols; ++j) {
+            const int r = ty + kRegTy * i, c = tx + 64 * j;
+            if (r < s && c < s) it.Ainv[(size_t)r * it.ldinv + dst[c]] = a[i][j];
+        }
 }
 
 // Gauss-Jordan inversion with partial pivoting of an s x s matrix per
@@ -161,6 +308,67 @@ __global__ __launch_bounds__(256) void k_gemv(const double *__restrict__ A, long
     if (lane == 0) y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
 }
 
+// Same product for 16-byte aligned rows (even lda): each wave owns GR rows and
+// reads 16 bytes per lane per row, loading every x chunk once for its GR rows;
+// two chunks per iteration keep 2 GR KiB of each wave's loads in flight.
+constexpr int GR = 4;
+__global__ __launch_bounds__(256) void k_gemv_rows(const double *__restrict__ A, long lda,
+                                                   const double *__restrict__ x, const double *c, double *y,
+                                                   int n_rows, int n_cols, double alpha, double beta) {
+    typedef double double2_t __attribute__((ext_vector_type(2)));
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int row0 = wave * GR;
+    if (row0 >= n_rows) return;
+    const double *arow[GR];
+#pragma unroll
+    for (int r = 0; r < GR; ++r) arow[r] = A + (size_t)min(row0 + r, n_rows - 1) * lda;
+    double acc[GR] = {};
+    const int pairs = n_cols >> 1;
+    int q = lane;
+    for (; q + 64 < pairs; q += 128) {
+        const double2_t x0 = *reinterpret_cast<const double2_t *>(x + 2 * q);
+        const double2_t x1 = *reinterpret_cast<const double2_t *>(x + 2 * (q + 64));
+        double2_t a0[GR], a1[GR];
+#pragma unroll
+        for (int r = 0; r < GR; ++r) {
+            a0[r] = *reinterpret_cast<const double2_t *>(arow[r] + 2 * q);
+            a1[r] = *reinterpret_cast<const double2_t *>(arow[r] + 2 * (q + 64));
+        }
+#pragma unroll
+        for (int r = 0; r < GR; ++r) {
+            acc[r] = fma(a0[r][0], x0[0], acc[r]);
+            acc[r] = fma(a0[r][1], x0[1], acc[r]);
+            acc[r] = fma(a1[r][0], x1[0], acc[r]);
+            acc[r] = fma(a1[r][1], x1[1], acc[r]);
+        }
+    }
+    for (; q < pairs; q += 64) {
+        const double2_t x0 = *reinterpret_cast<const double2_t *>(x + 2 * q);
+#pragma unroll
+        for (int r = 0; r < GR; ++r) {
+            const double2_t a0 = *reinterpret_cast<const double2_t *>(arow[r] + 2 * q);
+            acc[r] = fma(a0[0], x0[0], acc[r]);
+            acc[r] = fma(a0[1], x0[1], acc[r]);
+        }
+    }
+    if ((n_cols & 1) && lane == 0) {
+        const int j = n_cols - 1;
+#pragma unroll
+        for (int r = 0; r < GR; ++r) acc[r] = fma(arow[r][j], x[j], acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < GR; ++r)
+        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, 64);
+    if (lane < GR && row0 + lane < n_rows) {
+        double v = acc[0];
+#pragma unroll
+        for (int r = 1; r < GR; ++r) v = (lane == r) ? acc[r] : v;
+        const int row = row0 + lane;
+        y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
+    }
+}
+
 // y_l = alpha sum_{m in band} B[l][m] x_m + beta c_l for slice-block-banded B
 // (blocks s x s, half-width w): one wave per row of y.
 __global__ __launch_bounds__(256) void k_bandmv(const double *__restrict__ band, int M, int w, int s,
@@ -209,13 +417,21 @@ int gemm_enqueue(const GemmItem *items_dev, int batch, int m, int n, int k, int 
 int invert_enqueue(const InvItem *items_dev, int batch, int s_dim, double *work, int *info, hipStream_t s) {
     if (s_dim > kMaxS) return fail(BIM_EINVAL, "block too large to invert");
     if (batch <= 0) return BIM_OK;
-    hipLaunchKernelGGL(k_invert, dim3(batch), dim3(kInvThreads), 0, s, items_dev, s_dim, work, info);
+    if (s_dim <= kRegMaxS)
+        hipLaunchKernelGGL(k_invert_reg, dim3(batch), dim3(kRegThreads), 0, s, items_dev, s_dim, info);
+    else
+        hipLaunchKernelGGL(k_invert, dim3(batch), dim3(kInvThreads), 0, s, items_dev, s_dim, work, info);
     return hip_check(hipGetLastError(), "invert launch");
 }
 
 int gemv_enqueue(const double *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
                  double alpha, double beta, hipStream_t s) {
-    hipLaunchKernelGGL(k_gemv, dim3(cdiv(rows, 4)), dim3(256), 0, s, A, lda, x, c, y, rows, cols, alpha, beta);
+    const bool aligned = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)x % 16 == 0);
+    if (aligned)
+        hipLaunchKernelGGL(k_gemv_rows, dim3(cdiv(rows, 4 * GR)), dim3(256), 0, s, A, lda, x, c, y, rows, cols,
+                           alpha, beta);
+    else
+        hipLaunchKernelGGL(k_gemv, dim3(cdiv(rows, 4)), dim3(256), 0, s, A, lda, x, c, y, rows, cols, alpha, beta);
     return hip_check(hipGetLastError(), "gemv launch");
 }
 

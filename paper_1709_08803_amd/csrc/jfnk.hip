@@ -357,6 +357,8 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
         if (!std::isfinite(fn2)) return finish(fail(BIM_EDOMAIN, "non-finite residual"));
         if (finf <= o->ftol) return finish(BIM_OK);
         if (k >= o->max_newton) return finish(BIM_NOT_CONVERGED);
+        if (o->stall_steps > 0 && k >= o->stall_steps && k < maxh && finf > 0.5 * R.history[k - o->stall_steps])
+            return finish(BIM_NOT_CONVERGED);
         // inner Jacobian action around u in the requested precision
         K.u = u_io;
         K.prec = o->inner_prec;
@@ -425,12 +427,13 @@ void jfnk_default_opts(bim_jfnk_opts *o) {
     o->use_precond = 1;
     o->use_graphs = 1;
     o->fd_eps = 0.0;
+    o->stall_steps = 0;
 }
 
 static int check_opts(const bim_jfnk_opts *o) {
     if (!o) return fail(BIM_EINVAL, "options are NULL");
     if (!(o->ftol > 0) || !(o->gmres_rtol > 0) || o->restart < 1 || o->restart > 200 || o->max_restarts < 0 ||
-        o->max_newton < 0 || o->max_backtracks < 0 || !(o->fd_eps < 1.0))
+        o->max_newton < 0 || o->max_backtracks < 0 || !(o->fd_eps < 1.0) || o->stall_steps < 0)
         return fail(BIM_EINVAL, "invalid solver options");
     if (o->inner_prec != BIM_FP64 && o->inner_prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
     return BIM_OK;

@@ -439,6 +439,11 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
                 if (!std::isfinite(q.fn2)) { fail(BIM_EDOMAIN, "non-finite residual"); finish_inst(q, BIM_EDOMAIN); return; }
                 if (q.finf <= o->ftol) { finish_inst(q, BIM_OK); return; }
                 if (k >= o->max_newton) { finish_inst(q, BIM_NOT_CONVERGED); return; }
+                if (o->stall_steps > 0 && k >= o->stall_steps && k < maxh &&
+                    q.finf > 0.5 * q.R.history[k - o->stall_steps]) {
+                    finish_inst(q, BIM_NOT_CONVERGED);
+                    return;
+                }
                 q.phase = (o->inner_prec == BIM_FP64) ? PH_ARNOLDI : PH_INNER;
                 q.pending |= PD_GMRES_START;
                 q.j = 0;
@@ -604,7 +609,7 @@ extern "C" int jfnk_solve_batched(const bim_problem *probs, int count, bim_preco
     jfnk_default_opts(&o);
     if (opts) o = *opts;
     if (!(o.ftol > 0) || !(o.gmres_rtol > 0) || o.restart < 1 || o.restart > 30 || o.max_restarts < 0 ||
-        o.max_newton < 0 || o.max_backtracks < 0 || !(o.fd_eps < 1.0) ||
+        o.max_newton < 0 || o.max_backtracks < 0 || !(o.fd_eps < 1.0) || o.stall_steps < 0 ||
         (o.inner_prec != BIM_FP64 && o.inner_prec != BIM_FP32C))
         return fail(BIM_EINVAL, "invalid solver options (batched restart must be <= 30)");
     return solve_batched_impl(probs, count, Ps, us, &o, reps, (hipStream_t)stream);

@@ -96,26 +96,33 @@ __global__ void k_nodes(const double *__restrict__ u, const double *__restrict__
     const double cj = (j == 0 || j == M - 1) ? 0.5 : 1.0;
     const double w = dx * dy * ci * cj;
     // linear mode: the boundaries are the planes z = 0 and z = -1 (Section 4.2);
-    // the layer densities are unchanged
+    // the layer densities are unchanged.
+    // FP32 records are in grid units (lengths / dx, node x = its column index):
+    // the double-layer and single-layer products are unchanged by the scaling
+    // (w / dx^2 times K1 dx^2; w sigma / dx times K2 dx), the S2 sum carries a
+    // factor 1 / dx that the all-pairs kernel removes, and s = x - x* is exact.
+    const bool grid = sizeof(T) == 4;
+    const double g = grid ? 1.0 / dx : 1.0;
+    const double xr = grid ? (double)i : x;
     SrcRec<T> a;
-    a.x = (T)x;
-    a.z = linear ? (T)0 : (T)zeta[n];
+    a.x = (T)xr;
+    a.z = linear ? (T)0 : (T)(zeta[n] * g);
     a.zx = linear ? (T)0 : (T)zx;
     a.zy = linear ? (T)0 : (T)zy;
-    a.wD = (T)(w * (phi[n] - x));
-    a.ws = (T)(w * zx);
-    a.w = (T)w;
+    a.wD = (T)(w * g * g * (phi[n] - x));
+    a.ws = (T)(w * g * zx);
+    a.w = (T)(w * g * g);
     a.pad = (T)0;
     srcS[n] = a;
     // bottom: outward normal points down, so both layers enter with -w
     SrcRec<T> b;
-    b.x = (T)x;
-    b.z = linear ? (T)-1 : (T)beta[n];
+    b.x = (T)xr;
+    b.z = (T)((linear ? -1.0 : beta[n]) * g);
     b.zx = linear ? (T)0 : (T)beta_x[n];
     b.zy = linear ? (T)0 : (T)beta_y[n];
-    b.wD = (T)(-w * (psi[n] - x));
-    b.ws = (T)(-w * beta_x[n]);
-    b.w = (T)(-w);
+    b.wD = (T)(-w * g * g * (psi[n] - x));
+    b.ws = (T)(-w * g * beta_x[n]);
+    b.w = (T)(-w * g * g);
     b.pad = (T)0;
     srcB[n] = b;
     (void)nb;
@@ -123,7 +130,8 @@ __global__ void k_nodes(const double *__restrict__ u, const double *__restrict__
 
 // ------------------------------------------------------------------ collocation-point records
 // tg layout: 8 arrays of 2 ntg entries: x*, y*, d, D*, A, B, C, sigma*; target
-// t = st ntg + l (N-1) + k, st = 0 on the free surface, 1 on the bottom.
+// t = st ntg + l (N-1) + k, st = 0 on the free surface, 1 on the bottom.  The
+// FP32 copy tg32 holds the first 7 in grid units (x* = k + 1/2, y*, d / dx).
 __global__ void k_targets(const double *__restrict__ nodes, const double *__restrict__ ydiv,
                           const double *__restrict__ u, const double *__restrict__ beta,
                           const double *__restrict__ beta_x, const double *__restrict__ beta_y,
@@ -161,7 +169,9 @@ __global__ void k_targets(const double *__restrict__ nodes, const double *__rest
     const size_t T2 = (size_t)2 * ntg;
     const double v[8] = {xs, ys, d, D, 1.0 + ax * ax, 2.0 * ax * ay, 1.0 + ay * ay, sig};
     for (int q = 0; q < 8; ++q) tg[q * T2 + t] = v[q];
-    for (int q = 0; q < 7; ++q) tg32[q * T2 + t] = (float)v[q];
+    // FP32 copies in the grid units of the FP32 node records (x* = k + 1/2)
+    const double g[7] = {0.0, 1.0 / dx, 1.0 / dx, 1.0, 1.0, 1.0, 1.0};
+    for (int q = 0; q < 7; ++q) tg32[q * T2 + t] = (float)(q == 0 ? k + 0.5 : v[q] * g[q]);
 }
 
 // ------------------------------------------------------------------ A2: all-pairs sums (hot loop)
@@ -243,7 +253,8 @@ __device__ __forceinline__ void walk_row(const SrcRec<T> *__restrict__ src, int 
 // compensated summation; the chunk result is written in FP64.
 template <typename T, int NI>
 struct TargetState {
-    T ys, d, Dst, A, B, C;                       // collocation data
+    double ys;                                   // y* (FP64, physical units)
+    T d, Dst, A, B, C;                           // collocation data
     T t[NI], ti[NI], t2[NI], Bt[NI], Ct2[NI];    // per source row and image
     T acc, acc2;                                 // per source row sums
     T sum, comp, s2sum, s2comp;                  // across rows
@@ -265,11 +276,14 @@ __device__ __forceinline__ void row_end(TargetState<T, NI> &g) {
 }
 
 // NI = 2: half domain (both images per source row); NI = 1: full domain.
+// FP32 (grid units): t = (y_j - y*) / dx is formed in FP64 for every source row
+// and the S2 sum is multiplied by dx on output; FP64 works in physical units.
 template <typename T, bool COMP, int TPL, int UNROLL, int NI>
 __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
-                                          const T *__restrict__ tg, int N, int M, double y1, double dy,
-                                          int tiles_per_bnd, int row_groups, int rows_per_chunk,
-                                          double *__restrict__ part, int tt, int c, int lane) {
+                                          const T *__restrict__ tg, const double *__restrict__ tg64, int N, int M,
+                                          double y1, double dx, double dy, int tiles_per_bnd, int row_groups,
+                                          int rows_per_chunk, double *__restrict__ part, int tt, int c, int lane) {
+    const double gi = (sizeof(T) == 4) ? 1.0 / dx : 1.0;
     const int ntg = (N - 1) * M;
     const size_t T2 = (size_t)2 * ntg;
     const int st = tt / tiles_per_bnd;
@@ -286,7 +300,7 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
         const int l = min(lg * TPL + q, M - 1);
         const int tid = st * ntg + l * (N - 1) + k;
         xs = tg[0 * T2 + tid];
-        ts[q].ys = tg[1 * T2 + tid];
+        ts[q].ys = tg64[1 * T2 + tid];
         ts[q].d = tg[2 * T2 + tid];
         ts[q].Dst = tg[3 * T2 + tid];
         ts[q].A = tg[4 * T2 + tid];
@@ -299,13 +313,13 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
     for (int r = r0; r < r1; ++r) {
         const int ss = r & 1;  // interleave boundaries so every chunk mixes both
         const int j = r >> 1;
-        const T yj = T(y1 + j * dy);
+        const double yj = y1 + j * dy;
 #pragma unroll
         for (int q = 0; q < TPL; ++q) {
 #pragma unroll
             for (int i = 0; i < NI; ++i) {
                 // image i = 1 is (x, -y_j): a_y changes sign, which ti carries
-                const T t = (i == 0) ? yj - ts[q].ys : -yj - ts[q].ys;
+                const T t = (T)((((i == 0) ? yj : -yj) - ts[q].ys) * gi);
                 ts[q].t[i] = t;
                 ts[q].ti[i] = (i == 0) ? t : -t;
                 ts[q].t2[i] = t * t;
@@ -366,37 +380,38 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
             const int tid = st * ntg + l * (N - 1) + k;
             double *o = part + ((size_t)c * T2 + tid) * 2;
             o[0] = (double)ts[q].sum + (double)ts[q].comp;
-            o[1] = (double)ts[q].s2sum + (double)ts[q].s2comp;
+            o[1] = ((double)ts[q].s2sum + (double)ts[q].s2comp) * ((sizeof(T) == 4) ? dx : 1.0);
         }
     }
 }
 
 template <typename T, bool COMP, int TPL, int UNROLL>
 __device__ __forceinline__ void pair_item_any(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
-                                              const T *__restrict__ tg, int N, int M, int nimg, double y1,
-                                              double dy, int tiles_per_bnd, int row_groups, int rows_per_chunk,
-                                              double *__restrict__ part, int tt, int c, int lane) {
+                                              const T *__restrict__ tg, const double *__restrict__ tg64, int N,
+                                              int M, int nimg, double y1, double dx, double dy, int tiles_per_bnd,
+                                              int row_groups, int rows_per_chunk, double *__restrict__ part, int tt,
+                                              int c, int lane) {
     if (nimg == 2)
-        pair_item<T, COMP, TPL, UNROLL, 2>(srcS, srcB, tg, N, M, y1, dy, tiles_per_bnd, row_groups, rows_per_chunk,
-                                           part, tt, c, lane);
+        pair_item<T, COMP, TPL, UNROLL, 2>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
+                                           rows_per_chunk, part, tt, c, lane);
     else
-        pair_item<T, COMP, TPL, UNROLL, 1>(srcS, srcB, tg, N, M, y1, dy, tiles_per_bnd, row_groups, rows_per_chunk,
-                                           part, tt, c, lane);
+        pair_item<T, COMP, TPL, UNROLL, 1>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
+                                           rows_per_chunk, part, tt, c, lane);
 }
 
 // Single problem: one wave per (target tile, source chunk).
 template <typename T, bool COMP, int TPL, int UNROLL>
 __global__ __launch_bounds__(256) void k_allpairs(
     const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB, const T *__restrict__ tg,
-    int N, int M, int nimg, double y1, double dy, int tiles_per_bnd, int row_groups, int target_tiles,
-    int chunks, int rows_per_chunk, double *__restrict__ part) {
+    const double *__restrict__ tg64, int N, int M, int nimg, double y1, double dx, double dy, int tiles_per_bnd,
+    int row_groups, int target_tiles, int chunks, int rows_per_chunk, double *__restrict__ part) {
     const int lane = threadIdx.x & 63;
     // the wave index is uniform: keep it (and everything derived) in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = blockIdx.x * 4 + wave;
     const int tt = g % target_tiles, c = g / target_tiles;
     if (c >= chunks) return;
-    pair_item_any<T, COMP, TPL, UNROLL>(srcS, srcB, tg, N, M, nimg, y1, dy, tiles_per_bnd, row_groups,
+    pair_item_any<T, COMP, TPL, UNROLL>(srcS, srcB, tg, tg64, N, M, nimg, y1, dx, dy, tiles_per_bnd, row_groups,
                                         rows_per_chunk, part, tt, c, lane);
 }
 
@@ -416,8 +431,8 @@ __global__ __launch_bounds__(256) void k_allpairs_batched(const PairDesc *__rest
         const int local = (int)(item - D.item0);
         const int tt = local % D.target_tiles, c = local / D.target_tiles;
         pair_item_any<T, COMP, TPL, UNROLL>((const SrcRec<T> *)D.srcS, (const SrcRec<T> *)D.srcB,
-                                            (const T *)D.tg, D.N, D.M, D.nimg, D.y1, D.dy, D.tiles_per_bnd,
-                                            D.row_groups, D.rows_per_chunk, D.part, tt, c, lane);
+                                            (const T *)D.tg, D.tg64, D.N, D.M, D.nimg, D.y1, D.dx, D.dy,
+                                            D.tiles_per_bnd, D.row_groups, D.rows_per_chunk, D.part, tt, c, lane);
     }
 }
 
@@ -568,8 +583,8 @@ int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
     if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[0], s));
 #define BIM_LAUNCH_PAIRS(T, COMP, TPL, UNR, TG)                                                         \
     hipLaunchKernelGGL((k_allpairs<T, COMP, TPL, UNR>), dim3(pl.blocks), dim3(256), 0, s,               \
-                       (const SrcRec<T> *)w.srcS, (const SrcRec<T> *)w.srcB, TG, N, M, d.nimg, p->y1,   \
-                       p->dy, pl.tiles_per_bnd, pl.row_groups, pl.target_tiles, pl.chunks,              \
+                       (const SrcRec<T> *)w.srcS, (const SrcRec<T> *)w.srcB, TG, w.tg, N, M, d.nimg,    \
+                       p->y1, p->dx, p->dy, pl.tiles_per_bnd, pl.row_groups, pl.target_tiles, pl.chunks, \
                        pl.rows_per_chunk, w.part)
     const int vsel = (pl.tpl == 2 ? 3 : 0) + (pl.unroll == 2 ? 0 : pl.unroll == 4 ? 1 : 2);
     if (prec == BIM_FP64) {
@@ -630,6 +645,8 @@ int residual_batched_enqueue(const bim_problem *probs, int count, const double *
         D.srcS = w.srcS;
         D.srcB = w.srcB;
         D.tg = (prec == BIM_FP64) ? (const void *)w.tg : (const void *)w.tg32;
+        D.tg64 = w.tg;
+        D.dx = p->dx;
         D.part = w.part;
         D.N = N;
         D.M = M;

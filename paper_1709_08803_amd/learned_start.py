@@ -1,18 +1,21 @@
 """Learned initial guess: data generation with the solver, training, evaluation.
 
-The network (libbim's lg_* kernels) maps (F, bottom beta on the mesh) to a
-correction of the discrete linear start in (zeta_x, phi_x).  Training data are
-converged solutions of the method itself (FP64 JFNK), produced here by the
-batched solver over seeded sweeps of topographies and Froude numbers; the
-evaluation compares Newton solves from the learned start with solves from the
-linear start on held-out problems.  Every numerical step runs in the library;
-this module only orchestrates (batches, epochs, bookkeeping).
+The network (libbim's lg_* kernels) maps (F, bottom beta on the mesh) and,
+optionally, the discrete linear start's (zeta_x, phi_x) to a correction of the
+linear start's (zeta_x, phi_x).  Training data are converged solutions of the
+method itself, produced here by the batched JFNK solver over seeded sweeps of
+topographies and Froude numbers.  The evaluation runs Newton from the learned
+start and from the linear start on held-out problems and compares iterations
+and time; if Newton fails from the learned start the solve is repeated from
+the linear start (the fallback), and that cost is charged to the learned side.
+Every numerical step runs in the library; this module only orchestrates
+(batches, epochs, bookkeeping).
 """
 from __future__ import annotations
 
 import dataclasses
 import time
-from typing import List, Optional
+from typing import List
 
 import numpy as np
 import torch
@@ -24,22 +27,24 @@ from . import workloads as W
 @dataclasses.dataclass
 class Sample:
     problem: W.Problem
-    X0: torch.Tensor       # bf16 bits [M][N][2]
+    X0: torch.Tensor       # bf16 bits [M][N][C0]
     ffeat: torch.Tensor    # [1]
     target: torch.Tensor   # FP32 [2 M N]: (u*_x - u_lin_x) / out_scale for zeta and phi
-    u_star: np.ndarray
-    u_lin: np.ndarray
+    newton_from_linear: int
 
 
-def _xblocks(p: W.Problem, u: np.ndarray) -> np.ndarray:
+def xplanes(p: W.Problem, u: np.ndarray) -> np.ndarray:
     """(zeta_x, phi_x) planes [2][M][N] of u."""
     nb = (p.N + 1) * p.M
     return np.stack([u[f * nb:(f + 1) * nb].reshape(p.M, p.N + 1)[:, 1:] for f in range(2)])
 
 
 def generate(problems: List[W.Problem], net: B.LearnedNet, batch: int = 32, ftol: float = 1e-10,
-             inner_prec: str = "fp64", log=print) -> List[Sample]:
-    """Solve every problem from its linear start (batched); keep the converged ones."""
+             inner_prec: str = "fp64", max_newton: int = 10, log=print) -> List[Sample]:
+    """Solve every problem from its linear start (batched); keep the converged ones.
+
+    Newton is capped at max_newton steps: the batch advances in lockstep, so a
+    problem that does not converge would otherwise hold the whole batch."""
     out: List[Sample] = []
     scale = net.arch.out_scale
     t0 = time.perf_counter()
@@ -48,15 +53,16 @@ def generate(problems: List[W.Problem], net: B.LearnedNet, batch: int = 32, ftol
         dps = [B.DeviceProblem(p) for p in probs]
         ulin = [B.linear_start(dp, rtol=1e-10) for dp in dps]
         us = [u.clone() for u in ulin]
-        rc, reps = B.solve_batched(dps, us, ftol=ftol, inner_prec=inner_prec, check=False)
+        _, reps = B.solve_batched(dps, us, ftol=ftol, inner_prec=inner_prec, check=False, max_newton=max_newton,
+                                  stall_steps=4)
         for p, dp, ul, u, rep in zip(probs, dps, ulin, us, reps):
             if rep["status"] != 0:
                 continue
-            uh, lh = u.cpu().numpy(), ul.cpu().numpy()
             X0, f = net.make_input(dp, ul)
-            tgt = ((_xblocks(p, uh) - _xblocks(p, lh)) / scale).astype(np.float32).reshape(-1)
-            out.append(Sample(p, X0, f, torch.as_tensor(tgt, device=X0.device), uh, lh))
-        log(f"  generated {len(out)}/{b0 + len(probs)} converged ({time.perf_counter() - t0:.1f} s)")
+            tgt = ((xplanes(p, u.cpu().numpy()) - xplanes(p, ul.cpu().numpy())) / scale).astype(np.float32)
+            out.append(Sample(p, X0, f, torch.as_tensor(tgt.reshape(-1), device=X0.device), rep["newton_iters"]))
+        if log:
+            log(f"  generated {len(out)}/{b0 + len(probs)} converged ({time.perf_counter() - t0:.1f} s)")
     return out
 
 
@@ -69,6 +75,7 @@ def stack(samples: List[Sample]):
 
 def train(net: B.LearnedNet, samples: List[Sample], epochs: int = 100, batch: int = 32, lr: float = 1e-3,
           seed: int = 0, log=print) -> List[float]:
+    """Adam on the mean-squared error of the correction, shuffled mini-batches."""
     X, F, T = stack(samples)
     n = len(samples)
     rng = np.random.default_rng(seed)
@@ -78,47 +85,108 @@ def train(net: B.LearnedNet, samples: List[Sample], epochs: int = 100, batch: in
         tot = 0.0
         for b0 in range(0, n, batch):
             idx = torch.as_tensor(perm[b0:b0 + batch], device=X.device)
-            if idx.numel() == 0:
-                continue
             loss = net.train_step(X[idx].contiguous(), F[idx].contiguous(), T[idx].contiguous(), lr)
             tot += loss * idx.numel()
         hist.append(tot / n)
-        if ep % max(1, epochs // 10) == 0 or ep == epochs - 1:
+        if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
             log(f"  epoch {ep}: loss {hist[-1]:.4e}")
     return hist
 
 
-def evaluate(net: B.LearnedNet, problems: List[W.Problem], ftol: float = 1e-10, inner_prec: str = "fp64") -> dict:
-    """Newton solves from the linear start and from the learned start on each problem."""
+def _timed_solve(dp, u, P, **opts):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = B.solve(dp, u, P, check=False, **opts)
+    torch.cuda.synchronize()
+    return rep, (time.perf_counter() - t0) * 1e3
+
+
+def evaluate(net: B.LearnedNet, problems: List[W.Problem], ftol: float = 1e-10, inner_prec: str = "fp64",
+             learned_max_newton: int = 8) -> dict:
+    """Newton from the linear start and from the learned start on each problem.
+
+    Times include building the start (the linear start's GMRES; for the learned
+    start lg_infer_start, which computes the linear start itself and then runs
+    the network) and, if Newton from the learned start has not converged within
+    learned_max_newton steps, the fallback solve from that linear start.  The
+    preconditioner is shared and not timed (it depends only on the mesh and F).
+    """
     rows = []
     for p in problems:
         dp = B.DeviceProblem(p)
         P = B.Preconditioner(dp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ul = B.linear_start(dp, P, rtol=1e-10)
-        t_lin = time.perf_counter() - t0
+        ul = B.linear_start(dp, P)
+        torch.cuda.synchronize()
+        t_lin = (time.perf_counter() - t0) * 1e3
         t0 = time.perf_counter()
         ulearn = net.infer_start(dp, P)
         torch.cuda.synchronize()
-        t_learn = time.perf_counter() - t0
-        res = {}
-        for name, u0, tstart in (("linear", ul, t_lin), ("learned", ulearn, t_learn)):
-            u = u0.clone()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rep = B.solve(dp, u, P, ftol=ftol, inner_prec=inner_prec, check=False)
-            torch.cuda.synchronize()
-            res[name] = dict(status=rep["status"], newton=rep["newton_iters"], gmres=rep["gmres_iters"],
-                             f0=rep["fnorm0_inf"], ms=(time.perf_counter() - t0 + tstart) * 1e3, u=u.cpu().numpy())
-        dz = float(np.abs(_xblocks(p, res["linear"]["u"]) - _xblocks(p, res["learned"]["u"])).max())
-        rows.append(dict(name=p.name, F=p.froude, dz_between_starts=dz,
-                         **{f"{k}_{m}": res[k][m] for k in res for m in ("status", "newton", "gmres", "f0", "ms")}))
+        t_learn = (time.perf_counter() - t0) * 1e3
+        u1 = ul.clone()
+        r1, ms1 = _timed_solve(dp, u1, P, ftol=ftol, inner_prec=inner_prec)
+        u2 = ulearn.clone()
+        r2, ms2 = _timed_solve(dp, u2, P, ftol=ftol, inner_prec=inner_prec, max_newton=learned_max_newton)
+        newton2, fallback = r2["newton_iters"], False
+        if r2["status"] != 0:
+            fallback = True
+            u2 = ul.clone()
+            r2b, ms2b = _timed_solve(dp, u2, P, ftol=ftol, inner_prec=inner_prec)
+            ms2 += ms2b
+            newton2 += r2b["newton_iters"]
+            r2 = dict(r2b, newton_iters=newton2, gmres_iters=r2["gmres_iters"] + r2b["gmres_iters"])
+        dz = float(np.abs(xplanes(p, u1.cpu().numpy()) - xplanes(p, u2.cpu().numpy())).max())
+        rows.append(dict(name=p.name, F=p.froude, linear_status=r1["status"], learned_status=r2["status"],
+                         linear_newton=r1["newton_iters"], learned_newton=newton2,
+                         linear_gmres=r1["gmres_iters"], learned_gmres=r2["gmres_iters"],
+                         linear_ms=t_lin + ms1, learned_ms=t_learn + ms2, fallback=fallback,
+                         linear_f0=r1["fnorm0_inf"], learned_f0=r2["fnorm0_inf"], dx_between_solutions=dz))
         P.close()
     ok = [r for r in rows if r["linear_status"] == 0 and r["learned_status"] == 0]
-    summ = dict(n=len(rows), both_converged=len(ok))
+    summ = dict(n=len(rows), both_converged=len(ok), fallbacks=sum(r["fallback"] for r in rows))
     if ok:
         for m in ("newton", "gmres", "ms", "f0"):
             summ[f"linear_{m}_mean"] = float(np.mean([r[f"linear_{m}"] for r in ok]))
             summ[f"learned_{m}_mean"] = float(np.mean([r[f"learned_{m}"] for r in ok]))
+        summ["max_dx_between_solutions"] = float(max(r["dx_between_solutions"] for r in ok))
     return dict(summary=summ, rows=rows)
+
+
+def experiment(n_mesh: int = 121, n_train: int = 4096, n_test: int = 256, epochs: int = 100, batch: int = 64,
+               train_seed: int = 1, test_seed: int = 2, in_linear: int = 1, log=print, **sweep) -> dict:
+    """Generate, train and evaluate on seeded sweeps at one mesh (N = n_mesh, M = (N-1)/3 + 1)."""
+    M = (n_mesh - 1) // 3 + 1
+    train_p = W.sweep_instances(n_train, seed=train_seed, fixed_n=n_mesh, **sweep)
+    test_p = W.sweep_instances(n_test, seed=test_seed, fixed_n=n_mesh, **sweep)
+    net = B.LearnedNet(n_mesh, M, seed=0, max_batch=batch, in_linear=in_linear)
+    t0 = time.perf_counter()
+    data = generate(train_p, net, batch=batch, log=log)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = train(net, data, epochs=epochs, batch=min(batch, 32), log=log)
+    t_train = time.perf_counter() - t0
+    ev = evaluate(net, test_p)
+    net.close()
+    return dict(mesh=f"{n_mesh}x{M}", n_train=n_train, converged_training=len(data), n_test=n_test,
+                epochs=epochs, generate_s=t_gen, train_s=t_train, loss_first=hist[0], loss_last=hist[-1],
+                summary=ev["summary"])
+
+
+def main():
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="learned-start experiment on a seeded sweep")
+    ap.add_argument("--mesh", type=int, default=121, help="N (M = (N-1)/3 + 1)")
+    ap.add_argument("--train", type=int, default=4096)
+    ap.add_argument("--test", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--in-linear", type=int, default=1)
+    args = ap.parse_args()
+    res = experiment(args.mesh, args.train, args.test, args.epochs, in_linear=args.in_linear,
+                     log=lambda m: print(m, flush=True))
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

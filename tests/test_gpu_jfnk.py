@@ -126,3 +126,22 @@ def test_full_size_solution_matches_stored_oracle_solution(bim, inner, tol):
     print("max |dzeta|", dz, "max |dphi|", dphi)
     assert dz <= tol and dphi <= 10 * tol
     P.close()
+
+
+def test_stall_stop_ends_a_stagnating_solve(bim):
+    # F = 0.7 on the 181 x 61 working domain stagnates near ||F|| = 3.7e-3 (in the
+    # oracle as here); with stall_steps = 3 the solve stops as soon as ||F||_inf
+    # has not halved over three Newton steps, instead of running to max_newton
+    p = W.working(0.7)
+    dp = bim.DeviceProblem(p)
+    P = bim.Preconditioner(dp)
+    u = bim.linear_start(dp, P)
+    rep = bim.solve(dp, u, P, check=False, stall_steps=3, max_newton=30)
+    h = rep["history"][: rep["newton_iters"] + 1]
+    print(rep["status"], rep["newton_iters"], h)
+    assert rep["status"] == 1  # BIM_NOT_CONVERGED
+    k = rep["newton_iters"]
+    assert 3 <= k < 30
+    assert h[k] > 0.5 * h[k - 3]
+    assert all(h[i] <= 0.5 * h[i - 3] for i in range(3, k))  # it did not stop earlier
+    P.close()

@@ -61,6 +61,19 @@ def test_residual_fp32c_matches_oracle(bim, name, mk, seed):
     assert err.max() <= 1e-5
 
 
+def test_residual_fp32c_full_size_against_fp64(bim):
+    # 181 x 61 (|x| up to 30): the FP32C sums against the FP64 ones, per row
+    # relative to the row's sum of term magnitudes (computed by the oracle)
+    p = W.working(1.4)
+    u = W.perturbed_state(p, 11)
+    F64 = _gpu_F(bim, p, u, "fp64")
+    F32 = _gpu_F(bim, p, u, "fp32c")
+    scale = R.term_magnitude_rows(p, u)
+    err = np.abs(F32 - F64) / scale
+    print("181x61 fp32c max rel err", err.max(), "median", np.median(err))
+    assert err.max() <= 1e-5
+
+
 @pytest.mark.parametrize("F_num", [0.7, 1.4])
 def test_residual_full_size_sampled_rows(bim, F_num):
     # 181 x 61 at the benchmark's launch configuration; the oracle computes a
