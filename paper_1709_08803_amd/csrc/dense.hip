@@ -14,9 +14,14 @@ namespace {
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
-// C = alpha A B + beta C (row-major).  64 x 64 output tile per 256-thread
-// workgroup, 4 x 4 outputs per thread, K staged through LDS in steps of 16.
+// C = alpha A B + beta C (row-major, FP64) on the matrix cores.  64 x 64 output
+// tile per 256-thread workgroup; each wave owns 32 x 32 = 2 x 2 tiles of
+// v_mfma_f64_16x16x4f64 and K advances through LDS in steps of 16.  Operand
+// layout of the 16x16x4 FP64 MFMA: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; the accumulator's element v of lane l is
+// D[l / 16 + 4 v][l % 16] (lane layout checked on gfx950).
 constexpr int TM = 64, TN = 64, TK = 16;
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items, int m, int n, int k,
                                               int lda, int ldb, int ldc, double alpha, double beta) {
@@ -24,51 +29,56 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
     const double *__restrict__ A = it.A;
     const double *__restrict__ B = it.B;
     double *__restrict__ C = it.C;
-    __shared__ double As[TK][TM + 1];
+    __shared__ double As[TM][TK + 1];
     __shared__ double Bs[TK][TN + 1];
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
-    double acc[4][4] = {};
+    const int li = lane & 15, lk = lane >> 4;
+    double4_t acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) acc[t][u] = double4_t{0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < k; k0 += TK) {
-        // A tile: 64 rows x 16 cols; B tile: 16 rows x 64 cols (4 loads each per thread)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = tid + q * 256;
             const int ar = e >> 4, ac = e & 15;
             const int gr = row0 + ar, gc = k0 + ac;
-            As[ac][ar] = (gr < m && gc < k) ? A[(size_t)gr * lda + gc] : 0.0;
+            As[ar][ac] = (gr < m && gc < k) ? A[(size_t)gr * lda + gc] : 0.0;
             const int br = e >> 6, bc = e & 63;
             const int hr = k0 + br, hc = col0 + bc;
             Bs[br][bc] = (hr < k && hc < n) ? B[(size_t)hr * ldb + hc] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < TK; ++kk) {
-            double a[4], b[4];
+        for (int kk = 0; kk < TK; kk += 4) {
+            double a[2], b[2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+            for (int t = 0; t < 2; ++t) {
+                a[t] = As[wm + 16 * t + li][kk + lk];
+                b[t] = Bs[kk + lk][wn + 16 * t + li];
+            }
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+            for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+                for (int u = 0; u < 2; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int gr = row0 + ty * 4 + r;
-        if (gr >= m) continue;
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int gc = col0 + tx * 4 + c;
-            if (gc >= n) continue;
-            double *p = C + (size_t)gr * ldc + gc;
-            *p = (beta == 0.0) ? alpha * acc[r][c] : fma(alpha, acc[r][c], beta * (*p));
-        }
-    }
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gr = row0 + wm + 16 * t + lk + 4 * v, gc = col0 + wn + 16 * u + li;
+                if (gr < m && gc < n) {
+                    double *p = C + (size_t)gr * ldc + gc;
+                    *p = (beta == 0.0) ? alpha * acc[t][u][v] : fma(alpha, acc[t][u][v], beta * (*p));
+                }
+            }
 }
 
 // In-place Gauss-Jordan inversion with partial pivoting of one s x s block
@@ -389,6 +399,49 @@ __global__ __launch_bounds__(256) void k_bandmv(const double *__restrict__ band,
     if (lane == 0) y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
 }
 
+// Same banded product for even s and 16-byte aligned operands: each wave owns
+// GR consecutive rows of one slice and reads 16 bytes per lane per row, loading
+// every x segment once for its rows.
+__global__ __launch_bounds__(256) void k_bandmv_rows(const double *__restrict__ band, int M, int w, int s,
+                                                     const double *__restrict__ x, const double *c, double *y,
+                                                     double alpha, double beta) {
+    typedef double double2_t __attribute__((ext_vector_type(2)));
+    const int gps = (s + GR - 1) / GR;  // row groups per slice
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= M * gps) return;
+    const int l = wave / gps, r0 = (wave - l * gps) * GR;
+    const int m0 = max(0, l - w), m1 = min(M - 1, l + w);
+    const int pairs = s >> 1;
+    double acc[GR] = {};
+    for (int m = m0; m <= m1; ++m) {
+        const double *blk = band + ((size_t)l * (2 * w + 1) + (m - l + w)) * s * s;
+        const double *xm = x + (size_t)m * s;
+        for (int q = lane; q < pairs; q += 64) {
+            const double2_t xv = *reinterpret_cast<const double2_t *>(xm + 2 * q);
+            double2_t a[GR];
+#pragma unroll
+            for (int r = 0; r < GR; ++r)
+                a[r] = *reinterpret_cast<const double2_t *>(blk + (size_t)min(r0 + r, s - 1) * s + 2 * q);
+#pragma unroll
+            for (int r = 0; r < GR; ++r) {
+                acc[r] = fma(a[r][0], xv[0], acc[r]);
+                acc[r] = fma(a[r][1], xv[1], acc[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < GR; ++r)
+        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, 64);
+    if (lane < GR && r0 + lane < s) {
+        double v = acc[0];
+#pragma unroll
+        for (int r = 1; r < GR; ++r) v = (lane == r) ? acc[r] : v;
+        const int row = l * s + r0 + lane;
+        y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
+    }
+}
+
 __global__ void k_copy2d(const double *__restrict__ src, long lds, double *__restrict__ dst, long ldd, int rows,
                          int cols) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -437,8 +490,13 @@ int gemv_enqueue(const double *A, long lda, const double *x, const double *c, do
 
 int bandmv_enqueue(const double *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
                    double alpha, double beta, hipStream_t s) {
-    hipLaunchKernelGGL(k_bandmv, dim3(cdiv((long)M * s_dim, 4)), dim3(256), 0, s, band, M, w, s_dim, x, c, y,
-                       alpha, beta);
+    const bool aligned = (s_dim % 2 == 0) && ((uintptr_t)band % 16 == 0) && ((uintptr_t)x % 16 == 0);
+    if (aligned)
+        hipLaunchKernelGGL(k_bandmv_rows, dim3(cdiv((long)M * ((s_dim + GR - 1) / GR), 4)), dim3(256), 0, s, band, M,
+                           w, s_dim, x, c, y, alpha, beta);
+    else
+        hipLaunchKernelGGL(k_bandmv, dim3(cdiv((long)M * s_dim, 4)), dim3(256), 0, s, band, M, w, s_dim, x, c, y,
+                           alpha, beta);
     return hip_check(hipGetLastError(), "bandmv launch");
 }
 

@@ -154,12 +154,13 @@ def evaluate(net: B.LearnedNet, problems: List[W.Problem], ftol: float = 1e-10, 
 
 
 def experiment(n_mesh: int = 121, n_train: int = 4096, n_test: int = 256, epochs: int = 100, batch: int = 64,
-               train_seed: int = 1, test_seed: int = 2, in_linear: int = 1, log=print, **sweep) -> dict:
+               train_seed: int = 1, test_seed: int = 2, in_linear: int = 1, hidden: int = 256, log=print,
+               **sweep) -> dict:
     """Generate, train and evaluate on seeded sweeps at one mesh (N = n_mesh, M = (N-1)/3 + 1)."""
     M = (n_mesh - 1) // 3 + 1
     train_p = W.sweep_instances(n_train, seed=train_seed, fixed_n=n_mesh, **sweep)
     test_p = W.sweep_instances(n_test, seed=test_seed, fixed_n=n_mesh, **sweep)
-    net = B.LearnedNet(n_mesh, M, seed=0, max_batch=batch, in_linear=in_linear)
+    net = B.LearnedNet(n_mesh, M, seed=0, max_batch=batch, in_linear=in_linear, D3=hidden)
     t0 = time.perf_counter()
     data = generate(train_p, net, batch=batch, log=log)
     t_gen = time.perf_counter() - t0
@@ -173,6 +174,12 @@ def experiment(n_mesh: int = 121, n_train: int = 4096, n_test: int = 256, epochs
                 summary=ev["summary"])
 
 
+# Problem families for the experiment: "sweep" is the full parameter sweep of
+# workloads.sweep_instances; "bumps" keeps Gaussian and two-bump bottoms with
+# F in [0.8, 1.8], heights 0.1-0.3 and widths 0.7-1.5.
+FAMILIES = {"sweep": {}, "bumps": dict(kinds=(0, 2), froude=(0.8, 1.8), height=(0.1, 0.3), width=(0.7, 1.5))}
+
+
 def main():
     import argparse
     import json
@@ -182,9 +189,12 @@ def main():
     ap.add_argument("--test", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=100)
     ap.add_argument("--in-linear", type=int, default=1)
+    ap.add_argument("--family", default="sweep", choices=sorted(FAMILIES))
+    ap.add_argument("--hidden", type=int, default=256, help="width of the hidden fully connected layer")
     args = ap.parse_args()
-    res = experiment(args.mesh, args.train, args.test, args.epochs, in_linear=args.in_linear,
-                     log=lambda m: print(m, flush=True))
+    res = experiment(args.mesh, args.train, args.test, args.epochs, in_linear=args.in_linear, hidden=args.hidden,
+                     log=lambda m: print(m, flush=True), **FAMILIES[args.family])
+    res["family"] = args.family
     print(json.dumps(res))
 
 
