@@ -163,8 +163,11 @@ int precond_band(const bim_precond *P);
  *                   products (BIM_FP64 or BIM_FP32C); the Newton residual,
  *                   the line search and the update are always FP64;
  *   band_halfwidth: band of the preconditioner built when none is passed;
- *   use_precond:    0 runs GMRES without preconditioning.
- * jfnk_default_opts fills 1e-10, 1e-8, 30, 10, 30, 20, BIM_FP64, -1, 1, 1.
+ *   use_precond:    0 runs GMRES without preconditioning;
+ *   use_graphs, fd_eps, stall_steps: see the fields.
+ * jfnk_default_opts fills 1e-10, 1e-8, 30, 10, 30, 20, BIM_FP64, -1, 1, 1, 0.0, 0.
+ * Invalid values (non-positive tolerances, restart outside [1, 200], negative
+ * counts, fd_eps >= 1 or NaN, unknown precision) give BIM_EINVAL.
  */
 typedef struct bim_jfnk_opts {
     double ftol;
@@ -213,8 +216,8 @@ void jfnk_default_opts(bim_jfnk_opts *opts);
  *   opts: NULL for the defaults.  rep: host, may be NULL.
  * Synchronises `stream` repeatedly (the host takes the Newton and Krylov
  * decisions).  Returns BIM_OK when ||F||_inf <= ftol, BIM_NOT_CONVERGED after
- * max_newton steps, BIM_LINESEARCH_FAIL when no step length decreases ||F||,
- * BIM_EDOMAIN on a non-finite residual.
+ * max_newton steps (or on the stall stop), BIM_LINESEARCH_FAIL when no step
+ * length decreases ||F||, BIM_EDOMAIN on a non-finite residual.
  */
 int jfnk_solve(const bim_problem *prob, const bim_precond *P, double *u, const bim_jfnk_opts *opts,
                bim_jfnk_report *rep, void *stream);

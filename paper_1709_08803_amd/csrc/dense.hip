@@ -16,11 +16,12 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 // C = alpha A B + beta C (row-major, FP64) on the matrix cores.  64 x 64 output
 // tile per 256-thread workgroup; each wave owns 32 x 32 = 2 x 2 tiles of
-// v_mfma_f64_16x16x4f64 and K advances through LDS in steps of 16.  Operand
-// layout of the 16x16x4 FP64 MFMA: lane l holds A[l % 16][l / 16] and
+// v_mfma_f64_16x16x4f64.  K advances through LDS in steps of 32, and the next
+// step's operands are loaded into registers while the current step's MFMAs run.
+// Operand layout of the 16x16x4 FP64 MFMA: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; the accumulator's element v of lane l is
 // D[l / 16 + 4 v][l % 16] (lane layout checked on gfx950).
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TM = 64, TN = 64, TK = 32;
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items, int m, int n, int k,
@@ -35,23 +36,41 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
     const int li = lane & 15, lk = lane >> 4;
+    // each thread stages 8 elements of A (rows e >> 5, cols e & 31) and 8 of B (rows e >> 6, cols e & 63)
+    double ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + q * 256;
+            const int ar = e >> 5, ac = e & 31;
+            const int gr = row0 + ar, gc = k0 + ac;
+            ra[q] = (gr < m && gc < k) ? A[(size_t)gr * lda + gc] : 0.0;
+            const int br = e >> 6, bc = e & 63;
+            const int hr = k0 + br, hc = col0 + bc;
+            rb[q] = (hr < k && hc < n) ? B[(size_t)hr * ldb + hc] : 0.0;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + q * 256;
+            As[e >> 5][e & 31] = ra[q];
+            Bs[e >> 6][e & 63] = rb[q];
+        }
+    };
     double4_t acc[2][2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int u = 0; u < 2; ++u) acc[t][u] = double4_t{0.0, 0.0, 0.0, 0.0};
+    if (k > 0) {
+        load(0);
+        store();
+    }
+    __syncthreads();
     for (int k0 = 0; k0 < k; k0 += TK) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = tid + q * 256;
-            const int ar = e >> 4, ac = e & 15;
-            const int gr = row0 + ar, gc = k0 + ac;
-            As[ar][ac] = (gr < m && gc < k) ? A[(size_t)gr * lda + gc] : 0.0;
-            const int br = e >> 6, bc = e & 63;
-            const int hr = k0 + br, hc = col0 + bc;
-            Bs[br][bc] = (hr < k && hc < n) ? B[(size_t)hr * ldb + hc] : 0.0;
-        }
-        __syncthreads();
+        const bool more = k0 + TK < k;
+        if (more) load(k0 + TK);
 #pragma unroll
         for (int kk = 0; kk < TK; kk += 4) {
             double a[2], b[2];
@@ -66,6 +85,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
                 for (int u = 0; u < 2; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
         }
         __syncthreads();
+        if (more) {
+            store();
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -83,13 +106,15 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
 
 // In-place Gauss-Jordan inversion with partial pivoting of one s x s block
 // (s <= 192) per 512-thread workgroup, with the matrix held in registers:
-// thread (ty, tx) = (tid / 64, tid % 64) owns rows ty + 8 i (i < 24) and
-// columns tx + 64 j (j < 3).  Step k: the owners of column k find the pivot
-// row p, rows k and p and column k are staged in LDS, and every thread updates
-// its elements (row k becomes the scaled pivot row with A[k][k] replaced by 1,
-// row r != k loses fac[r] times it, column k of those rows starting from 0).
-// The row interchanges are undone as column interchanges, in reverse order,
-// when the result is written.
+// wave ty (= tid / 64, uniform in the wave) owns rows ty + 8 i (i < 24) and lane
+// tx columns tx + 64 j (j < 3).  Step k: the owners of column k find the pivot
+// row p, rows k and p and column k are staged in LDS, row p takes the old row
+// k, every row r then loses f_r times the scaled pivot row (its column-k entry
+// starting from 0), and row k becomes the scaled pivot row with A[k][k]
+// replaced by 1.  Row decisions depend only on the wave, so they are scalar
+// branches; the element update is a multiply and an FMA.  The row interchanges
+// are undone as column interchanges, in reverse order, when the result is
+// written.
 constexpr int kRegTy = 8, kRegRows = 24, kRegCols = 3;
 constexpr int kRegThreads = 64 * kRegTy;
 constexpr int kRegMaxS = kRegTy * kRegRows;  // = 64 kRegCols = 192
@@ -97,7 +122,8 @@ constexpr int kRegMaxS = kRegTy * kRegRows;  // = 64 kRegCols = 192
 __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__restrict__ items, int s,
                                                             int *__restrict__ info) {
     const InvItem it = items[blockIdx.x];
-    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    const int tx = threadIdx.x & 63;
+    const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     __shared__ double rowk[kRegMaxS], rowp[kRegMaxS], fac[kRegMaxS];
     __shared__ double redv[kRegTy];
     __shared__ int redi[kRegTy];
@@ -110,13 +136,13 @@ __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__res
             const int r = ty + kRegTy * i, c = tx + 64 * j;
             a[i][j] = (r < s && c < s) ? it.A[(size_t)r * it.lda + c] : 0.0;
         }
-    for (int e = tid; e < kRegMaxS; e += kRegThreads) rowk[e] = rowp[e] = fac[e] = 0.0;
+    for (int e = threadIdx.x; e < kRegMaxS; e += kRegThreads) rowk[e] = rowp[e] = fac[e] = 0.0;
     __syncthreads();
     int bad = 0;
     for (int k = 0; k < s; ++k) {
-        const int jk = k >> 6;
-        // pivot candidates of column k, one per thread row
-        if (tx == (k & 63)) {
+        const int jk = k >> 6, tk = k & 63;
+        // pivot candidates of column k, one per wave
+        if (tx == tk) {
             double bv = -1.0;
             int bi = k;
 #pragma unroll
@@ -130,6 +156,25 @@ __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__res
             }
             redv[ty] = bv;
             redi[ty] = bi;
+            // column k before the interchange
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i) {
+                const int r = ty + kRegTy * i;
+                if (r < s) fac[r] = (jk == 0 ? a[i][0] : (jk == 1 ? a[i][1] : a[i][2]));
+            }
+        }
+        // row k before the interchange
+        if (ty == k % kRegTy) {
+            const int ir = k / kRegTy;
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i)
+                if (i == ir) {
+#pragma unroll
+                    for (int j = 0; j < kRegCols; ++j) {
+                        const int c = tx + 64 * j;
+                        if (c < s) rowk[c] = a[i][j];
+                    }
+                }
         }
         __syncthreads();
         // every thread reduces the candidates in the same order (uniform result)
@@ -143,28 +188,16 @@ __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__res
                 p = q;
             }
         }
+        p = __builtin_amdgcn_readfirstlane(p);
         if (!(pv > 0.0) || !isfinite(pv)) {
             bad = k + 1;
             break;
         }
-        // stage rows k, p and column k
-        if (ty == k % kRegTy) {
-            const int ir = k / kRegTy;
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i)
-                if (i == ir) {
-#pragma unroll
-                    for (int j = 0; j < kRegCols; ++j) {
-                        const int c = tx + 64 * j;
-                        if (c < s) rowk[c] = a[i][j];
-                    }
-                }
-        }
+        const int ip = p / kRegTy;
         if (ty == p % kRegTy) {
-            const int ir = p / kRegTy;
 #pragma unroll
             for (int i = 0; i < kRegRows; ++i)
-                if (i == ir) {
+                if (i == ip) {
 #pragma unroll
                     for (int j = 0; j < kRegCols; ++j) {
                         const int c = tx + 64 * j;
@@ -172,41 +205,49 @@ __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__res
                     }
                 }
         }
-        if (tx == (k & 63)) {
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i) {
-                const int r = ty + kRegTy * i;
-                if (r < s) fac[r] = (jk == 0 ? a[i][0] : (jk == 1 ? a[i][1] : a[i][2]));
-            }
-        }
-        if (tid == 0) ipiv[k] = p;
+        if (threadIdx.x == 0) ipiv[k] = p;
         __syncthreads();
         const double pivinv = 1.0 / rowp[k];
         const double fk = fac[k];
-        double pc[kRegCols], rk[kRegCols];
+        double pc[kRegCols], z[kRegCols];
 #pragma unroll
         for (int j = 0; j < kRegCols; ++j) {
             const int c = tx + 64 * j;
             pc[j] = ((c == k) ? 1.0 : rowp[c]) * pivinv;
-            rk[j] = (c == k) ? 0.0 : rowk[c];
+            z[j] = (c == k) ? 0.0 : 1.0;
+        }
+        // row p takes the old row k (a no-op when p = k)
+        if (ty == p % kRegTy) {
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i)
+                if (i == ip) {
+#pragma unroll
+                    for (int j = 0; j < kRegCols; ++j) a[i][j] = rowk[tx + 64 * j];
+                }
         }
 #pragma unroll
         for (int i = 0; i < kRegRows; ++i) {
             const int r = ty + kRegTy * i;
             const double f = (r == p) ? fk : fac[r];
 #pragma unroll
-            for (int j = 0; j < kRegCols; ++j) {
-                const int c = tx + 64 * j;
-                const double old = (r == p) ? rk[j] : ((c == k) ? 0.0 : a[i][j]);
-                a[i][j] = (r == k) ? pc[j] : fma(-f, pc[j], old);
-            }
+            for (int j = 0; j < kRegCols; ++j) a[i][j] = fma(-f, pc[j], a[i][j] * z[j]);
+        }
+        // row k becomes the scaled pivot row
+        if (ty == k % kRegTy) {
+            const int ir = k / kRegTy;
+#pragma unroll
+            for (int i = 0; i < kRegRows; ++i)
+                if (i == ir) {
+#pragma unroll
+                    for (int j = 0; j < kRegCols; ++j) a[i][j] = pc[j];
+                }
         }
         __syncthreads();  // LDS rows are rewritten by the next step
     }
-    if (tid == 0 && info) info[blockIdx.x] = bad;
+    if (threadIdx.x == 0 && info) info[blockIdx.x] = bad;
     if (bad) return;
     // column interchanges in reverse order: output column dst[c] holds column c
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
         for (int c = 0; c < s; ++c) dst[c] = c;  // src[c]: which column lands in output column c
         for (int k = s - 1; k >= 0; --k) {
             const int q = ipiv[k];

@@ -18,7 +18,7 @@ def bim():
     return B
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 5e-7)])
 def test_batched_residual_matches_oracle_per_instance(bim, prec, tol):
     probs = W.sweep_instances(6, seed=0, n_choices=[31, 34, 46, 61])
     probs.append(W.tiny(0.9))

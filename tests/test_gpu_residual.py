@@ -58,7 +58,7 @@ def test_residual_fp32c_matches_oracle(bim, name, mk, seed):
     F = _gpu_F(bim, p, u, "fp32c")
     err = np.abs(F - F_ref) / scale
     print(name, "fp32c max rel err", err.max())
-    assert err.max() <= 1e-5
+    assert err.max() <= 5e-7
 
 
 def test_residual_fp32c_full_size_against_fp64(bim):
@@ -71,7 +71,7 @@ def test_residual_fp32c_full_size_against_fp64(bim):
     scale = R.term_magnitude_rows(p, u)
     err = np.abs(F32 - F64) / scale
     print("181x61 fp32c max rel err", err.max(), "median", np.median(err))
-    assert err.max() <= 1e-5
+    assert err.max() <= 5e-7
 
 
 @pytest.mark.parametrize("F_num", [0.7, 1.4])
@@ -95,7 +95,7 @@ def test_residual_full_size_sampled_rows(bim, F_num):
     e32 = (np.abs(F32[rows] - ref) / scale).max()
     print("181x61 F", F_num, "fp64", e64, "fp32c", e32)
     assert e64 <= 1e-12
-    assert e32 <= 1e-5
+    assert e32 <= 5e-7
 
 
 def test_residual_is_deterministic(bim):
@@ -156,7 +156,7 @@ def test_jv_default_shift_and_zero_direction(bim):
 VARIANTS = [(tpl, unr, rpc) for tpl in (1, 2) for unr in (2, 4, 8) for rpc in (1, 3)]
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 5e-7)])
 def test_every_launch_variant_matches_oracle(bim, prec, tol):
     # the autotuner may pick any of these; all must meet the same bar
     p = W.make_problem(45, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)])  # M odd: a lone last row pair
