@@ -140,8 +140,8 @@ def main():
                          "the reference for scaling hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the method's sharding "
-              f"across GPUs is described in DESIGN.md, not run).", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (row sharding of the residual "
+              f"and the preconditioner across GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

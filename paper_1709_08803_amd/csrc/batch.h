@@ -57,7 +57,8 @@ struct BBand {
     int M, w, s;
     double alpha, beta;
 };
-int b_bandmv(const BBand *ops, int count, int max_rows, hipStream_t s);
+// max_groups: the largest M ceil(s / 4) over the ops (waves needed by the largest problem)
+int b_bandmv(const BBand *ops, int count, int max_groups, hipStream_t s);
 // One dense product y = alpha A x + beta c (rows x cols, row stride lda).
 struct BGemv {
     const double *A;

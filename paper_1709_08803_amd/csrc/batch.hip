@@ -3,6 +3,8 @@
 // two-pass with fixed order, so every problem's result is deterministic.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
 #include "batch.h"
 #include "bim_common.h"
 
@@ -116,33 +118,85 @@ __global__ void k_bshift(const BOp *__restrict__ ops, int count) {
     }
 }
 
+// Banded and dense products of many problems in one launch (blockIdx.y picks
+// the problem).  Each wave owns kBGR consecutive rows (of one slice for the
+// banded product) and reads 16 bytes per lane per row when the rows are
+// 16-byte aligned (even s or lda), loading each x segment once for its rows;
+// otherwise 8 bytes per lane.
+constexpr int kBGR = 4;
+typedef double bdouble2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void brows_dot(const double *const (&row)[kBGR], const double *__restrict__ x, int len,
+                                          bool vec, int lane, double (&acc)[kBGR]) {
+    if (vec) {
+        for (int q = lane; q < (len >> 1); q += 64) {
+            const bdouble2 xv = *reinterpret_cast<const bdouble2 *>(x + 2 * q);
+#pragma unroll
+            for (int r = 0; r < kBGR; ++r) {
+                const bdouble2 av = *reinterpret_cast<const bdouble2 *>(row[r] + 2 * q);
+                acc[r] = fma(av[0], xv[0], acc[r]);
+                acc[r] = fma(av[1], xv[1], acc[r]);
+            }
+        }
+        if ((len & 1) && lane == 0)
+#pragma unroll
+            for (int r = 0; r < kBGR; ++r) acc[r] = fma(row[r][len - 1], x[len - 1], acc[r]);
+    } else {
+        for (int j = lane; j < len; j += 64) {
+            const double xv = x[j];
+#pragma unroll
+            for (int r = 0; r < kBGR; ++r) acc[r] = fma(row[r][j], xv, acc[r]);
+        }
+    }
+}
+
+__device__ __forceinline__ void brows_store(double (&acc)[kBGR], int lane, int nvalid, double *y, const double *c,
+                                            int row0, double alpha, double beta) {
+#pragma unroll
+    for (int r = 0; r < kBGR; ++r)
+        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, 64);
+    if (lane < nvalid) {
+        double v = acc[0];
+#pragma unroll
+        for (int r = 1; r < kBGR; ++r) v = (lane == r) ? acc[r] : v;
+        const int row = row0 + lane;
+        y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_bbandmv(const BBand *__restrict__ ops) {
     const BBand o = ops[blockIdx.y];
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int gps = (o.s + kBGR - 1) / kBGR;  // row groups per slice
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (row >= o.M * o.s) return;
-    const int l = row / o.s, r = row - l * o.s;
-    double v = 0.0;
+    if (wave >= o.M * gps) return;
+    const int l = wave / gps, r0 = (wave - l * gps) * kBGR;
     const int m0 = max(0, l - o.w), m1 = min(o.M - 1, l + o.w);
+    const bool vec = (o.s % 2 == 0) && ((uintptr_t)o.band % 16 == 0) && ((uintptr_t)o.x % 16 == 0);
+    double acc[kBGR] = {};
     for (int m = m0; m <= m1; ++m) {
-        const double *b = o.band + (((size_t)l * (2 * o.w + 1) + (m - l + o.w)) * o.s + r) * o.s;
-        const double *xm = o.x + (size_t)m * o.s;
-        for (int j = lane; j < o.s; j += 64) v = fma(b[j], xm[j], v);
+        const double *blk = o.band + ((size_t)l * (2 * o.w + 1) + (m - l + o.w)) * o.s * o.s;
+        const double *row[kBGR];
+#pragma unroll
+        for (int r = 0; r < kBGR; ++r) row[r] = blk + (size_t)min(r0 + r, o.s - 1) * o.s;
+        brows_dot(row, o.x + (size_t)m * o.s, o.s, vec, lane, acc);
     }
-    for (int q = 32; q > 0; q >>= 1) v += __shfl_xor(v, q, 64);
-    if (lane == 0) o.y[row] = (o.beta == 0.0) ? o.alpha * v : fma(o.alpha, v, o.beta * o.c[row]);
+    brows_store(acc, lane, min(kBGR, o.s - r0), o.y, o.c, l * o.s + r0, o.alpha, o.beta);
 }
 
 __global__ __launch_bounds__(256) void k_bgemv(const BGemv *__restrict__ ops) {
     const BGemv o = ops[blockIdx.y];
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (row >= o.rows) return;
-    const double *a = o.A + (size_t)row * o.lda;
-    double v = 0.0;
-    for (int j = lane; j < o.cols; j += 64) v = fma(a[j], o.x[j], v);
-    for (int q = 32; q > 0; q >>= 1) v += __shfl_xor(v, q, 64);
-    if (lane == 0) o.y[row] = (o.beta == 0.0) ? o.alpha * v : fma(o.alpha, v, o.beta * o.c[row]);
+    const int row0 = wave * kBGR;
+    if (row0 >= o.rows) return;
+    const bool vec = (o.lda % 2 == 0) && ((uintptr_t)o.A % 16 == 0) && ((uintptr_t)o.x % 16 == 0);
+    const double *row[kBGR];
+#pragma unroll
+    for (int r = 0; r < kBGR; ++r) row[r] = o.A + (size_t)min(row0 + r, o.rows - 1) * o.lda;
+    double acc[kBGR] = {};
+    brows_dot(row, o.x, o.cols, vec, lane, acc);
+    brows_store(acc, lane, min(kBGR, o.rows - row0), o.y, o.c, row0, o.alpha, o.beta);
 }
 
 __global__ void k_bgather(const BOp *__restrict__ ops) {
@@ -211,15 +265,15 @@ int b_gather(const BOp *ops, int count, hipStream_t s) {
     return hip_check(hipGetLastError(), "batched gather launch");
 }
 
-int b_bandmv(const BBand *ops, int count, int max_rows, hipStream_t s) {
+int b_bandmv(const BBand *ops, int count, int max_groups, hipStream_t s) {
     if (count <= 0) return BIM_OK;
-    hipLaunchKernelGGL(k_bbandmv, dim3(cdiv(max_rows, 4), count), dim3(256), 0, s, ops);
+    hipLaunchKernelGGL(k_bbandmv, dim3(cdiv(max_groups, 4), count), dim3(256), 0, s, ops);
     return hip_check(hipGetLastError(), "batched bandmv launch");
 }
 
 int b_gemv(const BGemv *ops, int count, int max_rows, hipStream_t s) {
     if (count <= 0) return BIM_OK;
-    hipLaunchKernelGGL(k_bgemv, dim3(cdiv(max_rows, 4), count), dim3(256), 0, s, ops);
+    hipLaunchKernelGGL(k_bgemv, dim3(cdiv(cdiv(max_rows, kBGR), 4), count), dim3(256), 0, s, ops);
     return hip_check(hipGetLastError(), "batched gemv launch");
 }
 

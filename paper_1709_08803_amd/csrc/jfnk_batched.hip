@@ -356,8 +356,9 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         // products per problem (5 before the dense Schur product, 2 after); gather them stage by stage
         if (!hgemv.empty()) {
             const int napp = (int)hgemv.size(), per = 7;
-            int max_rows = 0;
+            int max_rows = 0, max_groups = 0;
             for (int a = 0; a < napp; ++a) max_rows = std::max(max_rows, hgemv[a].rows);
+            for (const BBand &bb : hband) max_groups = std::max(max_groups, bb.M * ((bb.s + 3) / 4));
             std::vector<BBand> gathered;
             gathered.reserve((size_t)napp * per);
             for (int stg = 0; stg < per; ++stg)
@@ -366,10 +367,10 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
                                                hipMemcpyHostToDevice, s), "copy")))
                 return rc;
             for (int stg = 0; stg < 5; ++stg)
-                if ((rc = b_bandmv(banddev + (size_t)stg * napp, napp, max_rows, s))) return rc;
+                if ((rc = b_bandmv(banddev + (size_t)stg * napp, napp, max_groups, s))) return rc;
             if ((rc = b_gemv(gemvdev, napp, max_rows, s))) return rc;
             for (int stg = 5; stg < per; ++stg)
-                if ((rc = b_bandmv(banddev + (size_t)stg * napp, napp, max_rows, s))) return rc;
+                if ((rc = b_bandmv(banddev + (size_t)stg * napp, napp, max_groups, s))) return rc;
         }
         if ((rc = b_axpby(S(sl_ls), C(sl_ls), s))) return rc;  // unpreconditioned copies and line-search points
         if ((rc = b_dot(S(sl_shu), C(sl_shu), true, s))) return rc;
