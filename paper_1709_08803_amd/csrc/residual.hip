@@ -175,6 +175,20 @@ __global__ void k_targets(const double *__restrict__ nodes, const double *__rest
 }
 
 // ------------------------------------------------------------------ A2: all-pairs sums (hot loop)
+// The sums read through address-space qualified pointers.  Per-lane arrays are
+// global memory.  Node records are read-only for a whole launch; the batched
+// kernel, whose pointers come from a descriptor in memory and so carry no
+// address space (flat loads, which count on the same counter as the scalar
+// loads and break the record prefetch), reads them through the constant
+// address space, where a wave-uniform address gives a scalar load.  The
+// single-problem kernel keeps the kernel-argument pointers: the compiler infers
+// them as global and keeps several FP64 record loads in flight, which it does
+// not do for constant-space loads (measured: 3% on the FP64 sums).
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T *;
+template <typename T>
+using GlobalPtr = __attribute__((address_space(1))) T *;
+
 // One source record as a single 8-wide vector load (one scalar load per node).
 template <typename T>
 struct RecVec;
@@ -186,9 +200,22 @@ template <>
 struct RecVec<double> {
     typedef double type __attribute__((ext_vector_type(8)));
 };
+template <typename T, bool CREC>
+struct RecPtrs {  // generic pointers
+    typedef const SrcRec<T> *rec;
+    typedef const typename RecVec<T>::type *vec;
+};
 template <typename T>
-__device__ __forceinline__ SrcRec<T> load_rec(const SrcRec<T> *__restrict__ p) {
-    const typename RecVec<T>::type v = *reinterpret_cast<const typename RecVec<T>::type *>(p);
+struct RecPtrs<T, true> {  // constant address space
+    typedef ConstPtr<SrcRec<T>> rec;
+    typedef ConstPtr<typename RecVec<T>::type> vec;
+};
+template <typename T, bool CREC>
+using RecPtr = typename RecPtrs<T, CREC>::rec;
+
+template <typename T, bool CREC>
+__device__ __forceinline__ SrcRec<T> load_rec(RecPtr<T, CREC> p) {
+    const typename RecVec<T>::type v = *reinterpret_cast<typename RecPtrs<T, CREC>::vec>(p);
     SrcRec<T> r;
     r.x = v[0];
     r.z = v[1];
@@ -211,29 +238,56 @@ __device__ __forceinline__ SrcRec<T> load_rec(const SrcRec<T> *__restrict__ p) {
 // values read there are never used).
 // FP64 records (two scalar loads of 16 dwords per pair of records) gain
 // nothing from it (measured), so they keep the plain loop.
-template <typename T, int UNROLL, typename Body>
-__device__ __forceinline__ void walk_row(const SrcRec<T> *__restrict__ src, int N, Body &&body) {
+// The FP32 walk also calls seg() after every kSeg records, where the running
+// FP32 partial sums are folded into the compensated sums.
+// body(p) does the first part of record p's work (distances and every
+// reciprocal square root) and returns the rest (the accumulations) as a
+// closure; a group runs every record's first part before any second part, so
+// the independent rsq of the group are issued ahead of their uses (second
+// parts in reverse record order).
+constexpr int kSeg = 32;
+template <int U, int K = 0, typename Body, typename Rec>
+__device__ __forceinline__ void run_group(Body &body, const Rec *cur) {
+    if constexpr (K < U) {
+        auto rest = body(cur[K]);
+        run_group<U, K + 1>(body, cur);
+        rest();
+    }
+}
+template <typename T, int UNROLL, bool CREC, typename Body, typename Seg>
+__device__ __forceinline__ void walk_row(RecPtr<T, CREC> src, int N, Body &&body, Seg &&seg) {
     static_assert(UNROLL <= kRecPad, "prefetch beyond the record padding");
+    static_assert(kSeg % 8 == 0, "segments hold whole groups of every unroll");
     if constexpr (sizeof(T) == 8) {
 #pragma unroll UNROLL
-        for (int i = 0; i < N; ++i) body(load_rec(src + i));
+        for (int i = 0; i < N; ++i) body(load_rec<T, CREC>(src + i))();
         return;
     }
     const int full = N - N % UNROLL;
     SrcRec<T> cur[UNROLL];
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) cur[u] = load_rec(src + u);
-    for (int i0 = 0; i0 < full; i0 += UNROLL) {
-        SrcRec<T> nxt[UNROLL];
+    for (int u = 0; u < UNROLL; ++u) cur[u] = load_rec<T, CREC>(src + u);
+    // The fold sits outside the pipelined loop: a branch inside it splits the
+    // loop body, and the compiler then sinks the next group's loads into the
+    // latch, right in front of their wait.
+    for (int s0 = 0; s0 < full; s0 += kSeg) {
+        const int s1 = min(s0 + kSeg, full);
+        for (int i0 = s0; i0 < s1; i0 += UNROLL) {
+            SrcRec<T> nxt[UNROLL];
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) nxt[u] = load_rec(src + i0 + UNROLL + u);
-        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
+            for (int u = 0; u < UNROLL; ++u) nxt[u] = load_rec<T, CREC>(src + i0 + UNROLL + u);
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
+            run_group<UNROLL>(body, cur);
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) body(cur[u]);
-#pragma unroll
-        for (int u = 0; u < UNROLL; ++u) cur[u] = nxt[u];
+            for (int u = 0; u < UNROLL; ++u) cur[u] = nxt[u];
+        }
+        seg();
     }
-    for (int u = 0; u < N - full; ++u) body(cur[u]);
+    // the tail indexes cur[] with constants only (a runtime index would put the
+    // array in private memory)
+#pragma unroll
+    for (int u = 0; u < UNROLL - 1; ++u)
+        if (u < N - full) body(cur[u])();
 }
 
 // One wave = 64 collocation points of one boundary: consecutive entries of
@@ -249,8 +303,8 @@ __device__ __forceinline__ void walk_row(const SrcRec<T> *__restrict__ src, int 
 //   own boundary:   w (D - D*) K1 + w sigma K2  and  w S2   (two rsqrt)
 //   other boundary: w D K1 + w sigma K2                      (one rsqrt)
 // written as  ri (coef num ri^2 + w sigma)  with ri = 1/R.
-// FP32C: FP32 sums over one source row, combined across rows with Neumaier's
-// compensated summation; the chunk result is written in FP64.
+// FP32C: FP32 sums over segments of kSeg nodes of a source row, combined with
+// Neumaier's compensated summation; the chunk result is written in FP64.
 template <typename T, int NI>
 struct TargetState {
     double ys;                                   // y* (FP64, physical units)
@@ -260,29 +314,35 @@ struct TargetState {
     T sum, comp, s2sum, s2comp;                  // across rows
 };
 
-template <typename T, bool COMP, int NI>
+// S2: the row also carries the S2 sum (only rows of the target's own boundary).
+template <typename T, bool COMP, int NI, bool S2 = true>
 __device__ __forceinline__ void row_end(TargetState<T, NI> &g) {
     if (COMP) {
         T tsum = g.sum + g.acc;
         g.comp += (fabs(g.sum) >= fabs(g.acc)) ? ((g.sum - tsum) + g.acc) : ((g.acc - tsum) + g.sum);
         g.sum = tsum;
-        T tq = g.s2sum + g.acc2;
-        g.s2comp += (fabs(g.s2sum) >= fabs(g.acc2)) ? ((g.s2sum - tq) + g.acc2) : ((g.acc2 - tq) + g.s2sum);
-        g.s2sum = tq;
+        if (S2) {
+            T tq = g.s2sum + g.acc2;
+            g.s2comp += (fabs(g.s2sum) >= fabs(g.acc2)) ? ((g.s2sum - tq) + g.acc2) : ((g.acc2 - tq) + g.s2sum);
+            g.s2sum = tq;
+        }
     } else {
         g.sum += g.acc;
-        g.s2sum += g.acc2;
+        if (S2) g.s2sum += g.acc2;
     }
 }
 
 // NI = 2: half domain (both images per source row); NI = 1: full domain.
 // FP32 (grid units): t = (y_j - y*) / dx is formed in FP64 for every source row
 // and the S2 sum is multiplied by dx on output; FP64 works in physical units.
-template <typename T, bool COMP, int TPL, int UNROLL, int NI>
+template <typename T, bool COMP, int TPL, int UNROLL, int NI, bool CREC>
 __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
                                           const T *__restrict__ tg, const double *__restrict__ tg64, int N, int M,
                                           double y1, double dx, double dy, int tiles_per_bnd, int row_groups,
                                           int rows_per_chunk, double *__restrict__ part, int tt, int c, int lane) {
+    const RecPtr<T, CREC> recS = (RecPtr<T, CREC>)srcS, recB = (RecPtr<T, CREC>)srcB;
+    const GlobalPtr<const T> gtg = (GlobalPtr<const T>)tg;
+    const GlobalPtr<const double> gtg64 = (GlobalPtr<const double>)tg64;
     const double gi = (sizeof(T) == 4) ? 1.0 / dx : 1.0;
     const int ntg = (N - 1) * M;
     const size_t T2 = (size_t)2 * ntg;
@@ -299,13 +359,13 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
     for (int q = 0; q < TPL; ++q) {
         const int l = min(lg * TPL + q, M - 1);
         const int tid = st * ntg + l * (N - 1) + k;
-        xs = tg[0 * T2 + tid];
-        ts[q].ys = tg64[1 * T2 + tid];
-        ts[q].d = tg[2 * T2 + tid];
-        ts[q].Dst = tg[3 * T2 + tid];
-        ts[q].A = tg[4 * T2 + tid];
-        ts[q].B = tg[5 * T2 + tid];
-        ts[q].C = tg[6 * T2 + tid];
+        xs = gtg[0 * T2 + tid];
+        ts[q].ys = gtg64[1 * T2 + tid];
+        ts[q].d = gtg[2 * T2 + tid];
+        ts[q].Dst = gtg[3 * T2 + tid];
+        ts[q].A = gtg[4 * T2 + tid];
+        ts[q].B = gtg[5 * T2 + tid];
+        ts[q].C = gtg[6 * T2 + tid];
         ts[q].sum = ts[q].comp = ts[q].s2sum = ts[q].s2comp = 0;
     }
     const int r0 = c * rows_per_chunk;
@@ -329,46 +389,79 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
             ts[q].acc = 0;
             ts[q].acc2 = 0;
         }
-        const SrcRec<T> *__restrict__ src = (ss ? srcB : srcS) + (size_t)j * N;
+        const RecPtr<T, CREC> src = (ss ? recB : recS) + (size_t)j * N;
+        auto seg_own = [&]() {
+#pragma unroll
+            for (int q = 0; q < TPL; ++q) {
+                row_end<T, COMP, NI>(ts[q]);
+                ts[q].acc = 0;
+                ts[q].acc2 = 0;
+            }
+        };
+        auto seg_other = [&]() {  // acc2 stays zero on the other boundary
+#pragma unroll
+            for (int q = 0; q < TPL; ++q) {
+                row_end<T, COMP, NI, false>(ts[q]);
+                ts[q].acc = 0;
+            }
+        };
         if (ss == st) {
-            walk_row<T, UNROLL>(src, N, [&](const SrcRec<T> &p) {
+            walk_row<T, UNROLL, CREC>(src, N, [&](const SrcRec<T> &p) {
                 const T s = p.x - xs;
+                T nb0[TPL], coef[TPL], ri[TPL][NI], rq[TPL][NI];
 #pragma unroll
                 for (int q = 0; q < TPL; ++q) {
-                    TargetState<T, NI> &e = ts[q];
+                    const TargetState<T, NI> &e = ts[q];
                     const T dz = p.z - e.d;
                     const T base = (NI == 2) ? fma(s, s, dz * dz) : fma(s, s, e.t2[0]);
-                    const T nb0 = fma(-s, p.zx, dz);
-                    const T coef = fma(-e.Dst, p.w, p.wD);
+                    nb0[q] = fma(-s, p.zx, dz);
+                    coef[q] = fma(-e.Dst, p.w, p.wD);
 #pragma unroll
                     for (int i = 0; i < NI; ++i) {
-                        const T ri = rsq((NI == 2) ? base + e.t2[i] : fma(dz, dz, base));
-                        const T num = fma(-e.ti[i], p.zy, nb0);
-                        const T bsum = fma(coef * num, ri * ri, p.ws);
-                        e.acc = fma(bsum, ri, e.acc);
-                        const T Q = fma(s, fma(e.A, s, e.Bt[i]), e.Ct2[i]);
-                        e.acc2 = fma(p.w, rsq(Q), e.acc2);
+                        ri[q][i] = rsq((NI == 2) ? base + e.t2[i] : fma(dz, dz, base));
+                        rq[q][i] = rsq(fma(s, fma(e.A, s, e.Bt[i]), e.Ct2[i]));
                     }
                 }
-            });
+                return [&, p, nb0, coef, ri, rq]() {
+#pragma unroll
+                    for (int q = 0; q < TPL; ++q) {
+                        TargetState<T, NI> &e = ts[q];
+#pragma unroll
+                        for (int i = 0; i < NI; ++i) {
+                            const T num = fma(-e.ti[i], p.zy, nb0[q]);
+                            const T bsum = fma(coef[q] * num, ri[q][i] * ri[q][i], p.ws);
+                            e.acc = fma(bsum, ri[q][i], e.acc);
+                            e.acc2 = fma(p.w, rq[q][i], e.acc2);
+                        }
+                    }
+                };
+            }, seg_own);
         } else {
-            walk_row<T, UNROLL>(src, N, [&](const SrcRec<T> &p) {
+            walk_row<T, UNROLL, CREC>(src, N, [&](const SrcRec<T> &p) {
                 const T s = p.x - xs;
+                T nb0[TPL], ri[TPL][NI];
 #pragma unroll
                 for (int q = 0; q < TPL; ++q) {
-                    TargetState<T, NI> &e = ts[q];
+                    const TargetState<T, NI> &e = ts[q];
                     const T dz = p.z - e.d;
                     const T base = (NI == 2) ? fma(s, s, dz * dz) : fma(s, s, e.t2[0]);
-                    const T nb0 = fma(-s, p.zx, dz);
+                    nb0[q] = fma(-s, p.zx, dz);
 #pragma unroll
-                    for (int i = 0; i < NI; ++i) {
-                        const T ri = rsq((NI == 2) ? base + e.t2[i] : fma(dz, dz, base));
-                        const T num = fma(-e.ti[i], p.zy, nb0);
-                        const T bsum = fma(p.wD * num, ri * ri, p.ws);
-                        e.acc = fma(bsum, ri, e.acc);
-                    }
+                    for (int i = 0; i < NI; ++i) ri[q][i] = rsq((NI == 2) ? base + e.t2[i] : fma(dz, dz, base));
                 }
-            });
+                return [&, p, nb0, ri]() {
+#pragma unroll
+                    for (int q = 0; q < TPL; ++q) {
+                        TargetState<T, NI> &e = ts[q];
+#pragma unroll
+                        for (int i = 0; i < NI; ++i) {
+                            const T num = fma(-e.ti[i], p.zy, nb0[q]);
+                            const T bsum = fma(p.wD * num, ri[q][i] * ri[q][i], p.ws);
+                            e.acc = fma(bsum, ri[q][i], e.acc);
+                        }
+                    }
+                };
+            }, seg_other);
         }
 #pragma unroll
         for (int q = 0; q < TPL; ++q) row_end<T, COMP, NI>(ts[q]);
@@ -378,24 +471,24 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
         const int l = lg * TPL + q;
         if (valid && l < M) {
             const int tid = st * ntg + l * (N - 1) + k;
-            double *o = part + ((size_t)c * T2 + tid) * 2;
+            const GlobalPtr<double> o = (GlobalPtr<double>)part + ((size_t)c * T2 + tid) * 2;
             o[0] = (double)ts[q].sum + (double)ts[q].comp;
             o[1] = ((double)ts[q].s2sum + (double)ts[q].s2comp) * ((sizeof(T) == 4) ? dx : 1.0);
         }
     }
 }
 
-template <typename T, bool COMP, int TPL, int UNROLL>
+template <typename T, bool COMP, int TPL, int UNROLL, bool CREC>
 __device__ __forceinline__ void pair_item_any(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
                                               const T *__restrict__ tg, const double *__restrict__ tg64, int N,
                                               int M, int nimg, double y1, double dx, double dy, int tiles_per_bnd,
                                               int row_groups, int rows_per_chunk, double *__restrict__ part, int tt,
                                               int c, int lane) {
     if (nimg == 2)
-        pair_item<T, COMP, TPL, UNROLL, 2>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
+        pair_item<T, COMP, TPL, UNROLL, 2, CREC>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
                                            rows_per_chunk, part, tt, c, lane);
     else
-        pair_item<T, COMP, TPL, UNROLL, 1>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
+        pair_item<T, COMP, TPL, UNROLL, 1, CREC>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
                                            rows_per_chunk, part, tt, c, lane);
 }
 
@@ -411,8 +504,8 @@ __global__ __launch_bounds__(256) void k_allpairs(
     const int g = blockIdx.x * 4 + wave;
     const int tt = g % target_tiles, c = g / target_tiles;
     if (c >= chunks) return;
-    pair_item_any<T, COMP, TPL, UNROLL>(srcS, srcB, tg, tg64, N, M, nimg, y1, dx, dy, tiles_per_bnd, row_groups,
-                                        rows_per_chunk, part, tt, c, lane);
+    pair_item_any<T, COMP, TPL, UNROLL, false>(srcS, srcB, tg, tg64, N, M, nimg, y1, dx, dy, tiles_per_bnd,
+                                               row_groups, rows_per_chunk, part, tt, c, lane);
 }
 
 // Many problems in one persistent launch: the work items (target tile, source
@@ -430,7 +523,7 @@ __global__ __launch_bounds__(256) void k_allpairs_batched(const PairDesc *__rest
         const PairDesc &D = descs[inst];
         const int local = (int)(item - D.item0);
         const int tt = local % D.target_tiles, c = local / D.target_tiles;
-        pair_item_any<T, COMP, TPL, UNROLL>((const SrcRec<T> *)D.srcS, (const SrcRec<T> *)D.srcB,
+        pair_item_any<T, COMP, TPL, UNROLL, true>((const SrcRec<T> *)D.srcS, (const SrcRec<T> *)D.srcB,
                                             (const T *)D.tg, D.tg64, D.N, D.M, D.nimg, D.y1, D.dx, D.dy,
                                             D.tiles_per_bnd, D.row_groups, D.rows_per_chunk, D.part, tt, c, lane);
     }
