@@ -93,16 +93,22 @@ int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const dou
            double h, double *Jv, int prec, void *stream);
 
 /*
- * Launch shape of the all-pairs kernel (the sums of the boundary-integral rows):
+ * Launch shape of the all-pairs kernel (the sums of the boundary-integral rows).
+ * The source side (2 M source-row visits of N nodes each, both boundaries) is
+ * split into `chunks` contiguous, equal ranges of nodes (a range may start and
+ * end inside a row); every (target tile, chunk) pair is one wave.
  *   targets_per_lane: collocation rows handled by one lane (1 or 2);
  *   unroll:           unroll depth of the loop over source nodes (2, 4 or 8);
- *   rows_per_chunk:   source rows per workgroup chunk (split of the source
- *                     dimension across workgroups); <= 0 picks a default.
+ *   rows_per_chunk:   if chunks <= 0: chunks = ceil(2 M / rows_per_chunk);
+ *   chunks:           number of source chunks (> 0 overrides rows_per_chunk).
+ * With both <= 0 the library picks the chunk count that gives the launch about
+ * 24 waves per SIMD of the GPU (24576 waves).
  */
 typedef struct bim_pair_config {
     int32_t targets_per_lane;
     int32_t unroll;
     int32_t rows_per_chunk;
+    int32_t chunks;
 } bim_pair_config;
 
 /*

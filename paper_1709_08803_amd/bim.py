@@ -110,10 +110,10 @@ def _dptr(t: torch.Tensor) -> int:
 
 class PairConfig(ctypes.Structure):
     _fields_ = [("targets_per_lane", ctypes.c_int32), ("unroll", ctypes.c_int32),
-                ("rows_per_chunk", ctypes.c_int32)]
+                ("rows_per_chunk", ctypes.c_int32), ("chunks", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.targets_per_lane, self.unroll, self.rows_per_chunk)
+        return (self.targets_per_lane, self.unroll, self.rows_per_chunk, self.chunks)
 
 
 class JfnkOpts(ctypes.Structure):
@@ -191,7 +191,7 @@ def residual_timed(dp: DeviceProblem, u: torch.Tensor, prec="fp64", iters: int =
                    stream=None):
     """(all-pairs kernel ms, whole evaluation ms), averaged over `iters` evaluations (HIP events).
 
-    config: (targets_per_lane, unroll, rows_per_chunk) or None for the current choice.
+    config: (targets_per_lane, unroll, rows_per_chunk[, chunks]) or None for the current choice.
     """
     F = torch.empty_like(u)
     k, t = ctypes.c_double(), ctypes.c_double()
@@ -202,7 +202,7 @@ def residual_timed(dp: DeviceProblem, u: torch.Tensor, prec="fp64", iters: int =
 
 
 def tune_residual(dp: DeviceProblem, u: torch.Tensor, prec="fp64", stream=None):
-    """Run the in-library autotuner; returns ((tpl, unroll, rows_per_chunk), kernel ms)."""
+    """Run the in-library autotuner; returns ((tpl, unroll, rows_per_chunk, chunks), kernel ms)."""
     best, ms = PairConfig(), ctypes.c_double()
     _check(lib().bim_tune_residual(dp.ref(), _dptr(u), _PREC[prec], _stream(stream), ctypes.byref(best),
                                    ctypes.byref(ms)))

@@ -88,8 +88,7 @@ int bim_residual_timed(const bim_problem *prob, const double *u, double *F, int 
     if (iters < 1 || !kernel_ms || !total_ms) return fail(BIM_EINVAL, "iters >= 1 and result pointers required");
     hipStream_t s = (hipStream_t)stream;
     const Dims d(prob);
-    const PairLaunch pl = cfg ? pair_launch(d, cfg->targets_per_lane, cfg->unroll, cfg->rows_per_chunk)
-                              : pair_launch_for(prob, prec);
+    const PairLaunch pl = cfg ? pair_launch_cfg(d, prec, *cfg) : pair_launch_for(prob, prec);
     Scratch sc(s);
     if ((rc = sc.alloc(residual_work_bytes(d, pl)))) return rc;
     ResidualWork w;
@@ -154,12 +153,10 @@ int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const dou
 // ------------------------------------------------------------------ batched residual
 namespace bim {
 
-// Rows per chunk that give every work item about the same number of pairs
-// (~`pairs_target` source nodes per lane) across problems of different sizes.
-int balanced_rows_per_chunk(const Dims &d, int pairs_target) {
-    // one source-row visit covers nimg images of N nodes
-    const int per_row = d.nimg * d.N;
-    return std::max(1, std::min(2 * d.M, (pairs_target + per_row - 1) / per_row));
+int balanced_chunks(const Dims &d, int pairs_target) {
+    // a node of a source-row visit covers nimg images
+    const long pairs = (long)2 * d.M * d.N * d.nimg;
+    return (int)std::max(1L, (pairs + pairs_target - 1) / pairs_target);
 }
 
 }  // namespace bim
@@ -187,7 +184,7 @@ extern "C" int bim_residual_batched(const bim_problem *probs, int count, const d
     std::vector<size_t> offs(count);
     for (int i = 0; i < count; ++i) {
         const Dims d(&probs[i]);
-        pls[i] = pair_launch(d, ref.tpl, ref.unroll, balanced_rows_per_chunk(d, 6 * 181));
+        pls[i] = pair_launch(d, ref.tpl, ref.unroll, balanced_chunks(d, 6 * 181));
         offs[i] = total;
         total += (residual_work_bytes(d, pls[i]) + 255) & ~(size_t)255;
     }

@@ -46,7 +46,9 @@ struct alignas(8 * sizeof(T)) SrcRec {
 };
 
 // Launch shape of the all-pairs kernel: target tiles of 64 collocation points
-// on one mesh row, source rows split into chunks (split-K over sources).
+// on one mesh row; the source side (2 M source-row visits of N nodes, rows of
+// the two boundaries interleaved) split into `chunks` equal contiguous node
+// ranges (split-K over sources).  One wave per (target tile, chunk).
 struct PairLaunch {
     int tpl;             // collocation rows per lane (1 or 2)
     int unroll;          // inner-loop unroll over source nodes (2, 4 or 8)
@@ -54,19 +56,24 @@ struct PairLaunch {
     int tiles_per_bnd;   // ceil(row_groups (N-1) / 64): 64-lane tiles per boundary
     int target_tiles;    // 2 tiles_per_bnd
     int src_rows;        // 2 M source-row visits (both images of a row in one visit)
-    int rows_per_chunk;
-    int chunks;
+    int chunks;          // source chunks, 1 .. 2 M N
     int blocks;          // workgroups of 4 waves
 };
-// tpl/unroll outside the supported set fall back to 1/4; rows_per_chunk <= 0
-// splits the source rows so that the launch has about want_waves waves.
-PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk, long want_waves = 16384);
+// tpl/unroll outside the supported set fall back to 1/4; chunks is clamped to
+// [1, 2 M N].
+PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int chunks);
+// Launch for the config fields: chunks > 0 wins, else rows_per_chunk > 0,
+// else the default wave count (chunks_for_waves).
+PairLaunch pair_launch_cfg(const Dims &d, int prec, const bim_pair_config &cfg);
+// Chunks that give the launch about want_waves waves.
+int chunks_for_waves(const Dims &d, int tpl, int unroll, long want_waves);
 // The launch used by the public entry points: the autotuned choice for this
 // (mesh, precision) if bim_tune_residual has run, else the default.
 PairLaunch pair_launch_for(const bim_problem *p, int prec);
-// Source rows per chunk giving about pairs_target pairs per (collocation point,
-// chunk) work item; used to even out work items across the meshes of a batch.
-int balanced_rows_per_chunk(const Dims &d, int pairs_target);
+// Chunks giving every work item about pairs_target pairs per collocation
+// point (node ranges of pairs_target / nimg nodes), to even out work items
+// across the meshes of a batch.
+int balanced_chunks(const Dims &d, int pairs_target);
 
 // Spare source records after each record array (read, never used, by the
 // all-pairs prefetch at the end of a row).
@@ -82,7 +89,7 @@ struct PairDesc {
     double *part;
     int N, M, nimg;
     double y1, dx, dy;
-    int tiles_per_bnd, row_groups, target_tiles, chunks, rows_per_chunk;
+    int tiles_per_bnd, row_groups, target_tiles, chunks;
     long item0;  // index of this problem's first work item in the batch
 };
 

@@ -107,7 +107,7 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         const Dims d(&probs[i]);
         I[i].p = &probs[i];
         I[i].n = d.nvec;
-        I[i].pl = pair_launch(d, ref.tpl, ref.unroll, balanced_rows_per_chunk(d, 6 * 181));
+        I[i].pl = pair_launch(d, ref.tpl, ref.unroll, balanced_chunks(d, 6 * 181));
         off[i] = bytes;
         bytes += al256(residual_work_bytes(d, I[i].pl));
         const size_t vb = al256(sizeof(double) * d.nvec);

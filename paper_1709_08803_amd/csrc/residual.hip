@@ -339,7 +339,7 @@ template <typename T, bool COMP, int TPL, int UNROLL, int NI, bool CREC>
 __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
                                           const T *__restrict__ tg, const double *__restrict__ tg64, int N, int M,
                                           double y1, double dx, double dy, int tiles_per_bnd, int row_groups,
-                                          int rows_per_chunk, double *__restrict__ part, int tt, int c, int lane) {
+                                          int chunks, double *__restrict__ part, int tt, int c, int lane) {
     const RecPtr<T, CREC> recS = (RecPtr<T, CREC>)srcS, recB = (RecPtr<T, CREC>)srcB;
     const GlobalPtr<const T> gtg = (GlobalPtr<const T>)tg;
     const GlobalPtr<const double> gtg64 = (GlobalPtr<const double>)tg64;
@@ -368,10 +368,15 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
         ts[q].C = gtg[6 * T2 + tid];
         ts[q].sum = ts[q].comp = ts[q].s2sum = ts[q].s2comp = 0;
     }
-    const int r0 = c * rows_per_chunk;
-    const int r1 = min(2 * M, r0 + rows_per_chunk);
-    for (int r = r0; r < r1; ++r) {
-        const int ss = r & 1;  // interleave boundaries so every chunk mixes both
+    // chunk c: nodes [e0, e1) of the 2 M N source nodes in visit order (row r =
+    // 2 j + boundary, so that every chunk mixes both boundaries); a chunk may
+    // start and end inside a row.
+    const long nsrc = (long)2 * M * N;
+    const long e0 = (long)c * nsrc / chunks, e1 = (long)(c + 1) * nsrc / chunks;
+    for (int r = (int)(e0 / N); (long)r * N < e1; ++r) {
+        const int i0 = (int)max(e0 - (long)r * N, 0L);
+        const int i1 = (int)min(e1 - (long)r * N, (long)N);
+        const int ss = r & 1;
         const int j = r >> 1;
         const double yj = y1 + j * dy;
 #pragma unroll
@@ -389,7 +394,7 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
             ts[q].acc = 0;
             ts[q].acc2 = 0;
         }
-        const RecPtr<T, CREC> src = (ss ? recB : recS) + (size_t)j * N;
+        const RecPtr<T, CREC> src = (ss ? recB : recS) + (size_t)j * N + i0;
         auto seg_own = [&]() {
 #pragma unroll
             for (int q = 0; q < TPL; ++q) {
@@ -406,7 +411,7 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
             }
         };
         if (ss == st) {
-            walk_row<T, UNROLL, CREC>(src, N, [&](const SrcRec<T> &p) {
+            walk_row<T, UNROLL, CREC>(src, i1 - i0, [&](const SrcRec<T> &p) {
                 const T s = p.x - xs;
                 T nb0[TPL], coef[TPL], ri[TPL][NI], rq[TPL][NI];
 #pragma unroll
@@ -437,7 +442,7 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                 };
             }, seg_own);
         } else {
-            walk_row<T, UNROLL, CREC>(src, N, [&](const SrcRec<T> &p) {
+            walk_row<T, UNROLL, CREC>(src, i1 - i0, [&](const SrcRec<T> &p) {
                 const T s = p.x - xs;
                 T nb0[TPL], ri[TPL][NI];
 #pragma unroll
@@ -482,14 +487,14 @@ template <typename T, bool COMP, int TPL, int UNROLL, bool CREC>
 __device__ __forceinline__ void pair_item_any(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
                                               const T *__restrict__ tg, const double *__restrict__ tg64, int N,
                                               int M, int nimg, double y1, double dx, double dy, int tiles_per_bnd,
-                                              int row_groups, int rows_per_chunk, double *__restrict__ part, int tt,
+                                              int row_groups, int chunks, double *__restrict__ part, int tt,
                                               int c, int lane) {
     if (nimg == 2)
         pair_item<T, COMP, TPL, UNROLL, 2, CREC>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
-                                           rows_per_chunk, part, tt, c, lane);
+                                                 chunks, part, tt, c, lane);
     else
         pair_item<T, COMP, TPL, UNROLL, 1, CREC>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
-                                           rows_per_chunk, part, tt, c, lane);
+                                                 chunks, part, tt, c, lane);
 }
 
 // Single problem: one wave per (target tile, source chunk).
@@ -497,7 +502,7 @@ template <typename T, bool COMP, int TPL, int UNROLL>
 __global__ __launch_bounds__(256) void k_allpairs(
     const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB, const T *__restrict__ tg,
     const double *__restrict__ tg64, int N, int M, int nimg, double y1, double dx, double dy, int tiles_per_bnd,
-    int row_groups, int target_tiles, int chunks, int rows_per_chunk, double *__restrict__ part) {
+    int row_groups, int target_tiles, int chunks, double *__restrict__ part) {
     const int lane = threadIdx.x & 63;
     // the wave index is uniform: keep it (and everything derived) in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -505,7 +510,7 @@ __global__ __launch_bounds__(256) void k_allpairs(
     const int tt = g % target_tiles, c = g / target_tiles;
     if (c >= chunks) return;
     pair_item_any<T, COMP, TPL, UNROLL, false>(srcS, srcB, tg, tg64, N, M, nimg, y1, dx, dy, tiles_per_bnd,
-                                               row_groups, rows_per_chunk, part, tt, c, lane);
+                                               row_groups, chunks, part, tt, c, lane);
 }
 
 // Many problems in one persistent launch: the work items (target tile, source
@@ -525,7 +530,7 @@ __global__ __launch_bounds__(256) void k_allpairs_batched(const PairDesc *__rest
         const int tt = local % D.target_tiles, c = local / D.target_tiles;
         pair_item_any<T, COMP, TPL, UNROLL, true>((const SrcRec<T> *)D.srcS, (const SrcRec<T> *)D.srcB,
                                             (const T *)D.tg, D.tg64, D.N, D.M, D.nimg, D.y1, D.dx, D.dy,
-                                            D.tiles_per_bnd, D.row_groups, D.rows_per_chunk, D.part, tt, c, lane);
+                                            D.tiles_per_bnd, D.row_groups, D.chunks, D.part, tt, c, lane);
     }
 }
 
@@ -606,7 +611,7 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
-PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk, long want_waves) {
+PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int chunks) {
     PairLaunch pl;
     pl.tpl = (tpl == 2) ? 2 : 1;
     pl.unroll = (unroll == 2 || unroll == 8) ? unroll : 4;
@@ -614,17 +619,25 @@ PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int rows_per_chunk, l
     pl.tiles_per_bnd = cdiv(pl.row_groups * (d.N - 1), 64);
     pl.target_tiles = 2 * pl.tiles_per_bnd;
     pl.src_rows = 2 * d.M;
-    int rpc = rows_per_chunk;
-    if (rpc <= 0) {
-        // many waves per SIMD (1024 SIMDs) so the last round of waves is a small tail
-        int chunks = std::max(1, std::min(pl.src_rows, cdiv(want_waves, pl.target_tiles)));
-        rpc = cdiv(pl.src_rows, chunks);
-    }
-    rpc = std::max(1, std::min(rpc, pl.src_rows));
-    pl.rows_per_chunk = rpc;
-    pl.chunks = cdiv(pl.src_rows, rpc);
+    pl.chunks = (int)std::max(1L, std::min((long)chunks, (long)pl.src_rows * d.N));
     pl.blocks = cdiv((long)pl.target_tiles * pl.chunks, 4);
     return pl;
+}
+
+int chunks_for_waves(const Dims &d, int tpl, int unroll, long want_waves) {
+    const PairLaunch base = pair_launch(d, tpl, unroll, 1);
+    return (int)std::max(1L, (want_waves + base.target_tiles / 2) / base.target_tiles);
+}
+
+PairLaunch pair_launch_cfg(const Dims &d, int prec, const bim_pair_config &cfg) {
+    (void)prec;
+    int chunks = cfg.chunks;
+    if (chunks <= 0 && cfg.rows_per_chunk > 0) chunks = cdiv(2 * d.M, cfg.rows_per_chunk);
+    // default: about 24 waves per SIMD (1024 SIMDs), the best count measured at
+    // 181 x 61 for both precisions (fewer waves hide less latency; many more
+    // only add partial sums)
+    if (chunks <= 0) chunks = chunks_for_waves(d, cfg.targets_per_lane, cfg.unroll, 24576);
+    return pair_launch(d, cfg.targets_per_lane, cfg.unroll, chunks);
 }
 
 size_t residual_work_bytes(const Dims &d, const PairLaunch &pl) {
@@ -678,7 +691,7 @@ int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
     hipLaunchKernelGGL((k_allpairs<T, COMP, TPL, UNR>), dim3(pl.blocks), dim3(256), 0, s,               \
                        (const SrcRec<T> *)w.srcS, (const SrcRec<T> *)w.srcB, TG, w.tg, N, M, d.nimg,    \
                        p->y1, p->dx, p->dy, pl.tiles_per_bnd, pl.row_groups, pl.target_tiles, pl.chunks, \
-                       pl.rows_per_chunk, w.part)
+                       w.part)
     const int vsel = (pl.tpl == 2 ? 3 : 0) + (pl.unroll == 2 ? 0 : pl.unroll == 4 ? 1 : 2);
     if (prec == BIM_FP64) {
         switch (vsel) {
@@ -750,7 +763,6 @@ int residual_batched_enqueue(const bim_problem *probs, int count, const double *
         D.row_groups = pl.row_groups;
         D.target_tiles = pl.target_tiles;
         D.chunks = pl.chunks;
-        D.rows_per_chunk = pl.rows_per_chunk;
         D.item0 = total;
         total += (long)pl.target_tiles * pl.chunks;
     }

@@ -22,13 +22,12 @@ PairLaunch pair_launch_for(const bim_problem *p, int prec) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_best.find(Key(p->N, p->M, p->half_domain ? 1 : 0, prec));
-        if (it != g_best.end())
-            return pair_launch(d, it->second.targets_per_lane, it->second.unroll, it->second.rows_per_chunk);
+        if (it != g_best.end()) return pair_launch_cfg(d, prec, it->second);
     }
     // untuned defaults: the fastest shapes measured at 181 x 61 (FP64: 4-way
-    // unroll, ~16 waves per SIMD; FP32C: 2-way unroll, ~24 waves per SIMD)
-    if (prec == BIM_FP32C) return pair_launch(d, 1, 2, 0, 24576);
-    return pair_launch(d, 1, 4, 0, 16384);
+    // unroll; FP32C: 2-way unroll; about 24 waves per SIMD)
+    const bim_pair_config def = {1, prec == BIM_FP32C ? 2 : 4, 0, 0};
+    return pair_launch_cfg(d, prec, def);
 }
 
 }  // namespace bim
@@ -45,19 +44,16 @@ extern "C" int bim_tune_residual(const bim_problem *prob, const double *u, int p
     hipStream_t s = (hipStream_t)stream;
     double *F = nullptr;
     if ((rc = hip_check(hipMallocAsync((void **)&F, sizeof(double) * d.nvec, s), "hipMallocAsync"))) return rc;
+    // every variant at chunk counts giving 8 to 48 waves per SIMD (1024 SIMDs)
     std::vector<bim_pair_config> cands;
-    const int src_rows = 2 * d.M;
     for (int tpl : {1, 2})
         for (int unr : {2, 4, 8})
-            for (long want : {8192L, 16384L, 32768L}) {
-                const PairLaunch base = pair_launch(d, tpl, unr, 1);
-                const long tiles = base.target_tiles;
-                int chunks = (int)std::max(1L, std::min((long)src_rows, (want + tiles - 1) / tiles));
-                int rpc = (src_rows + chunks - 1) / chunks;
-                bim_pair_config c{tpl, unr, rpc};
+            for (long want : {8192L, 16384L, 24576L, 32768L, 49152L}) {
+                const int chunks = pair_launch(d, tpl, unr, chunks_for_waves(d, tpl, unr, want)).chunks;
+                bim_pair_config c{tpl, unr, 0, chunks};
                 bool dup = false;
                 for (auto &o : cands)
-                    dup |= (o.targets_per_lane == tpl && o.unroll == unr && o.rows_per_chunk == rpc);
+                    dup |= (o.targets_per_lane == tpl && o.unroll == unr && o.chunks == chunks);
                 if (!dup) cands.push_back(c);
             }
     bim_pair_config pick = cands[0];

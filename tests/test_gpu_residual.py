@@ -154,6 +154,9 @@ def test_jv_default_shift_and_zero_direction(bim):
 
 
 VARIANTS = [(tpl, unr, rpc) for tpl in (1, 2) for unr in (2, 4, 8) for rpc in (1, 3)]
+# explicit chunk counts at 45 x 9 (2 M N = 810 source nodes): ranges that start
+# and end inside rows, down to one node per chunk, and one chunk for everything
+VARIANTS += [(1, 2, 0, 7), (2, 4, 0, 13), (1, 8, 0, 50), (1, 4, 0, 810), (2, 2, 0, 1), (1, 4, 0, 0), (2, 8, 0, 0)]
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 5e-7)])
