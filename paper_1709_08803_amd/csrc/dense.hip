@@ -104,30 +104,51 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
             }
 }
 
-// In-place Gauss-Jordan inversion with partial pivoting of one s x s block
-// (s <= 192) per 512-thread workgroup, with the matrix held in registers:
-// wave ty (= tid / 64, uniform in the wave) owns rows ty + 8 i (i < 24) and lane
-// tx columns tx + 64 j (j < 3).  Step k: the owners of column k find the pivot
-// row p, rows k and p and column k are staged in LDS, row p takes the old row
-// k, every row r then loses f_r times the scaled pivot row (its column-k entry
-// starting from 0), and row k becomes the scaled pivot row with A[k][k]
-// replaced by 1.  Row decisions depend only on the wave, so they are scalar
-// branches; the element update is a multiply and an FMA.  The row interchanges
-// are undone as column interchanges, in reverse order, when the result is
-// written.
+// In-place Gauss-Jordan inversion of one s x s block (s <= 192) per 512-thread
+// workgroup, with the matrix held in registers: wave ty (= tid / 64, uniform in
+// the wave) owns rows ty + 8 i (i < 24) and lane tx columns tx + 64 j (j < 3).
+// Rows are eliminated in their natural order k = 0 .. s-1 with partial
+// pivoting over the columns (the pivot of row k is its largest entry among the
+// columns not yet used: partial pivoting of the transpose), so that the row
+// being eliminated is known to every wave, and the pivot column q is read out
+// of lane q % 64 with wave-uniform lane reads.  A column that has served as a
+// pivot column is kept in its own scale: its true values are the stored ones
+// times sc[q] = -1/p (row operations commute with column scaling), so that
+// no step has to rescale it.  Step k:
+//   wave k % 8 (row k is its register row k / 8) finds q and stages row k,
+//   scaled by 1/p and with 0 at column q, in LDS;
+//   every row r: a[r][c] -= a[r][q] * rowk[c] (column q keeps a[r][q], which
+//   is its new value -a[r][q]/p in the scale sc[q]);
+//   row k becomes the staged row with -1 (= 1/p in that scale) at column q.
+// After s steps the registers hold the inverse with rows and columns permuted
+// by the pivot columns, storage[r][q_c] sc[q_c] = inverse[q_r][c]; the
+// write-out applies the scales and undoes the permutation.  Only the owner
+// wave indexes its registers by k / 8 (a switch); the update of all rows uses
+// constant register indices.
 constexpr int kRegTy = 8, kRegRows = 24, kRegCols = 3;
 constexpr int kRegThreads = 64 * kRegTy;
 constexpr int kRegMaxS = kRegTy * kRegRows;  // = 64 kRegCols = 192
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+#define BIM_ROW_CASES(X)                                                                                        \
+    X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) \
+        X(19) X(20) X(21) X(22) X(23)
+
 __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__restrict__ items, int s,
                                                             int *__restrict__ info) {
+    static_assert(kRegRows == 24, "BIM_ROW_CASES lists 24 register rows");
     const InvItem it = items[blockIdx.x];
     const int tx = threadIdx.x & 63;
     const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    __shared__ double rowk[kRegMaxS], rowp[kRegMaxS], fac[kRegMaxS];
-    __shared__ double redv[kRegTy];
-    __shared__ int redi[kRegTy];
-    __shared__ int ipiv[kRegMaxS], dst[kRegMaxS];
+    __shared__ double rowk[kRegMaxS], sc[kRegMaxS];
+    __shared__ int qcol[kRegMaxS], qinv[kRegMaxS];
+    __shared__ int s_bad;
     double a[kRegRows][kRegCols];
 #pragma unroll
     for (int i = 0; i < kRegRows; ++i)
@@ -136,135 +157,115 @@ __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__res
             const int r = ty + kRegTy * i, c = tx + 64 * j;
             a[i][j] = (r < s && c < s) ? it.A[(size_t)r * it.lda + c] : 0.0;
         }
-    for (int e = threadIdx.x; e < kRegMaxS; e += kRegThreads) rowk[e] = rowp[e] = fac[e] = 0.0;
+    unsigned used = 0;  // bit j: column tx + 64 j is a pivot column already (or lies beyond s)
+#pragma unroll
+    for (int j = 0; j < kRegCols; ++j)
+        if (tx + 64 * j >= s) used |= 1u << j;
+    if (threadIdx.x == 0) s_bad = 0;
+    for (int c = threadIdx.x; c < kRegMaxS; c += kRegThreads) sc[c] = 1.0;
     __syncthreads();
-    int bad = 0;
     for (int k = 0; k < s; ++k) {
-        const int jk = k >> 6, tk = k & 63;
-        // pivot candidates of column k, one per wave
-        if (tx == tk) {
+        const int w = k & (kRegTy - 1), ik = k / kRegTy;
+        if (ty == w) {  // owner of row k: pivot column and the staged row
+            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+            switch (ik) {
+#define BIM_GET(I)      \
+    case I:             \
+        r0 = a[I][0];   \
+        r1 = a[I][1];   \
+        r2 = a[I][2];   \
+        break;
+                BIM_ROW_CASES(BIM_GET)
+#undef BIM_GET
+            }
             double bv = -1.0;
-            int bi = k;
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i) {
-                const int r = ty + kRegTy * i;
-                const double v = fabs(jk == 0 ? a[i][0] : (jk == 1 ? a[i][1] : a[i][2]));
-                if (r >= k && r < s && v > bv) {
-                    bv = v;
-                    bi = r;
+            int bc = 0x7fffffff;
+            if (!(used & 1u) && fabs(r0) > bv) {
+                bv = fabs(r0);
+                bc = tx;
+            }
+            if (!(used & 2u) && fabs(r1) > bv) {
+                bv = fabs(r1);
+                bc = tx + 64;
+            }
+            if (!(used & 4u) && fabs(r2) > bv) {
+                bv = fabs(r2);
+                bc = tx + 128;
+            }
+            for (int off = 32; off >= 1; off >>= 1) {  // largest, lowest column on ties
+                const double ov = __shfl_xor(bv, off, 64);
+                const int oc = __shfl_xor(bc, off, 64);
+                if (ov > bv || (ov == bv && oc < bc)) {
+                    bv = ov;
+                    bc = oc;
                 }
             }
-            redv[ty] = bv;
-            redi[ty] = bi;
-            // column k before the interchange
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i) {
-                const int r = ty + kRegTy * i;
-                if (r < s) fac[r] = (jk == 0 ? a[i][0] : (jk == 1 ? a[i][1] : a[i][2]));
+            const int q = __builtin_amdgcn_readfirstlane(bc);
+            const double best = readlane_f64(bv, 0);
+            const bool ok = best > 0.0 && best <= 1.79e308 && q < s;
+            const int jq = ok ? (q >> 6) : 0, lq = ok ? (q & 63) : 0;
+            const double piv = readlane_f64(jq == 0 ? r0 : (jq == 1 ? r1 : r2), lq);
+            const double pinv = 1.0 / piv;
+            rowk[tx] = (tx == q) ? 0.0 : r0 * pinv;
+            rowk[tx + 64] = (tx + 64 == q) ? 0.0 : r1 * pinv;
+            rowk[tx + 128] = (tx + 128 == q) ? 0.0 : r2 * pinv;
+            if (tx == 0) {
+                qcol[k] = ok ? q : 0;
+                sc[ok ? q : 0] = -pinv;
+                if (!ok) s_bad = k + 1;
             }
-        }
-        // row k before the interchange
-        if (ty == k % kRegTy) {
-            const int ir = k / kRegTy;
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i)
-                if (i == ir) {
-#pragma unroll
-                    for (int j = 0; j < kRegCols; ++j) {
-                        const int c = tx + 64 * j;
-                        if (c < s) rowk[c] = a[i][j];
-                    }
-                }
         }
         __syncthreads();
-        // every thread reduces the candidates in the same order (uniform result)
-        double pv = -1.0;
-        int p = k;
-        for (int t = 0; t < kRegTy; ++t) {
-            const double v = redv[t];
-            const int q = redi[t];
-            if (v > pv || (v == pv && q < p)) {
-                pv = v;
-                p = q;
+        if (s_bad) break;
+        const int q = __builtin_amdgcn_readfirstlane(qcol[k]);
+        const int jq = q >> 6, lq = q & 63;
+        const double p0 = rowk[tx], p1 = rowk[tx + 64], p2 = rowk[tx + 128];
+        if (tx == lq) used |= 1u << jq;
+        // factors a[r][q] of this wave's rows, from lane lq (wave-uniform)
+        double f[kRegRows];
+        if (jq == 0) {
+#pragma unroll
+            for (int r = 0; r < kRegRows; ++r) f[r] = readlane_f64(a[r][0], lq);
+        } else if (jq == 1) {
+#pragma unroll
+            for (int r = 0; r < kRegRows; ++r) f[r] = readlane_f64(a[r][1], lq);
+        } else {
+#pragma unroll
+            for (int r = 0; r < kRegRows; ++r) f[r] = readlane_f64(a[r][2], lq);
+        }
+#pragma unroll
+        for (int r = 0; r < kRegRows; ++r) {
+            a[r][0] = fma(-f[r], p0, a[r][0]);
+            a[r][1] = fma(-f[r], p1, a[r][1]);
+            a[r][2] = fma(-f[r], p2, a[r][2]);
+        }
+        if (ty == w) {  // row k: the staged row, -1 (1/p in the column's scale) at column q
+            const double n0 = (tx == q) ? -1.0 : p0, n1 = (tx + 64 == q) ? -1.0 : p1,
+                         n2 = (tx + 128 == q) ? -1.0 : p2;
+            switch (ik) {
+#define BIM_SET(I)      \
+    case I:             \
+        a[I][0] = n0;   \
+        a[I][1] = n1;   \
+        a[I][2] = n2;   \
+        break;
+                BIM_ROW_CASES(BIM_SET)
+#undef BIM_SET
             }
         }
-        p = __builtin_amdgcn_readfirstlane(p);
-        if (!(pv > 0.0) || !isfinite(pv)) {
-            bad = k + 1;
-            break;
-        }
-        const int ip = p / kRegTy;
-        if (ty == p % kRegTy) {
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i)
-                if (i == ip) {
-#pragma unroll
-                    for (int j = 0; j < kRegCols; ++j) {
-                        const int c = tx + 64 * j;
-                        if (c < s) rowp[c] = a[i][j];
-                    }
-                }
-        }
-        if (threadIdx.x == 0) ipiv[k] = p;
-        __syncthreads();
-        const double pivinv = 1.0 / rowp[k];
-        const double fk = fac[k];
-        double pc[kRegCols], z[kRegCols];
-#pragma unroll
-        for (int j = 0; j < kRegCols; ++j) {
-            const int c = tx + 64 * j;
-            pc[j] = ((c == k) ? 1.0 : rowp[c]) * pivinv;
-            z[j] = (c == k) ? 0.0 : 1.0;
-        }
-        // row p takes the old row k (a no-op when p = k)
-        if (ty == p % kRegTy) {
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i)
-                if (i == ip) {
-#pragma unroll
-                    for (int j = 0; j < kRegCols; ++j) a[i][j] = rowk[tx + 64 * j];
-                }
-        }
-#pragma unroll
-        for (int i = 0; i < kRegRows; ++i) {
-            const int r = ty + kRegTy * i;
-            const double f = (r == p) ? fk : fac[r];
-#pragma unroll
-            for (int j = 0; j < kRegCols; ++j) a[i][j] = fma(-f, pc[j], a[i][j] * z[j]);
-        }
-        // row k becomes the scaled pivot row
-        if (ty == k % kRegTy) {
-            const int ir = k / kRegTy;
-#pragma unroll
-            for (int i = 0; i < kRegRows; ++i)
-                if (i == ir) {
-#pragma unroll
-                    for (int j = 0; j < kRegCols; ++j) a[i][j] = pc[j];
-                }
-        }
-        __syncthreads();  // LDS rows are rewritten by the next step
+        __syncthreads();  // rowk is rewritten by the next step
     }
-    if (threadIdx.x == 0 && info) info[blockIdx.x] = bad;
-    if (bad) return;
-    // column interchanges in reverse order: output column dst[c] holds column c
-    if (threadIdx.x == 0) {
-        for (int c = 0; c < s; ++c) dst[c] = c;  // src[c]: which column lands in output column c
-        for (int k = s - 1; k >= 0; --k) {
-            const int q = ipiv[k];
-            const int t = dst[k];
-            dst[k] = dst[q];
-            dst[q] = t;
-        }
-        for (int c = 0; c < s; ++c) rowk[dst[c]] = (double)c;  // inverse permutation
-        for (int c = 0; c < s; ++c) dst[c] = (int)rowk[c];
-    }
+#undef BIM_ROW_CASES
+    if (threadIdx.x == 0 && info) info[blockIdx.x] = s_bad;
+    if (s_bad) return;
+    for (int c = threadIdx.x; c < s; c += kRegThreads) qinv[qcol[c]] = c;
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kRegRows; ++i)
 #pragma unroll
         for (int j = 0; j < kRegCols; ++j) {
             const int r = ty + kRegTy * i, c = tx + 64 * j;
-            if (r < s && c < s) it.Ainv[(size_t)r * it.ldinv + dst[c]] = a[i][j];
+            if (r < s && c < s) it.Ainv[(size_t)qcol[r] * it.ldinv + qinv[c]] = a[i][j] * sc[c];
         }
 }
 
