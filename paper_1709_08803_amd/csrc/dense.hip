@@ -115,8 +115,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
 // pivot column is kept in its own scale: its true values are the stored ones
 // times sc[q] = -1/p (row operations commute with column scaling), so that
 // no step has to rescale it.  Step k:
-//   wave k % 8 (row k is its register row k / 8) finds q and stages row k,
-//   scaled by 1/p and with 0 at column q, in LDS;
+//   wave k % 8 (row k is its register row k / 8) finds q (a DPP maximum of
+//   packed pivot keys) and stages row k, scaled by 1/p and with 0 at column q,
+//   in one of two LDS buffers (one barrier per step);
 //   every row r: a[r][c] -= a[r][q] * rowk[c] (column q keeps a[r][q], which
 //   is its new value -a[r][q]/p in the scale sc[q]);
 //   row k becomes the staged row with -1 (= 1/p in that scale) at column q.
@@ -128,6 +129,27 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
 constexpr int kRegTy = 8, kRegRows = 24, kRegCols = 3;
 constexpr int kRegThreads = 64 * kRegTy;
 constexpr int kRegMaxS = kRegTy * kRegRows;  // = 64 kRegCols = 192
+
+// Largest value over the wave (unsigned): DPP shifts within rows of 16 lanes,
+// then the row broadcasts of lanes 15 and 31; lane 63 ends with the maximum.
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Pivot key of column c with value v: the upper 24 bits of the upper word of
+// |v| (a non-negative double orders like its bit pattern; 12 mantissa bits
+// are ample to choose a pivot), then 255 - c, so that ties go to the lowest
+// column.  Columns already used (or beyond s) have key 0.
+__device__ __forceinline__ unsigned pivot_key(double v, int c, bool usable) {
+    const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(fabs(v)) >> 32);
+    return usable ? ((hi & 0xffffff00u) | (unsigned)(255 - c)) : 0u;
+}
 
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -146,7 +168,7 @@ __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__res
     const InvItem it = items[blockIdx.x];
     const int tx = threadIdx.x & 63;
     const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    __shared__ double rowk[kRegMaxS], sc[kRegMaxS];
+    __shared__ double rowk[2][kRegMaxS], sc[kRegMaxS];
     __shared__ int qcol[kRegMaxS], qinv[kRegMaxS];
     __shared__ int s_bad;
     double a[kRegRows][kRegCols];
@@ -178,37 +200,19 @@ __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__res
                 BIM_ROW_CASES(BIM_GET)
 #undef BIM_GET
             }
-            double bv = -1.0;
-            int bc = 0x7fffffff;
-            if (!(used & 1u) && fabs(r0) > bv) {
-                bv = fabs(r0);
-                bc = tx;
-            }
-            if (!(used & 2u) && fabs(r1) > bv) {
-                bv = fabs(r1);
-                bc = tx + 64;
-            }
-            if (!(used & 4u) && fabs(r2) > bv) {
-                bv = fabs(r2);
-                bc = tx + 128;
-            }
-            for (int off = 32; off >= 1; off >>= 1) {  // largest, lowest column on ties
-                const double ov = __shfl_xor(bv, off, 64);
-                const int oc = __shfl_xor(bc, off, 64);
-                if (ov > bv || (ov == bv && oc < bc)) {
-                    bv = ov;
-                    bc = oc;
-                }
-            }
-            const int q = __builtin_amdgcn_readfirstlane(bc);
-            const double best = readlane_f64(bv, 0);
-            const bool ok = best > 0.0 && best <= 1.79e308 && q < s;
-            const int jq = ok ? (q >> 6) : 0, lq = ok ? (q & 63) : 0;
+            unsigned key = pivot_key(r0, tx, !(used & 1u));
+            key = max(key, pivot_key(r1, tx + 64, !(used & 2u)));
+            key = max(key, pivot_key(r2, tx + 128, !(used & 4u)));
+            const int q = 255 - (int)(wave_max_u32(key) & 0xffu);
+            const bool inrange = q >= 0 && q < s;
+            const int jq = inrange ? (q >> 6) : 0, lq = inrange ? (q & 63) : 0;
             const double piv = readlane_f64(jq == 0 ? r0 : (jq == 1 ? r1 : r2), lq);
+            const bool ok = inrange && fabs(piv) > 0.0 && fabs(piv) <= 1.79e308;
             const double pinv = 1.0 / piv;
-            rowk[tx] = (tx == q) ? 0.0 : r0 * pinv;
-            rowk[tx + 64] = (tx + 64 == q) ? 0.0 : r1 * pinv;
-            rowk[tx + 128] = (tx + 128 == q) ? 0.0 : r2 * pinv;
+            double *rk = rowk[k & 1];
+            rk[tx] = (tx == q) ? 0.0 : r0 * pinv;
+            rk[tx + 64] = (tx + 64 == q) ? 0.0 : r1 * pinv;
+            rk[tx + 128] = (tx + 128 == q) ? 0.0 : r2 * pinv;
             if (tx == 0) {
                 qcol[k] = ok ? q : 0;
                 sc[ok ? q : 0] = -pinv;
@@ -219,7 +223,8 @@ __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__res
         if (s_bad) break;
         const int q = __builtin_amdgcn_readfirstlane(qcol[k]);
         const int jq = q >> 6, lq = q & 63;
-        const double p0 = rowk[tx], p1 = rowk[tx + 64], p2 = rowk[tx + 128];
+        const double *rk = rowk[k & 1];
+        const double p0 = rk[tx], p1 = rk[tx + 64], p2 = rk[tx + 128];
         if (tx == lq) used |= 1u << jq;
         // factors a[r][q] of this wave's rows, from lane lq (wave-uniform)
         double f[kRegRows];
@@ -253,8 +258,11 @@ __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__res
 #undef BIM_SET
             }
         }
-        __syncthreads();  // rowk is rewritten by the next step
+        // no barrier here: the next step stages its row in the other buffer, and
+        // this buffer is rewritten only after every wave has passed the next
+        // step's barrier, i.e. has finished this step
     }
+    __syncthreads();
 #undef BIM_ROW_CASES
     if (threadIdx.x == 0 && info) info[blockIdx.x] = s_bad;
     if (s_bad) return;
