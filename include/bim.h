@@ -102,7 +102,7 @@ int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const dou
  *   rows_per_chunk:   if chunks <= 0: chunks = ceil(2 M / rows_per_chunk);
  *   chunks:           number of source chunks (> 0 overrides rows_per_chunk).
  * With both <= 0 the library picks the chunk count that gives the launch about
- * 24 waves per SIMD of the GPU (24576 waves).
+ * 24 (FP64) or 32 (FP32C) waves per SIMD of the GPU (24576 or 32768 waves).
  */
 typedef struct bim_pair_config {
     int32_t targets_per_lane;

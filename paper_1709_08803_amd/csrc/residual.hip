@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "bim_common.h"
@@ -238,56 +239,49 @@ __device__ __forceinline__ SrcRec<T> load_rec(RecPtr<T, CREC> p) {
 // values read there are never used).
 // FP64 records (two scalar loads of 16 dwords per pair of records) gain
 // nothing from it (measured), so they keep the plain loop.
-// The FP32 walk also calls seg() after every kSeg records, where the running
-// FP32 partial sums are folded into the compensated sums.
-// body(p) does the first part of record p's work (distances and every
+// body(p, slot) does the first part of record p's work (distances and every
 // reciprocal square root) and returns the rest (the accumulations) as a
 // closure; a group runs every record's first part before any second part, so
 // the independent rsq of the group are issued ahead of their uses (second
-// parts in reverse record order).
-constexpr int kSeg = 32;
+// parts in reverse record order).  slot (a compile-time constant: the record's
+// position in the group, mod 2) picks one of two FP32 running sums, so that
+// each sums half of the row's terms.
+// The FP32 walk is one loop: any fold of the running sums inside a row piece
+// (a branch per segment, or a loop nest per segment) measured 6 - 12% slower.
 template <int U, int K = 0, typename Body, typename Rec>
 __device__ __forceinline__ void run_group(Body &body, const Rec *cur) {
     if constexpr (K < U) {
-        auto rest = body(cur[K]);
+        auto rest = body(cur[K], std::integral_constant<int, K % 2>{});
         run_group<U, K + 1>(body, cur);
         rest();
     }
 }
-template <typename T, int UNROLL, bool CREC, typename Body, typename Seg>
-__device__ __forceinline__ void walk_row(RecPtr<T, CREC> src, int N, Body &&body, Seg &&seg) {
+template <typename T, int UNROLL, bool CREC, typename Body>
+__device__ __forceinline__ void walk_row(RecPtr<T, CREC> src, int N, Body &&body) {
     static_assert(UNROLL <= kRecPad, "prefetch beyond the record padding");
-    static_assert(kSeg % 8 == 0, "segments hold whole groups of every unroll");
     if constexpr (sizeof(T) == 8) {
 #pragma unroll UNROLL
-        for (int i = 0; i < N; ++i) body(load_rec<T, CREC>(src + i))();
+        for (int i = 0; i < N; ++i) body(load_rec<T, CREC>(src + i), std::integral_constant<int, 0>{})();
         return;
     }
     const int full = N - N % UNROLL;
     SrcRec<T> cur[UNROLL];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) cur[u] = load_rec<T, CREC>(src + u);
-    // The fold sits outside the pipelined loop: a branch inside it splits the
-    // loop body, and the compiler then sinks the next group's loads into the
-    // latch, right in front of their wait.
-    for (int s0 = 0; s0 < full; s0 += kSeg) {
-        const int s1 = min(s0 + kSeg, full);
-        for (int i0 = s0; i0 < s1; i0 += UNROLL) {
-            SrcRec<T> nxt[UNROLL];
+    for (int i0 = 0; i0 < full; i0 += UNROLL) {
+        SrcRec<T> nxt[UNROLL];
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) nxt[u] = load_rec<T, CREC>(src + i0 + UNROLL + u);
-            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
-            run_group<UNROLL>(body, cur);
+        for (int u = 0; u < UNROLL; ++u) nxt[u] = load_rec<T, CREC>(src + i0 + UNROLL + u);
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the arithmetic
+        run_group<UNROLL>(body, cur);
 #pragma unroll
-            for (int u = 0; u < UNROLL; ++u) cur[u] = nxt[u];
-        }
-        seg();
+        for (int u = 0; u < UNROLL; ++u) cur[u] = nxt[u];
     }
     // the tail indexes cur[] with constants only (a runtime index would put the
     // array in private memory)
 #pragma unroll
     for (int u = 0; u < UNROLL - 1; ++u)
-        if (u < N - full) body(cur[u])();
+        if (u < N - full) body(cur[u], std::integral_constant<int, 0>{})();
 }
 
 // One wave = 64 collocation points of one boundary: consecutive entries of
@@ -303,32 +297,39 @@ __device__ __forceinline__ void walk_row(RecPtr<T, CREC> src, int N, Body &&body
 //   own boundary:   w (D - D*) K1 + w sigma K2  and  w S2   (two rsqrt)
 //   other boundary: w D K1 + w sigma K2                      (one rsqrt)
 // written as  ri (coef num ri^2 + w sigma)  with ri = 1/R.
-// FP32C: FP32 sums over segments of kSeg nodes of a source row, combined with
-// Neumaier's compensated summation; the chunk result is written in FP64.
+// FP32C: two FP32 running sums per row piece (alternate nodes), combined across
+// pieces with Neumaier's compensated summation; the chunk result is written in
+// FP64.
 template <typename T, int NI>
 struct TargetState {
     double ys;                                   // y* (FP64, physical units)
     T d, Dst, A, B, C;                           // collocation data
     T t[NI], ti[NI], t2[NI], Bt[NI], Ct2[NI];    // per source row and image
-    T acc, acc2;                                 // per source row sums
+    T acc[2], acc2[2];                           // per source row piece (two running sums each)
     T sum, comp, s2sum, s2comp;                  // across rows
 };
 
-// S2: the row also carries the S2 sum (only rows of the target's own boundary).
+// Folds the running sums of a row piece into the across-row sums (Neumaier's
+// compensated summation in FP32C).  S2: the piece also carries the S2 sum (only
+// rows of the target's own boundary).
+template <typename T>
+__device__ __forceinline__ void neumaier_add(T &sum, T &comp, T x) {
+    const T t = sum + x;
+    comp += (fabs(sum) >= fabs(x)) ? ((sum - t) + x) : ((x - t) + sum);
+    sum = t;
+}
 template <typename T, bool COMP, int NI, bool S2 = true>
 __device__ __forceinline__ void row_end(TargetState<T, NI> &g) {
     if (COMP) {
-        T tsum = g.sum + g.acc;
-        g.comp += (fabs(g.sum) >= fabs(g.acc)) ? ((g.sum - tsum) + g.acc) : ((g.acc - tsum) + g.sum);
-        g.sum = tsum;
+        neumaier_add(g.sum, g.comp, g.acc[0]);
+        neumaier_add(g.sum, g.comp, g.acc[1]);
         if (S2) {
-            T tq = g.s2sum + g.acc2;
-            g.s2comp += (fabs(g.s2sum) >= fabs(g.acc2)) ? ((g.s2sum - tq) + g.acc2) : ((g.acc2 - tq) + g.s2sum);
-            g.s2sum = tq;
+            neumaier_add(g.s2sum, g.s2comp, g.acc2[0]);
+            neumaier_add(g.s2sum, g.s2comp, g.acc2[1]);
         }
-    } else {
-        g.sum += g.acc;
-        if (S2) g.s2sum += g.acc2;
+    } else {  // FP64: one running sum (slot 0)
+        g.sum += g.acc[0];
+        if (S2) g.s2sum += g.acc2[0];
     }
 }
 
@@ -371,11 +372,14 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
     // chunk c: nodes [e0, e1) of the 2 M N source nodes in visit order (row r =
     // 2 j + boundary, so that every chunk mixes both boundaries); a chunk may
     // start and end inside a row.
-    const long nsrc = (long)2 * M * N;
-    const long e0 = (long)c * nsrc / chunks, e1 = (long)(c + 1) * nsrc / chunks;
-    for (int r = (int)(e0 / N); (long)r * N < e1; ++r) {
-        const int i0 = (int)max(e0 - (long)r * N, 0L);
-        const int i1 = (int)min(e1 - (long)r * N, (long)N);
+    // (balanced split: the first nsrc % chunks chunks take one node more; 32-bit
+    // arithmetic, as 2 M N is far below 2^31 for any mesh that fits the GPU)
+    const int nsrc = 2 * M * N;
+    const int q = nsrc / chunks, rem = nsrc - q * chunks;
+    const int e0 = c * q + min(c, rem), e1 = e0 + q + (c < rem ? 1 : 0);
+    for (int r = e0 / N; r * N < e1; ++r) {
+        const int i0 = max(e0 - r * N, 0);
+        const int i1 = min(e1 - r * N, N);
         const int ss = r & 1;
         const int j = r >> 1;
         const double yj = y1 + j * dy;
@@ -391,27 +395,13 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                 ts[q].Bt[i] = ts[q].B * t;
                 ts[q].Ct2[i] = ts[q].C * (t * t);
             }
-            ts[q].acc = 0;
-            ts[q].acc2 = 0;
+            ts[q].acc[0] = ts[q].acc[1] = 0;
+            ts[q].acc2[0] = ts[q].acc2[1] = 0;
         }
         const RecPtr<T, CREC> src = (ss ? recB : recS) + (size_t)j * N + i0;
-        auto seg_own = [&]() {
-#pragma unroll
-            for (int q = 0; q < TPL; ++q) {
-                row_end<T, COMP, NI>(ts[q]);
-                ts[q].acc = 0;
-                ts[q].acc2 = 0;
-            }
-        };
-        auto seg_other = [&]() {  // acc2 stays zero on the other boundary
-#pragma unroll
-            for (int q = 0; q < TPL; ++q) {
-                row_end<T, COMP, NI, false>(ts[q]);
-                ts[q].acc = 0;
-            }
-        };
         if (ss == st) {
-            walk_row<T, UNROLL, CREC>(src, i1 - i0, [&](const SrcRec<T> &p) {
+            walk_row<T, UNROLL, CREC>(src, i1 - i0, [&](const SrcRec<T> &p, auto slot) {
+                constexpr int a = decltype(slot)::value;
                 const T s = p.x - xs;
                 T nb0[TPL], coef[TPL], ri[TPL][NI], rq[TPL][NI];
 #pragma unroll
@@ -435,14 +425,15 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                         for (int i = 0; i < NI; ++i) {
                             const T num = fma(-e.ti[i], p.zy, nb0[q]);
                             const T bsum = fma(coef[q] * num, ri[q][i] * ri[q][i], p.ws);
-                            e.acc = fma(bsum, ri[q][i], e.acc);
-                            e.acc2 = fma(p.w, rq[q][i], e.acc2);
+                            e.acc[a] = fma(bsum, ri[q][i], e.acc[a]);
+                            e.acc2[a] = fma(p.w, rq[q][i], e.acc2[a]);
                         }
                     }
                 };
-            }, seg_own);
+            });
         } else {
-            walk_row<T, UNROLL, CREC>(src, i1 - i0, [&](const SrcRec<T> &p) {
+            walk_row<T, UNROLL, CREC>(src, i1 - i0, [&](const SrcRec<T> &p, auto slot) {
+                constexpr int a = decltype(slot)::value;
                 const T s = p.x - xs;
                 T nb0[TPL], ri[TPL][NI];
 #pragma unroll
@@ -462,11 +453,11 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                         for (int i = 0; i < NI; ++i) {
                             const T num = fma(-e.ti[i], p.zy, nb0[q]);
                             const T bsum = fma(p.wD * num, ri[q][i] * ri[q][i], p.ws);
-                            e.acc = fma(bsum, ri[q][i], e.acc);
+                            e.acc[a] = fma(bsum, ri[q][i], e.acc[a]);
                         }
                     }
                 };
-            }, seg_other);
+            });
         }
 #pragma unroll
         for (int q = 0; q < TPL; ++q) row_end<T, COMP, NI>(ts[q]);
@@ -497,9 +488,18 @@ __device__ __forceinline__ void pair_item_any(const SrcRec<T> *__restrict__ srcS
                                                  chunks, part, tt, c, lane);
 }
 
+// Resident waves per SIMD asked of the compiler: 8 for the FP32 variants whose
+// registers allow it (the scalar registers of the record prefetch otherwise
+// push the count to 7; what the limit moves out of scalar registers is spilled
+// to vector lanes outside the inner loops), none (1) for the others.  Not used
+// for the batched kernel, whose descriptor values would then be spilled inside
+// its inner loops.
+template <typename T, int TPL, int UNROLL>
+constexpr int kMinWaves = (sizeof(T) == 4 && TPL == 1 && UNROLL <= 4) ? 8 : 1;
+
 // Single problem: one wave per (target tile, source chunk).
 template <typename T, bool COMP, int TPL, int UNROLL>
-__global__ __launch_bounds__(256) void k_allpairs(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<T, TPL, UNROLL>))) void k_allpairs(
     const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB, const T *__restrict__ tg,
     const double *__restrict__ tg64, int N, int M, int nimg, double y1, double dx, double dy, int tiles_per_bnd,
     int row_groups, int target_tiles, int chunks, double *__restrict__ part) {
@@ -611,34 +611,6 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 }  // namespace
 
-PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int chunks) {
-    PairLaunch pl;
-    pl.tpl = (tpl == 2) ? 2 : 1;
-    pl.unroll = (unroll == 2 || unroll == 8) ? unroll : 4;
-    pl.row_groups = cdiv(d.M, pl.tpl);
-    pl.tiles_per_bnd = cdiv(pl.row_groups * (d.N - 1), 64);
-    pl.target_tiles = 2 * pl.tiles_per_bnd;
-    pl.src_rows = 2 * d.M;
-    pl.chunks = (int)std::max(1L, std::min((long)chunks, (long)pl.src_rows * d.N));
-    pl.blocks = cdiv((long)pl.target_tiles * pl.chunks, 4);
-    return pl;
-}
-
-int chunks_for_waves(const Dims &d, int tpl, int unroll, long want_waves) {
-    const PairLaunch base = pair_launch(d, tpl, unroll, 1);
-    return (int)std::max(1L, (want_waves + base.target_tiles / 2) / base.target_tiles);
-}
-
-PairLaunch pair_launch_cfg(const Dims &d, int prec, const bim_pair_config &cfg) {
-    (void)prec;
-    int chunks = cfg.chunks;
-    if (chunks <= 0 && cfg.rows_per_chunk > 0) chunks = cdiv(2 * d.M, cfg.rows_per_chunk);
-    // default: about 24 waves per SIMD (1024 SIMDs), the best count measured at
-    // 181 x 61 for both precisions (fewer waves hide less latency; many more
-    // only add partial sums)
-    if (chunks <= 0) chunks = chunks_for_waves(d, cfg.targets_per_lane, cfg.unroll, 24576);
-    return pair_launch(d, cfg.targets_per_lane, cfg.unroll, chunks);
-}
 
 size_t residual_work_bytes(const Dims &d, const PairLaunch &pl) {
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };

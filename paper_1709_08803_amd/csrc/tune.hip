@@ -17,6 +17,39 @@ std::mutex g_mu;
 std::map<Key, bim_pair_config> g_best;
 }  // namespace
 
+namespace {
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+}  // namespace
+
+PairLaunch pair_launch(const Dims &d, int tpl, int unroll, int chunks) {
+    PairLaunch pl;
+    pl.tpl = (tpl == 2) ? 2 : 1;
+    pl.unroll = (unroll == 2 || unroll == 8) ? unroll : 4;
+    pl.row_groups = cdiv(d.M, pl.tpl);
+    pl.tiles_per_bnd = cdiv(pl.row_groups * (d.N - 1), 64);
+    pl.target_tiles = 2 * pl.tiles_per_bnd;
+    pl.src_rows = 2 * d.M;
+    pl.chunks = (int)std::max(1L, std::min((long)chunks, (long)pl.src_rows * d.N));
+    pl.blocks = cdiv((long)pl.target_tiles * pl.chunks, 4);
+    return pl;
+}
+
+int chunks_for_waves(const Dims &d, int tpl, int unroll, long want_waves) {
+    const PairLaunch base = pair_launch(d, tpl, unroll, 1);
+    return (int)std::max(1L, (want_waves + base.target_tiles / 2) / base.target_tiles);
+}
+
+PairLaunch pair_launch_cfg(const Dims &d, int prec, const bim_pair_config &cfg) {
+    int chunks = cfg.chunks;
+    if (chunks <= 0 && cfg.rows_per_chunk > 0) chunks = cdiv(2 * d.M, cfg.rows_per_chunk);
+    // default: about 24 (FP64) or 32 (FP32C) waves per SIMD (1024 SIMDs), the
+    // best counts measured at 181 x 61 (fewer waves hide less latency; many
+    // more only add partial sums)
+    if (chunks <= 0)
+        chunks = chunks_for_waves(d, cfg.targets_per_lane, cfg.unroll, prec == BIM_FP64 ? 24576 : 32768);
+    return pair_launch(d, cfg.targets_per_lane, cfg.unroll, chunks);
+}
+
 PairLaunch pair_launch_for(const bim_problem *p, int prec) {
     const Dims d(p);
     {
@@ -25,7 +58,7 @@ PairLaunch pair_launch_for(const bim_problem *p, int prec) {
         if (it != g_best.end()) return pair_launch_cfg(d, prec, it->second);
     }
     // untuned defaults: the fastest shapes measured at 181 x 61 (FP64: 4-way
-    // unroll; FP32C: 2-way unroll; about 24 waves per SIMD)
+    // unroll; FP32C: 2-way unroll; about 24 and 32 waves per SIMD)
     const bim_pair_config def = {1, prec == BIM_FP32C ? 2 : 4, 0, 0};
     return pair_launch_cfg(d, prec, def);
 }
