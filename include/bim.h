@@ -170,10 +170,12 @@ int precond_band(const bim_precond *P);
  *                   the line search and the update are always FP64;
  *   band_halfwidth: band of the preconditioner built when none is passed;
  *   use_precond:    0 runs GMRES without preconditioning;
- *   use_graphs, fd_eps, stall_steps: see the fields.
- * jfnk_default_opts fills 1e-10, 1e-8, 30, 10, 30, 20, BIM_FP64, -1, 1, 1, 0.0, 0.
+ *   use_graphs, fd_eps, stall_steps, fp64_below, fp32c_gmres_rtol: see the fields.
+ * jfnk_default_opts fills 1e-10, 1e-8, 30, 10, 30, 20, BIM_FP64, -1, 1, 1, 0.0, 0,
+ * 0.0, 1e-4.
  * Invalid values (non-positive tolerances, restart outside [1, 200], negative
- * counts, fd_eps >= 1 or NaN, unknown precision) give BIM_EINVAL.
+ * counts, fd_eps >= 1 or NaN, negative or NaN fp64_below, unknown precision)
+ * give BIM_EINVAL.
  */
 typedef struct bim_jfnk_opts {
     double ftol;
@@ -190,6 +192,13 @@ typedef struct bim_jfnk_opts {
                             unit roundoff of the inner precision (2^-52 or 2^-23) */
     int32_t stall_steps; /* s > 0: stop (BIM_NOT_CONVERGED) once ||F||_inf has not halved over
                             the last s Newton steps; 0: no such stop */
+    double fp64_below;   /* with inner_prec BIM_FP32C: a Newton step taken at ||F||_inf <=
+                            fp64_below uses FP64 inner sums (the FP32 sums' rounding limits the
+                            Jacobian action once F is small); 0: never.  Ignored for FP64. */
+    double fp32c_gmres_rtol; /* relative tolerance of the GMRES solves of Newton steps that use
+                            FP32C inner sums (their Jacobian action carries rounding noise of
+                            order 1e-6 relative, below which GMRES stalls): the effective
+                            tolerance is max(this, gmres_rtol); default 1e-4, <= 0: gmres_rtol */
 } bim_jfnk_opts;
 
 /* Outcome of a solve (host struct).  history[k] = ||F||_inf after k Newton steps. */

@@ -120,7 +120,8 @@ class JfnkOpts(ctypes.Structure):
     _fields_ = [("ftol", ctypes.c_double), ("gmres_rtol", ctypes.c_double), ("restart", ctypes.c_int32),
                 ("max_restarts", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("max_backtracks", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("band_halfwidth", ctypes.c_int32), ("use_precond", ctypes.c_int32),
-                ("use_graphs", ctypes.c_int32), ("fd_eps", ctypes.c_double), ("stall_steps", ctypes.c_int32)]
+                ("use_graphs", ctypes.c_int32), ("fd_eps", ctypes.c_double), ("stall_steps", ctypes.c_int32),
+                ("fp64_below", ctypes.c_double), ("fp32c_gmres_rtol", ctypes.c_double)]
 
 
 class JfnkReport(ctypes.Structure):

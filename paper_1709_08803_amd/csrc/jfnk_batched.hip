@@ -47,6 +47,7 @@ struct Inst {
     bim_jfnk_report R{};
     bool new_cycle = true;
     bool gm_first = true;
+    bool inner64 = true;  // inner precision of the current Newton step (FP64 sums)
 };
 
 }  // namespace
@@ -190,8 +191,8 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         hops.insert(hops.end(), v.begin(), v.end());
         return (int)slices.size() - 1;
     };
-    const double eps_in = (o->fd_eps > 0) ? o->fd_eps
-                          : (o->inner_prec == BIM_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
+    const double eps64 = (o->fd_eps > 0) ? o->fd_eps : std::ldexp(1.0, -52);
+    const double eps32 = (o->fd_eps > 0) ? o->fd_eps : std::ldexp(1.0, -23);
     const int maxh = (int)(sizeof(I[0].R.history) / sizeof(I[0].R.history[0]));
     int rounds = 0;
 
@@ -239,7 +240,7 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         std::vector<int> arn, rst, lsr, bas;
         for (int i : act) {
             Inst &q = I[i];
-            const bool inner64 = (o->inner_prec == BIM_FP64);
+            const bool inner64 = q.inner64;
             switch (q.phase) {
                 case PH_BASE:
                     eval64.push_back(i); in64.push_back(q.u); out64.push_back(q.F); bas.push_back(i);
@@ -276,7 +277,8 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
                     }
                     sh_u.push_back({q.u, q.u, nullptr, nullptr, q.scal + 0, q.part, q.n, 0, 0, 0, 0});
                     sh_z.push_back({z, z, nullptr, nullptr, q.scal + 1, q.part + kBRedBlocks, q.n, 0, 0, 0, 0});
-                    sh_shift.push_back({nullptr, nullptr, nullptr, nullptr, q.scal, nullptr, 0, 0, 0, 0.0, eps_in});
+                    sh_shift.push_back({nullptr, nullptr, nullptr, nullptr, q.scal, nullptr, 0, 0, 0, 0.0,
+                                        inner64 ? eps64 : eps32});
                     sh_axpy.push_back({q.u, z, q.ut, q.scal + 2, nullptr, nullptr, q.n, 0, 0, 0, 0});
                     if (inner64) { eval64.push_back(i); in64.push_back(q.ut); out64.push_back(q.Ft); }
                     else { eval32.push_back(i); in32.push_back(q.ut); out32.push_back(q.Ft); }
@@ -295,7 +297,7 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         int max_nv = 1;
         for (int i : arn) {
             Inst &q = I[i];
-            const double *Fb = (o->inner_prec == BIM_FP64) ? q.F : q.Fin;
+            const double *Fb = q.inner64 ? q.F : q.Fin;
             quo.push_back({q.Ft, Fb, q.w, q.scal + 2, nullptr, nullptr, q.n, 0, 0, 0, 0});
             md1.push_back({q.V, q.w, nullptr, nullptr, q.hdev, q.part, q.n, q.n, q.j + 1, 0, 0});
             or1.push_back({q.V, nullptr, q.w, q.hdev, nullptr, nullptr, q.n, q.n, q.j + 1, 0, 0});
@@ -307,7 +309,7 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         }
         for (int i : rst) {
             Inst &q = I[i];
-            const double *Fb = (o->inner_prec == BIM_FP64) ? q.F : q.Fin;
+            const double *Fb = q.inner64 ? q.F : q.Fin;
             quo.push_back({q.Ft, Fb, q.w, q.scal + 2, nullptr, nullptr, q.n, 0, 0, 0, 0});
             rs_r.push_back({q.rhs, q.w, q.r, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, -1.0});
             rs_b.push_back({q.r, q.r, nullptr, nullptr, q.scal + 3, q.part, q.n, 0, 0, 0, 0});
@@ -445,7 +447,9 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
                     finish_inst(q, BIM_NOT_CONVERGED);
                     return;
                 }
-                q.phase = (o->inner_prec == BIM_FP64) ? PH_ARNOLDI : PH_INNER;
+                // FP32C inner sums, or FP64 ones once ||F||_inf <= fp64_below
+                q.inner64 = (o->inner_prec == BIM_FP64) || (q.finf <= o->fp64_below);
+                q.phase = q.inner64 ? PH_ARNOLDI : PH_INNER;
                 q.pending |= PD_GMRES_START;
                 q.j = 0;
                 q.cyc = 0;
@@ -504,7 +508,8 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
                     q.g[jj] = q.cs[jj] * q.g[jj];
                     const double relres = std::fabs(q.g[jj + 1]) / q.beta0;
                     q.R.gmres_relres_last = relres;
-                    const bool conv = relres <= o->gmres_rtol || hn == 0.0;
+                    const double rtol_q = q.inner64 ? o->gmres_rtol : std::max(o->gmres_rtol, o->fp32c_gmres_rtol);
+                    const bool conv = relres <= rtol_q || hn == 0.0;
                     if (conv || jj == m - 1) {
                         const int jend = jj + 1;
                         for (int a = jend - 1; a >= 0; --a) {
@@ -530,7 +535,7 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
                     q.beta = hs[3];
                     const double relres = q.beta / q.beta0;
                     q.R.gmres_relres_last = relres;
-                    if (relres <= o->gmres_rtol) {
+                    if (relres <= (q.inner64 ? o->gmres_rtol : std::max(o->gmres_rtol, o->fp32c_gmres_rtol))) {
                         q.phase = PH_LINESEARCH;
                         q.mu = 1.0;
                         q.bt = 0;
@@ -611,6 +616,7 @@ extern "C" int jfnk_solve_batched(const bim_problem *probs, int count, bim_preco
     if (opts) o = *opts;
     if (!(o.ftol > 0) || !(o.gmres_rtol > 0) || o.restart < 1 || o.restart > 30 || o.max_restarts < 0 ||
         o.max_newton < 0 || o.max_backtracks < 0 || !(o.fd_eps < 1.0) || o.stall_steps < 0 ||
+        !(o.fp64_below >= 0.0) ||
         (o.inner_prec != BIM_FP64 && o.inner_prec != BIM_FP32C))
         return fail(BIM_EINVAL, "invalid solver options (batched restart must be <= 30)");
     return solve_batched_impl(probs, count, Ps, us, &o, reps, (hipStream_t)stream);

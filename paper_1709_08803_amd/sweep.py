@@ -51,7 +51,8 @@ def run(count: int = 64, seed: int = 0, inner: str = "fp32c", ftol: float = 1e-1
         res[f"batched_residual_{prec}"] = {"ms": dt * 1e3, "pairs_per_s": pairs / dt}
     # the sweep: preconditioners, linear starts, lockstep JFNK
     Ps, t_setup = _sync_time(lambda: [B.Preconditioner(dp) for dp in dps])
-    ulin, t_lin = _sync_time(lambda: [B.linear_start(dp, P) for dp, P in zip(dps, Ps)])
+    # linear starts to the relative tolerance of the Newton steps' GMRES
+    ulin, t_lin = _sync_time(lambda: [B.linear_start(dp, P, rtol=1e-8) for dp, P in zip(dps, Ps)])
     ub = [u.clone() for u in ulin]
     (rc, reps), t_solve = _sync_time(lambda: B.solve_batched(dps, ub, Ps, check=False, ftol=ftol,
                                                             inner_prec=inner, max_newton=max_newton,

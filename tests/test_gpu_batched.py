@@ -80,3 +80,24 @@ def test_batched_solve_mixed_precision(bim):
         print(p.name, r["status"], r["newton_iters"], r["gmres_iters"])
         if r["status"] == 0:
             assert np.abs(R.residual(p, u.cpu().numpy())).max() < 1e-9
+
+
+def test_batched_solve_switches_precision_like_sequential(bim):
+    # per-instance switch to FP64 inner sums below ||F||_inf = 1e-5: the lockstep
+    # batch takes the same decisions as the single solves
+    probs = W.sweep_instances(4, seed=5, n_choices=[31, 46, 61], froude=(1.2, 1.8), height=(0.05, 0.15))
+    dps = [bim.DeviceProblem(p) for p in probs]
+    us = [bim.linear_start(dp) for dp in dps]
+    ub = [u.clone() for u in us]
+    opts = dict(ftol=1e-10, inner_prec="fp32c", fp64_below=1e-5)
+    rc, reps = bim.solve_batched(dps, ub, check=False, **opts)
+    for p, dp, u0, ubi, rb in zip(probs, dps, us, ub, reps):
+        us_ = u0.clone()
+        rs = bim.solve(dp, us_, check=False, **opts)
+        print(p.name, rb["status"], rs["status"], rb["newton_iters"], rs["newton_iters"], rb["inner_residual_evals"],
+              rs["inner_residual_evals"])
+        assert rb["status"] == rs["status"]
+        if rb["status"] == 0:
+            assert rb["inner_residual_evals"] < rb["newton_iters"]
+            assert (ubi - us_).abs().max().item() <= 1e-8
+            assert np.abs(R.residual(p, ubi.cpu().numpy())).max() < 1e-9

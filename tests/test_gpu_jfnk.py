@@ -145,3 +145,36 @@ def test_stall_stop_ends_a_stagnating_solve(bim):
     assert h[k] > 0.5 * h[k - 3]
     assert all(h[i] <= 0.5 * h[i - 3] for i in range(3, k))  # it did not stop earlier
     P.close()
+
+
+@pytest.mark.parametrize("opts", [dict(fp64_below=1e-5), dict(fp32c_gmres_rtol=0.0), dict(fp32c_gmres_rtol=1e-4)],
+                         ids=["switch-to-fp64", "fp32c-strict-gmres", "fp32c-forcing-1e-4"])
+def test_fp32c_solve_options_reach_the_fp64_solution(bim, opts):
+    # FP32C inner sums with the precision switch or either GMRES tolerance:
+    # the same FP64-converged discrete solution as the plain FP64 solve
+    p = W.working(1.4, N=61, M=21)
+    dp = bim.DeviceProblem(p)
+    P = bim.Preconditioner(dp)
+    u0 = bim.linear_start(dp, P)
+    u64 = u0.clone()
+    r64 = bim.solve(dp, u64, P, ftol=1e-11, inner_prec="fp64")
+    u32 = u0.clone()
+    r32 = bim.solve(dp, u32, P, ftol=1e-11, inner_prec="fp32c", **opts)
+    print(opts, "fp64", r64["newton_iters"], r64["gmres_iters"], "fp32c", r32["newton_iters"], r32["gmres_iters"],
+          "inner evals", r32["inner_residual_evals"])
+    assert r64["status"] == 0 and r32["status"] == 0
+    assert r32["fnorm_inf"] <= 1e-11
+    assert (u32 - u64).abs().max().item() <= 1e-9
+    if "fp64_below" in opts:  # the last steps ran with FP64 sums (no FP32C base evaluation)
+        assert r32["inner_residual_evals"] < r32["newton_iters"]
+    else:
+        assert r32["inner_residual_evals"] == r32["newton_iters"]
+    P.close()
+
+
+def test_solver_rejects_bad_switch_threshold(bim):
+    p = W.tiny(0.7)
+    dp = bim.DeviceProblem(p)
+    u = bim.linear_start(dp)
+    rep = bim.solve(dp, u, check=False, inner_prec="fp32c", fp64_below=-1.0)
+    assert rep["status"] == -1  # BIM_EINVAL
