@@ -7,6 +7,10 @@ A timed step is one evaluation of the dense residual F(u) in FP64 through the
 C ABI (unpack and x-integration, node and collocation records, all-pairs sums,
 closed-form singular term, dynamic and radiation rows, assembly).  `value` is
 pair-interactions per second (collocation point x source node x y-image).
+The default warm-up is 100 evaluations (about 70 ms): a GPU that comes out of
+idle runs its first tens of milliseconds of work at lower clocks (measured on
+this workload: 0.720 ms per evaluation over the 50 evaluations after a
+5-evaluation warm-up from idle, 0.670 ms once warm).
 
 Also reported: the FP32-compensated evaluation, the all-pairs kernel's
 roofline fraction from HIP events on the launch stream, the time to a converged
@@ -144,7 +148,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",

@@ -77,7 +77,12 @@ typedef struct bim_problem {
  *   u: device [3(N+1)M] input; F: device [3(N+1)M] output (must not alias u).
  *   prec: BIM_FP64, or BIM_FP32C (all-pairs sums in FP32 with compensated
  *         accumulation; reconstruction, analytic terms and assembly in FP64).
- * Scratch memory is taken from the stream-ordered allocator on `stream`.
+ * Scratch memory: a workspace kept by the library per (device, stream) and
+ * reused in stream order by later calls on that stream (see
+ * bim_release_workspaces); it grows, with a synchronisation of `stream`, when a
+ * call needs more.  Calls from several host threads are serialised while they
+ * enqueue.  A call captured into a graph needs a workspace of sufficient size
+ * from an earlier call on the same stream.
  */
 int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, void *stream);
 
@@ -91,6 +96,13 @@ int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, 
  */
 int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const double *v,
            double h, double *Jv, int prec, void *stream);
+
+/*
+ * Frees the workspaces bim_residual and bim_jv keep per (device, stream), after
+ * waiting for the work of every stream that used one.  Later calls allocate
+ * again.  Must not run concurrently with other calls of the library.
+ */
+int bim_release_workspaces(void);
 
 /*
  * Launch shape of the all-pairs kernel (the sums of the boundary-integral rows).

@@ -49,6 +49,7 @@ def lib():
         pp = ctypes.POINTER(_Problem)
         L.bim_residual.argtypes = [pp, vp, vp, i32, vp]
         L.bim_jv.argtypes = [pp, vp, vp, vp, dbl, vp, i32, vp]
+        L.bim_release_workspaces.argtypes = []
         L.bim_residual_timed.argtypes = [pp, vp, vp, i32, i32, ctypes.POINTER(PairConfig), vp,
                                          ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
         L.bim_tune_residual.argtypes = [pp, vp, i32, vp, ctypes.POINTER(PairConfig), ctypes.POINTER(dbl)]
@@ -186,6 +187,11 @@ def jv(dp: DeviceProblem, u: torch.Tensor, Fu: torch.Tensor, v: torch.Tensor, h:
     _check(lib().bim_jv(dp.ref(), _dptr(u), _dptr(Fu), _dptr(v), float(h), _dptr(J), _PREC[prec],
                         _stream(stream)))
     return J
+
+
+def release_workspaces() -> None:
+    """Frees the per-stream workspaces kept by residual() and jv()."""
+    _check(lib().bim_release_workspaces())
 
 
 def residual_timed(dp: DeviceProblem, u: torch.Tensor, prec="fp64", iters: int = 10, config=None,

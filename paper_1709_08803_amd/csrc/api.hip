@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -51,6 +53,37 @@ struct Scratch {
     }
 };
 
+// Workspace of the per-call entry points, kept per (device, stream) and grown
+// on demand: successive calls on one stream reuse it in stream order.  The lock
+// is held from the lookup until the call's work is enqueued, so a growth by
+// another host thread (which waits for the stream before freeing) cannot free
+// memory that a call is about to use.
+struct StreamWorkspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_ws_mutex;
+std::map<std::pair<int, hipStream_t>, StreamWorkspace> g_ws;
+
+int stream_workspace(hipStream_t s, size_t bytes, void **out) {
+    int dev = 0;
+    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    StreamWorkspace &ws = g_ws[{dev, s}];
+    if (ws.bytes < bytes) {
+        if (ws.ptr) {
+            if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
+            if ((rc = hip_check(hipFree(ws.ptr), "hipFree"))) return rc;
+            ws.ptr = nullptr;
+            ws.bytes = 0;
+        }
+        if ((rc = hip_check(hipMalloc(&ws.ptr, bytes), "hipMalloc"))) return rc;
+        ws.bytes = bytes;
+    }
+    *out = ws.ptr;
+    return BIM_OK;
+}
+
 }  // namespace bim
 
 using namespace bim;
@@ -71,10 +104,11 @@ int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, 
     hipStream_t s = (hipStream_t)stream;
     const Dims d(prob);
     const PairLaunch pl = pair_launch_for(prob, prec);
-    Scratch sc(s);
-    if ((rc = sc.alloc(residual_work_bytes(d, pl)))) return rc;
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    void *ws = nullptr;
+    if ((rc = stream_workspace(s, residual_work_bytes(d, pl), &ws))) return rc;
     ResidualWork w;
-    residual_work_carve(sc.ptr, d, pl, &w);
+    residual_work_carve(ws, d, pl, &w);
     return residual_enqueue(prob, u, F, prec, pl, w, s);
 }
 
@@ -134,11 +168,12 @@ int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const dou
     const PairLaunch pl = pair_launch_for(prob, prec);
     const size_t vec_bytes = ((sizeof(double) * d.nvec) + 255) & ~(size_t)255;
     const size_t red_bytes = ((sizeof(double) * reduce_parts()) + 255) & ~(size_t)255;
-    Scratch sc(s);
-    if ((rc = sc.alloc(residual_work_bytes(d, pl) + 2 * vec_bytes + red_bytes))) return rc;
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    void *ws = nullptr;
+    if ((rc = stream_workspace(s, residual_work_bytes(d, pl) + 2 * vec_bytes + red_bytes, &ws))) return rc;
     ResidualWork w;
-    residual_work_carve(sc.ptr, d, pl, &w);
-    double *uw = (double *)((char *)sc.ptr + w.bytes);
+    residual_work_carve(ws, d, pl, &w);
+    double *uw = (double *)((char *)ws + w.bytes);
     double *Fw = (double *)((char *)uw + vec_bytes);
     double *part = (double *)((char *)Fw + vec_bytes);
     const double eps = (prec == BIM_FP64) ? std::ldexp(1.0, -52) : std::ldexp(1.0, -23);
@@ -146,6 +181,23 @@ int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const dou
     if ((rc = axpy_dev_enqueue(u, v, w.scal + 2, uw, d.nvec, s))) return rc;
     if ((rc = residual_enqueue(prob, uw, Fw, prec, pl, w, s))) return rc;
     return quotient_enqueue(Fw, Fu, w.scal + 2, Jv, d.nvec, s);
+}
+
+int bim_release_workspaces(void) {
+    g_last_error.clear();
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    int rc = BIM_OK, cur = 0;
+    if ((rc = hip_check(hipGetDevice(&cur), "hipGetDevice"))) return rc;
+    for (auto &kv : g_ws) {
+        if (!kv.second.ptr) continue;
+        int r2 = hip_check(hipSetDevice(kv.first.first), "hipSetDevice");
+        if (!r2) r2 = hip_check(hipStreamSynchronize(kv.first.second), "hipStreamSynchronize");
+        if (!r2) r2 = hip_check(hipFree(kv.second.ptr), "hipFree");
+        if (r2 && !rc) rc = r2;
+    }
+    g_ws.clear();
+    const int r3 = hip_check(hipSetDevice(cur), "hipSetDevice");
+    return rc ? rc : r3;
 }
 
 }  // extern "C"

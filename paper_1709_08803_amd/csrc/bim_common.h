@@ -79,18 +79,30 @@ int balanced_chunks(const Dims &d, int pairs_target);
 // all-pairs prefetch at the end of a row).
 constexpr int kRecPad = 8;
 
-// One problem of a batched all-pairs launch (device array entry).  srcS, srcB
-// and tg point at SrcRec<T> / T data of the batch's precision.
+// One problem of a residual evaluation: the arguments of its node-level
+// kernels (unpack, records, finalize) and of its all-pairs work.  Passed by
+// value to the single-problem kernels; a batched evaluation keeps an array of
+// them in device memory.  tg points at the T-precision collocation records of
+// the all-pairs sums (tg64 or tg32).
 struct PairDesc {
-    const void *srcS;
-    const void *srcB;
+    void *srcS;
+    void *srcB;
     const void *tg;
-    const double *tg64;  // FP64 collocation records (y* for the per-row t)
+    double *tg64;  // FP64 collocation records (y* for the per-row t)
     double *part;
     int N, M, nimg;
     double y1, dx, dy;
     int tiles_per_bnd, row_groups, target_tiles, chunks;
     long item0;  // index of this problem's first work item in the batch
+    // node-level kernels
+    const double *u;
+    double *F;
+    double *nodes, *ydiv;
+    float *tg32;
+    const double *beta, *beta_x, *beta_y;
+    double x1, n_decay, froude;
+    int half, linear;
+    int blk_int, blk_rec, blk_fin;  // first workgroup of this problem in each batched node-level launch
 };
 
 // Device workspace of one residual evaluation.

@@ -2,13 +2,17 @@
 //
 // Four kernels, stream-ordered:
 //   k_integrate   unpack u and integrate f_x along each slice (trapezoidal rule)
-//   k_nodes       y-derivatives at the nodes; source-node records for S and B
-//   k_targets     collocation-point records at (x_{k+1/2}, y_l)
+//   k_records     y-derivatives at the nodes; source-node records for S and B;
+//                 collocation-point records at (x_{k+1/2}, y_l)
 //   k_allpairs    the dense sums of eq. (new_finite_boundary_integral): every
 //                 collocation point against every node of both boundaries and
 //                 both y-images (hot loop)
-//   k_finalize    closed-form S2 integral, 2 pi term, dynamic condition,
-//                 radiation rows, and the row order of Appendix B
+//   k_finalize    reduction of the all-pairs partial sums, closed-form S2
+//                 integral, 2 pi term, dynamic condition, radiation rows, and
+//                 the row order of Appendix B
+// The three node-level kernels take a PairDesc by value; their _batched forms
+// serve many problems in one launch, each workgroup finding its problem from
+// the first-workgroup offsets in the descriptors.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,18 +41,37 @@ __device__ __forceinline__ double rsq(double x) {
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
+// ------------------------------------------------------------------ batched lookup
+// Problem of workgroup b in a batched node-level launch: the number of
+// problems whose first workgroup is <= b, minus one (a wave-wide count over
+// the descriptors; uniform across the workgroup).  PART selects the launch.
+template <int PART>
+__device__ __forceinline__ int first_block(const PairDesc &D) {
+    return PART == 0 ? D.blk_int : PART == 1 ? D.blk_rec : D.blk_fin;
+}
+template <int PART>
+__device__ __forceinline__ int find_problem(const PairDesc *__restrict__ descs, int count, int b) {
+    const int lane = threadIdx.x & 63;
+    int n = 0;
+    for (int base = 0; base < count; base += 64) {
+        const int i = base + lane;
+        const bool le = i < count && first_block<PART>(descs[i]) <= b;
+        n += __popcll(__ballot(le));
+    }
+    return n - 1;
+}
+
 // ------------------------------------------------------------------ A1: unpack + x-integration
 // f_{1,j} + trapezoidal integral of f_x along slice j (Section 3.1).  One wave
 // per (field, slice): 64-wide inclusive scans of the trapezoid increments with
 // the running total carried from one 64-node segment to the next.
-__global__ __launch_bounds__(64) void k_integrate(const double *__restrict__ u, double *__restrict__ nodes,
-                                                  int N, int M, double dx) {
-    const int idx = blockIdx.x;  // field * M + slice
-    const int f = idx / M, j = idx - f * M;
+__device__ __forceinline__ void integrate_body(const PairDesc &D, int idx) {
+    const int N = D.N, M = D.M;
+    const int f = idx / M, j = idx - f * M;  // idx = field * M + slice
     const int lane = threadIdx.x;
-    const double *s = u + (size_t)f * (N + 1) * M + (size_t)j * (N + 1);
-    double *o = nodes + ((size_t)f * M + j) * N;
-    const double hdx = 0.5 * dx;
+    const double *s = D.u + (size_t)f * (N + 1) * M + (size_t)j * (N + 1);
+    double *o = D.nodes + ((size_t)f * M + j) * N;
+    const double hdx = 0.5 * D.dx;
     double carry = s[0];
     for (int base = 0; base < N; base += 64) {
         const int i = base + lane;
@@ -61,6 +84,11 @@ __global__ __launch_bounds__(64) void k_integrate(const double *__restrict__ u, 
         if (i < N) o[i] = carry + v;
         carry += __shfl(v, 63, 64);
     }
+}
+__global__ __launch_bounds__(64) void k_integrate(PairDesc D) { integrate_body(D, blockIdx.x); }
+__global__ __launch_bounds__(64) void k_integrate_batched(const PairDesc *__restrict__ descs, int count) {
+    const PairDesc &D = descs[find_problem<0>(descs, count, blockIdx.x)];
+    integrate_body(D, blockIdx.x - D.blk_int);
 }
 
 // y-derivative of node field g at (j, i): central differences inside, the
@@ -75,27 +103,26 @@ __device__ __forceinline__ double ddy(const double *g, int j, int i, int N, int 
     return (-3.0 * g[i] + 4.0 * g[(size_t)N + i] - g[(size_t)2 * N + i]) * inv2;
 }
 
-// ------------------------------------------------------------------ node records
+// ------------------------------------------------------------------ records
+// Node part (one thread per node of the mesh): y-derivatives of zeta and phi,
+// and the source-node records of both boundaries.
 template <typename T>
-__global__ void k_nodes(const double *__restrict__ u, const double *__restrict__ nodes,
-                        const double *__restrict__ beta, const double *__restrict__ beta_x,
-                        const double *__restrict__ beta_y, double *__restrict__ ydiv,
-                        SrcRec<T> *__restrict__ srcS, SrcRec<T> *__restrict__ srcB, int N, int M,
-                        double x1, double dx, double dy, int half, int linear) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N * M) return;
+__device__ __forceinline__ void node_records(const PairDesc &D, int n) {
+    const int N = D.N, M = D.M;
     const int j = n / N, i = n - j * N;
-    const size_t nb = (size_t)(N + 1) * M;
+    const double dx = D.dx, dy = D.dy;
+    const double *nodes = D.nodes;
     const double *zeta = nodes, *phi = nodes + (size_t)N * M, *psi = nodes + (size_t)2 * N * M;
-    const double zy = ddy(zeta, j, i, N, M, dy, half);
-    const double py = ddy(phi, j, i, N, M, dy, half);
-    ydiv[n] = zy;
-    ydiv[(size_t)N * M + n] = py;
-    const double zx = u[(size_t)j * (N + 1) + 1 + i];
-    const double x = x1 + i * dx;
+    const double zy = ddy(zeta, j, i, N, M, dy, D.half);
+    const double py = ddy(phi, j, i, N, M, dy, D.half);
+    D.ydiv[n] = zy;
+    D.ydiv[(size_t)N * M + n] = py;
+    const double zx = D.u[(size_t)j * (N + 1) + 1 + i];
+    const double x = D.x1 + i * dx;
     const double ci = (i == 0 || i == N - 1) ? 0.5 : 1.0;
     const double cj = (j == 0 || j == M - 1) ? 0.5 : 1.0;
     const double w = dx * dy * ci * cj;
+    const bool linear = D.linear;
     // linear mode: the boundaries are the planes z = 0 and z = -1 (Section 4.2);
     // the layer densities are unchanged.
     // FP32 records are in grid units (lengths / dx, node x = its column index):
@@ -114,65 +141,84 @@ __global__ void k_nodes(const double *__restrict__ u, const double *__restrict__
     a.ws = (T)(w * g * zx);
     a.w = (T)(w * g * g);
     a.pad = (T)0;
-    srcS[n] = a;
+    ((SrcRec<T> *)D.srcS)[n] = a;
     // bottom: outward normal points down, so both layers enter with -w
     SrcRec<T> b;
     b.x = (T)xr;
-    b.z = (T)((linear ? -1.0 : beta[n]) * g);
-    b.zx = linear ? (T)0 : (T)beta_x[n];
-    b.zy = linear ? (T)0 : (T)beta_y[n];
+    b.z = (T)((linear ? -1.0 : D.beta[n]) * g);
+    b.zx = linear ? (T)0 : (T)D.beta_x[n];
+    b.zy = linear ? (T)0 : (T)D.beta_y[n];
     b.wD = (T)(-w * g * g * (psi[n] - x));
-    b.ws = (T)(-w * g * beta_x[n]);
+    b.ws = (T)(-w * g * D.beta_x[n]);
     b.w = (T)(-w * g * g);
     b.pad = (T)0;
-    srcB[n] = b;
-    (void)nb;
+    ((SrcRec<T> *)D.srcB)[n] = b;
 }
 
-// ------------------------------------------------------------------ collocation-point records
-// tg layout: 8 arrays of 2 ntg entries: x*, y*, d, D*, A, B, C, sigma*; target
-// t = st ntg + l (N-1) + k, st = 0 on the free surface, 1 on the bottom.  The
-// FP32 copy tg32 holds the first 7 in grid units (x* = k + 1/2, y*, d / dx).
-__global__ void k_targets(const double *__restrict__ nodes, const double *__restrict__ ydiv,
-                          const double *__restrict__ u, const double *__restrict__ beta,
-                          const double *__restrict__ beta_x, const double *__restrict__ beta_y,
-                          double *__restrict__ tg, float *__restrict__ tg32, int N, int M, double x1,
-                          double dx, double y1, double dy, int linear) {
+// Collocation part (one thread per collocation point).  tg layout: 8 arrays of
+// 2 ntg entries: x*, y*, d, D*, A, B, C, sigma*; target t = st ntg + l (N-1) + k,
+// st = 0 on the free surface, 1 on the bottom.  The FP32 copy tg32 holds the
+// first 7 in grid units (x* = k + 1/2, y*, d / dx).  zeta_y at the two
+// neighbouring nodes is formed here by the node part's own stencil.
+__device__ __forceinline__ void target_records(const PairDesc &D, int t) {
+    const int N = D.N, M = D.M;
     const int ntg = (N - 1) * M;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * ntg) return;
     const int st = t / ntg, r = t - st * ntg;
     const int l = r / (N - 1), k = r - l * (N - 1);
     const size_t n0 = (size_t)l * N + k, n1 = n0 + 1;
-    const double xs = x1 + (k + 0.5) * dx, ys = y1 + l * dy;
-    double d, D, ax, ay, sig;
+    const double dx = D.dx;
+    const double xs = D.x1 + (k + 0.5) * dx, ys = D.y1 + l * D.dy;
+    double d, Dst, ax, ay, sig;
     if (st == 0) {
-        const double *zeta = nodes, *phi = nodes + (size_t)N * M;
-        const double *zy = ydiv;
-        const double zx0 = u[(size_t)l * (N + 1) + 1 + k], zx1 = u[(size_t)l * (N + 1) + 2 + k];
+        const double *zeta = D.nodes, *phi = D.nodes + (size_t)N * M;
+        const double zx0 = D.u[(size_t)l * (N + 1) + 1 + k], zx1 = D.u[(size_t)l * (N + 1) + 2 + k];
         d = 0.5 * (zeta[n0] + zeta[n1]);
-        D = 0.5 * (phi[n0] + phi[n1]) - xs;
+        Dst = 0.5 * (phi[n0] + phi[n1]) - xs;
         ax = 0.5 * (zx0 + zx1);
-        ay = 0.5 * (zy[n0] + zy[n1]);
+        ay = 0.5 * (ddy(zeta, l, k, N, M, D.dy, D.half) + ddy(zeta, l, k + 1, N, M, D.dy, D.half));
         sig = ax;
     } else {
-        const double *psi = nodes + (size_t)2 * N * M;
-        d = 0.5 * (beta[n0] + beta[n1]);
-        D = 0.5 * (psi[n0] + psi[n1]) - xs;
-        ax = 0.5 * (beta_x[n0] + beta_x[n1]);
-        ay = 0.5 * (beta_y[n0] + beta_y[n1]);
+        const double *psi = D.nodes + (size_t)2 * N * M;
+        d = 0.5 * (D.beta[n0] + D.beta[n1]);
+        Dst = 0.5 * (psi[n0] + psi[n1]) - xs;
+        ax = 0.5 * (D.beta_x[n0] + D.beta_x[n1]);
+        ay = 0.5 * (D.beta_y[n0] + D.beta_y[n1]);
         sig = -ax;
     }
-    if (linear) {  // flat boundaries: elevation 0 or -1, S2 = 1/r
+    if (D.linear) {  // flat boundaries: elevation 0 or -1, S2 = 1/r
         d = st ? -1.0 : 0.0;
         ax = ay = 0.0;
     }
     const size_t T2 = (size_t)2 * ntg;
-    const double v[8] = {xs, ys, d, D, 1.0 + ax * ax, 2.0 * ax * ay, 1.0 + ay * ay, sig};
-    for (int q = 0; q < 8; ++q) tg[q * T2 + t] = v[q];
+    const double v[8] = {xs, ys, d, Dst, 1.0 + ax * ax, 2.0 * ax * ay, 1.0 + ay * ay, sig};
+    for (int q = 0; q < 8; ++q) D.tg64[q * T2 + t] = v[q];
     // FP32 copies in the grid units of the FP32 node records (x* = k + 1/2)
     const double g[7] = {0.0, 1.0 / dx, 1.0 / dx, 1.0, 1.0, 1.0, 1.0};
-    for (int q = 0; q < 7; ++q) tg32[q * T2 + t] = (float)(q == 0 ? k + 0.5 : v[q] * g[q]);
+    for (int q = 0; q < 7; ++q) D.tg32[q * T2 + t] = (float)(q == 0 ? k + 0.5 : v[q] * g[q]);
+}
+
+// Workgroups [0, node_blocks) cover the nodes, the rest the collocation points.
+__host__ __device__ __forceinline__ int node_blocks(int N, int M) { return (N * M + 255) / 256; }
+__host__ __device__ __forceinline__ int record_blocks(int N, int M) {
+    return node_blocks(N, M) + (2 * (N - 1) * M + 255) / 256;
+}
+template <typename T>
+__device__ __forceinline__ void records_body(const PairDesc &D, int b) {
+    const int nbn = node_blocks(D.N, D.M);
+    if (b < nbn) {
+        const int n = b * 256 + threadIdx.x;
+        if (n < D.N * D.M) node_records<T>(D, n);
+    } else {
+        const int t = (b - nbn) * 256 + threadIdx.x;
+        if (t < 2 * (D.N - 1) * D.M) target_records(D, t);
+    }
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_records(PairDesc D) { records_body<T>(D, blockIdx.x); }
+template <typename T>
+__global__ __launch_bounds__(256) void k_records_batched(const PairDesc *__restrict__ descs, int count) {
+    const PairDesc &D = descs[find_problem<1>(descs, count, blockIdx.x)];
+    records_body<T>(D, blockIdx.x - D.blk_rec);
 }
 
 // ------------------------------------------------------------------ A2: all-pairs sums (hot loop)
@@ -546,65 +592,135 @@ __device__ double s2_antideriv(double A, double B, double C, double s, double t)
     return g;
 }
 
-__global__ void k_finalize(const double *__restrict__ u, const double *__restrict__ nodes,
-                           const double *__restrict__ ydiv, const double *__restrict__ tg,
-                           const double *__restrict__ part, double *__restrict__ F, int N, int M,
-                           int chunks, double x1, double dx, double xlo, double xhi, double ylo,
-                           double yhi, double n_decay, double froude, int linear) {
+// Workgroups [0, bie_blocks) hold 64 boundary-integral rows each (4 waves: wave
+// w sums a quarter of the source chunks' partial sums and the w-th corner term
+// of the closed-form S2 integral; wave 0 combines them in a fixed order), the
+// rest one dynamic or radiation row per thread.
+__host__ __device__ __forceinline__ int bie_blocks(int N, int M) { return (2 * (N - 1) * M + 63) / 64; }
+__host__ __device__ __forceinline__ int finalize_blocks(int N, int M) {
+    return bie_blocks(N, M) + ((N + 1) * M + 4 * M + 255) / 256;
+}
+
+__device__ __forceinline__ void finalize_bie(const PairDesc &D, int b, double (*red)[3][64]) {
+    const int N = D.N, M = D.M;
+    const int ntg = (N - 1) * M;
+    const size_t T2 = (size_t)2 * ntg;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tid = b * 64 + lane;
+    const bool valid = tid < 2 * ntg;
+    const int t = valid ? tid : 2 * ntg - 1;
+    // partial sums of chunks [c0, c1), in chunk order, eight loads in flight
+    const int chunks = D.chunks;
+    const int c0 = (w * chunks) >> 2, c1 = ((w + 1) * chunks) >> 2;
+    const double2 *pp = (const double2 *)D.part + t;
+    double acc = 0.0, acc2 = 0.0;
+    int c = c0;
+    for (; c + 8 <= c1; c += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = pp[(size_t)(c + q) * T2];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            acc += v[q].x;
+            acc2 += v[q].y;
+        }
+    }
+    for (; c < c1; ++c) {
+        const double2 v = pp[(size_t)c * T2];
+        acc += v.x;
+        acc2 += v.y;
+    }
+    // corner w of the rectangle [xlo, xhi] x [ylo, yhi] relative to the target
+    const double *tg = D.tg64;
+    const double xs = tg[0 * T2 + t], ys = tg[1 * T2 + t];
+    const double A = tg[4 * T2 + t], B = tg[5 * T2 + t], C = tg[6 * T2 + t];
+    const double xN = D.x1 + (N - 1) * D.dx, yM = D.y1 + (M - 1) * D.dy;
+    const double ylo = D.half ? -yM : D.y1;
+    const double sc = (w & 1) ? D.x1 - xs : xN - xs;
+    const double tc = (w & 2) ? ylo - ys : yM - ys;
+    const double corner = s2_antideriv(A, B, C, sc, tc);
+    if (w > 0) {
+        red[w - 1][0][lane] = acc;
+        red[w - 1][1][lane] = acc2;
+        red[w - 1][2][lane] = corner;
+    }
+    __syncthreads();
+    if (w > 0 || !valid) return;
+    acc = ((acc + red[0][0][lane]) + red[1][0][lane]) + red[2][0][lane];
+    acc2 = ((acc2 + red[0][1][lane]) + red[1][1][lane]) + red[2][1][lane];
+    // corners in the order (xhi, yhi) - (xlo, yhi) - (xhi, ylo) + (xlo, ylo)
+    const double I2 = ((corner - red[0][2][lane]) - red[1][2][lane]) + red[2][2][lane];
+    const int st = t / ntg, r = t - st * ntg;
+    const int l = r / (N - 1), k = r - l * (N - 1);
+    const int row = (st + 1) * (N + 1) * M + l * (N + 1) + k + 2;
+    const double s2 = st ? -acc2 : acc2;  // bottom records carry -w
+    const double Dst = tg[3 * T2 + t], sig = tg[7 * T2 + t];
+    D.F[row] = acc - sig * s2 + sig * I2 - kTwoPi * Dst;
+}
+
+// Dynamic rows (block 0, columns >= 2) and radiation rows (columns 0, 1 of the
+// three blocks); r enumerates block 0 and then the radiation pairs of blocks 1, 2.
+__device__ __forceinline__ void finalize_rows(const PairDesc &D, int r) {
+    const int N = D.N, M = D.M;
     const int nblk = (N + 1) * M;
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= 3 * nblk) return;
-    const int blk = row / nblk;
-    const int rem = row - blk * nblk;
-    const int l = rem / (N + 1), col = rem - l * (N + 1);
+    if (r >= nblk + 4 * M) return;
+    int blk, l, col;
+    if (r < nblk) {
+        blk = 0;
+        l = r / (N + 1);
+        col = r - l * (N + 1);
+    } else {
+        const int q = r - nblk;
+        blk = 1 + q / (2 * M);
+        const int e = q - (blk - 1) * 2 * M;
+        l = e >> 1;
+        col = e & 1;
+    }
+    const int row = blk * nblk + l * (N + 1) + col;
+    const double dx = D.dx, x1 = D.x1;
+    const double *u = D.u, *nodes = D.nodes, *ydiv = D.ydiv;
     const double *fx = u + (size_t)blk * nblk + (size_t)l * (N + 1) + 1;  // (f_x)_{., l}
     const double *fv = nodes + ((size_t)blk * M + l) * N;                  // f_{., l}
     if (col < 2) {
         // radiation rows (eqs. scullen1-6 as discretised in Appendix B)
         const double fxx = (fx[1] - fx[0]) / dx;
+        const double n_decay = D.n_decay;
         double v;
         if (blk == 0) {
             v = (col == 0) ? x1 * fx[0] + n_decay * fv[0] : x1 * fxx + n_decay * fx[0];
         } else {
             v = (col == 0) ? x1 * (fx[0] - 1.0) + n_decay * (fv[0] - x1) : x1 * fxx + n_decay * (fx[0] - 1.0);
         }
-        F[row] = v;
+        D.F[row] = v;
         return;
     }
+    // dynamic condition, eq. (new_finite_dynamic), at (x_{k+1/2}, y_l)
     const int k = col - 2;
-    if (blk == 0) {
-        // dynamic condition, eq. (new_finite_dynamic), at (x_{k+1/2}, y_l)
-        const size_t n0 = (size_t)l * N + k, n1 = n0 + 1;
-        const double *zx = u + (size_t)l * (N + 1) + 1;
-        const double *px = u + (size_t)nblk + (size_t)l * (N + 1) + 1;
-        const double z = 0.5 * (nodes[n0] + nodes[n1]);
-        const double a = 0.5 * (zx[k] + zx[k + 1]);
-        const double b = 0.5 * (ydiv[n0] + ydiv[n1]);
-        const double p = 0.5 * (px[k] + px[k + 1]);
-        const double q = 0.5 * (ydiv[(size_t)N * M + n0] + ydiv[(size_t)N * M + n1]);
-        const double kin = 0.5 * ((1.0 + a * a) * q * q + (1.0 + b * b) * p * p - 2.0 * a * b * p * q) /
-                           (1.0 + a * a + b * b);
-        // linear mode: eq. (linear_dynamic2), phi*_x + zeta*/F^2 - 1
-        F[row] = linear ? p + z / (froude * froude) - 1.0 : kin + z / (froude * froude) - 0.5;
-        return;
-    }
-    // boundary-integral rows: F2 (blk 1, free surface), F7 (blk 2, bottom)
-    const int ntg = (N - 1) * M;
-    const size_t T2 = (size_t)2 * ntg;
-    const int tid = (blk - 1) * ntg + l * (N - 1) + k;
-    double acc = 0.0, acc2 = 0.0;
-    for (int c = 0; c < chunks; ++c) {  // fixed order: deterministic
-        const double *o = part + ((size_t)c * T2 + tid) * 2;
-        acc += o[0];
-        acc2 += o[1];
-    }
-    const double s2 = (blk == 2) ? -acc2 : acc2;  // bottom records carry -w
-    const double xs = tg[0 * T2 + tid], ys = tg[1 * T2 + tid], D = tg[3 * T2 + tid];
-    const double A = tg[4 * T2 + tid], B = tg[5 * T2 + tid], C = tg[6 * T2 + tid], sig = tg[7 * T2 + tid];
-    const double s1 = xlo - xs, s2e = xhi - xs, t1 = ylo - ys, t2 = yhi - ys;
-    const double I2 = s2_antideriv(A, B, C, s2e, t2) - s2_antideriv(A, B, C, s1, t2) -
-                      s2_antideriv(A, B, C, s2e, t1) + s2_antideriv(A, B, C, s1, t1);
-    F[row] = acc - sig * s2 + sig * I2 - kTwoPi * D;
+    const size_t n0 = (size_t)l * N + k, n1 = n0 + 1;
+    const double *zx = u + (size_t)l * (N + 1) + 1;
+    const double *px = u + (size_t)nblk + (size_t)l * (N + 1) + 1;
+    const double z = 0.5 * (nodes[n0] + nodes[n1]);
+    const double a = 0.5 * (zx[k] + zx[k + 1]);
+    const double b = 0.5 * (ydiv[n0] + ydiv[n1]);
+    const double p = 0.5 * (px[k] + px[k + 1]);
+    const double q = 0.5 * (ydiv[(size_t)N * M + n0] + ydiv[(size_t)N * M + n1]);
+    const double kin = 0.5 * ((1.0 + a * a) * q * q + (1.0 + b * b) * p * p - 2.0 * a * b * p * q) /
+                       (1.0 + a * a + b * b);
+    const double fr2 = D.froude * D.froude;
+    // linear mode: eq. (linear_dynamic2), phi*_x + zeta*/F^2 - 1
+    D.F[row] = D.linear ? p + z / fr2 - 1.0 : kin + z / fr2 - 0.5;
+}
+
+__device__ __forceinline__ void finalize_body(const PairDesc &D, int b) {
+    __shared__ double red[3][3][64];
+    const int nb = bie_blocks(D.N, D.M);
+    if (b < nb) finalize_bie(D, b, red);
+    else finalize_rows(D, (b - nb) * 256 + threadIdx.x);
+}
+__global__ __launch_bounds__(256) void k_finalize(PairDesc D) { finalize_body(D, blockIdx.x); }
+__global__ __launch_bounds__(256) void k_finalize_batched(const PairDesc *__restrict__ descs, int count) {
+    const PairDesc &D = descs[find_problem<2>(descs, count, blockIdx.x)];
+    finalize_body(D, blockIdx.x - D.blk_fin);
 }
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
@@ -639,25 +755,55 @@ void residual_work_carve(void *base, const Dims &d, const PairLaunch &pl, Residu
     w->bytes = (size_t)(p - (char *)base);
 }
 
+namespace {
+
+PairDesc make_desc(const bim_problem *p, const Dims &d, const PairLaunch &pl, const ResidualWork &w,
+                   const double *u, double *F, int prec, int linear) {
+    PairDesc D{};
+    D.srcS = w.srcS;
+    D.srcB = w.srcB;
+    D.tg = (prec == BIM_FP64) ? (const void *)w.tg : (const void *)w.tg32;
+    D.tg64 = w.tg;
+    D.part = w.part;
+    D.N = d.N;
+    D.M = d.M;
+    D.nimg = d.nimg;
+    D.y1 = p->y1;
+    D.dx = p->dx;
+    D.dy = p->dy;
+    D.tiles_per_bnd = pl.tiles_per_bnd;
+    D.row_groups = pl.row_groups;
+    D.target_tiles = pl.target_tiles;
+    D.chunks = pl.chunks;
+    D.item0 = 0;
+    D.u = u;
+    D.F = F;
+    D.nodes = w.nodes;
+    D.ydiv = w.ydiv;
+    D.tg32 = w.tg32;
+    D.beta = p->beta;
+    D.beta_x = p->beta_x;
+    D.beta_y = p->beta_y;
+    D.x1 = p->x1;
+    D.n_decay = p->n_decay;
+    D.froude = p->froude;
+    D.half = p->half_domain ? 1 : 0;
+    D.linear = linear;
+    return D;
+}
+
+}  // namespace
+
 int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec, const PairLaunch &pl,
                      const ResidualWork &w, hipStream_t s, hipEvent_t *ev_pair, int linear) {
     const Dims d(p);
     const int N = d.N, M = d.M;
-    const double xN = p->x1 + (N - 1) * p->dx, yM = p->y1 + (M - 1) * p->dy;
-    const double ylo = p->half_domain ? -yM : p->y1;
-    hipLaunchKernelGGL(k_integrate, dim3(3 * M), dim3(64), 0, s, u, w.nodes, N, M, p->dx);
-    const int nb = cdiv(d.nnode, 256);
-    if (prec == BIM_FP64) {
-        hipLaunchKernelGGL(k_nodes<double>, dim3(nb), dim3(256), 0, s, u, w.nodes, p->beta, p->beta_x,
-                           p->beta_y, w.ydiv, (SrcRec<double> *)w.srcS, (SrcRec<double> *)w.srcB, N, M,
-                           p->x1, p->dx, p->dy, p->half_domain, linear);
-    } else {
-        hipLaunchKernelGGL(k_nodes<float>, dim3(nb), dim3(256), 0, s, u, w.nodes, p->beta, p->beta_x,
-                           p->beta_y, w.ydiv, (SrcRec<float> *)w.srcS, (SrcRec<float> *)w.srcB, N, M,
-                           p->x1, p->dx, p->dy, p->half_domain, linear);
-    }
-    hipLaunchKernelGGL(k_targets, dim3(cdiv(2 * d.ntg, 256)), dim3(256), 0, s, w.nodes, w.ydiv, u, p->beta,
-                       p->beta_x, p->beta_y, w.tg, w.tg32, N, M, p->x1, p->dx, p->y1, p->dy, linear);
+    const PairDesc D = make_desc(p, d, pl, w, u, F, prec, linear);
+    hipLaunchKernelGGL(k_integrate, dim3(3 * M), dim3(64), 0, s, D);
+    if (prec == BIM_FP64)
+        hipLaunchKernelGGL(k_records<double>, dim3(record_blocks(N, M)), dim3(256), 0, s, D);
+    else
+        hipLaunchKernelGGL(k_records<float>, dim3(record_blocks(N, M)), dim3(256), 0, s, D);
     if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[0], s));
 #define BIM_LAUNCH_PAIRS(T, COMP, TPL, UNR, TG)                                                         \
     hipLaunchKernelGGL((k_allpairs<T, COMP, TPL, UNR>), dim3(pl.blocks), dim3(256), 0, s,               \
@@ -686,9 +832,7 @@ int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
     }
 #undef BIM_LAUNCH_PAIRS
     if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[1], s));
-    hipLaunchKernelGGL(k_finalize, dim3(cdiv(d.nvec, 256)), dim3(256), 0, s, u, w.nodes, w.ydiv, w.tg,
-                       w.part, F, N, M, pl.chunks, p->x1, p->dx, p->x1, xN, ylo, yM, p->n_decay,
-                       p->froude, linear);
+    hipLaunchKernelGGL(k_finalize, dim3(finalize_blocks(N, M)), dim3(256), 0, s, D);
     return hip_check(hipGetLastError(), "residual kernel launch");
 }
 
@@ -700,45 +844,29 @@ int residual_batched_enqueue(const bim_problem *probs, int count, const double *
     const int tpl = pls[0].tpl, unroll = pls[0].unroll;
     std::vector<PairDesc> descs(count);
     long total = 0;
+    int b_int = 0, b_rec = 0, b_fin = 0;
     for (int i = 0; i < count; ++i) {
         const bim_problem *p = &probs[i];
         const Dims d(p);
         const PairLaunch &pl = pls[i];
         if (pl.tpl != tpl || pl.unroll != unroll) return fail(BIM_EINVAL, "batched launch needs one kernel variant");
-        const ResidualWork &w = ws[i];
-        const int N = d.N, M = d.M;
-        hipLaunchKernelGGL(k_integrate, dim3(3 * M), dim3(64), 0, s, u[i], w.nodes, N, M, p->dx);
-        const int nb = cdiv(d.nnode, 256);
-        if (prec == BIM_FP64)
-            hipLaunchKernelGGL(k_nodes<double>, dim3(nb), dim3(256), 0, s, u[i], w.nodes, p->beta, p->beta_x,
-                               p->beta_y, w.ydiv, (SrcRec<double> *)w.srcS, (SrcRec<double> *)w.srcB, N, M, p->x1,
-                               p->dx, p->dy, p->half_domain, 0);
-        else
-            hipLaunchKernelGGL(k_nodes<float>, dim3(nb), dim3(256), 0, s, u[i], w.nodes, p->beta, p->beta_x,
-                               p->beta_y, w.ydiv, (SrcRec<float> *)w.srcS, (SrcRec<float> *)w.srcB, N, M, p->x1,
-                               p->dx, p->dy, p->half_domain, 0);
-        hipLaunchKernelGGL(k_targets, dim3(cdiv(2 * d.ntg, 256)), dim3(256), 0, s, w.nodes, w.ydiv, u[i], p->beta,
-                           p->beta_x, p->beta_y, w.tg, w.tg32, N, M, p->x1, p->dx, p->y1, p->dy, 0);
         PairDesc &D = descs[i];
-        D.srcS = w.srcS;
-        D.srcB = w.srcB;
-        D.tg = (prec == BIM_FP64) ? (const void *)w.tg : (const void *)w.tg32;
-        D.tg64 = w.tg;
-        D.dx = p->dx;
-        D.part = w.part;
-        D.N = N;
-        D.M = M;
-        D.nimg = d.nimg;
-        D.y1 = p->y1;
-        D.dy = p->dy;
-        D.tiles_per_bnd = pl.tiles_per_bnd;
-        D.row_groups = pl.row_groups;
-        D.target_tiles = pl.target_tiles;
-        D.chunks = pl.chunks;
+        D = make_desc(p, d, pl, ws[i], u[i], F[i], prec, 0);
         D.item0 = total;
         total += (long)pl.target_tiles * pl.chunks;
+        D.blk_int = b_int;
+        D.blk_rec = b_rec;
+        D.blk_fin = b_fin;
+        b_int += 3 * d.M;
+        b_rec += record_blocks(d.N, d.M);
+        b_fin += finalize_blocks(d.N, d.M);
     }
     BIM_HIP(hipMemcpyAsync(descs_dev, descs.data(), sizeof(PairDesc) * count, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_integrate_batched, dim3(b_int), dim3(64), 0, s, descs_dev, count);
+    if (prec == BIM_FP64)
+        hipLaunchKernelGGL(k_records_batched<double>, dim3(b_rec), dim3(256), 0, s, descs_dev, count);
+    else
+        hipLaunchKernelGGL(k_records_batched<float>, dim3(b_rec), dim3(256), 0, s, descs_dev, count);
     const long want = (total + 3) / 4;
     const int blocks = (int)std::max(1L, std::min(want, (long)(max_blocks > 0 ? max_blocks : 2048)));
     if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[0], s));
@@ -767,16 +895,7 @@ int residual_batched_enqueue(const bim_problem *probs, int count, const double *
     }
 #undef BIM_LAUNCH_BATCH
     if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[1], s));
-    for (int i = 0; i < count; ++i) {
-        const bim_problem *p = &probs[i];
-        const Dims d(p);
-        const int N = d.N, M = d.M;
-        const double xN = p->x1 + (N - 1) * p->dx, yM = p->y1 + (M - 1) * p->dy;
-        const double ylo = p->half_domain ? -yM : p->y1;
-        hipLaunchKernelGGL(k_finalize, dim3(cdiv(d.nvec, 256)), dim3(256), 0, s, u[i], ws[i].nodes, ws[i].ydiv,
-                           ws[i].tg, ws[i].part, F[i], N, M, pls[i].chunks, p->x1, p->dx, p->x1, xN, ylo, yM,
-                           p->n_decay, p->froude, 0);
-    }
+    hipLaunchKernelGGL(k_finalize_batched, dim3(b_fin), dim3(256), 0, s, descs_dev, count);
     return hip_check(hipGetLastError(), "batched residual launch");
 }
 
