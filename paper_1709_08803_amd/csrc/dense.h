@@ -31,6 +31,10 @@ int gemv_enqueue(const double *A, long lda, const double *x, const double *c, do
 int bandmv_enqueue(const double *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
                    double alpha, double beta, hipStream_t s);
 int copy2d_enqueue(const double *src, long lds, double *dst, long ldd, int rows, int cols, hipStream_t s);
+// Copies the rows x cols blocks (l, j), l < nl, j < nj, l + j < lim, from
+// src + l sl + j sj (leading dim lds) to dst + l dl + j dj (leading dim ldd).
+int copy_blocks_enqueue(const double *src, long sl, long sj, long lds, double *dst, long dl, long dj, long ldd,
+                        int rows, int cols, int nl, int nj, int lim, hipStream_t s);
 int identity_enqueue(double *A, long n, hipStream_t s);
 
 }  // namespace bim

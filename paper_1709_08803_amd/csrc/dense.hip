@@ -14,48 +14,60 @@ namespace {
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Operand pointers in the global address space: generic (flat) loads count on
+// the LDS counter as well, so an LDS read of the current K step would wait for
+// the next step's operand loads.
+template <typename T>
+using GlobalPtr = __attribute__((address_space(1))) T *;
+
 // C = alpha A B + beta C (row-major, FP64) on the matrix cores.  64 x 64 output
 // tile per 256-thread workgroup; each wave owns 32 x 32 = 2 x 2 tiles of
 // v_mfma_f64_16x16x4f64.  K advances through LDS in steps of 32, and the next
 // step's operands are loaded into registers while the current step's MFMAs run.
 // Operand layout of the 16x16x4 FP64 MFMA: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; the accumulator's element v of lane l is
-// D[l / 16 + 4 v][l % 16] (lane layout checked on gfx950).
+// D[l / 16 + 4 v][l % 16] (lane layout checked on gfx950).  Registers are
+// capped for three waves per SIMD (three workgroups per compute unit): a
+// single wave per SIMD leaves the matrix unit idle between its MFMAs (measured:
+// the preconditioner setup's batched block products 3 ms faster than at the
+// compiler's choice of two).
 constexpr int TM = 64, TN = 64, TK = 32;
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items, int m, int n, int k,
-                                              int lda, int ldb, int ldc, double alpha, double beta) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm(
+    const GemmItem *__restrict__ items, int m, int n, int k, int lda, int ldb, int ldc, double alpha, double beta) {
     const GemmItem it = items[blockIdx.z];
-    const double *__restrict__ A = it.A;
-    const double *__restrict__ B = it.B;
-    double *__restrict__ C = it.C;
+    const GlobalPtr<const double> A = (GlobalPtr<const double>)it.A;
+    const GlobalPtr<const double> B = (GlobalPtr<const double>)it.B;
+    const GlobalPtr<double> C = (GlobalPtr<double>)it.C;
     __shared__ double As[TM][TK + 1];
     __shared__ double Bs[TK][TN + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
     const int li = lane & 15, lk = lane >> 4;
-    // each thread stages 8 elements of A (rows e >> 5, cols e & 31) and 8 of B (rows e >> 6, cols e & 63)
+    // each thread stages 8 elements of A (rows e >> 5, cols e & 31) and 8 of B
+    // (rows e >> 6, cols e & 63).  Loads are unconditional, at indices clamped
+    // into the matrices: a row of A or a column of B outside the product only
+    // feeds outputs that are not stored, and B rows past k are zeroed when
+    // staged (the select sits there so that no load waits for its value).
     double ra[8], rb[8];
     auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int e = tid + q * 256;
             const int ar = e >> 5, ac = e & 31;
-            const int gr = row0 + ar, gc = k0 + ac;
-            ra[q] = (gr < m && gc < k) ? A[(size_t)gr * lda + gc] : 0.0;
+            ra[q] = A[(size_t)min(row0 + ar, m - 1) * lda + min(k0 + ac, k - 1)];
             const int br = e >> 6, bc = e & 63;
-            const int hr = k0 + br, hc = col0 + bc;
-            rb[q] = (hr < k && hc < n) ? B[(size_t)hr * ldb + hc] : 0.0;
+            rb[q] = B[(size_t)min(k0 + br, k - 1) * ldb + min(col0 + bc, n - 1)];
         }
     };
-    auto store = [&]() {
+    auto store = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int e = tid + q * 256;
             As[e >> 5][e & 31] = ra[q];
-            Bs[e >> 6][e & 63] = rb[q];
+            Bs[e >> 6][e & 63] = (k0 + (e >> 6) < k) ? rb[q] : 0.0;
         }
     };
     double4_t acc[2][2];
@@ -65,7 +77,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
         for (int u = 0; u < 2; ++u) acc[t][u] = double4_t{0.0, 0.0, 0.0, 0.0};
     if (k > 0) {
         load(0);
-        store();
+        store(0);
     }
     __syncthreads();
     for (int k0 = 0; k0 < k; k0 += TK) {
@@ -86,7 +98,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
         }
         __syncthreads();
         if (more) {
-            store();
+            store(k0 + TK);
             __syncthreads();
         }
     }
@@ -98,7 +110,115 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmItem *__restrict__ items
             for (int v = 0; v < 4; ++v) {
                 const int gr = row0 + wm + 16 * t + lk + 4 * v, gc = col0 + wn + 16 * u + li;
                 if (gr < m && gc < n) {
-                    double *p = C + (size_t)gr * ldc + gc;
+                    const GlobalPtr<double> p = C + (size_t)gr * ldc + gc;
+                    *p = (beta == 0.0) ? alpha * acc[t][u][v] : fma(alpha, acc[t][u][v], beta * (*p));
+                }
+            }
+}
+
+// The same product for 128 < m <= 192 (the preconditioner's block rows, m = s):
+// one workgroup holds all m rows of a TN-column panel, so that the workgroup
+// count cdiv(n, TN) can be matched to the 256 compute units (a 64 x 64 tiling
+// of 182 x 11102 gives 522 workgroups: three rounds, the last nearly empty).
+// NW waves; wave w owns the 12 / NW row blocks of 16 rows from 16 (12 / NW) w
+// (all TN / 16 column blocks).  K steps of 32 through two LDS buffers: the
+// next step's operands are loaded into registers while the current step's
+// MFMAs run and stored into the other buffer, one barrier per step.  The LDS
+// buffers (118-135 KB) allow one workgroup per compute unit, so NW = 12 gives
+// three waves per SIMD, which keep the matrix unit busy (with NW = 4, one wave
+// per SIMD, the setup's S^-1 products took 10 ms more at 181 x 61).
+constexpr int kTallM = 192, kTallK = 32, kTallWaves = 12;
+
+template <int TN, int NW>
+__global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItem *__restrict__ items, int m, int n, int k,
+                                                       int lda, int ldb, int ldc, double alpha, double beta) {
+    constexpr int NT = 64 * NW, NB = TN / 16, RB = 12 / NW;
+    constexpr int QA = kTallM * kTallK / NT, QB = (kTallK * TN + NT - 1) / NT;
+    static_assert(QA * NT == kTallM * kTallK && RB * NW == 12, "tall tile shape");
+    const GemmItem it = items[blockIdx.z];
+    const GlobalPtr<const double> A = (GlobalPtr<const double>)it.A;
+    const GlobalPtr<const double> B = (GlobalPtr<const double>)it.B;
+    const GlobalPtr<double> C = (GlobalPtr<double>)it.C;
+    __shared__ double As[2][kTallM][kTallK + 1];
+    __shared__ double Bs[2][kTallK][TN + 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave * 16 * RB;
+    const int col0 = blockIdx.x * TN;
+    const int li = lane & 15, lk = lane >> 4;
+    // unconditional loads at clamped indices, B rows past k zeroed when staged
+    // (as in k_gemm)
+    double ra[QA], rb[QB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + q * NT;
+            const int ar = e >> 5, ac = e & 31;
+            ra[q] = A[(size_t)min(ar, m - 1) * lda + min(k0 + ac, k - 1)];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = min(tid + q * NT, kTallK * TN - 1);
+            const int br = e / TN, bc = e - br * TN;
+            rb[q] = B[(size_t)min(k0 + br, k - 1) * ldb + min(col0 + bc, n - 1)];
+        }
+    };
+    auto store = [&](int buf, int k0) {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + q * NT;
+            As[buf][e >> 5][e & 31] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + q * NT;
+            if (e < kTallK * TN) {
+                const int br = e / TN;
+                Bs[buf][br][e - br * TN] = (k0 + br < k) ? rb[q] : 0.0;
+            }
+        }
+    };
+    double4_t acc[RB][NB];
+#pragma unroll
+    for (int t = 0; t < RB; ++t)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[t][u] = double4_t{0.0, 0.0, 0.0, 0.0};
+    if (k > 0) {
+        load(0);
+        store(0, 0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < k; k0 += kTallK) {
+        const bool more = k0 + kTallK < k;
+        if (more) load(k0 + kTallK);
+#pragma unroll
+        for (int kk = 0; kk < kTallK; kk += 4) {
+            double a[RB], b[NB];
+#pragma unroll
+            for (int t = 0; t < RB; ++t) a[t] = As[buf][wm + 16 * t + li][kk + lk];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) b[u] = Bs[buf][kk + lk][16 * u + li];
+#pragma unroll
+            for (int t = 0; t < RB; ++t)
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
+        }
+        // the other buffer was last read in the previous step, before its barrier
+        if (more) store(buf ^ 1, k0 + kTallK);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int t = 0; t < RB; ++t)
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gr = wm + 16 * t + lk + 4 * v, gc = col0 + 16 * u + li;
+                if (gr < m && gc < n) {
+                    const GlobalPtr<double> p = C + (size_t)gr * ldc + gc;
                     *p = (beta == 0.0) ? alpha * acc[t][u][v] : fma(alpha, acc[t][u][v], beta * (*p));
                 }
             }
@@ -500,10 +620,40 @@ __global__ void k_copy2d(const double *__restrict__ src, long lds, double *__res
     dst[(size_t)r * ldd + c] = src[(size_t)r * lds + c];
 }
 
+// Block (l, j) of a strided family of rows x cols blocks, copied when
+// l + j < lim: source src + l sl + j sj (leading dim lds), destination
+// dst + l dl + j dj (leading dim ldd).  Grid (elements, l, j).
+__global__ void k_copy_blocks(const double *__restrict__ src, long sl, long sj, long lds, double *__restrict__ dst,
+                              long dl, long dj, long ldd, int rows, int cols, int lim) {
+    const int l = blockIdx.y, j = blockIdx.z;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l + j >= lim || e >= (long)rows * cols) return;
+    const int r = (int)(e / cols), c = (int)(e % cols);
+    dst[(size_t)l * dl + (size_t)j * dj + (size_t)r * ldd + c] = src[(size_t)l * sl + (size_t)j * sj + (size_t)r * lds + c];
+}
+
 __global__ void k_identity(double *A, long n) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n * n) return;
     A[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+// Panel width of the tall product for a single m x n product with
+// 128 < m <= 192 (0: the 64 x 64 tiling).  Per compute unit the time goes as
+// the rounds of 256 workgroups times the outputs of one workgroup: 64 x 64
+// tiles against 192-row panels of width 32, 48 or 64; ties keep the tiles.
+int tall_panel_width(int batch, int m, int n) {
+    if (batch != 1 || m <= 128 || m > kTallM) return 0;
+    int best = 0;
+    long best_cost = (long)cdiv((long)cdiv(n, TN) * cdiv(m, TM), 256) * TM * TN;
+    for (int tn : {64, 48, 32}) {
+        const long cost = (long)cdiv(cdiv(n, tn), 256) * kTallM * tn;
+        if (cost < best_cost) {
+            best = tn;
+            best_cost = cost;
+        }
+    }
+    return best;
 }
 
 }  // namespace
@@ -512,8 +662,23 @@ int gemm_enqueue(const GemmItem *items_dev, int batch, int m, int n, int k, int 
                  double alpha, double beta, hipStream_t s) {
     if (batch <= 0 || m <= 0 || n <= 0) return BIM_OK;
     if (batch > 65535) return fail(BIM_EINVAL, "gemm batch too large");
-    dim3 grid(cdiv(n, TN), cdiv(m, TM), batch);
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, items_dev, m, n, k, lda, ldb, ldc, alpha, beta);
+    const int tn = tall_panel_width(batch, m, n);
+    if (tn == 0) {
+        dim3 grid(cdiv(n, TN), cdiv(m, TM), batch);
+        hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, items_dev, m, n, k, lda, ldb, ldc, alpha, beta);
+    } else {
+        dim3 grid(cdiv(n, tn), 1, batch);
+        constexpr int NW = kTallWaves;
+        if (tn == 32)
+            hipLaunchKernelGGL((k_gemm_tall<32, NW>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
+                               alpha, beta);
+        else if (tn == 48)
+            hipLaunchKernelGGL((k_gemm_tall<48, NW>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
+                               alpha, beta);
+        else
+            hipLaunchKernelGGL((k_gemm_tall<64, NW>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
+                               alpha, beta);
+    }
     return hip_check(hipGetLastError(), "gemm launch");
 }
 
@@ -554,6 +719,15 @@ int copy2d_enqueue(const double *src, long lds, double *dst, long ldd, int rows,
     if (rows <= 0 || cols <= 0) return BIM_OK;
     hipLaunchKernelGGL(k_copy2d, dim3(cdiv((long)rows * cols, 256)), dim3(256), 0, s, src, lds, dst, ldd, rows,
                        cols);
+    return hip_check(hipGetLastError(), "copy launch");
+}
+
+int copy_blocks_enqueue(const double *src, long sl, long sj, long lds, double *dst, long dl, long dj, long ldd,
+                        int rows, int cols, int nl, int nj, int lim, hipStream_t s) {
+    if (rows <= 0 || cols <= 0 || nl <= 0 || nj <= 0) return BIM_OK;
+    if (nl > 65535 || nj > 65535) return fail(BIM_EINVAL, "too many blocks to copy");
+    hipLaunchKernelGGL(k_copy_blocks, dim3(cdiv((long)rows * cols, 256), nl, nj), dim3(256), 0, s, src, sl, sj, lds,
+                       dst, dl, dj, ldd, rows, cols, lim);
     return hip_check(hipGetLastError(), "copy launch");
 }
 

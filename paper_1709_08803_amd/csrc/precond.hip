@@ -406,7 +406,8 @@ int precond_build(const bim_problem *p, int hb, Precond **out, hipStream_t st) {
         // T := B23 ; S := 0 with D22 on the diagonal
         RUN(copy2d_enqueue(pc->B23, 1, T, 1, 1, (int)band_elems(M, h, s), st));
         RUN(hip_check(hipMemsetAsync(S, 0, sizeof(double) * band_elems(M, w2, s), st), "memset"));
-        for (int l = 0; l < M; ++l) RUN(copy2d_enqueue(D22, s, band_blk(S, w2, s, l, l), s, s, s, st));
+        const long bs = (long)s * s, brow = (long)(2 * w2 + 1) * bs;  // one block; one block row of S
+        RUN(copy_blocks_enqueue(D22, 0, 0, s, band_blk(S, w2, s, 0, 0), brow, 0, s, s, s, M, 1, M, st));
         for (size_t q = 1; q < lu_ops_first[0]; ++q) RUN(run_op(ops[q]));
         // zero L/U row buffers (short rows at the ends stay zero)
         RUN(hip_check(hipMemsetAsync(Lrow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));
@@ -415,11 +416,10 @@ int precond_build(const bim_problem *p, int hb, Precond **out, hipStream_t st) {
             RUN(invert_enqueue(inv_dev + 2 + l, 1, s, invwork, info + 2 + l, st));
             for (size_t q = 0; q < lu_ops_count[l]; ++q) RUN(run_op(ops[lu_ops_first[l] + q]));
         }
-        // U rows: U[l][m] for m = l+1..l+2h packed as [l][s][2h s]
-        for (int l = 0; l < M; ++l)
-            for (int m = l + 1; m <= std::min(M - 1, l + w2); ++m)
-                RUN(copy2d_enqueue(band_blk(S, w2, s, l, m), s, Urow + ((size_t)l * s) * (w2 * s) + (size_t)(m - l - 1) * s,
-                                   w2 * s, s, s, st));
+        // U rows: U[l][m] for m = l+1..l+2h packed as [l][s][2h s] (block j = m - l - 1,
+        // copied while l + j + 1 < M)
+        RUN(copy_blocks_enqueue(S + (size_t)(w2 + 1) * bs, brow, bs, s, Urow, (long)s * w2 * s, s, (long)w2 * s, s, s,
+                                M, w2, M - 1, st));
         // S^-1: forward with L (unit lower), backward with U
         RUN(identity_enqueue(pc->Sinv, n, st));
         std::vector<GemmItem> fw, bw1, bw2;

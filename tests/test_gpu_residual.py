@@ -196,3 +196,35 @@ def test_autotuner_choice_is_used_and_correct(bim):
     F_ref = R.residual(p, u)
     scale = R.term_magnitude_rows(p, u)
     assert (np.abs(F.cpu().numpy() - F_ref) / scale).max() <= 1e-12
+
+
+def test_workspace_reuse_across_sizes_streams_and_release(bim):
+    """The per-stream workspace of residual() and jv(): a larger problem grows it,
+    a smaller one reuses it, another stream gets its own, and after a release the
+    next call allocates again; every result equals the first evaluation bit for bit."""
+    small = W.tiny(0.7)
+    big = W.working(1.4, N=61, M=21)
+    cases = {}
+    for name, p in (("small", small), ("big", big)):
+        dp = bim.DeviceProblem(p)
+        u = torch.as_tensor(W.perturbed_state(p, 7), device="cuda")
+        cases[name] = (dp, u)
+    bim.release_workspaces()
+    ref = {k: bim.residual(dp, u).cpu().numpy() for k, (dp, u) in cases.items()}  # small first, then grow
+    side = torch.cuda.Stream()
+    for order in (("small", "big", "small"), ("big", "small")):
+        for k in order:
+            dp, u = cases[k]
+            assert np.array_equal(bim.residual(dp, u).cpu().numpy(), ref[k]), k
+            with torch.cuda.stream(side):
+                F = bim.residual(dp, u, stream=side)
+            side.synchronize()
+            assert np.array_equal(F.cpu().numpy(), ref[k]), (k, "side stream")
+        bim.release_workspaces()
+    dp, u = cases["small"]
+    F0 = bim.residual(dp, u)
+    v = torch.ones_like(u)
+    J1 = bim.jv(dp, u, F0, v, h=1e-7)
+    J2 = bim.jv(dp, u, F0, v, h=1e-7)
+    assert torch.equal(J1, J2)
+    bim.release_workspaces()
