@@ -15,9 +15,10 @@ this workload: 0.720 ms per evaluation over the 50 evaluations after a
 Also reported: the FP32-compensated evaluation, the all-pairs kernel's
 roofline fraction from HIP events on the launch stream, the time to a converged
 solve (preconditioner setup, linear start and JFNK with FP64 or FP32-compensated
-inner sums, with the distance between the two solutions and, where a stored
-oracle solution of the same problem exists, to it), and the CPU oracle timed on
-a bounded sample of the same workload on this host's cores.
+inner sums and an FP64- or FP32-stored preconditioner, with the distance between
+the solutions and, where a stored oracle solution of the same problem exists, to
+it), and the CPU oracle timed on a bounded sample of the same workload on this
+host's cores.
 """
 import argparse
 import json
@@ -81,56 +82,70 @@ LINEAR_START_RTOL = 1e-8
 
 
 def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15):
-    """Wall time from the mesh to ||F||_inf <= ftol on the 181 x 61 problem at one F."""
+    """Wall time from the mesh to ||F||_inf <= ftol on the 181 x 61 problem at one F.
+
+    Each preconditioner storage (FP64, FP32) has its own setup and linear start;
+    a leg's total is its storage's setup and linear start plus its solve."""
     p = W.working(froude)
     dp = B.DeviceProblem(p)
     nb = (p.N + 1) * p.M
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    P = B.Preconditioner(dp)
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    # the start solves the linear system to the relative tolerance of every
-    # Newton step's GMRES (1e-8): a tighter one changes no Newton count
-    ulin = B.linear_start(dp, P, rtol=LINEAR_START_RTOL)
-    torch.cuda.synchronize()
-    t_lin = time.perf_counter() - t0
-    res = {"froude": froude, "band_halfwidth": P.band, "precond_setup_ms": t_setup * 1e3,
-           "linear_start_ms": t_lin * 1e3, "linear_start_rtol": LINEAR_START_RTOL}
+    res = {"froude": froude, "linear_start_rtol": LINEAR_START_RTOL}
+    # leg: (preconditioner storage, solver options)
+    #   fp64:         FP64 sums, FP64-stored P (the plain FP64 solve)
+    #   fp32c:        FP32C sums with the library's GMRES tolerance for such steps
+    #                 (1e-4, the level their Jacobian action resolves), FP32-stored P
+    #   fp32c_p64:    the same with the FP64-stored P
+    #   fp32c_strict: FP32C sums with every GMRES solve at 1e-8, FP64-stored P
+    #   fp64_p32:     FP64 sums, FP32-stored P
+    legs = {"fp64": ("fp64", dict(inner_prec="fp64")),
+            "fp32c": ("fp32", dict(inner_prec="fp32c")),
+            "fp32c_p64": ("fp64", dict(inner_prec="fp32c")),
+            "fp32c_strict": ("fp64", dict(inner_prec="fp32c", fp32c_gmres_rtol=0.0)),
+            "fp64_p32": ("fp32", dict(inner_prec="fp64"))}
     sols = {}
-    # fp32c: FP32C inner sums with the library's default GMRES tolerance for
-    # such steps (1e-4, the level their Jacobian action resolves);
-    # fp32c_strict: the same sums with every GMRES solve at 1e-8
-    legs = {"fp64": dict(inner_prec="fp64"), "fp32c": dict(inner_prec="fp32c"),
-            "fp32c_strict": dict(inner_prec="fp32c", fp32c_gmres_rtol=0.0)}
-    for prec, kw in legs.items():
-        u = ulin.clone()
+    for storage in ("fp64", "fp32"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rep = B.solve(dp, u, P, ftol=ftol, check=False, max_newton=max_newton, **kw)
+        P = B.Preconditioner(dp, storage=storage)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        sols[prec] = u.cpu().numpy()
-        res[prec] = {"status": rep["status"], "solve_ms": dt * 1e3,
-                     "total_ms": (dt + t_setup + t_lin) * 1e3, "newton": rep["newton_iters"],
-                     "gmres": rep["gmres_iters"], "jv_evals": rep["jv_evals"],
-                     "residual_evals": rep["residual_evals"], "fnorm_inf": rep["fnorm_inf"]}
-    P.close()
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        # the start solves the linear system to the relative tolerance of every
+        # Newton step's GMRES (1e-8): a tighter one changes no Newton count
+        ulin = B.linear_start(dp, P, rtol=LINEAR_START_RTOL)
+        torch.cuda.synchronize()
+        t_lin = time.perf_counter() - t0
+        res[f"precond_{storage}"] = {"setup_ms": t_setup * 1e3, "linear_start_ms": t_lin * 1e3,
+                                     "band_halfwidth": P.band, "bytes": P.nbytes}
+        for leg, (st, kw) in legs.items():
+            if st != storage:
+                continue
+            u = ulin.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = B.solve(dp, u, P, ftol=ftol, check=False, max_newton=max_newton, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            sols[leg] = u.cpu().numpy()
+            res[leg] = {"precond_storage": storage, "status": rep["status"], "solve_ms": dt * 1e3,
+                        "total_ms": (dt + t_setup + t_lin) * 1e3, "newton": rep["newton_iters"],
+                        "gmres": rep["gmres_iters"], "jv_evals": rep["jv_evals"],
+                        "residual_evals": rep["residual_evals"], "fnorm_inf": rep["fnorm_inf"]}
+        P.close()
     d = sols["fp32c"] - sols["fp64"]
     res["fp32c_vs_fp64"] = {"max_dzeta_x": float(np.abs(d[:nb]).max()),
                             "max_dphi_x": float(np.abs(d[nb:2 * nb]).max())}
-    for leg in ("fp32c", "fp32c_strict"):
-        if res["fp64"]["status"] == 0 and res[leg]["status"] == 0:
+    for leg in legs:
+        if leg != "fp64" and res["fp64"]["status"] == 0 and res[leg]["status"] == 0:
             res[f"speedup_{leg}"] = res["fp64"]["solve_ms"] / res[leg]["solve_ms"]
             res[f"speedup_{leg}_total"] = res["fp64"]["total_ms"] / res[leg]["total_ms"]
     gold = os.path.join(HERE, "tests", "golden", f"working_181x61_F{froude}.npz")
     if os.path.exists(gold):
         ref = np.load(gold)["u"]
         zr, pr = node_values(p, ref, 0), node_values(p, ref, 1)
-        for prec, u in sols.items():
-            res[prec]["max_dzeta_vs_oracle"] = float(np.abs(node_values(p, u, 0) - zr).max())
-            res[prec]["max_dphi_vs_oracle"] = float(np.abs(node_values(p, u, 1) - pr).max())
+        for leg, u in sols.items():
+            res[leg]["max_dzeta_vs_oracle"] = float(np.abs(node_values(p, u, 0) - zr).max())
+            res[leg]["max_dphi_vs_oracle"] = float(np.abs(node_values(p, u, 1) - pr).max())
     return res
 
 

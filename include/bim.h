@@ -48,6 +48,9 @@ enum {
 
 /* Precision of the all-pairs boundary-integral sums (the rest is always FP64). */
 enum { BIM_FP64 = 0, BIM_FP32C = 1 };
+/* Storage of the preconditioner's operator (precond_setup_ex): FP64, or FP32
+ * elements applied with FP64 products and sums. */
+enum { BIM_STORE_FP64 = 0, BIM_STORE_FP32 = 1 };
 
 /*
  * One discrete problem (Section 3.1): the truncated mesh x_i = x1 + i dx
@@ -163,6 +166,19 @@ int bim_tune_residual(const bim_problem *prob, const double *u, int prec, void *
  */
 typedef struct bim_precond bim_precond;
 int precond_setup(const bim_problem *prob, int band_halfwidth, bim_precond **out, void *stream);
+/*
+ * precond_setup with the storage of the factored operator: BIM_STORE_FP64 (as
+ * precond_setup), or BIM_STORE_FP32: the arrays the apply reads (the banded
+ * blocks, the replicated diagonal inverses and the dense Schur-complement
+ * inverse) are rounded to FP32 after the FP64 factorisation, halving the
+ * apply's memory traffic and precond_bytes().  The apply still forms its
+ * products and sums in FP64.  P is then a fixed operator within ~1e-7 relative of
+ * the FP64 one.  GMRES sees a slightly different but equally good
+ * preconditioner; the Newton residual, and so the solution, is unchanged.
+ * Returns BIM_EINVAL for any other storage value.
+ */
+int precond_setup_ex(const bim_problem *prob, int band_halfwidth, int storage, bim_precond **out, void *stream);
+int precond_storage(const bim_precond *P);
 int precond_apply(const bim_precond *P, const double *r, double *z, void *stream);
 void precond_destroy(bim_precond *P);
 int64_t precond_bytes(const bim_precond *P);
@@ -184,9 +200,10 @@ int precond_band(const bim_precond *P);
  *   use_precond:    0 runs GMRES without preconditioning;
  *   use_graphs, fd_eps, stall_steps, fp64_below, fp32c_gmres_rtol: see the fields.
  * jfnk_default_opts fills 1e-10, 1e-8, 30, 10, 30, 20, BIM_FP64, -1, 1, 1, 0.0, 0,
- * 0.0, 1e-4.
+ * 0.0, 1e-4, BIM_STORE_FP64.
  * Invalid values (non-positive tolerances, restart outside [1, 200], negative
- * counts, fd_eps >= 1 or NaN, negative or NaN fp64_below, unknown precision)
+ * counts, fd_eps >= 1 or NaN, negative or NaN fp64_below, unknown precision
+ * or storage)
  * give BIM_EINVAL.
  */
 typedef struct bim_jfnk_opts {
@@ -211,6 +228,8 @@ typedef struct bim_jfnk_opts {
                             FP32C inner sums (their Jacobian action carries rounding noise of
                             order 1e-6 relative, below which GMRES stalls): the effective
                             tolerance is max(this, gmres_rtol); default 1e-4, <= 0: gmres_rtol */
+    int32_t precond_storage; /* storage of a preconditioner the solver builds itself (P == NULL):
+                            BIM_STORE_FP64 or BIM_STORE_FP32 (see precond_setup_ex) */
 } bim_jfnk_opts;
 
 /* Outcome of a solve (host struct).  history[k] = ||F||_inf after k Newton steps. */

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libbim.so")
 FP64 = 0
 FP32C = 1
 _PREC = {"fp64": FP64, "fp32c": FP32C, FP64: FP64, FP32C: FP32C}
+STORE_FP64, STORE_FP32 = 0, 1
+_STORE = {"fp64": STORE_FP64, "fp32": STORE_FP32, STORE_FP64: STORE_FP64, STORE_FP32: STORE_FP32}
 
 _lib = None
 
@@ -54,6 +56,8 @@ def lib():
                                          ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
         L.bim_tune_residual.argtypes = [pp, vp, i32, vp, ctypes.POINTER(PairConfig), ctypes.POINTER(dbl)]
         L.precond_setup.argtypes = [pp, i32, ctypes.POINTER(vp), vp]
+        L.precond_setup_ex.argtypes = [pp, i32, i32, ctypes.POINTER(vp), vp]
+        L.precond_storage.argtypes = [vp]
         L.precond_apply.argtypes = [vp, vp, vp, vp]
         L.precond_destroy.argtypes = [vp]
         L.precond_destroy.restype = None
@@ -83,7 +87,7 @@ def lib():
         L.lg_make_input.argtypes = [pp, vp, i32, vp, vp, vp]
         L.lg_infer_start.argtypes = [vp, pp, vp, vp, vp]
         for name in ("bim_residual", "bim_jv", "bim_residual_timed", "bim_tune_residual", "precond_setup",
-                     "precond_apply", "precond_band", "jfnk_solve", "bim_linear_start", "lg_create",
+                     "precond_setup_ex", "precond_storage", "precond_apply", "precond_band", "jfnk_solve", "bim_linear_start", "lg_create",
                      "lg_num_params", "lg_set_params", "lg_get_params", "lg_forward", "lg_train_step",
                      "lg_make_input", "lg_infer_start"):
             getattr(L, name).restype = i32
@@ -122,7 +126,8 @@ class JfnkOpts(ctypes.Structure):
                 ("max_restarts", ctypes.c_int32), ("max_newton", ctypes.c_int32), ("max_backtracks", ctypes.c_int32),
                 ("inner_prec", ctypes.c_int32), ("band_halfwidth", ctypes.c_int32), ("use_precond", ctypes.c_int32),
                 ("use_graphs", ctypes.c_int32), ("fd_eps", ctypes.c_double), ("stall_steps", ctypes.c_int32),
-                ("fp64_below", ctypes.c_double), ("fp32c_gmres_rtol", ctypes.c_double)]
+                ("fp64_below", ctypes.c_double), ("fp32c_gmres_rtol", ctypes.c_double),
+                ("precond_storage", ctypes.c_int32)]
 
 
 class JfnkReport(ctypes.Structure):
@@ -219,10 +224,17 @@ def tune_residual(dp: DeviceProblem, u: torch.Tensor, prec="fp64", stream=None):
 class Preconditioner:
     """Library-owned block-banded preconditioner P (freed with close() or on deletion)."""
 
-    def __init__(self, dp: DeviceProblem, band_halfwidth: int = -1, stream=None):
+    def __init__(self, dp: DeviceProblem, band_halfwidth: int = -1, stream=None, storage="fp64"):
+        """storage: "fp64", or "fp32" (operator rounded to FP32 after the FP64
+        factorisation; products and sums of the apply stay FP64)."""
         self._h = ctypes.c_void_p()
         self.dp = dp
-        _check(lib().precond_setup(dp.ref(), int(band_halfwidth), ctypes.byref(self._h), _stream(stream)))
+        _check(lib().precond_setup_ex(dp.ref(), int(band_halfwidth), _STORE[storage], ctypes.byref(self._h),
+                                      _stream(stream)))
+
+    @property
+    def storage(self) -> str:
+        return {STORE_FP64: "fp64", STORE_FP32: "fp32"}[lib().precond_storage(self._h)]
 
     @property
     def handle(self):
@@ -259,6 +271,8 @@ def default_opts(**kw) -> JfnkOpts:
     for k, v in kw.items():
         if k == "inner_prec":
             v = _PREC[v]
+        if k == "precond_storage":
+            v = _STORE.get(v, v)  # names, or the library's integer values (which it validates)
         setattr(o, k, v)
     return o
 

@@ -49,25 +49,29 @@ int b_shift(const BOp *ops, int count, hipStream_t s);
 int b_gather(const BOp *ops, int count, hipStream_t s);
 
 // One slice-block-banded product y = alpha B x + beta c of one problem.
+// band holds FP64 elements, or FP32 ones when f32 != 0 (products and sums in FP64).
 struct BBand {
-    const double *band;
+    const void *band;
     const double *x;
     const double *c;
     double *y;
     int M, w, s;
     double alpha, beta;
+    int f32;
 };
 // max_groups: the largest M ceil(s / 4) over the ops (waves needed by the largest problem)
 int b_bandmv(const BBand *ops, int count, int max_groups, hipStream_t s);
 // One dense product y = alpha A x + beta c (rows x cols, row stride lda).
+// A holds FP64 elements, or FP32 ones when f32 != 0.
 struct BGemv {
-    const double *A;
+    const void *A;
     const double *x;
     const double *c;
     double *y;
     long lda;
     int rows, cols;
     double alpha, beta;
+    int f32;
 };
 int b_gemv(const BGemv *ops, int count, int max_rows, hipStream_t s);
 

@@ -120,32 +120,34 @@ __global__ void k_bshift(const BOp *__restrict__ ops, int count) {
 
 // Banded and dense products of many problems in one launch (blockIdx.y picks
 // the problem).  Each wave owns kBGR consecutive rows (of one slice for the
-// banded product) and reads 16 bytes per lane per row when the rows are
-// 16-byte aligned (even s or lda), loading each x segment once for its rows;
-// otherwise 8 bytes per lane.
+// banded product) and reads two elements per lane per row (16 bytes in FP64,
+// 8 in FP32) when the rows are aligned to two elements (even s or lda),
+// loading each x segment once for its rows; otherwise one element per lane.
 constexpr int kBGR = 4;
 typedef double bdouble2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void brows_dot(const double *const (&row)[kBGR], const double *__restrict__ x, int len,
+template <typename TA>
+__device__ __forceinline__ void brows_dot(const TA *const (&row)[kBGR], const double *__restrict__ x, int len,
                                           bool vec, int lane, double (&acc)[kBGR]) {
+    typedef TA ta2 __attribute__((ext_vector_type(2)));
     if (vec) {
         for (int q = lane; q < (len >> 1); q += 64) {
             const bdouble2 xv = *reinterpret_cast<const bdouble2 *>(x + 2 * q);
 #pragma unroll
             for (int r = 0; r < kBGR; ++r) {
-                const bdouble2 av = *reinterpret_cast<const bdouble2 *>(row[r] + 2 * q);
-                acc[r] = fma(av[0], xv[0], acc[r]);
-                acc[r] = fma(av[1], xv[1], acc[r]);
+                const ta2 av = *reinterpret_cast<const ta2 *>(row[r] + 2 * q);
+                acc[r] = fma((double)av[0], xv[0], acc[r]);
+                acc[r] = fma((double)av[1], xv[1], acc[r]);
             }
         }
         if ((len & 1) && lane == 0)
 #pragma unroll
-            for (int r = 0; r < kBGR; ++r) acc[r] = fma(row[r][len - 1], x[len - 1], acc[r]);
+            for (int r = 0; r < kBGR; ++r) acc[r] = fma((double)row[r][len - 1], x[len - 1], acc[r]);
     } else {
         for (int j = lane; j < len; j += 64) {
             const double xv = x[j];
 #pragma unroll
-            for (int r = 0; r < kBGR; ++r) acc[r] = fma(row[r][j], xv, acc[r]);
+            for (int r = 0; r < kBGR; ++r) acc[r] = fma((double)row[r][j], xv, acc[r]);
         }
     }
 }
@@ -164,6 +166,20 @@ __device__ __forceinline__ void brows_store(double (&acc)[kBGR], int lane, int n
     }
 }
 
+template <typename TA>
+__device__ __forceinline__ void bband_rows(const BBand &o, int l, int r0, int lane, double (&acc)[kBGR]) {
+    const TA *band = (const TA *)o.band;
+    const int m0 = max(0, l - o.w), m1 = min(o.M - 1, l + o.w);
+    const bool vec = (o.s % 2 == 0) && ((uintptr_t)band % (2 * sizeof(TA)) == 0) && ((uintptr_t)o.x % 16 == 0);
+    for (int m = m0; m <= m1; ++m) {
+        const TA *blk = band + ((size_t)l * (2 * o.w + 1) + (m - l + o.w)) * o.s * o.s;
+        const TA *row[kBGR];
+#pragma unroll
+        for (int r = 0; r < kBGR; ++r) row[r] = blk + (size_t)min(r0 + r, o.s - 1) * o.s;
+        brows_dot<TA>(row, o.x + (size_t)m * o.s, o.s, vec, lane, acc);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_bbandmv(const BBand *__restrict__ ops) {
     const BBand o = ops[blockIdx.y];
     const int gps = (o.s + kBGR - 1) / kBGR;  // row groups per slice
@@ -171,17 +187,20 @@ __global__ __launch_bounds__(256) void k_bbandmv(const BBand *__restrict__ ops) 
     const int lane = threadIdx.x & 63;
     if (wave >= o.M * gps) return;
     const int l = wave / gps, r0 = (wave - l * gps) * kBGR;
-    const int m0 = max(0, l - o.w), m1 = min(o.M - 1, l + o.w);
-    const bool vec = (o.s % 2 == 0) && ((uintptr_t)o.band % 16 == 0) && ((uintptr_t)o.x % 16 == 0);
     double acc[kBGR] = {};
-    for (int m = m0; m <= m1; ++m) {
-        const double *blk = o.band + ((size_t)l * (2 * o.w + 1) + (m - l + o.w)) * o.s * o.s;
-        const double *row[kBGR];
-#pragma unroll
-        for (int r = 0; r < kBGR; ++r) row[r] = blk + (size_t)min(r0 + r, o.s - 1) * o.s;
-        brows_dot(row, o.x + (size_t)m * o.s, o.s, vec, lane, acc);
-    }
+    if (o.f32) bband_rows<float>(o, l, r0, lane, acc);
+    else bband_rows<double>(o, l, r0, lane, acc);
     brows_store(acc, lane, min(kBGR, o.s - r0), o.y, o.c, l * o.s + r0, o.alpha, o.beta);
+}
+
+template <typename TA>
+__device__ __forceinline__ void bgemv_rows(const BGemv &o, int row0, int lane, double (&acc)[kBGR]) {
+    const TA *A = (const TA *)o.A;
+    const bool vec = (o.lda % 2 == 0) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) && ((uintptr_t)o.x % 16 == 0);
+    const TA *row[kBGR];
+#pragma unroll
+    for (int r = 0; r < kBGR; ++r) row[r] = A + (size_t)min(row0 + r, o.rows - 1) * o.lda;
+    brows_dot<TA>(row, o.x, o.cols, vec, lane, acc);
 }
 
 __global__ __launch_bounds__(256) void k_bgemv(const BGemv *__restrict__ ops) {
@@ -190,12 +209,9 @@ __global__ __launch_bounds__(256) void k_bgemv(const BGemv *__restrict__ ops) {
     const int lane = threadIdx.x & 63;
     const int row0 = wave * kBGR;
     if (row0 >= o.rows) return;
-    const bool vec = (o.lda % 2 == 0) && ((uintptr_t)o.A % 16 == 0) && ((uintptr_t)o.x % 16 == 0);
-    const double *row[kBGR];
-#pragma unroll
-    for (int r = 0; r < kBGR; ++r) row[r] = o.A + (size_t)min(row0 + r, o.rows - 1) * o.lda;
     double acc[kBGR] = {};
-    brows_dot(row, o.x, o.cols, vec, lane, acc);
+    if (o.f32) bgemv_rows<float>(o, row0, lane, acc);
+    else bgemv_rows<double>(o, row0, lane, acc);
     brows_store(acc, lane, min(kBGR, o.rows - row0), o.y, o.c, row0, o.alpha, o.beta);
 }
 

@@ -25,11 +25,18 @@ int gemm_enqueue(const GemmItem *items_dev, int batch, int m, int n, int k, int 
 // work: device scratch of batch * s * 2s doubles; info[b] = 0 or (1 + column of a zero pivot).
 int invert_enqueue(const InvItem *items_dev, int batch, int s_dim, double *work, int *info, hipStream_t s);
 // y = alpha A x + beta c (dense, rows x cols, row-major with leading dim lda); c may equal y.
+// A in FP64 or FP32 (products and sums in FP64).
 int gemv_enqueue(const double *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
+                 double alpha, double beta, hipStream_t s);
+int gemv_enqueue(const float *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
                  double alpha, double beta, hipStream_t s);
 // y = alpha B x + beta c for a slice-block-banded B stored [M][2w+1][s][s]; c may equal y.
 int bandmv_enqueue(const double *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
                    double alpha, double beta, hipStream_t s);
+int bandmv_enqueue(const float *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
+                   double alpha, double beta, hipStream_t s);
+// dst[e] = (float) src[e], e < count
+int to_float_enqueue(const double *src, float *dst, size_t count, hipStream_t s);
 int copy2d_enqueue(const double *src, long lds, double *dst, long ldd, int rows, int cols, hipStream_t s);
 // Copies the rows x cols blocks (l, j), l < nl, j < nj, l + j < lim, from
 // src + l sl + j sj (leading dim lds) to dst + l dl + j dj (leading dim ldd).

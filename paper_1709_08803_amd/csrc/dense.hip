@@ -2,6 +2,7 @@
 // Gauss-Jordan inversion with partial pivoting, matrix-vector products.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -473,34 +474,39 @@ __global__ __launch_bounds__(kInvThreads) void k_invert(const InvItem *__restric
     }
 }
 
-// y[r] = alpha A[r, :] x + beta c[r] for a dense row-major n_rows x n_cols A:
-// one wave per row.
-__global__ __launch_bounds__(256) void k_gemv(const double *__restrict__ A, long lda, const double *__restrict__ x,
+// y[r] = alpha A[r, :] x + beta c[r] for a dense row-major n_rows x n_cols A
+// with elements of type TA (FP64, or FP32 for a preconditioner stored in FP32;
+// products and sums in FP64): one wave per row.
+template <typename TA>
+__global__ __launch_bounds__(256) void k_gemv(const TA *__restrict__ A, long lda, const double *__restrict__ x,
                                               const double *c, double *y, int n_rows, int n_cols,
                                               double alpha, double beta) {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= n_rows) return;
-    const double *a = A + (size_t)row * lda;
+    const TA *a = A + (size_t)row * lda;
     double v = 0.0;
-    for (int j = lane; j < n_cols; j += 64) v = fma(a[j], x[j], v);
+    for (int j = lane; j < n_cols; j += 64) v = fma((double)a[j], x[j], v);
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if (lane == 0) y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
 }
 
-// Same product for 16-byte aligned rows (even lda): each wave owns GR rows and
-// reads 16 bytes per lane per row, loading every x chunk once for its GR rows;
-// two chunks per iteration keep 2 GR KiB of each wave's loads in flight.
+// Same product for rows aligned to two elements (even lda): each wave owns GR
+// rows and reads two elements per lane per row (16 bytes in FP64, 8 in FP32),
+// loading every x chunk once for its GR rows; two chunks per iteration keep
+// each wave's loads of 2 GR chunks in flight.
 constexpr int GR = 4;
-__global__ __launch_bounds__(256) void k_gemv_rows(const double *__restrict__ A, long lda,
+template <typename TA>
+__global__ __launch_bounds__(256) void k_gemv_rows(const TA *__restrict__ A, long lda,
                                                    const double *__restrict__ x, const double *c, double *y,
                                                    int n_rows, int n_cols, double alpha, double beta) {
     typedef double double2_t __attribute__((ext_vector_type(2)));
+    typedef TA ta2_t __attribute__((ext_vector_type(2)));
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int row0 = wave * GR;
     if (row0 >= n_rows) return;
-    const double *arow[GR];
+    const TA *arow[GR];
 #pragma unroll
     for (int r = 0; r < GR; ++r) arow[r] = A + (size_t)min(row0 + r, n_rows - 1) * lda;
     double acc[GR] = {};
@@ -509,33 +515,33 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const double *__restrict__ A,
     for (; q + 64 < pairs; q += 128) {
         const double2_t x0 = *reinterpret_cast<const double2_t *>(x + 2 * q);
         const double2_t x1 = *reinterpret_cast<const double2_t *>(x + 2 * (q + 64));
-        double2_t a0[GR], a1[GR];
+        ta2_t a0[GR], a1[GR];
 #pragma unroll
         for (int r = 0; r < GR; ++r) {
-            a0[r] = *reinterpret_cast<const double2_t *>(arow[r] + 2 * q);
-            a1[r] = *reinterpret_cast<const double2_t *>(arow[r] + 2 * (q + 64));
+            a0[r] = *reinterpret_cast<const ta2_t *>(arow[r] + 2 * q);
+            a1[r] = *reinterpret_cast<const ta2_t *>(arow[r] + 2 * (q + 64));
         }
 #pragma unroll
         for (int r = 0; r < GR; ++r) {
-            acc[r] = fma(a0[r][0], x0[0], acc[r]);
-            acc[r] = fma(a0[r][1], x0[1], acc[r]);
-            acc[r] = fma(a1[r][0], x1[0], acc[r]);
-            acc[r] = fma(a1[r][1], x1[1], acc[r]);
+            acc[r] = fma((double)a0[r][0], x0[0], acc[r]);
+            acc[r] = fma((double)a0[r][1], x0[1], acc[r]);
+            acc[r] = fma((double)a1[r][0], x1[0], acc[r]);
+            acc[r] = fma((double)a1[r][1], x1[1], acc[r]);
         }
     }
     for (; q < pairs; q += 64) {
         const double2_t x0 = *reinterpret_cast<const double2_t *>(x + 2 * q);
 #pragma unroll
         for (int r = 0; r < GR; ++r) {
-            const double2_t a0 = *reinterpret_cast<const double2_t *>(arow[r] + 2 * q);
-            acc[r] = fma(a0[0], x0[0], acc[r]);
-            acc[r] = fma(a0[1], x0[1], acc[r]);
+            const ta2_t a0 = *reinterpret_cast<const ta2_t *>(arow[r] + 2 * q);
+            acc[r] = fma((double)a0[0], x0[0], acc[r]);
+            acc[r] = fma((double)a0[1], x0[1], acc[r]);
         }
     }
     if ((n_cols & 1) && lane == 0) {
         const int j = n_cols - 1;
 #pragma unroll
-        for (int r = 0; r < GR; ++r) acc[r] = fma(arow[r][j], x[j], acc[r]);
+        for (int r = 0; r < GR; ++r) acc[r] = fma((double)arow[r][j], x[j], acc[r]);
     }
 #pragma unroll
     for (int r = 0; r < GR; ++r)
@@ -550,8 +556,9 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const double *__restrict__ A,
 }
 
 // y_l = alpha sum_{m in band} B[l][m] x_m + beta c_l for slice-block-banded B
-// (blocks s x s, half-width w): one wave per row of y.
-__global__ __launch_bounds__(256) void k_bandmv(const double *__restrict__ band, int M, int w, int s,
+// (blocks s x s, half-width w, elements of type TA): one wave per row of y.
+template <typename TA>
+__global__ __launch_bounds__(256) void k_bandmv(const TA *__restrict__ band, int M, int w, int s,
                                                 const double *__restrict__ x, const double *c, double *y,
                                                 double alpha, double beta) {
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -561,21 +568,23 @@ __global__ __launch_bounds__(256) void k_bandmv(const double *__restrict__ band,
     double v = 0.0;
     const int m0 = max(0, l - w), m1 = min(M - 1, l + w);
     for (int m = m0; m <= m1; ++m) {
-        const double *b = band + (((size_t)l * (2 * w + 1) + (m - l + w)) * s + r) * s;
+        const TA *b = band + (((size_t)l * (2 * w + 1) + (m - l + w)) * s + r) * s;
         const double *xm = x + (size_t)m * s;
-        for (int j = lane; j < s; j += 64) v = fma(b[j], xm[j], v);
+        for (int j = lane; j < s; j += 64) v = fma((double)b[j], xm[j], v);
     }
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if (lane == 0) y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
 }
 
-// Same banded product for even s and 16-byte aligned operands: each wave owns
-// GR consecutive rows of one slice and reads 16 bytes per lane per row, loading
-// every x segment once for its rows.
-__global__ __launch_bounds__(256) void k_bandmv_rows(const double *__restrict__ band, int M, int w, int s,
+// Same banded product for even s and rows aligned to two elements: each wave
+// owns GR consecutive rows of one slice and reads two elements per lane per
+// row, loading every x segment once for its rows.
+template <typename TA>
+__global__ __launch_bounds__(256) void k_bandmv_rows(const TA *__restrict__ band, int M, int w, int s,
                                                      const double *__restrict__ x, const double *c, double *y,
                                                      double alpha, double beta) {
     typedef double double2_t __attribute__((ext_vector_type(2)));
+    typedef TA ta2_t __attribute__((ext_vector_type(2)));
     const int gps = (s + GR - 1) / GR;  // row groups per slice
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -585,18 +594,18 @@ __global__ __launch_bounds__(256) void k_bandmv_rows(const double *__restrict__ 
     const int pairs = s >> 1;
     double acc[GR] = {};
     for (int m = m0; m <= m1; ++m) {
-        const double *blk = band + ((size_t)l * (2 * w + 1) + (m - l + w)) * s * s;
+        const TA *blk = band + ((size_t)l * (2 * w + 1) + (m - l + w)) * s * s;
         const double *xm = x + (size_t)m * s;
         for (int q = lane; q < pairs; q += 64) {
             const double2_t xv = *reinterpret_cast<const double2_t *>(xm + 2 * q);
-            double2_t a[GR];
+            ta2_t a[GR];
 #pragma unroll
             for (int r = 0; r < GR; ++r)
-                a[r] = *reinterpret_cast<const double2_t *>(blk + (size_t)min(r0 + r, s - 1) * s + 2 * q);
+                a[r] = *reinterpret_cast<const ta2_t *>(blk + (size_t)min(r0 + r, s - 1) * s + 2 * q);
 #pragma unroll
             for (int r = 0; r < GR; ++r) {
-                acc[r] = fma(a[r][0], xv[0], acc[r]);
-                acc[r] = fma(a[r][1], xv[1], acc[r]);
+                acc[r] = fma((double)a[r][0], xv[0], acc[r]);
+                acc[r] = fma((double)a[r][1], xv[1], acc[r]);
             }
         }
     }
@@ -610,6 +619,12 @@ __global__ __launch_bounds__(256) void k_bandmv_rows(const double *__restrict__ 
         const int row = l * s + r0 + lane;
         y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
     }
+}
+
+// FP64 -> FP32 element copy (grid-stride)
+__global__ void k_to_float(const double *__restrict__ src, float *__restrict__ dst, size_t count) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
+        dst[e] = (float)src[e];
 }
 
 __global__ void k_copy2d(const double *__restrict__ src, long lds, double *__restrict__ dst, long ldd, int rows,
@@ -692,27 +707,57 @@ int invert_enqueue(const InvItem *items_dev, int batch, int s_dim, double *work,
     return hip_check(hipGetLastError(), "invert launch");
 }
 
-int gemv_enqueue(const double *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
-                 double alpha, double beta, hipStream_t s) {
-    const bool aligned = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0) && ((uintptr_t)x % 16 == 0);
+namespace {
+template <typename TA>
+int gemv_launch(const TA *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
+                double alpha, double beta, hipStream_t s) {
+    const bool aligned = (lda % 2 == 0) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) && ((uintptr_t)x % 16 == 0);
     if (aligned)
-        hipLaunchKernelGGL(k_gemv_rows, dim3(cdiv(rows, 4 * GR)), dim3(256), 0, s, A, lda, x, c, y, rows, cols,
+        hipLaunchKernelGGL(k_gemv_rows<TA>, dim3(cdiv(rows, 4 * GR)), dim3(256), 0, s, A, lda, x, c, y, rows, cols,
                            alpha, beta);
     else
-        hipLaunchKernelGGL(k_gemv, dim3(cdiv(rows, 4)), dim3(256), 0, s, A, lda, x, c, y, rows, cols, alpha, beta);
+        hipLaunchKernelGGL(k_gemv<TA>, dim3(cdiv(rows, 4)), dim3(256), 0, s, A, lda, x, c, y, rows, cols, alpha,
+                           beta);
     return hip_check(hipGetLastError(), "gemv launch");
+}
+
+template <typename TA>
+int bandmv_launch(const TA *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
+                  double alpha, double beta, hipStream_t s) {
+    const bool aligned = (s_dim % 2 == 0) && ((uintptr_t)band % (2 * sizeof(TA)) == 0) && ((uintptr_t)x % 16 == 0);
+    if (aligned)
+        hipLaunchKernelGGL(k_bandmv_rows<TA>, dim3(cdiv((long)M * ((s_dim + GR - 1) / GR), 4)), dim3(256), 0, s,
+                           band, M, w, s_dim, x, c, y, alpha, beta);
+    else
+        hipLaunchKernelGGL(k_bandmv<TA>, dim3(cdiv((long)M * s_dim, 4)), dim3(256), 0, s, band, M, w, s_dim, x, c,
+                           y, alpha, beta);
+    return hip_check(hipGetLastError(), "bandmv launch");
+}
+}  // namespace
+
+int gemv_enqueue(const double *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
+                 double alpha, double beta, hipStream_t s) {
+    return gemv_launch(A, lda, x, c, y, rows, cols, alpha, beta, s);
+}
+int gemv_enqueue(const float *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
+                 double alpha, double beta, hipStream_t s) {
+    return gemv_launch(A, lda, x, c, y, rows, cols, alpha, beta, s);
 }
 
 int bandmv_enqueue(const double *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
                    double alpha, double beta, hipStream_t s) {
-    const bool aligned = (s_dim % 2 == 0) && ((uintptr_t)band % 16 == 0) && ((uintptr_t)x % 16 == 0);
-    if (aligned)
-        hipLaunchKernelGGL(k_bandmv_rows, dim3(cdiv((long)M * ((s_dim + GR - 1) / GR), 4)), dim3(256), 0, s, band, M,
-                           w, s_dim, x, c, y, alpha, beta);
-    else
-        hipLaunchKernelGGL(k_bandmv, dim3(cdiv((long)M * s_dim, 4)), dim3(256), 0, s, band, M, w, s_dim, x, c, y,
-                           alpha, beta);
-    return hip_check(hipGetLastError(), "bandmv launch");
+    return bandmv_launch(band, M, w, s_dim, x, c, y, alpha, beta, s);
+}
+int bandmv_enqueue(const float *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
+                   double alpha, double beta, hipStream_t s) {
+    return bandmv_launch(band, M, w, s_dim, x, c, y, alpha, beta, s);
+}
+
+int to_float_enqueue(const double *src, float *dst, size_t count, hipStream_t s) {
+    if (count == 0) return BIM_OK;
+    const int blocks = (int)std::min<size_t>((count + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_to_float, dim3(blocks), dim3(256), 0, s, src, dst, count);
+    return hip_check(hipGetLastError(), "conversion launch");
 }
 
 int copy2d_enqueue(const double *src, long lds, double *dst, long ldd, int rows, int cols, hipStream_t s) {

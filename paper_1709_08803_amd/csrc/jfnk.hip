@@ -293,7 +293,7 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
     double precond_ms = 0.0;
     if (!P && o->use_precond) {
         auto tp = std::chrono::steady_clock::now();
-        if ((rc = precond_setup(p, o->band_halfwidth, &own, s))) return rc;
+        if ((rc = precond_setup_ex(p, o->band_halfwidth, o->precond_storage, &own, s))) return rc;
         precond_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
         P = own;
     }
@@ -436,6 +436,7 @@ void jfnk_default_opts(bim_jfnk_opts *o) {
     // resolve (measured at 181 x 61: 1.5 - 1.9x faster solves than FP64 with
     // the same converged ||F||_inf <= ftol)
     o->fp32c_gmres_rtol = 1e-4;
+    o->precond_storage = BIM_STORE_FP64;
 }
 
 static int check_opts(const bim_jfnk_opts *o) {
@@ -445,6 +446,8 @@ static int check_opts(const bim_jfnk_opts *o) {
         !(o->fp64_below >= 0.0))
         return fail(BIM_EINVAL, "invalid solver options");
     if (o->inner_prec != BIM_FP64 && o->inner_prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
+    if (o->precond_storage != BIM_STORE_FP64 && o->precond_storage != BIM_STORE_FP32)
+        return fail(BIM_EINVAL, "unknown preconditioner storage");
     return BIM_OK;
 }
 

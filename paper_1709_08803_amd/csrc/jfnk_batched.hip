@@ -89,7 +89,7 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         const bim_precond *P = Ps_in ? Ps_in[i] : nullptr;
         if (!P && o->use_precond) {
             auto tp = std::chrono::steady_clock::now();
-            if ((rc = precond_setup(&probs[i], o->band_halfwidth, &own[i], s))) return rc;
+            if ((rc = precond_setup_ex(&probs[i], o->band_halfwidth, o->precond_storage, &own[i], s))) return rc;
             pms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp).count();
             P = own[i];
         }
@@ -260,14 +260,16 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
                             const double *r1 = v, *r2 = v + nn, *r3 = v + 2 * nn;
                             double *z1 = z, *z2 = z + nn, *z3 = z + 2 * nn;
                             const int M = pc->M, ss = pc->s, h = pc->h;
-                            hband.push_back({pc->Dinv11, r1, nullptr, a1, M, 0, ss, 1.0, 0.0});
-                            hband.push_back({pc->B31, a1, r3, t3, M, h, ss, -1.0, 1.0});
-                            hband.push_back({pc->Dinv22, t3, nullptr, a3, M, 0, ss, 1.0, 0.0});
-                            hband.push_back({pc->B21, a1, r2, t2, M, h, ss, -1.0, 1.0});
-                            hband.push_back({pc->B23, a3, t2, t2, M, h, ss, -1.0, 1.0});
-                            hgemv.push_back({pc->Sinv, t2, nullptr, z2, nn, (int)nn, (int)nn, 1.0, 0.0});
-                            hband.push_back({pc->G, z2, a3, z3, M, h, ss, -1.0, 1.0});
-                            hband.push_back({pc->E, z2, a1, z1, M, 0, ss, -1.0, 1.0});
+                            const int f = pc->storage == BIM_STORE_FP32;
+                            auto arr = [&](int which) { return precond_array(pc, which); };
+                            hband.push_back({arr(0), r1, nullptr, a1, M, 0, ss, 1.0, 0.0, f});   // Dinv11
+                            hband.push_back({arr(5), a1, r3, t3, M, h, ss, -1.0, 1.0, f});       // B31
+                            hband.push_back({arr(1), t3, nullptr, a3, M, 0, ss, 1.0, 0.0, f});   // Dinv22
+                            hband.push_back({arr(3), a1, r2, t2, M, h, ss, -1.0, 1.0, f});       // B21
+                            hband.push_back({arr(4), a3, t2, t2, M, h, ss, -1.0, 1.0, f});       // B23
+                            hgemv.push_back({arr(7), t2, nullptr, z2, nn, (int)nn, (int)nn, 1.0, 0.0, f});  // S^-1
+                            hband.push_back({arr(6), z2, a3, z3, M, h, ss, -1.0, 1.0, f});       // G
+                            hband.push_back({arr(2), z2, a1, z1, M, 0, ss, -1.0, 1.0, f});       // E
                         } else {
                             ls_axpby.push_back({v, nullptr, z, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, 0.0});
                         }
@@ -616,8 +618,8 @@ extern "C" int jfnk_solve_batched(const bim_problem *probs, int count, bim_preco
     if (opts) o = *opts;
     if (!(o.ftol > 0) || !(o.gmres_rtol > 0) || o.restart < 1 || o.restart > 30 || o.max_restarts < 0 ||
         o.max_newton < 0 || o.max_backtracks < 0 || !(o.fd_eps < 1.0) || o.stall_steps < 0 ||
-        !(o.fp64_below >= 0.0) ||
-        (o.inner_prec != BIM_FP64 && o.inner_prec != BIM_FP32C))
+        !(o.fp64_below >= 0.0) || (o.inner_prec != BIM_FP64 && o.inner_prec != BIM_FP32C) ||
+        (o.precond_storage != BIM_STORE_FP64 && o.precond_storage != BIM_STORE_FP32))
         return fail(BIM_EINVAL, "invalid solver options (batched restart must be <= 30)");
     return solve_batched_impl(probs, count, Ps, us, &o, reps, (hipStream_t)stream);
 }

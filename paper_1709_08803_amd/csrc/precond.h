@@ -7,20 +7,34 @@
 
 namespace bim {
 
+// The eight arrays the apply reads, in one element type.
+template <typename T>
+struct PrecondArrays {
+    T *Dinv11, *Dinv22, *E;  // band-0 arrays [M][s][s] (same block on every slice)
+    T *B21, *B23, *B31, *G;  // band-h arrays [M][2h+1][s][s]
+    T *Sinv;                 // dense [n][n]
+};
+
 struct Precond {
     int N, M, s, h;
     long n;
-    void *mem = nullptr;     // one device allocation holding everything below
+    int storage = BIM_STORE_FP64;  // element type of the stored operator
+    void *mem = nullptr;           // one device allocation holding the arrays and the scratch
     size_t bytes = 0;
-    double *Dinv11, *Dinv22, *E;  // band-0 arrays [M][s][s] (same block on every slice)
-    double *B21, *B23, *B31, *G;  // band-h arrays [M][2h+1][s][s]
-    double *Sinv;                 // dense [n][n]
+    // FP64 arrays (built first; kept when storage is FP64, else released)
+    double *Dinv11, *Dinv22, *E;
+    double *B21, *B23, *B31, *G;
+    double *Sinv;
+    PrecondArrays<float> f32{};   // FP32 copies when storage is FP32
     double *scratch;              // [4 n] apply temporaries
 };
 
-int precond_build(const bim_problem *p, int hb, Precond **out, hipStream_t st);
+int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipStream_t st);
 int precond_apply_enqueue(const Precond *pc, const double *r, double *z, hipStream_t st);
 void precond_free(Precond *pc);
+// The array `which` (0..7: Dinv11, Dinv22, E, B21, B23, B31, G, Sinv) as stored
+// (FP64 or FP32 per pc->storage).
+const void *precond_array(const Precond *pc, int which);
 
 }  // namespace bim
 

@@ -199,7 +199,46 @@ static double *band_blk(double *band, int w, int s, int l, int m) {
     return band + ((size_t)l * (2 * w + 1) + (m - l + w)) * s * s;
 }
 
-int precond_build(const bim_problem *p, int hb, Precond **out, hipStream_t st) {
+// FP32 storage: the eight arrays the apply reads are rounded into a new, half-
+// sized allocation (with the apply scratch), and the FP64 allocation is freed.
+static int precond_round_to_fp32(Precond *pc, hipStream_t st) {
+    const int M = pc->M, s = pc->s, h = pc->h;
+    const long n = pc->n;
+    const size_t cnt[8] = {band_elems(M, 0, s), band_elems(M, 0, s), band_elems(M, 0, s), band_elems(M, h, s),
+                           band_elems(M, h, s), band_elems(M, h, s), band_elems(M, h, s), (size_t)n * n};
+    double *src[8] = {pc->Dinv11, pc->Dinv22, pc->E, pc->B21, pc->B23, pc->B31, pc->G, pc->Sinv};
+    size_t bytes = 0;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    for (size_t c : cnt) bytes += al(sizeof(float) * c);
+    bytes += al(sizeof(double) * 4 * n);
+    void *mem = nullptr;
+    int rc = hip_check(hipMalloc(&mem, bytes), "hipMalloc(preconditioner, FP32)");
+    if (rc) return rc;
+    DevArena ar{(char *)mem, 0, bytes};
+    float **dst[8] = {&pc->f32.Dinv11, &pc->f32.Dinv22, &pc->f32.E, &pc->f32.B21,
+                      &pc->f32.B23,    &pc->f32.B31,    &pc->f32.G, &pc->f32.Sinv};
+    for (int q = 0; q < 8 && !rc; ++q) {
+        *dst[q] = ar.take<float>(cnt[q]);
+        rc = to_float_enqueue(src[q], *dst[q], cnt[q], st);
+    }
+    double *scratch = ar.take<double>((size_t)4 * n);
+    if (!rc) rc = hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (rc) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(mem);
+        pc->f32 = PrecondArrays<float>{};
+        return rc;
+    }
+    (void)hipFree(pc->mem);
+    pc->mem = mem;
+    pc->bytes = bytes;
+    pc->scratch = scratch;
+    pc->Dinv11 = pc->Dinv22 = pc->E = pc->B21 = pc->B23 = pc->B31 = pc->G = pc->Sinv = nullptr;
+    pc->storage = BIM_STORE_FP32;
+    return BIM_OK;
+}
+
+int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipStream_t st) {
     const Dims d(p);
     const int N = d.N, M = d.M, s = N + 1;
     const int h = hb;
@@ -469,6 +508,7 @@ int precond_build(const bim_problem *p, int hb, Precond **out, hipStream_t st) {
     }();
 #undef RUN
     (void)hipFreeAsync(tbase, st);
+    if (!rc && storage == BIM_STORE_FP32) rc = precond_round_to_fp32(pc, st);
     if (rc) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(pc->mem);
@@ -479,21 +519,47 @@ int precond_build(const bim_problem *p, int hb, Precond **out, hipStream_t st) {
     return BIM_OK;
 }
 
-int precond_apply_enqueue(const Precond *pc, const double *r, double *z, hipStream_t st) {
+template <typename T>
+static int precond_apply_impl(const Precond *pc, const PrecondArrays<const T> &a, const double *r, double *z,
+                              hipStream_t st) {
     const int M = pc->M, s = pc->s, h = pc->h;
     const long n = pc->n;
     const double *r1 = r, *r2 = r + n, *r3 = r + 2 * n;
     double *z1 = z, *z2 = z + n, *z3 = z + 2 * n;
     double *a1 = pc->scratch, *a3 = a1 + n, *t2 = a3 + n, *t3 = t2 + n;
     int rc;
-    if ((rc = bandmv_enqueue(pc->Dinv11, M, 0, s, r1, nullptr, a1, 1.0, 0.0, st))) return rc;       // a1
-    if ((rc = bandmv_enqueue(pc->B31, M, h, s, a1, r3, t3, -1.0, 1.0, st))) return rc;              // r3 - P31 a1
-    if ((rc = bandmv_enqueue(pc->Dinv22, M, 0, s, t3, nullptr, a3, 1.0, 0.0, st))) return rc;       // a3
-    if ((rc = bandmv_enqueue(pc->B21, M, h, s, a1, r2, t2, -1.0, 1.0, st))) return rc;              // r2 - P21 a1
-    if ((rc = bandmv_enqueue(pc->B23, M, h, s, a3, t2, t2, -1.0, 1.0, st))) return rc;              // - P23 a3
-    if ((rc = gemv_enqueue(pc->Sinv, n, t2, nullptr, z2, (int)n, (int)n, 1.0, 0.0, st))) return rc; // z2
-    if ((rc = bandmv_enqueue(pc->G, M, h, s, z2, a3, z3, -1.0, 1.0, st))) return rc;                // z3
-    return bandmv_enqueue(pc->E, M, 0, s, z2, a1, z1, -1.0, 1.0, st);                               // z1
+    if ((rc = bandmv_enqueue(a.Dinv11, M, 0, s, r1, nullptr, a1, 1.0, 0.0, st))) return rc;       // a1
+    if ((rc = bandmv_enqueue(a.B31, M, h, s, a1, r3, t3, -1.0, 1.0, st))) return rc;              // r3 - P31 a1
+    if ((rc = bandmv_enqueue(a.Dinv22, M, 0, s, t3, nullptr, a3, 1.0, 0.0, st))) return rc;       // a3
+    if ((rc = bandmv_enqueue(a.B21, M, h, s, a1, r2, t2, -1.0, 1.0, st))) return rc;              // r2 - P21 a1
+    if ((rc = bandmv_enqueue(a.B23, M, h, s, a3, t2, t2, -1.0, 1.0, st))) return rc;              // - P23 a3
+    if ((rc = gemv_enqueue(a.Sinv, n, t2, nullptr, z2, (int)n, (int)n, 1.0, 0.0, st))) return rc; // z2
+    if ((rc = bandmv_enqueue(a.G, M, h, s, z2, a3, z3, -1.0, 1.0, st))) return rc;                // z3
+    return bandmv_enqueue(a.E, M, 0, s, z2, a1, z1, -1.0, 1.0, st);                               // z1
+}
+
+int precond_apply_enqueue(const Precond *pc, const double *r, double *z, hipStream_t st) {
+    if (pc->storage == BIM_STORE_FP32) {
+        const PrecondArrays<const float> a{pc->f32.Dinv11, pc->f32.Dinv22, pc->f32.E, pc->f32.B21,
+                                           pc->f32.B23,    pc->f32.B31,    pc->f32.G, pc->f32.Sinv};
+        return precond_apply_impl(pc, a, r, z, st);
+    }
+    const PrecondArrays<const double> a{pc->Dinv11, pc->Dinv22, pc->E, pc->B21, pc->B23, pc->B31, pc->G, pc->Sinv};
+    return precond_apply_impl(pc, a, r, z, st);
+}
+
+const void *precond_array(const Precond *pc, int which) {
+    const bool f = pc->storage == BIM_STORE_FP32;
+    switch (which) {
+        case 0: return f ? (const void *)pc->f32.Dinv11 : (const void *)pc->Dinv11;
+        case 1: return f ? (const void *)pc->f32.Dinv22 : (const void *)pc->Dinv22;
+        case 2: return f ? (const void *)pc->f32.E : (const void *)pc->E;
+        case 3: return f ? (const void *)pc->f32.B21 : (const void *)pc->B21;
+        case 4: return f ? (const void *)pc->f32.B23 : (const void *)pc->B23;
+        case 5: return f ? (const void *)pc->f32.B31 : (const void *)pc->B31;
+        case 6: return f ? (const void *)pc->f32.G : (const void *)pc->G;
+        default: return f ? (const void *)pc->f32.Sinv : (const void *)pc->Sinv;
+    }
 }
 
 void precond_free(Precond *pc) {
@@ -514,15 +580,20 @@ using namespace bim;
 extern "C" {
 
 int precond_setup(const bim_problem *prob, int band_halfwidth, bim_precond **out, void *stream) {
+    return precond_setup_ex(prob, band_halfwidth, BIM_STORE_FP64, out, stream);
+}
+
+int precond_setup_ex(const bim_problem *prob, int band_halfwidth, int storage, bim_precond **out, void *stream) {
     int rc = validate(prob);
     if (rc) return rc;
     if (!out) return fail(BIM_EINVAL, "out must not be NULL");
     *out = nullptr;
+    if (storage != BIM_STORE_FP64 && storage != BIM_STORE_FP32) return fail(BIM_EINVAL, "unknown storage");
     const int hb = band_halfwidth < 0 ? std::max(1, (int)std::lround(prob->M / 6.0)) : band_halfwidth;
     if (hb < 1 || hb >= prob->M) return fail(BIM_EINVAL, "band half-width must be in [1, M-1]");
     if (prob->N + 1 > 1024) return fail(BIM_EINVAL, "N + 1 must not exceed 1024");
     Precond *pc = nullptr;
-    rc = precond_build(prob, hb, &pc, (hipStream_t)stream);
+    rc = precond_build(prob, hb, storage, &pc, (hipStream_t)stream);
     if (rc) return rc;
     *out = new bim_precond{pc};
     return BIM_OK;
@@ -544,6 +615,8 @@ void precond_destroy(bim_precond *P) {
 int64_t precond_bytes(const bim_precond *P) { return (P && P->pc) ? (int64_t)P->pc->bytes : 0; }
 
 int precond_band(const bim_precond *P) { return (P && P->pc) ? P->pc->h : 0; }
+
+int precond_storage(const bim_precond *P) { return (P && P->pc) ? P->pc->storage : -1; }
 
 }  // extern "C"
 

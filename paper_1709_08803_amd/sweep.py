@@ -1,6 +1,6 @@
 """Parameter sweep over many uneven problems on one GPU.
 
-    python -m paper_1709_08803_amd.sweep [--count 64] [--seed 0] [--inner fp32c]
+    python -m paper_1709_08803_amd.sweep [--count 64] [--seed 0] [--inner fp32c] [--storage fp32]
 
 Instances: the seeded sweep of workloads.sweep_instances (meshes N x M with N
 in 61..181, M = (N-1)/3 + 1 over x in [-30, 30], y in [0, 20]; F ~ U[0.5, 2];
@@ -10,7 +10,8 @@ line:
     launch, aggregate pair-interactions/s in FP64 and FP32C;
   * the sweep itself (Newton capped at 10 steps and stopped once ||F|| has not
     halved over 4 steps): preconditioner setup for every instance, linear starts,
-    and the lockstep batched JFNK (inner sums in the chosen precision), with
+    and the lockstep batched JFNK (inner sums in the chosen precision,
+    preconditioners stored in FP32 or FP64), with
     per-instance status, Newton and GMRES counts; and the same instances solved
     one after another with jfnk_solve, for the batching speedup.
 Only library calls do numerical work; this module times and reports.
@@ -37,7 +38,7 @@ def _sync_time(fn, reps=1):
 
 
 def run(count: int = 64, seed: int = 0, inner: str = "fp32c", ftol: float = 1e-10, sequential: bool = True,
-        max_newton: int = 10, stall_steps: int = 4) -> dict:
+        max_newton: int = 10, stall_steps: int = 4, storage: str = "fp32") -> dict:
     probs = W.sweep_instances(count, seed)
     dps = [B.DeviceProblem(p) for p in probs]
     pairs = sum(p.pairs_per_eval() for p in probs)
@@ -50,7 +51,7 @@ def run(count: int = 64, seed: int = 0, inner: str = "fp32c", ftol: float = 1e-1
         _, dt = _sync_time(lambda: B.residual_batched(dps, us, prec), reps=5)
         res[f"batched_residual_{prec}"] = {"ms": dt * 1e3, "pairs_per_s": pairs / dt}
     # the sweep: preconditioners, linear starts, lockstep JFNK
-    Ps, t_setup = _sync_time(lambda: [B.Preconditioner(dp) for dp in dps])
+    Ps, t_setup = _sync_time(lambda: [B.Preconditioner(dp, storage=storage) for dp in dps])
     # linear starts to the relative tolerance of the Newton steps' GMRES
     ulin, t_lin = _sync_time(lambda: [B.linear_start(dp, P, rtol=1e-8) for dp, P in zip(dps, Ps)])
     ub = [u.clone() for u in ulin]
@@ -58,7 +59,7 @@ def run(count: int = 64, seed: int = 0, inner: str = "fp32c", ftol: float = 1e-1
                                                             inner_prec=inner, max_newton=max_newton,
                                                             stall_steps=stall_steps))
     conv = [r["status"] == 0 for r in reps]
-    res["sweep"] = {"inner": inner, "precond_setup_s": t_setup, "linear_starts_s": t_lin,
+    res["sweep"] = {"inner": inner, "precond_storage": storage, "precond_setup_s": t_setup, "linear_starts_s": t_lin,
                     "batched_solve_s": t_solve, "converged": int(sum(conv)),
                     "newton_total": int(sum(r["newton_iters"] for r in reps)),
                     "gmres_total": int(sum(r["gmres_iters"] for r in reps)),
@@ -86,9 +87,11 @@ def main():
     ap.add_argument("--count", type=int, default=64)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--inner", default="fp32c", choices=("fp64", "fp32c"))
+    ap.add_argument("--storage", default="fp32", choices=("fp64", "fp32"))
     ap.add_argument("--no-sequential", action="store_true")
     args = ap.parse_args()
-    print(json.dumps(run(args.count, args.seed, args.inner, sequential=not args.no_sequential)))
+    print(json.dumps(run(args.count, args.seed, args.inner, sequential=not args.no_sequential,
+                         storage=args.storage)))
 
 
 if __name__ == "__main__":

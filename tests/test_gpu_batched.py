@@ -101,3 +101,23 @@ def test_batched_solve_switches_precision_like_sequential(bim):
             assert rb["inner_residual_evals"] < rb["newton_iters"]
             assert (ubi - us_).abs().max().item() <= 1e-8
             assert np.abs(R.residual(p, ubi.cpu().numpy())).max() < 1e-9
+
+
+def test_batched_solve_with_fp32_stored_preconditioners(bim):
+    # the batched apply reads FP32-stored operators: the lockstep batch ends
+    # where the single solves with the same preconditioner storage end
+    probs = W.sweep_instances(3, seed=7, n_choices=[31, 46], froude=(1.2, 1.8), height=(0.05, 0.15))
+    dps = [bim.DeviceProblem(p) for p in probs]
+    us = [bim.linear_start(dp) for dp in dps]
+    ub = [u.clone() for u in us]
+    opts = dict(ftol=1e-10, inner_prec="fp32c", precond_storage="fp32")
+    rc, reps = bim.solve_batched(dps, ub, check=False, **opts)
+    for p, dp, u0, ubi, rb in zip(probs, dps, us, ub, reps):
+        us_ = u0.clone()
+        rs = bim.solve(dp, us_, check=False, **opts)
+        print(p.name, rb["status"], rs["status"], rb["newton_iters"], rs["newton_iters"], rb["gmres_iters"],
+              rs["gmres_iters"])
+        assert rb["status"] == rs["status"]
+        if rb["status"] == 0:
+            assert (ubi - us_).abs().max().item() <= 1e-8
+            assert np.abs(R.residual(p, ubi.cpu().numpy())).max() < 1e-9

@@ -178,3 +178,37 @@ def test_solver_rejects_bad_switch_threshold(bim):
     u = bim.linear_start(dp)
     rep = bim.solve(dp, u, check=False, inner_prec="fp32c", fp64_below=-1.0)
     assert rep["status"] == -1  # BIM_EINVAL
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32c"])
+def test_fp32_stored_preconditioner_reaches_the_same_solution(bim, inner):
+    # a preconditioner stored in FP32 (passed in, or built by the solver from
+    # the option) changes GMRES's path, not the Newton residual: the same
+    # discrete solution as the FP64-stored one, with about as many iterations
+    p = W.working(1.4, N=61, M=21)
+    dp = bim.DeviceProblem(p)
+    P64 = bim.Preconditioner(dp)
+    P32 = bim.Preconditioner(dp, storage="fp32")
+    u0 = bim.linear_start(dp, P64)
+    ua = u0.clone()
+    ra = bim.solve(dp, ua, P64, ftol=1e-11, inner_prec=inner)
+    ub = u0.clone()
+    rb = bim.solve(dp, ub, P32, ftol=1e-11, inner_prec=inner)
+    uc = u0.clone()
+    rc = bim.solve(dp, uc, None, ftol=1e-11, inner_prec=inner, precond_storage="fp32")
+    print(inner, "P64", ra["newton_iters"], ra["gmres_iters"], "P32", rb["newton_iters"], rb["gmres_iters"],
+          "internal P32", rc["newton_iters"], rc["gmres_iters"])
+    assert ra["status"] == 0 and rb["status"] == 0 and rc["status"] == 0
+    assert (ub - ua).abs().max().item() <= 1e-9
+    assert torch.equal(uc, ub)  # the internal FP32 build is the same operator
+    assert rb["gmres_iters"] <= 1.2 * ra["gmres_iters"] + 2
+    P64.close()
+    P32.close()
+
+
+def test_solver_rejects_unknown_precond_storage(bim):
+    p = W.tiny(0.7)
+    dp = bim.DeviceProblem(p)
+    u = bim.linear_start(dp)
+    rep = bim.solve(dp, u, check=False, precond_storage=2)
+    assert rep["status"] == -1  # BIM_EINVAL

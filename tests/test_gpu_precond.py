@@ -70,3 +70,44 @@ def test_precond_rejects_bad_band(bim):
     dp = bim.DeviceProblem(p)
     with pytest.raises(bim.BimError):
         bim.Preconditioner(dp, p.M)
+
+
+def test_fp32_storage_is_the_fp64_operator_rounded(bim):
+    """FP32 storage: the same factored operator rounded to FP32 (half the bytes);
+    at 181 x 61 its apply still solves the banded system P z = r of the oracle's
+    banded product, next to the FP64 one, to FP32 rounding amplified by the
+    conditioning of the Schur complement."""
+    p = W.working(0.7)
+    dp = bim.DeviceProblem(p)
+    r = np.random.default_rng(6).standard_normal(p.n_unknowns)
+    rd = torch.as_tensor(r, device="cuda")
+    P64 = bim.Preconditioner(dp)
+    z64 = P64.apply(rd).cpu().numpy()
+    b64 = P64.nbytes
+    P64.close()
+    P32 = bim.Preconditioner(dp, storage="fp32")
+    assert P32.storage == "fp32" and P32.band == 10
+    z32 = P32.apply(rd).cpu().numpy()
+    z32b = P32.apply(rd).cpu().numpy()
+    print("bytes", b64, P32.nbytes)
+    assert np.array_equal(z32, z32b)  # a fixed operator
+    assert P32.nbytes < 0.51 * b64
+    dz = np.abs(z32 - z64).max() / np.abs(z64).max()
+    res = np.abs(Lin.banded_matvec(p, z32, 10) - r).max() / np.abs(r).max()
+    print("181x61 fp32 storage: |z32 - z64| / |z64|", dz, "|P z32 - r| / |r|", res)
+    # FP32 elements carry 6e-8 relative rounding, which the dense Schur-complement
+    # inverse amplifies by its conditioning (its products cancel): measured 1.0e-3
+    # and 2.6e-3.  A wrong or misplaced array gives O(1); the solves with this P
+    # (test_gpu_jfnk) reach the FP64-P solution with about as many iterations.
+    assert dz <= 1e-2
+    assert res <= 1e-2
+    P32.close()
+
+
+def test_precond_rejects_unknown_storage(bim):
+    import ctypes
+    p = W.tiny(0.7)
+    dp = bim.DeviceProblem(p)
+    h = ctypes.c_void_p()
+    assert bim.lib().precond_setup_ex(dp.ref(), -1, 2, ctypes.byref(h), None) == -1
+    assert not h.value
