@@ -78,7 +78,6 @@ def measured_traffic():
         return None
 
 
-LINEAR_START_RTOL = 1e-8
 
 
 def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15):
@@ -89,19 +88,23 @@ def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15):
     p = W.working(froude)
     dp = B.DeviceProblem(p)
     nb = (p.N + 1) * p.M
-    res = {"froude": froude, "linear_start_rtol": LINEAR_START_RTOL}
+    res = {"froude": froude}
+    # per preconditioner storage: the linear start's precision and GMRES tolerance
+    #   fp64: FP64 products to 1e-8, the relative tolerance of every FP64 Newton
+    #         step's GMRES (a tighter one changes no Newton count)
+    #   fp32: FP32C products to 1e-4, the forcing term of the FP32C Newton steps
+    starts = {"fp64": ("fp64", 1e-8), "fp32": ("fp32c", 1e-4)}
     # leg: (preconditioner storage, solver options)
-    #   fp64:         FP64 sums, FP64-stored P (the plain FP64 solve)
+    #   fp64:         FP64 sums, FP64-stored P, FP64 linear start (plain FP64)
     #   fp32c:        FP32C sums with the library's GMRES tolerance for such steps
-    #                 (1e-4, the level their Jacobian action resolves), FP32-stored P
-    #   fp32c_p64:    the same with the FP64-stored P
+    #                 (1e-4, the level their Jacobian action resolves), FP32-stored
+    #                 P, FP32C linear start
+    #   fp32c_p64:    FP32C sums, FP64-stored P and linear start
     #   fp32c_strict: FP32C sums with every GMRES solve at 1e-8, FP64-stored P
-    #   fp64_p32:     FP64 sums, FP32-stored P
     legs = {"fp64": ("fp64", dict(inner_prec="fp64")),
             "fp32c": ("fp32", dict(inner_prec="fp32c")),
             "fp32c_p64": ("fp64", dict(inner_prec="fp32c")),
-            "fp32c_strict": ("fp64", dict(inner_prec="fp32c", fp32c_gmres_rtol=0.0)),
-            "fp64_p32": ("fp32", dict(inner_prec="fp64"))}
+            "fp32c_strict": ("fp64", dict(inner_prec="fp32c", fp32c_gmres_rtol=0.0))}
     sols = {}
     for storage in ("fp64", "fp32"):
         torch.cuda.synchronize()
@@ -109,13 +112,13 @@ def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15):
         P = B.Preconditioner(dp, storage=storage)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
+        lprec, lrtol = starts[storage]
         t0 = time.perf_counter()
-        # the start solves the linear system to the relative tolerance of every
-        # Newton step's GMRES (1e-8): a tighter one changes no Newton count
-        ulin = B.linear_start(dp, P, rtol=LINEAR_START_RTOL)
+        ulin = B.linear_start(dp, P, rtol=lrtol, prec=lprec)
         torch.cuda.synchronize()
         t_lin = time.perf_counter() - t0
         res[f"precond_{storage}"] = {"setup_ms": t_setup * 1e3, "linear_start_ms": t_lin * 1e3,
+                                     "linear_start_prec": lprec, "linear_start_rtol": lrtol,
                                      "band_halfwidth": P.band, "bytes": P.nbytes}
         for leg, (st, kw) in legs.items():
             if st != storage:

@@ -277,6 +277,15 @@ int jfnk_solve(const bim_problem *prob, const bim_precond *P, double *u, const b
  * rtol (<= 0: 1e-12).  u_out: device [3(N+1)M].
  */
 int bim_linear_start(const bim_problem *prob, const bim_precond *P, double *u_out, double rtol, void *stream);
+/*
+ * bim_linear_start with the precision of the linear operator's products: prec =
+ * BIM_FP64 (as bim_linear_start) or BIM_FP32C (the products of J~ use FP32C
+ * sums; the right-hand side F_lin(u0) stays FP64).  The FP32C operator resolves
+ * about 1e-6 relative, so rtol should not be set below ~1e-5.  The start only
+ * seeds Newton, which then converges on the FP64 residual.
+ */
+int bim_linear_start_ex(const bim_problem *prob, const bim_precond *P, double *u_out, double rtol, int prec,
+                        void *stream);
 
 /*
  * F_i = F(u_i) for `count` problems (possibly of different mesh sizes) whose

@@ -70,6 +70,7 @@ def lib():
         L.jfnk_default_opts.restype = None
         L.jfnk_solve.argtypes = [pp, vp, vp, ctypes.POINTER(JfnkOpts), ctypes.POINTER(JfnkReport), vp]
         L.bim_linear_start.argtypes = [pp, vp, vp, dbl, vp]
+        L.bim_linear_start_ex.argtypes = [pp, vp, vp, dbl, i32, vp]
         L.jfnk_solve_batched.argtypes = [pp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(JfnkOpts),
                                          ctypes.POINTER(JfnkReport), vp]
         L.jfnk_solve_batched.restype = i32
@@ -87,7 +88,8 @@ def lib():
         L.lg_make_input.argtypes = [pp, vp, i32, vp, vp, vp]
         L.lg_infer_start.argtypes = [vp, pp, vp, vp, vp]
         for name in ("bim_residual", "bim_jv", "bim_residual_timed", "bim_tune_residual", "precond_setup",
-                     "precond_setup_ex", "precond_storage", "precond_apply", "precond_band", "jfnk_solve", "bim_linear_start", "lg_create",
+                     "precond_setup_ex", "precond_storage", "precond_apply", "precond_band", "jfnk_solve",
+                     "bim_linear_start", "bim_linear_start_ex", "lg_create",
                      "lg_num_params", "lg_set_params", "lg_get_params", "lg_forward", "lg_train_step",
                      "lg_make_input", "lg_infer_start"):
             getattr(L, name).restype = i32
@@ -306,10 +308,11 @@ def solve_batched(dps, us, Ps=None, stream=None, check: bool = True, **opts):
 
 
 def linear_start(dp: DeviceProblem, P: Optional[Preconditioner] = None, rtol: float = 0.0,
-                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+                 out: Optional[torch.Tensor] = None, stream=None, prec="fp64") -> torch.Tensor:
+    """bim_linear_start_ex: prec "fp32c" forms the linear operator's products with FP32C sums."""
     u = out if out is not None else torch.empty(dp.n, dtype=torch.float64, device=dp.device)
-    rc = lib().bim_linear_start(dp.ref(), P.handle if P is not None else None, _dptr(u), float(rtol),
-                                _stream(stream))
+    rc = lib().bim_linear_start_ex(dp.ref(), P.handle if P is not None else None, _dptr(u), float(rtol),
+                                   _PREC[prec], _stream(stream))
     _check(rc)
     return u
 

@@ -318,11 +318,17 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
     if (linear_start_only) {
         // u_lin = u0 - J~^-1 F_lin(u0): one linear solve with the exact linear operator
         if ((rc = uniform_stream_enqueue(u_io, d.N, d.M, p->x1, s))) return rc;
+        // (with inner_prec BIM_FP32C the operator's products use FP32C sums, the
+        // base point included, and the right-hand side stays FP64)
         if ((rc = residual_enqueue(p, u_io, F, BIM_FP64, pl64, K.rw, s, nullptr, 1))) return rc;
         if ((rc = axpby_enqueue(-1.0, F, 0.0, nullptr, rhs, n, s))) return rc;
         K.u = u_io;
         K.Fin = F;
-        K.prec = BIM_FP64;
+        if (o->inner_prec == BIM_FP32C) {
+            if ((rc = residual_enqueue(p, u_io, Fin, BIM_FP32C, pl32, K.rw, s, nullptr, 1))) return rc;
+            K.Fin = Fin;
+        }
+        K.prec = o->inner_prec;
         K.linear = 1;
         K.eps = std::ldexp(1.0, -52);
         int it = 0;
@@ -464,11 +470,18 @@ int jfnk_solve(const bim_problem *prob, const bim_precond *P, double *u, const b
 }
 
 int bim_linear_start(const bim_problem *prob, const bim_precond *P, double *u_out, double rtol, void *stream) {
+    return bim_linear_start_ex(prob, P, u_out, rtol, BIM_FP64, stream);
+}
+
+int bim_linear_start_ex(const bim_problem *prob, const bim_precond *P, double *u_out, double rtol, int prec,
+                        void *stream) {
     int rc = validate(prob);
     if (rc) return rc;
     if (!u_out) return fail(BIM_EINVAL, "u_out must be a device pointer");
+    if (prec != BIM_FP64 && prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
     bim_jfnk_opts o;
     jfnk_default_opts(&o);
+    o.inner_prec = prec;
     o.gmres_rtol = rtol > 0 ? rtol : 1e-12;
     o.max_restarts = 20;
     bim_jfnk_report r{};

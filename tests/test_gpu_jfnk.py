@@ -212,3 +212,34 @@ def test_solver_rejects_unknown_precond_storage(bim):
     u = bim.linear_start(dp)
     rep = bim.solve(dp, u, check=False, precond_storage=2)
     assert rep["status"] == -1  # BIM_EINVAL
+
+
+@pytest.mark.parametrize("F", [0.7, 1.4])
+def test_fp32c_linear_start_seeds_the_same_newton_solve(bim, F):
+    # the linear start with FP32C products to 1e-4: within the FP32C operator's
+    # resolution of the FP64 start, and Newton from it ends at the same solution
+    # in as many steps
+    p = W.working(F, N=61, M=21) if F == 1.4 else W.tiny(F)
+    dp = bim.DeviceProblem(p)
+    P = bim.Preconditioner(dp)
+    u64 = bim.linear_start(dp, P, rtol=1e-8)
+    u32 = bim.linear_start(dp, P, rtol=1e-4, prec="fp32c")
+    d = (u32 - u64).abs().max().item() / u64.abs().max().item()
+    a, b = u64.clone(), u32.clone()
+    ra = bim.solve(dp, a, P, ftol=1e-11, inner_prec="fp32c")
+    rb = bim.solve(dp, b, P, ftol=1e-11, inner_prec="fp32c")
+    print(F, "start rel diff", d, "newton", ra["newton_iters"], rb["newton_iters"], "gmres", ra["gmres_iters"],
+          rb["gmres_iters"])
+    assert d <= 1e-2
+    assert ra["status"] == 0 and rb["status"] == 0
+    assert abs(ra["newton_iters"] - rb["newton_iters"]) <= 1
+    assert (a - b).abs().max().item() <= 1e-9
+    P.close()
+
+
+def test_linear_start_rejects_unknown_precision(bim):
+    import ctypes
+    p = W.tiny(0.7)
+    dp = bim.DeviceProblem(p)
+    u = torch.empty(dp.n, dtype=torch.float64, device="cuda")
+    assert bim.lib().bim_linear_start_ex(dp.ref(), None, u.data_ptr(), 1e-8, 3, None) == -1
