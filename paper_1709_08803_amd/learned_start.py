@@ -40,21 +40,27 @@ def xplanes(p: W.Problem, u: np.ndarray) -> np.ndarray:
 
 
 def generate(problems: List[W.Problem], net: B.LearnedNet, batch: int = 32, ftol: float = 1e-10,
-             inner_prec: str = "fp64", max_newton: int = 10, log=print) -> List[Sample]:
+             inner_prec: str = "fp32c", max_newton: int = 10, log=print) -> List[Sample]:
     """Solve every problem from its linear start (batched); keep the converged ones.
 
     Newton is capped at max_newton steps: the batch advances in lockstep, so a
-    problem that does not converge would otherwise hold the whole batch."""
+    problem that does not converge would otherwise hold the whole batch.  The
+    targets are converged on the FP64 residual (||F||_inf <= ftol) whatever the
+    inner precision; one FP32-stored preconditioner per problem serves its
+    linear start (FP64 products, as at inference) and its solve."""
     out: List[Sample] = []
     scale = net.arch.out_scale
     t0 = time.perf_counter()
     for b0 in range(0, len(problems), batch):
         probs = problems[b0:b0 + batch]
         dps = [B.DeviceProblem(p) for p in probs]
-        ulin = [B.linear_start(dp, rtol=1e-10) for dp in dps]
+        Ps = [B.Preconditioner(dp, storage="fp32") for dp in dps]
+        ulin = [B.linear_start(dp, P, rtol=1e-10) for dp, P in zip(dps, Ps)]
         us = [u.clone() for u in ulin]
-        _, reps = B.solve_batched(dps, us, ftol=ftol, inner_prec=inner_prec, check=False, max_newton=max_newton,
-                                  stall_steps=4)
+        _, reps = B.solve_batched(dps, us, Ps, ftol=ftol, inner_prec=inner_prec, check=False,
+                                  max_newton=max_newton, stall_steps=4)
+        for P in Ps:
+            P.close()
         for p, dp, ul, u, rep in zip(probs, dps, ulin, us, reps):
             if rep["status"] != 0:
                 continue
