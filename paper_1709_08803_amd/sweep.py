@@ -7,7 +7,9 @@ in 61..181, M = (N-1)/3 + 1 over x in [-30, 30], y in [0, 20]; F ~ U[0.5, 2];
 Gaussian, transverse-ridge and two-bump topographies).  Reports, as one JSON
 line:
   * the batched residual: every instance's all-pairs sums in one persistent
-    launch, aggregate pair-interactions/s in FP64 and FP32C;
+    launch, aggregate pair-interactions/s in FP64 and FP32C, with the library's
+    default launch shape and after the autotuner has picked one on the largest
+    mesh (which the sweep's solves then use);
   * the sweep itself (Newton capped at 10 steps and stopped once ||F|| has not
     halved over 4 steps): preconditioner setup for every instance, linear starts,
     and the lockstep batched JFNK (inner sums in the chosen precision,
@@ -38,7 +40,7 @@ def _sync_time(fn, reps=1):
 
 
 def run(count: int = 64, seed: int = 0, inner: str = "fp32c", ftol: float = 1e-10, sequential: bool = True,
-        max_newton: int = 10, stall_steps: int = 4, storage: str = "fp32") -> dict:
+        max_newton: int = 10, stall_steps: int = 4, storage: str = "fp32", tune: bool = True) -> dict:
     probs = W.sweep_instances(count, seed)
     dps = [B.DeviceProblem(p) for p in probs]
     pairs = sum(p.pairs_per_eval() for p in probs)
@@ -50,6 +52,18 @@ def run(count: int = 64, seed: int = 0, inner: str = "fp32c", ftol: float = 1e-1
         B.residual_batched(dps, us, prec)
         _, dt = _sync_time(lambda: B.residual_batched(dps, us, prec), reps=5)
         res[f"batched_residual_{prec}"] = {"ms": dt * 1e3, "pairs_per_s": pairs / dt}
+    if tune:
+        # the batched launch runs one kernel variant for all instances: the one the
+        # autotuner picks on the largest mesh of the sweep (it then also serves the
+        # batched solver, and every later call with that mesh)
+        big = max(range(count), key=lambda i: probs[i].N * probs[i].M)
+        for prec in ("fp64", "fp32c"):
+            cfg, ms = B.tune_residual(dps[big], us[big], prec)
+            B.residual_batched(dps, us, prec)
+            _, dt = _sync_time(lambda: B.residual_batched(dps, us, prec), reps=5)
+            res[f"batched_residual_{prec}_tuned"] = {"ms": dt * 1e3, "pairs_per_s": pairs / dt,
+                                                     "tuned_on": f"{probs[big].N}x{probs[big].M}",
+                                                     "config": list(cfg), "tuned_kernel_ms": ms}
     # the sweep: preconditioners, linear starts, lockstep JFNK
     Ps, t_setup = _sync_time(lambda: [B.Preconditioner(dp, storage=storage) for dp in dps])
     # linear starts in the inner precision, to the relative tolerance of the
@@ -92,9 +106,10 @@ def main():
     ap.add_argument("--inner", default="fp32c", choices=("fp64", "fp32c"))
     ap.add_argument("--storage", default="fp32", choices=("fp64", "fp32"))
     ap.add_argument("--no-sequential", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (library default launch shape)")
     args = ap.parse_args()
     print(json.dumps(run(args.count, args.seed, args.inner, sequential=not args.no_sequential,
-                         storage=args.storage)))
+                         storage=args.storage, tune=not args.no_tune)))
 
 
 if __name__ == "__main__":
