@@ -80,6 +80,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         load(0);
         store(0);
     }
+    // C (for beta != 0) is read at the start, at clamped indices, so that its
+    // loads are in flight during the products instead of after them
+    const bool rmw = beta != 0.0;
+    double cv[2][2][4];
+    if (rmw) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int gr = row0 + wm + 16 * t + lk + 4 * v, gc = col0 + wn + 16 * u + li;
+                    cv[t][u][v] = C[(size_t)min(gr, m - 1) * ldc + min(gc, n - 1)];
+                }
+    }
     __syncthreads();
     for (int k0 = 0; k0 < k; k0 += TK) {
         const bool more = k0 + TK < k;
@@ -110,10 +125,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int gr = row0 + wm + 16 * t + lk + 4 * v, gc = col0 + wn + 16 * u + li;
-                if (gr < m && gc < n) {
-                    const GlobalPtr<double> p = C + (size_t)gr * ldc + gc;
-                    *p = (beta == 0.0) ? alpha * acc[t][u][v] : fma(alpha, acc[t][u][v], beta * (*p));
-                }
+                if (gr < m && gc < n)
+                    C[(size_t)gr * ldc + gc] = rmw ? fma(alpha, acc[t][u][v], beta * cv[t][u][v]) : alpha * acc[t][u][v];
             }
 }
 
