@@ -117,9 +117,24 @@ def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15):
         ulin = B.linear_start(dp, P, rtol=lrtol, prec=lprec)
         torch.cuda.synchronize()
         t_lin = time.perf_counter() - t0
+        # the apply reads every stored array once: bytes ~ P.nbytes (less the
+        # 4 n FP64 apply scratch); timed with events on the current stream
+        r = torch.ones(dp.n, dtype=torch.float64, device="cuda")
+        z = torch.empty_like(r)
+        for _ in range(3):
+            P.apply(r, out=z)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            P.apply(r, out=z)
+        e1.record()
+        torch.cuda.synchronize()
+        apply_ms = e0.elapsed_time(e1) / 20
+        apply_bytes = P.nbytes - 4 * 8 * (dp.n // 3)
         res[f"precond_{storage}"] = {"setup_ms": t_setup * 1e3, "linear_start_ms": t_lin * 1e3,
                                      "linear_start_prec": lprec, "linear_start_rtol": lrtol,
-                                     "band_halfwidth": P.band, "bytes": P.nbytes}
+                                     "band_halfwidth": P.band, "bytes": P.nbytes, "apply_ms": apply_ms,
+                                     "apply_GBps": apply_bytes / (apply_ms * 1e-3) / 1e9}
         for leg, (st, kw) in legs.items():
             if st != storage:
                 continue
