@@ -347,23 +347,30 @@ def residual_rows(p, u: np.ndarray, rows: Sequence[int]) -> np.ndarray:
     return out
 
 
-def term_magnitude_rows(p, u: np.ndarray) -> np.ndarray:
+def term_magnitude_rows(p, u: np.ndarray, rows: Optional[Sequence[int]] = None) -> np.ndarray:
     """Scale of each row of F for comparison tolerances: 1 + sum of |terms|.
 
     Boundary-integral rows: the sums of |term| over all pairs plus
     |sigma*| (s2 + |iint S2|) + 2 pi |D*|.  Pointwise rows: 1 + the largest
     magnitude among their few terms (bounded by a generous constant).
+    rows: only these entries (in that order), computing only the sums they need.
     """
     nf = reconstruct(p, u)
     gS, DS, sigS, gB, DB, sigB = surface_and_bottom(p, nf)
-    nb = (p.N + 1) * p.M
-    scale = np.full(3 * nb, 1.0 + abs(p.x1) * 4.0 / p.dx)
+    N, M = p.N, p.M
+    nb = (N + 1) * M
+    sel = np.arange(3 * nb) if rows is None else np.asarray(rows, dtype=np.int64)
+    scale = np.full(sel.shape[0], 1.0 + abs(p.x1) * 4.0 / p.dx)
     xlo, xhi, ylo, yhi = integration_rectangle(p)
-    for blk, which in ((1, "S"), (2, "B")):
-        tg = targets_from_fields(p, nf, which)
+    blk, rem = np.divmod(sel, nb)
+    l, c = np.divmod(rem, N + 1)
+    for b, which in ((1, "S"), (2, "B")):
+        q = np.nonzero((blk == b) & (c >= 2))[0]
+        if q.size == 0:
+            continue
+        tg = subset(targets_from_fields(p, nf, which), l[q] * (N - 1) + c[q] - 2)
         raw = raw_sums(p, gS, DS, sigS, gB, DB, sigB, tg, absmode=True)
         I2pp = s2_integral(tg.A, tg.B, tg.C, xlo - tg.x, xhi - tg.x, ylo - tg.y, yhi - tg.y)
         mag = raw[:, :4].sum(axis=1) + np.abs(tg.sigma) * (raw[:, 4] + np.abs(I2pp)) + TWO_PI * np.abs(tg.D)
-        v = scale[blk * nb:(blk + 1) * nb].reshape(p.M, p.N + 1)
-        v[:, 2:] = 1.0 + mag.reshape(p.M, p.N - 1)
+        scale[q] = 1.0 + mag
     return scale

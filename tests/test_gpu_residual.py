@@ -228,3 +228,28 @@ def test_workspace_reuse_across_sizes_streams_and_release(bim):
     J2 = bim.jv(dp, u, F0, v, h=1e-7)
     assert torch.equal(J1, J2)
     bim.release_workspaces()
+
+
+def test_residual_large_mesh_sampled_rows(bim):
+    # 541 x 181 (three times finer than the working mesh on the same domain;
+    # 9.5e10 pairs per evaluation, 9x the working size) at the default launch
+    # shape: a seeded sample of rows, edges and corners included, against the
+    # oracle row by row
+    p = W.working(1.4, N=541, M=181)
+    u = W.perturbed_state(p, 5)
+    rng = np.random.default_rng(9)
+    nb = (p.N + 1) * p.M
+    rows = set(rng.choice(3 * nb, 60, replace=False).tolist())
+    for blk in range(3):
+        for l in (0, p.M - 1):
+            rows.update({blk * nb + l * (p.N + 1) + c for c in (0, 2, p.N)})
+    rows = np.array(sorted(rows))
+    ref = R.residual_rows(p, u, rows)
+    scale = R.term_magnitude_rows(p, u, rows)
+    F = _gpu_F(bim, p, u, "fp64")
+    F32 = _gpu_F(bim, p, u, "fp32c")
+    e64 = (np.abs(F[rows] - ref) / scale).max()
+    e32 = (np.abs(F32[rows] - ref) / scale).max()
+    print("541x181 fp64", e64, "fp32c", e32)
+    assert e64 <= 1e-12
+    assert e32 <= 5e-7
