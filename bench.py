@@ -92,13 +92,14 @@ def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15):
     # per preconditioner storage: the linear start's precision and GMRES tolerance
     #   fp64: FP64 products to 1e-8, the relative tolerance of every FP64 Newton
     #         step's GMRES (a tighter one changes no Newton count)
-    #   fp32: FP32C products to 1e-4, the forcing term of the FP32C Newton steps
+    #   fp32: FP32C products to 1e-4 (a looser start saves at most 2 ms at 181 x 61
+    #         and has cost a Newton step)
     starts = {"fp64": ("fp64", 1e-8), "fp32": ("fp32c", 1e-4)}
     # leg: (preconditioner storage, solver options)
     #   fp64:         FP64 sums, FP64-stored P, FP64 linear start (plain FP64)
     #   fp32c:        FP32C sums with the library's GMRES tolerance for such steps
-    #                 (1e-4, the level their Jacobian action resolves), FP32-stored
-    #                 P, FP32C linear start
+    #                 (1e-2, the contraction Newton reaches per FP32C step anyway),
+    #                 FP32-stored P, FP32C linear start
     #   fp32c_p64:    FP32C sums, FP64-stored P and linear start
     #   fp32c_strict: FP32C sums with every GMRES solve at 1e-8, FP64-stored P
     legs = {"fp64": ("fp64", dict(inner_prec="fp64")),

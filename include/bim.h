@@ -200,7 +200,7 @@ int precond_band(const bim_precond *P);
  *   use_precond:    0 runs GMRES without preconditioning;
  *   use_graphs, fd_eps, stall_steps, fp64_below, fp32c_gmres_rtol: see the fields.
  * jfnk_default_opts fills 1e-10, 1e-8, 30, 10, 30, 20, BIM_FP64, -1, 1, 1, 0.0, 0,
- * 0.0, 1e-4, BIM_STORE_FP64.
+ * 0.0, 1e-2, BIM_STORE_FP64.
  * Invalid values (non-positive tolerances, restart outside [1, 200], negative
  * counts, fd_eps >= 1 or NaN, negative or NaN fp64_below, unknown precision
  * or storage)
@@ -227,7 +227,8 @@ typedef struct bim_jfnk_opts {
     double fp32c_gmres_rtol; /* relative tolerance of the GMRES solves of Newton steps that use
                             FP32C inner sums (their Jacobian action carries rounding noise of
                             order 1e-6 relative, below which GMRES stalls): the effective
-                            tolerance is max(this, gmres_rtol); default 1e-4, <= 0: gmres_rtol */
+                            tolerance is max(this, gmres_rtol); default 1e-2, the contraction
+                            Newton reaches per FP32C step anyway; <= 0: gmres_rtol */
     int32_t precond_storage; /* storage of a preconditioner the solver builds itself (P == NULL):
                             BIM_STORE_FP64 or BIM_STORE_FP32 (see precond_setup_ex) */
 } bim_jfnk_opts;

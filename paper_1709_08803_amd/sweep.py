@@ -66,8 +66,8 @@ def run(count: int = 64, seed: int = 0, inner: str = "fp32c", ftol: float = 1e-1
                                                      "config": list(cfg), "tuned_kernel_ms": ms}
     # the sweep: preconditioners, linear starts, lockstep JFNK
     Ps, t_setup = _sync_time(lambda: [B.Preconditioner(dp, storage=storage) for dp in dps])
-    # linear starts in the inner precision, to the relative tolerance of the
-    # Newton steps' GMRES (FP64: 1e-8; FP32C: 1e-4, the level its products resolve)
+    # linear starts in the inner precision (FP64: to 1e-8, the Newton steps' GMRES
+    # tolerance; FP32C: to 1e-4, well above the level its products resolve)
     lrtol = 1e-4 if inner == "fp32c" else 1e-8
     ulin, t_lin = _sync_time(lambda: [B.linear_start(dp, P, rtol=lrtol, prec=inner) for dp, P in zip(dps, Ps)])
     ub = [u.clone() for u in ulin]

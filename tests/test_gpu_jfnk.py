@@ -147,8 +147,9 @@ def test_stall_stop_ends_a_stagnating_solve(bim):
     P.close()
 
 
-@pytest.mark.parametrize("opts", [dict(fp64_below=1e-5), dict(fp32c_gmres_rtol=0.0), dict(fp32c_gmres_rtol=1e-4)],
-                         ids=["switch-to-fp64", "fp32c-strict-gmres", "fp32c-forcing-1e-4"])
+@pytest.mark.parametrize("opts", [dict(fp64_below=1e-5), dict(fp32c_gmres_rtol=0.0), dict(fp32c_gmres_rtol=1e-4),
+                                  dict()],
+                         ids=["switch-to-fp64", "fp32c-strict-gmres", "fp32c-forcing-1e-4", "fp32c-default-forcing"])
 def test_fp32c_solve_options_reach_the_fp64_solution(bim, opts):
     # FP32C inner sums with the precision switch or either GMRES tolerance:
     # the same FP64-converged discrete solution as the plain FP64 solve
