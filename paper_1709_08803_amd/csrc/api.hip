@@ -191,7 +191,15 @@ int bim_release_workspaces(void) {
     for (auto &kv : g_ws) {
         if (!kv.second.ptr) continue;
         int r2 = hip_check(hipSetDevice(kv.first.first), "hipSetDevice");
-        if (!r2) r2 = hip_check(hipStreamSynchronize(kv.first.second), "hipStreamSynchronize");
+        if (r2) {
+            if (!rc) rc = r2;
+            continue;
+        }
+        // a stream destroyed by the caller cannot be waited on: wait for the device
+        if (hipStreamSynchronize(kv.first.second) != hipSuccess) {
+            (void)hipGetLastError();
+            r2 = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+        }
         if (!r2) r2 = hip_check(hipFree(kv.second.ptr), "hipFree");
         if (r2 && !rc) rc = r2;
     }
