@@ -6,11 +6,14 @@
 namespace bim {
 
 // One product of a batched GEMM: C = alpha A B + beta C (row-major).
-struct GemmItem {
-    const double *A;
-    const double *B;
-    double *C;
+template <typename T>
+struct GemmItemT {
+    const T *A;
+    const T *B;
+    T *C;
 };
+using GemmItem = GemmItemT<double>;
+using GemmItemF = GemmItemT<float>;
 // One matrix of a batched inversion: Ainv = A^-1 (s x s, row-major).
 struct InvItem {
     const double *A;
@@ -22,6 +25,10 @@ struct InvItem {
 // items_dev: device array of `batch` items; all share m, n, k and leading dims.
 int gemm_enqueue(const GemmItem *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
                  double alpha, double beta, hipStream_t s);
+// The same product in FP32 (FP32 operands, FP32 accumulation on the matrix
+// cores) for 128 < m <= 192 only (BIM_EINVAL otherwise).
+int gemm_f32_enqueue(const GemmItemF *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
+                     double alpha, double beta, hipStream_t s);
 // work: device scratch of batch * s * 2s doubles; info[b] = 0 or (1 + column of a zero pivot).
 int invert_enqueue(const InvItem *items_dev, int batch, int s_dim, double *work, int *info, hipStream_t s);
 // y = alpha A x + beta c (dense, rows x cols, row-major with leading dim lda); c may equal y.

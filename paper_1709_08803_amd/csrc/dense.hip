@@ -143,18 +143,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // per SIMD, the setup's S^-1 products took 10 ms more at 181 x 61).
 constexpr int kTallM = 192, kTallK = 32, kTallWaves = 12;
 
-template <int TN, int NW>
-__global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItem *__restrict__ items, int m, int n, int k,
+// The 16x16x4 MFMA of each precision: operands as in k_gemm; the FP64
+// accumulator holds D[l/16 + 4v][l%16], the FP32 one D[4(l/16) + v][l%16]
+// (both lane layouts checked on gfx950 by in-bounds probes).
+typedef float float4_t __attribute__((ext_vector_type(4)));
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<double> {
+    typedef double4_t acc;
+    static __device__ __forceinline__ acc step(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct Mfma16<float> {
+    typedef float4_t acc;
+    static __device__ __forceinline__ acc step(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+
+template <int TN, int NW, typename T = double>
+__global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItemT<T> *__restrict__ items, int m, int n, int k,
                                                        int lda, int ldb, int ldc, double alpha, double beta) {
     constexpr int NT = 64 * NW, NB = TN / 16, RB = 12 / NW;
     constexpr int QA = kTallM * kTallK / NT, QB = (kTallK * TN + NT - 1) / NT;
     static_assert(QA * NT == kTallM * kTallK && RB * NW == 12, "tall tile shape");
-    const GemmItem it = items[blockIdx.z];
-    const GlobalPtr<const double> A = (GlobalPtr<const double>)it.A;
-    const GlobalPtr<const double> B = (GlobalPtr<const double>)it.B;
-    const GlobalPtr<double> C = (GlobalPtr<double>)it.C;
-    __shared__ double As[2][kTallM][kTallK + 1];
-    __shared__ double Bs[2][kTallK][TN + 1];
+    typedef Mfma16<T> MF;
+    const GemmItemT<T> it = items[blockIdx.z];
+    const GlobalPtr<const T> A = (GlobalPtr<const T>)it.A;
+    const GlobalPtr<const T> B = (GlobalPtr<const T>)it.B;
+    const GlobalPtr<T> C = (GlobalPtr<T>)it.C;
+    __shared__ T As[2][kTallM][kTallK + 1];
+    __shared__ T Bs[2][kTallK][TN + 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave * 16 * RB;
@@ -162,7 +186,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItem *__restric
     const int li = lane & 15, lk = lane >> 4;
     // unconditional loads at clamped indices, B rows past k zeroed when staged
     // (as in k_gemm)
-    double ra[QA], rb[QB];
+    T ra[QA], rb[QB];
     auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < QA; ++q) {
@@ -188,15 +212,15 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItem *__restric
             const int e = tid + q * NT;
             if (e < kTallK * TN) {
                 const int br = e / TN;
-                Bs[buf][br][e - br * TN] = (k0 + br < k) ? rb[q] : 0.0;
+                Bs[buf][br][e - br * TN] = (k0 + br < k) ? rb[q] : (T)0;
             }
         }
     };
-    double4_t acc[RB][NB];
+    typename MF::acc acc[RB][NB];
 #pragma unroll
     for (int t = 0; t < RB; ++t)
 #pragma unroll
-        for (int u = 0; u < NB; ++u) acc[t][u] = double4_t{0.0, 0.0, 0.0, 0.0};
+        for (int u = 0; u < NB; ++u) acc[t][u] = typename MF::acc{0, 0, 0, 0};
     if (k > 0) {
         load(0);
         store(0, 0);
@@ -208,7 +232,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItem *__restric
         if (more) load(k0 + kTallK);
 #pragma unroll
         for (int kk = 0; kk < kTallK; kk += 4) {
-            double a[RB], b[NB];
+            T a[RB], b[NB];
 #pragma unroll
             for (int t = 0; t < RB; ++t) a[t] = As[buf][wm + 16 * t + li][kk + lk];
 #pragma unroll
@@ -217,7 +241,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItem *__restric
             for (int t = 0; t < RB; ++t)
 #pragma unroll
                 for (int u = 0; u < NB; ++u)
-                    acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
+                    acc[t][u] = MF::step(a[t], b[u], acc[t][u]);
         }
         // the other buffer was last read in the previous step, before its barrier
         if (more) store(buf ^ 1, k0 + kTallK);
@@ -230,10 +254,10 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItem *__restric
         for (int u = 0; u < NB; ++u)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gr = wm + 16 * t + lk + 4 * v, gc = col0 + 16 * u + li;
+                const int gr = wm + 16 * t + MF::row(lk, v), gc = col0 + 16 * u + li;
                 if (gr < m && gc < n) {
-                    const GlobalPtr<double> p = C + (size_t)gr * ldc + gc;
-                    *p = (beta == 0.0) ? alpha * acc[t][u][v] : fma(alpha, acc[t][u][v], beta * (*p));
+                    const GlobalPtr<T> p = C + (size_t)gr * ldc + gc;
+                    *p = (beta == 0.0) ? (T)alpha * acc[t][u][v] : fma((T)alpha, acc[t][u][v], (T)beta * (*p));
                 }
             }
 }
@@ -771,6 +795,34 @@ int to_float_enqueue(const double *src, float *dst, size_t count, hipStream_t s)
     const int blocks = (int)std::min<size_t>((count + 255) / 256, 8192);
     hipLaunchKernelGGL(k_to_float, dim3(blocks), dim3(256), 0, s, src, dst, count);
     return hip_check(hipGetLastError(), "conversion launch");
+}
+
+int gemm_f32_enqueue(const GemmItemF *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
+                     double alpha, double beta, hipStream_t s) {
+    if (batch <= 0 || m <= 0 || n <= 0) return BIM_OK;
+    if (batch > 65535) return fail(BIM_EINVAL, "gemm batch too large");
+    if (m <= 128 || m > kTallM) return fail(BIM_EINVAL, "FP32 gemm needs 128 < m <= 192");
+    int tn = 64;
+    long best = -1;
+    for (int c : {64, 48, 32}) {  // fewest rounds of 256 workgroups times panel width
+        const long cost = (long)cdiv((long)cdiv(n, c) * batch, 256) * c;
+        if (best < 0 || cost < best) {
+            best = cost;
+            tn = c;
+        }
+    }
+    dim3 grid(cdiv(n, tn), 1, batch);
+    constexpr int NW = kTallWaves;
+    if (tn == 32)
+        hipLaunchKernelGGL((k_gemm_tall<32, NW, float>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
+                           alpha, beta);
+    else if (tn == 48)
+        hipLaunchKernelGGL((k_gemm_tall<48, NW, float>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
+                           alpha, beta);
+    else
+        hipLaunchKernelGGL((k_gemm_tall<64, NW, float>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
+                           alpha, beta);
+    return hip_check(hipGetLastError(), "gemm launch");
 }
 
 int copy2d_enqueue(const double *src, long lds, double *dst, long ldd, int rows, int cols, hipStream_t s) {

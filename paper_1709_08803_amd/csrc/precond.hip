@@ -294,7 +294,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     addt(sizeof(double) * (size_t)4 * s * 2 * s);   // inversion work
     addt(sizeof(int) * (M + 2));                    // info
     const size_t nitems = 64 + (size_t)M * (2 * h + 1) * 4 + (size_t)M * (2 * w2 + 1) * (2 * h + 3) +
-                          (size_t)M * (w2 * w2 + w2 + 2) + 16;
+                          (size_t)M * (w2 * w2 + w2 + 2) + 2 * (size_t)M + 16;
     addt(sizeof(GemmItem) * nitems);
     addt(sizeof(InvItem) * (M + 4));
     void *tbase = nullptr;
@@ -459,7 +459,9 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         // copied while l + j + 1 < M)
         RUN(copy_blocks_enqueue(S + (size_t)(w2 + 1) * bs, brow, bs, s, Urow, (long)s * w2 * s, s, (long)w2 * s, s, s,
                                 M, w2, M - 1, st));
-        // S^-1: forward with L (unit lower), backward with U
+        // S^-1: forward with L (unit lower), backward with U (in FP32 when the
+        // operator is stored in FP32 and the block rows fit the FP32 panel kernel)
+        const bool bw32 = storage == BIM_STORE_FP32 && s > 128 && s <= 192;
         RUN(identity_enqueue(pc->Sinv, n, st));
         std::vector<GemmItem> fw, bw1, bw2;
         for (int l = 1; l < M; ++l) {
@@ -488,13 +490,49 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
             // only columns of block rows < l can be nonzero in rows q < l of L^-1
             RUN(gemm_enqueue(sv_dev + (l - 1), 1, s, l * s, (l - q0) * s, w2 * s, (int)n, (int)n, -1.0, 1.0, st));
         }
-        for (int t = 0; t < M; ++t) {
-            const int l = M - 1 - t;
-            const int kk = std::min(M - 1, l + w2) - l;  // number of blocks to the right
-            if (kk > 0)
-                RUN(gemm_enqueue(sv_dev + (M - 1) + t, 1, s, (int)n, kk * s, w2 * s, (int)n, (int)n, -1.0, 1.0, st));
-            RUN(gemm_enqueue(sv_dev + (M - 1) + M + t, 1, s, (int)n, s, s, (int)n, (int)n, 1.0, 0.0, st));
-            RUN(copy2d_enqueue(rowtmp, n, pc->Sinv + (size_t)l * s * n, n, s, (int)n, st));
+        if (bw32) {
+            // FP32 storage: round the operator (S^-1 holding L^-1 so far) to FP32
+            // now and run the backward substitution in FP32 on the matrix cores,
+            // into the FP32 S^-1.  U rows and pivot inverses are rounded into
+            // the L rows' memory, free after the forward pass; rowtmp holds an
+            // FP32 block row.
+            RUN(precond_round_to_fp32(pc, st));
+            float *U32 = (float *)Lrow;
+            float *Ui32 = U32 + (size_t)M * s * w2 * s;
+            float *row32 = (float *)rowtmp;
+            RUN(to_float_enqueue(Urow, U32, (size_t)M * s * w2 * s, st));
+            RUN(to_float_enqueue(Uinv, Ui32, (size_t)M * s * s, st));
+            float *S32 = pc->f32.Sinv;
+            std::vector<GemmItemF> bf;
+            for (int l = M - 1; l >= 0; --l) {
+                bf.push_back({U32 + ((size_t)l * s) * (w2 * s), S32 + (size_t)(l + 1) * s * n, S32 + (size_t)l * s * n});
+                bf.push_back({Ui32 + (size_t)l * s * s, S32 + (size_t)l * s * n, row32});
+            }
+            GemmItemF *bf_dev = (GemmItemF *)(sv_dev + all.size());
+            if (items.size() + all.size() + bf.size() > nitems)
+                return fail(BIM_EINVAL, "internal: preconditioner item buffer too small");
+            RUN(hip_check(hipMemcpyAsync(bf_dev, bf.data(), sizeof(GemmItemF) * bf.size(), hipMemcpyHostToDevice, st),
+                          "copy"));
+            for (int t = 0; t < M; ++t) {
+                const int l = M - 1 - t;
+                const int kk = std::min(M - 1, l + w2) - l;
+                if (kk > 0)
+                    RUN(gemm_f32_enqueue(bf_dev + 2 * t, 1, s, (int)n, kk * s, w2 * s, (int)n, (int)n, -1.0, 1.0, st));
+                RUN(gemm_f32_enqueue(bf_dev + 2 * t + 1, 1, s, (int)n, s, s, (int)n, (int)n, 1.0, 0.0, st));
+                RUN(hip_check(hipMemcpyAsync(S32 + (size_t)l * s * n, row32, sizeof(float) * (size_t)s * n,
+                                             hipMemcpyDeviceToDevice, st),
+                              "copy"));
+            }
+        } else {
+            for (int t = 0; t < M; ++t) {
+                const int l = M - 1 - t;
+                const int kk = std::min(M - 1, l + w2) - l;  // number of blocks to the right
+                if (kk > 0)
+                    RUN(gemm_enqueue(sv_dev + (M - 1) + t, 1, s, (int)n, kk * s, w2 * s, (int)n, (int)n, -1.0, 1.0,
+                                     st));
+                RUN(gemm_enqueue(sv_dev + (M - 1) + M + t, 1, s, (int)n, s, s, (int)n, (int)n, 1.0, 0.0, st));
+                RUN(copy2d_enqueue(rowtmp, n, pc->Sinv + (size_t)l * s * n, n, s, (int)n, st));
+            }
         }
         // a zero pivot in any inverted block makes P singular in this factorisation
         std::vector<int> hinfo(2 + M, 0);
@@ -508,7 +546,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     }();
 #undef RUN
     (void)hipFreeAsync(tbase, st);
-    if (!rc && storage == BIM_STORE_FP32) rc = precond_round_to_fp32(pc, st);
+    if (!rc && storage == BIM_STORE_FP32 && pc->storage != BIM_STORE_FP32) rc = precond_round_to_fp32(pc, st);
     if (rc) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(pc->mem);
