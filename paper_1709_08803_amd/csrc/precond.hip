@@ -290,11 +290,12 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     addt(sizeof(double) * (size_t)M * s * s);       // Uinv
     addt(sizeof(double) * (size_t)M * s * w2 * s);  // L rows
     addt(sizeof(double) * (size_t)M * s * w2 * s);  // U rows
+    if (storage == BIM_STORE_FP32) addt(sizeof(float) * (size_t)M * s * w2 * s);  // L rows in FP32
     addt(sizeof(double) * (size_t)s * n);           // one block row of S^-1 (temp)
     addt(sizeof(double) * (size_t)4 * s * 2 * s);   // inversion work
     addt(sizeof(int) * (M + 2));                    // info
     const size_t nitems = 64 + (size_t)M * (2 * h + 1) * 4 + (size_t)M * (2 * w2 + 1) * (2 * h + 3) +
-                          (size_t)M * (w2 * w2 + w2 + 2) + 2 * (size_t)M + 16;
+                          (size_t)M * (w2 * w2 + w2 + 2) + 3 * (size_t)M + 16;
     addt(sizeof(GemmItem) * nitems);
     addt(sizeof(InvItem) * (M + 4));
     void *tbase = nullptr;
@@ -317,6 +318,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     double *Uinv = ta.take<double>((size_t)M * s * s);
     double *Lrow = ta.take<double>((size_t)M * s * w2 * s);
     double *Urow = ta.take<double>((size_t)M * s * w2 * s);
+    float *L32 = (storage == BIM_STORE_FP32) ? ta.take<float>((size_t)M * s * w2 * s) : nullptr;
     double *rowtmp = ta.take<double>((size_t)s * n);
     double *invwork = ta.take<double>((size_t)4 * s * 2 * s);
     int *info = ta.take<int>(M + 2);
@@ -485,25 +487,34 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
             return fail(BIM_EINVAL, "internal: preconditioner item buffer too small");
         RUN(hip_check(hipMemcpyAsync(sv_dev, all.data(), sizeof(GemmItem) * all.size(), hipMemcpyHostToDevice, st),
                       "copy"));
-        for (int l = 1; l < M; ++l) {
-            const int q0 = std::max(0, l - w2);
-            // only columns of block rows < l can be nonzero in rows q < l of L^-1
-            RUN(gemm_enqueue(sv_dev + (l - 1), 1, s, l * s, (l - q0) * s, w2 * s, (int)n, (int)n, -1.0, 1.0, st));
+        if (!bw32) {
+            for (int l = 1; l < M; ++l) {
+                const int q0 = std::max(0, l - w2);
+                // only columns of block rows < l can be nonzero in rows q < l of L^-1
+                RUN(gemm_enqueue(sv_dev + (l - 1), 1, s, l * s, (l - q0) * s, w2 * s, (int)n, (int)n, -1.0, 1.0,
+                                 st));
+            }
         }
         if (bw32) {
-            // FP32 storage: round the operator (S^-1 holding L^-1 so far) to FP32
-            // now and run the backward substitution in FP32 on the matrix cores,
-            // into the FP32 S^-1.  U rows and pivot inverses are rounded into
-            // the L rows' memory, free after the forward pass; rowtmp holds an
-            // FP32 block row.
+            // FP32 storage: round the operator (S^-1 = I so far) to FP32 now and
+            // run both substitutions in FP32 on the matrix cores, into the FP32
+            // S^-1: the L rows are rounded into their own buffer, then the U rows
+            // and pivot inverses into the FP64 L rows' memory, which the rounding
+            // has read; rowtmp holds an FP32 block row.
             RUN(precond_round_to_fp32(pc, st));
+            float *S32 = pc->f32.Sinv;
+            RUN(to_float_enqueue(Lrow, L32, (size_t)M * s * w2 * s, st));
             float *U32 = (float *)Lrow;
             float *Ui32 = U32 + (size_t)M * s * w2 * s;
             float *row32 = (float *)rowtmp;
             RUN(to_float_enqueue(Urow, U32, (size_t)M * s * w2 * s, st));
             RUN(to_float_enqueue(Uinv, Ui32, (size_t)M * s * s, st));
-            float *S32 = pc->f32.Sinv;
-            std::vector<GemmItemF> bf;
+            std::vector<GemmItemF> bf;  // forward items (M - 1), then two per backward step
+            for (int l = 1; l < M; ++l) {
+                const int q0 = std::max(0, l - w2);
+                bf.push_back({L32 + ((size_t)l * s) * (w2 * s) + (size_t)(q0 - (l - w2)) * s,
+                              S32 + (size_t)q0 * s * n, S32 + (size_t)l * s * n});
+            }
             for (int l = M - 1; l >= 0; --l) {
                 bf.push_back({U32 + ((size_t)l * s) * (w2 * s), S32 + (size_t)(l + 1) * s * n, S32 + (size_t)l * s * n});
                 bf.push_back({Ui32 + (size_t)l * s * s, S32 + (size_t)l * s * n, row32});
@@ -513,6 +524,12 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                 return fail(BIM_EINVAL, "internal: preconditioner item buffer too small");
             RUN(hip_check(hipMemcpyAsync(bf_dev, bf.data(), sizeof(GemmItemF) * bf.size(), hipMemcpyHostToDevice, st),
                           "copy"));
+            for (int l = 1; l < M; ++l) {
+                const int q0 = std::max(0, l - w2);
+                RUN(gemm_f32_enqueue(bf_dev + (l - 1), 1, s, l * s, (l - q0) * s, w2 * s, (int)n, (int)n, -1.0, 1.0,
+                                     st));
+            }
+            bf_dev += M - 1;
             for (int t = 0; t < M; ++t) {
                 const int l = M - 1 - t;
                 const int kk = std::min(M - 1, l + w2) - l;
