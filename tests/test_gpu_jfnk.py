@@ -108,14 +108,18 @@ def test_graph_replay_matches_eager_solve(bim):
 GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
 
 
-@pytest.mark.parametrize("inner,tol", [("fp64", 1e-9), ("fp32c", 1e-8)])
-def test_full_size_solution_matches_stored_oracle_solution(bim, inner, tol):
-    # 181 x 61, F = 1.4: the oracle's converged solution (tests/golden/make_working_solutions.py)
+@pytest.mark.parametrize("inner,tol,storage,lin", [("fp64", 1e-9, "fp64", "fp64"), ("fp32c", 1e-8, "fp64", "fp64"),
+                                                    ("fp32c", 1e-8, "fp32", "fp32c")],
+                         ids=["fp64", "fp32c", "mixed-fp32-storage"])
+def test_full_size_solution_matches_stored_oracle_solution(bim, inner, tol, storage, lin):
+    # 181 x 61, F = 1.4: the oracle's converged solution (tests/golden/make_working_solutions.py);
+    # the mixed case runs the FP32-stored P (its S^-1 formed by FP32 substitutions)
+    # and the FP32C linear start
     p = W.working(1.4)
     ref = np.load(f"{GOLDEN}/working_181x61_F1.4.npz")["u"]
     dp = bim.DeviceProblem(p)
-    P = bim.Preconditioner(dp)
-    u = bim.linear_start(dp, P)
+    P = bim.Preconditioner(dp, storage=storage)
+    u = bim.linear_start(dp, P, rtol=1e-4 if lin == "fp32c" else 0.0, prec=lin)
     rep = bim.solve(dp, u, P, ftol=1e-11, inner_prec=inner)
     print(inner, {k: rep[k] for k in ("status", "newton_iters", "gmres_iters", "fnorm_inf", "time_ms")})
     assert rep["status"] == 0

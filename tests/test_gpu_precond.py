@@ -113,11 +113,19 @@ def test_precond_rejects_unknown_storage(bim):
     assert not h.value
 
 
-@pytest.mark.parametrize("name,mk,hb", [
-    ("odd-s-44x9-h2", lambda: W.make_problem(44, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 2),
-    ("even-s-45x9-h3", lambda: W.make_problem(45, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 3),
-], ids=["odd-s", "even-s"])
-def test_fp32_storage_small_meshes_match_oracle(bim, name, mk, hb):
+# bounds: the FP32 rounding of the elements (6e-8) amplified by the
+# cancellation in the products with the Schur-complement inverse, which grows as
+# the mesh is refined: measured 5.1e-5 and 5.6e-5 on the coarse meshes, 2.65e-3
+# at dx = 0.27 (4.1e-3 at 181 x 61, dx = 0.33, where the FP32 substitutions
+# leave it unchanged to three digits)
+@pytest.mark.parametrize("name,mk,hb,tol", [
+    ("odd-s-44x9-h2", lambda: W.make_problem(44, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 2, 2e-4),
+    ("even-s-45x9-h3", lambda: W.make_problem(45, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 3, 2e-4),
+    # 128 < s <= 192: the substitutions forming S^-1 run in FP32 (odd s)
+    ("fp32-substitutions-150x9-h2", lambda: W.make_problem(150, 9, -20, 20, 0, 4, 1.1, [W.Bump(0.2, 1.0, 1.0)]), 2,
+     1e-2),
+], ids=["odd-s", "even-s", "fp32-substitutions-odd-s"])
+def test_fp32_storage_small_meshes_match_oracle(bim, name, mk, hb, tol):
     # FP32 elements read one per lane (odd s: rows not aligned to two elements)
     # or two per lane (even s): both apply the oracle's P to FP32 rounding
     p = mk()
@@ -129,8 +137,5 @@ def test_fp32_storage_small_meshes_match_oracle(bim, name, mk, hb):
     z_ref = pc_ref.apply(r)
     err = np.abs(z - z_ref).max() / np.abs(z_ref).max()
     print(name, "fp32 storage rel err", err)
-    # rounded (not bit-equal to FP64), and close: measured 5.1e-5 (odd s) and
-    # 5.6e-5 (even s), the FP32 rounding of the elements amplified by the
-    # cancellation in the products with the Schur-complement inverse
-    assert 0 < err <= 2e-4
+    assert 0 < err <= tol  # rounded (not bit-equal to FP64), and close
     P.close()
