@@ -382,7 +382,13 @@ __device__ __forceinline__ void row_end(TargetState<T, NI> &g) {
 // NI = 2: half domain (both images per source row); NI = 1: full domain.
 // FP32 (grid units): t = (y_j - y*) / dx is formed in FP64 for every source row
 // and the S2 sum is multiplied by dx on output; FP64 works in physical units.
-template <typename T, bool COMP, int TPL, int UNROLL, int NI, bool CREC>
+// LIN: the linearised residual (Section 4.2), whose boundaries are the planes
+// z = 0 and z = -1 with zero slopes.  On a record of the target's own plane the
+// double-layer numerator is exactly zero, so the general body adds exactly
+// w sigma / R, and the S2 radicand is exactly s^2 + t^2; on the other plane the
+// numerator is exactly the plane separation.  The LIN bodies drop those zero
+// terms and give bit-identical sums.
+template <typename T, bool COMP, int TPL, int UNROLL, int NI, bool CREC, bool LIN = false>
 __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
                                           const T *__restrict__ tg, const double *__restrict__ tg64, int N, int M,
                                           double y1, double dx, double dy, int tiles_per_bnd, int row_groups,
@@ -445,7 +451,36 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
             ts[q].acc2[0] = ts[q].acc2[1] = 0;
         }
         const RecPtr<T, CREC> src = (ss ? recB : recS) + (size_t)j * N + i0;
-        if (ss == st) {
+        if (LIN && ss == st) {
+            walk_row<T, UNROLL, CREC>(src, i1 - i0, [&](const SrcRec<T> &p, auto slot) {
+                constexpr int a = decltype(slot)::value;
+                const T s = p.x - xs;
+                T ri[TPL][NI], rq[TPL][NI];
+#pragma unroll
+                for (int q = 0; q < TPL; ++q) {
+                    const TargetState<T, NI> &e = ts[q];
+                    const T dz = p.z - e.d;  // exactly zero: both points lie on one plane
+                    const T base = (NI == 2) ? fma(s, s, dz * dz) : fma(s, s, e.t2[0]);
+#pragma unroll
+                    for (int i = 0; i < NI; ++i) {
+                        ri[q][i] = rsq((NI == 2) ? base + e.t2[i] : fma(dz, dz, base));
+                        // A = C = 1, B = 0: the S2 radicand is s^2 + t^2, in one rounding
+                        rq[q][i] = (NI == 2) ? rsq(fma(s, s, e.t2[i])) : ri[q][i];
+                    }
+                }
+                return [&, p, ri, rq]() {
+#pragma unroll
+                    for (int q = 0; q < TPL; ++q) {
+                        TargetState<T, NI> &e = ts[q];
+#pragma unroll
+                        for (int i = 0; i < NI; ++i) {
+                            e.acc[a] = fma(p.ws, ri[q][i], e.acc[a]);
+                            e.acc2[a] = fma(p.w, rq[q][i], e.acc2[a]);
+                        }
+                    }
+                };
+            });
+        } else if (ss == st) {
             walk_row<T, UNROLL, CREC>(src, i1 - i0, [&](const SrcRec<T> &p, auto slot) {
                 constexpr int a = decltype(slot)::value;
                 const T s = p.x - xs;
@@ -487,7 +522,7 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                     const TargetState<T, NI> &e = ts[q];
                     const T dz = p.z - e.d;
                     const T base = (NI == 2) ? fma(s, s, dz * dz) : fma(s, s, e.t2[0]);
-                    nb0[q] = fma(-s, p.zx, dz);
+                    nb0[q] = LIN ? dz : fma(-s, p.zx, dz);
 #pragma unroll
                     for (int i = 0; i < NI; ++i) ri[q][i] = rsq((NI == 2) ? base + e.t2[i] : fma(dz, dz, base));
                 }
@@ -497,7 +532,7 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
                         TargetState<T, NI> &e = ts[q];
 #pragma unroll
                         for (int i = 0; i < NI; ++i) {
-                            const T num = fma(-e.ti[i], p.zy, nb0[q]);
+                            const T num = LIN ? nb0[q] : fma(-e.ti[i], p.zy, nb0[q]);
                             const T bsum = fma(p.wD * num, ri[q][i] * ri[q][i], p.ws);
                             e.acc[a] = fma(bsum, ri[q][i], e.acc[a]);
                         }
@@ -520,18 +555,18 @@ __device__ __forceinline__ void pair_item(const SrcRec<T> *__restrict__ srcS, co
     }
 }
 
-template <typename T, bool COMP, int TPL, int UNROLL, bool CREC>
+template <typename T, bool COMP, int TPL, int UNROLL, bool CREC, bool LIN = false>
 __device__ __forceinline__ void pair_item_any(const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB,
                                               const T *__restrict__ tg, const double *__restrict__ tg64, int N,
                                               int M, int nimg, double y1, double dx, double dy, int tiles_per_bnd,
                                               int row_groups, int chunks, double *__restrict__ part, int tt,
                                               int c, int lane) {
     if (nimg == 2)
-        pair_item<T, COMP, TPL, UNROLL, 2, CREC>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
-                                                 chunks, part, tt, c, lane);
+        pair_item<T, COMP, TPL, UNROLL, 2, CREC, LIN>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd,
+                                                      row_groups, chunks, part, tt, c, lane);
     else
-        pair_item<T, COMP, TPL, UNROLL, 1, CREC>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd, row_groups,
-                                                 chunks, part, tt, c, lane);
+        pair_item<T, COMP, TPL, UNROLL, 1, CREC, LIN>(srcS, srcB, tg, tg64, N, M, y1, dx, dy, tiles_per_bnd,
+                                                      row_groups, chunks, part, tt, c, lane);
 }
 
 // Resident waves per SIMD asked of the compiler: 8 for the FP32 variants whose
@@ -543,8 +578,9 @@ __device__ __forceinline__ void pair_item_any(const SrcRec<T> *__restrict__ srcS
 template <typename T, int TPL, int UNROLL>
 constexpr int kMinWaves = (sizeof(T) == 4 && TPL == 1 && UNROLL <= 4) ? 8 : 1;
 
-// Single problem: one wave per (target tile, source chunk).
-template <typename T, bool COMP, int TPL, int UNROLL>
+// Single problem: one wave per (target tile, source chunk).  LIN: the
+// linearised residual (one launch shape per precision).
+template <typename T, bool COMP, int TPL, int UNROLL, bool LIN = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<T, TPL, UNROLL>))) void k_allpairs(
     const SrcRec<T> *__restrict__ srcS, const SrcRec<T> *__restrict__ srcB, const T *__restrict__ tg,
     const double *__restrict__ tg64, int N, int M, int nimg, double y1, double dx, double dy, int tiles_per_bnd,
@@ -555,8 +591,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<T
     const int g = blockIdx.x * 4 + wave;
     const int tt = g % target_tiles, c = g / target_tiles;
     if (c >= chunks) return;
-    pair_item_any<T, COMP, TPL, UNROLL, false>(srcS, srcB, tg, tg64, N, M, nimg, y1, dx, dy, tiles_per_bnd,
-                                               row_groups, chunks, part, tt, c, lane);
+    pair_item_any<T, COMP, TPL, UNROLL, false, LIN>(srcS, srcB, tg, tg64, N, M, nimg, y1, dx, dy, tiles_per_bnd,
+                                                    row_groups, chunks, part, tt, c, lane);
 }
 
 // Many problems in one persistent launch: the work items (target tile, source
@@ -811,7 +847,21 @@ int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
                        p->y1, p->dx, p->dy, pl.tiles_per_bnd, pl.row_groups, pl.target_tiles, pl.chunks, \
                        w.part)
     const int vsel = (pl.tpl == 2 ? 3 : 0) + (pl.unroll == 2 ? 0 : pl.unroll == 4 ? 1 : 2);
-    if (prec == BIM_FP64) {
+    if (linear) {
+        // the same source chunks (the partial-sum buffer and the finalize use
+        // pl.chunks), one target row per lane and the default unroll
+        const PairLaunch ll = pair_launch(d, 1, prec == BIM_FP64 ? 4 : 2, pl.chunks);
+        if (prec == BIM_FP64)
+            hipLaunchKernelGGL((k_allpairs<double, false, 1, 4, true>), dim3(ll.blocks), dim3(256), 0, s,
+                               (const SrcRec<double> *)w.srcS, (const SrcRec<double> *)w.srcB, w.tg, w.tg, N, M,
+                               d.nimg, p->y1, p->dx, p->dy, ll.tiles_per_bnd, ll.row_groups, ll.target_tiles,
+                               ll.chunks, w.part);
+        else
+            hipLaunchKernelGGL((k_allpairs<float, true, 1, 2, true>), dim3(ll.blocks), dim3(256), 0, s,
+                               (const SrcRec<float> *)w.srcS, (const SrcRec<float> *)w.srcB, w.tg32, w.tg, N, M,
+                               d.nimg, p->y1, p->dx, p->dy, ll.tiles_per_bnd, ll.row_groups, ll.target_tiles,
+                               ll.chunks, w.part);
+    } else if (prec == BIM_FP64) {
         switch (vsel) {
             case 0: BIM_LAUNCH_PAIRS(double, false, 1, 2, w.tg); break;
             case 1: BIM_LAUNCH_PAIRS(double, false, 1, 4, w.tg); break;
