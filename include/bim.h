@@ -90,6 +90,17 @@ typedef struct bim_problem {
 int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, void *stream);
 
 /*
+ * F_lin(u): the residual of the linearised problem (Section 4.2, Appendix B),
+ * the operator whose root is the linear start.  The same discretisation and
+ * unknowns as bim_residual, with both boundaries the planes z = 0 and z = -1
+ * (zero slopes and elevations in the kernels; the layer densities phi - x,
+ * zeta_x on the free surface and psi - x, -beta_x on the bottom are unchanged)
+ * and the dynamic condition phi*_x + zeta* / F^2 - 1 = 0.  F_lin is affine in u.
+ * Arguments, layout, precision, scratch memory and errors as bim_residual.
+ */
+int bim_residual_linear(const bim_problem *prob, const double *u, double *F, int prec, void *stream);
+
+/*
  * Jv = (F(u + h v) - Fu) / h: the first-order difference quotient that
  * replaces the Jacobian action in the Krylov solver (Section 3.2).
  *   Fu: F(u) evaluated with the same `prec` (device [3(N+1)M]).

@@ -50,6 +50,7 @@ def lib():
         vp, i32, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         pp = ctypes.POINTER(_Problem)
         L.bim_residual.argtypes = [pp, vp, vp, i32, vp]
+        L.bim_residual_linear.argtypes = [pp, vp, vp, i32, vp]
         L.bim_jv.argtypes = [pp, vp, vp, vp, dbl, vp, i32, vp]
         L.bim_release_workspaces.argtypes = []
         L.bim_residual_timed.argtypes = [pp, vp, vp, i32, i32, ctypes.POINTER(PairConfig), vp,
@@ -87,7 +88,7 @@ def lib():
         L.lg_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, i32, fp, vp]
         L.lg_make_input.argtypes = [pp, vp, i32, vp, vp, vp]
         L.lg_infer_start.argtypes = [vp, pp, vp, vp, vp]
-        for name in ("bim_residual", "bim_jv", "bim_residual_timed", "bim_tune_residual", "precond_setup",
+        for name in ("bim_residual", "bim_residual_linear", "bim_jv", "bim_residual_timed", "bim_tune_residual", "precond_setup",
                      "precond_setup_ex", "precond_storage", "precond_apply", "precond_band", "jfnk_solve",
                      "bim_linear_start", "bim_linear_start_ex", "lg_create",
                      "lg_num_params", "lg_set_params", "lg_get_params", "lg_forward", "lg_train_step",
@@ -174,6 +175,14 @@ def residual(dp: DeviceProblem, u: torch.Tensor, prec="fp64", out: Optional[torc
              stream=None) -> torch.Tensor:
     F = out if out is not None else torch.empty_like(u)
     _check(lib().bim_residual(dp.ref(), _dptr(u), _dptr(F), _PREC[prec], _stream(stream)))
+    return F
+
+
+def residual_linear(dp: DeviceProblem, u: torch.Tensor, prec="fp64", out: Optional[torch.Tensor] = None,
+                    stream=None) -> torch.Tensor:
+    """bim_residual_linear: the linearised residual F_lin(u)."""
+    F = out if out is not None else torch.empty_like(u)
+    _check(lib().bim_residual_linear(dp.ref(), _dptr(u), _dptr(F), _PREC[prec], _stream(stream)))
     return F
 
 

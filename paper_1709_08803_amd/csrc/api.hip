@@ -94,7 +94,7 @@ const char *bim_last_error(void) { return g_last_error.c_str(); }
 
 const char *bim_version(void) { return "bim-mi355x 0.1"; }
 
-int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, void *stream) {
+static int residual_call(const bim_problem *prob, const double *u, double *F, int prec, void *stream, int linear) {
     g_last_error.clear();
     int rc = validate(prob);
     if (rc) return rc;
@@ -109,7 +109,15 @@ int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, 
     if ((rc = stream_workspace(s, residual_work_bytes(d, pl), &ws))) return rc;
     ResidualWork w;
     residual_work_carve(ws, d, pl, &w);
-    return residual_enqueue(prob, u, F, prec, pl, w, s);
+    return residual_enqueue(prob, u, F, prec, pl, w, s, nullptr, linear);
+}
+
+int bim_residual(const bim_problem *prob, const double *u, double *F, int prec, void *stream) {
+    return residual_call(prob, u, F, prec, stream, 0);
+}
+
+int bim_residual_linear(const bim_problem *prob, const double *u, double *F, int prec, void *stream) {
+    return residual_call(prob, u, F, prec, stream, 1);
 }
 
 int bim_residual_timed(const bim_problem *prob, const double *u, double *F, int prec, int iters,
