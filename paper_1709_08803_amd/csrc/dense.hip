@@ -262,9 +262,9 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItemT<T> *__res
             }
 }
 
-// In-place Gauss-Jordan inversion of one s x s block (s <= 192) per 512-thread
+// In-place Gauss-Jordan inversion of one s x s block (s <= 192) per 1024-thread
 // workgroup, with the matrix held in registers: wave ty (= tid / 64, uniform in
-// the wave) owns rows ty + 8 i (i < 24) and lane tx columns tx + 64 j (j < 3).
+// the wave) owns rows ty + 16 i (i < 12) and lane tx columns tx + 64 j (j < 3).
 // Rows are eliminated in their natural order k = 0 .. s-1 with partial
 // pivoting over the columns (the pivot of row k is its largest entry among the
 // columns not yet used: partial pivoting of the transpose), so that the row
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItemT<T> *__res
 // pivot column is kept in its own scale: its true values are the stored ones
 // times sc[q] = -1/p (row operations commute with column scaling), so that
 // no step has to rescale it.  Step k:
-//   wave k % 8 (row k is its register row k / 8) finds q (a DPP maximum of
+//   wave k % 16 (row k is its register row k / 16) finds q (a DPP maximum of
 //   packed pivot keys) and stages row k, scaled by 1/p and with 0 at column q,
 //   in one of two LDS buffers (one barrier per step);
 //   every row r: a[r][c] -= a[r][q] * rowk[c] (column q keeps a[r][q], which
@@ -282,9 +282,9 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItemT<T> *__res
 // After s steps the registers hold the inverse with rows and columns permuted
 // by the pivot columns, storage[r][q_c] sc[q_c] = inverse[q_r][c]; the
 // write-out applies the scales and undoes the permutation.  Only the owner
-// wave indexes its registers by k / 8 (a switch); the update of all rows uses
+// wave indexes its registers by k / 16 (a switch); the update of all rows uses
 // constant register indices.
-constexpr int kRegTy = 8, kRegRows = 24, kRegCols = 3;
+constexpr int kRegTy = 16, kRegRows = 12, kRegCols = 3;
 constexpr int kRegThreads = 64 * kRegTy;
 constexpr int kRegMaxS = kRegTy * kRegRows;  // = 64 kRegCols = 192
 
@@ -316,13 +316,11 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-#define BIM_ROW_CASES(X)                                                                                        \
-    X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) \
-        X(19) X(20) X(21) X(22) X(23)
+#define BIM_ROW_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
 
 __global__ __launch_bounds__(kRegThreads) void k_invert_reg(const InvItem *__restrict__ items, int s,
                                                             int *__restrict__ info) {
-    static_assert(kRegRows == 24, "BIM_ROW_CASES lists 24 register rows");
+    static_assert(kRegRows == 12, "BIM_ROW_CASES lists 12 register rows");
     const InvItem it = items[blockIdx.x];
     const int tx = threadIdx.x & 63;
     const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
