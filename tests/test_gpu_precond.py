@@ -28,6 +28,8 @@ CASES = [
     ("full-31x13", lambda: W.make_problem(31, 13, -10, 10, -6, 6, 1.2, [], half_domain=False), 1),
     # pivot blocks of s = N + 1 = 192, the largest the register inversion holds
     ("max-block-191x5-h1", lambda: W.make_problem(191, 5, -20, 20, 0, 1, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 1),
+    # s = 193: the augmented-matrix Gauss-Jordan kernel for blocks beyond that
+    ("big-block-192x5-h1", lambda: W.make_problem(192, 5, -20, 20, 0, 1, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 1),
 ]
 
 
