@@ -139,3 +139,43 @@ def test_trained_network_reduces_newton_iterations(bim):
     assert s["both_converged"] >= 36
     assert s["learned_newton_mean"] < s["linear_newton_mean"]
     assert s["max_dx_between_solutions"] <= 1e-8
+
+
+# The kernels keep inputs, weights, activations and the gradients fed to products
+# in bf16 (8 significant bits, unit roundoff u = 2^-8 relative to the spacing),
+# with FP32 accumulation.  Against the plain FP64 network (no rounding at all)
+# each layer's operands carry relative errors of order u, so the output differs
+# by a few u in the 2-norm: bound 4u.  The gradient of the linear output layer
+# follows the output error (4u); the three layers before it sit behind ReLUs
+# whose activation pattern flips where rounding moves a pre-activation across
+# zero, so their bound is on direction (cosine >= 0.98) and on a 2-norm error
+# of 0.25.  (The plain FP64 network under the same rounding, computed on the
+# CPU, stays within these bounds: forward 4-6e-3, output layer 4-5e-3, the
+# others 4e-3 to 0.14; on the GPU the ReLU layers measured 5e-3 to 4e-2.)
+BF16_U = 2.0 ** -8
+
+
+@pytest.mark.parametrize("N,M,B,lin", [(21, 9, 3, 0), (33, 15, 5, 1), (121, 41, 4, 1)])
+def test_network_within_bf16_bound_of_plain_fp64(bim, N, M, B, lin):
+    net, params = _net_and_params(bim, N, M, B, 11, lin)
+    X, f, T = _inputs(N, M, B, 12, net.in_channels)
+    Xd, fd = _bf16_tensor(X), torch.as_tensor(f, device="cuda")
+    Y = net.forward(Xd, fd).cpu().numpy().astype(np.float64)
+    Yref, cache = OL.forward(params, X, f, bf=False)
+    ef = np.linalg.norm(Y - Yref) / np.linalg.norm(Yref)
+    print("forward 2-norm rel err vs plain FP64", ef)
+    assert ef <= 4 * BF16_U
+    net.train_step(Xd, fd, torch.as_tensor(T, device="cuda"), lr=0.0, update=False)
+    _, dY = OL.loss_and_grad_out(Yref, T)
+    grads = OL.backward(params, cache, dY, bf=False)
+    for l in range(4):
+        _, _, gw, gb = net.get(l)
+        g = np.concatenate([gw.astype(np.float64), gb.astype(np.float64)])
+        r = np.concatenate([grads[l][0].reshape(-1), grads[l][1]])
+        e = np.linalg.norm(g - r) / np.linalg.norm(r)
+        cos = float(g @ r / (np.linalg.norm(g) * np.linalg.norm(r)))
+        print("layer", l, "grad 2-norm rel err", e, "cos", cos)
+        if l == 3:
+            assert e <= 4 * BF16_U
+        else:
+            assert cos >= 0.98 and e <= 0.25
