@@ -300,6 +300,24 @@ int bim_linear_start_ex(const bim_problem *prob, const bim_precond *P, double *u
                         void *stream);
 
 /*
+ * Bottom pressure and the force on the topography (Section 2.1, eq.
+ * (bottompressure)): once u is solved, Bernoulli's equation on z = beta gives
+ *   p = 1/2 - [(1 + b_x^2) psi_y^2 + (1 + b_y^2) psi_x^2 - 2 b_x b_y psi_x psi_y]
+ *             / (2 (1 + b_x^2 + b_y^2)) - beta / F^2
+ * at every bottom node.  psi is reconstructed from u as phi is for the residual
+ * (trapezoidal x-integral of psi_x from psi_1; psi_y by the same y-differences
+ * as zeta_y and phi_y).  The force on the topography is the plan-area integral
+ * of (p - 1/F^2) (beta_x, beta_y, -1) -- the pressure beyond that of the
+ * undisturbed stream, along the fluid's outward normal times the area element
+ * -- by the trapezoidal rule over the truncated mesh (over the mirrored mesh on
+ * a half domain, where the y-component is zero by symmetry).
+ *   u: device [3(N+1)M]; pres: device [M][N] output; force: device [3] output
+ *   (Fx, Fy, Fz), summed in a fixed order (deterministic).
+ * Uses stream-ordered scratch of about 8 N M bytes.
+ */
+int bim_bottom_pressure(const bim_problem *prob, const double *u, double *pres, double *force, void *stream);
+
+/*
  * F_i = F(u_i) for `count` problems (possibly of different mesh sizes) whose
  * all-pairs sums run in one persistent launch: the work items of all problems
  * form one list that every wave walks with a fixed stride, so each F_i is

@@ -12,4 +12,6 @@ Modules:
                the block-banded preconditioner of Appendix A, and the linear start
   jfnk      -- damped inexact Newton + right-preconditioned GMRES (Section 3.2)
   fourier   -- linear-theory reference values (Section 4.1)
+  pressure  -- the bottom pressure of eq. (bottompressure) and the force on the
+               topography (Section 2.1)
 """
