@@ -30,6 +30,7 @@
 #ifndef BIM_H
 #define BIM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -117,6 +118,31 @@ int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const dou
  * again.  Must not run concurrently with other calls of the library.
  */
 int bim_release_workspaces(void);
+
+/*
+ * F = F(u) without any allocation: for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Computes exactly what bim_residual computes (FP64 or
+ * FP32C sums, same kernels), with its workspace carved out of a fixed device
+ * array of bim_residual_noalloc_max_bytes() bytes (64 MiB) that the library
+ * holds on every GPU it runs on until the process ends; the array's device
+ * address is looked up once per device, on the first call made with that
+ * device current.  The call allocates nothing, frees nothing and never
+ * synchronises.
+ *   u, F, prec: as bim_residual.
+ * Size limit: the default launch is used while its workspace fits (27.5 MiB
+ * FP64 and 35.5 MiB FP32C at 181 x 61); a larger mesh runs with fewer source
+ * chunks, so that its partial sums fit, giving the same sums rounded in a
+ * different order; a mesh whose workspace does not fit even with one chunk
+ * (about 178,000 nodes per boundary, e.g. 730 x 244) is rejected with
+ * BIM_EINVAL before anything is enqueued.
+ * Every call on one GPU uses the same array, and each call overwrites every
+ * byte of it that it later reads: calls that may overlap on one GPU (two
+ * streams, two host threads) race and must be ordered by the caller.
+ */
+int bim_residual_noalloc(const bim_problem *prob, const double *u, double *F, int prec, void *stream);
+/* Size in bytes of the fixed device array used by bim_residual_noalloc. */
+size_t bim_residual_noalloc_max_bytes(void);
 
 /*
  * Launch shape of the all-pairs kernel (the sums of the boundary-integral rows).

@@ -51,7 +51,10 @@ def lib():
         pp = ctypes.POINTER(_Problem)
         L.bim_residual.argtypes = [pp, vp, vp, i32, vp]
         L.bim_residual_linear.argtypes = [pp, vp, vp, i32, vp]
+        L.bim_residual_noalloc.argtypes = [pp, vp, vp, i32, vp]
         L.bim_bottom_pressure.argtypes = [pp, vp, vp, vp, vp]
+        L.bim_residual_noalloc_max_bytes.argtypes = []
+        L.bim_residual_noalloc_max_bytes.restype = ctypes.c_size_t
         L.bim_jv.argtypes = [pp, vp, vp, vp, dbl, vp, i32, vp]
         L.bim_release_workspaces.argtypes = []
         L.bim_residual_timed.argtypes = [pp, vp, vp, i32, i32, ctypes.POINTER(PairConfig), vp,
@@ -89,7 +92,7 @@ def lib():
         L.lg_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, i32, fp, vp]
         L.lg_make_input.argtypes = [pp, vp, i32, vp, vp, vp]
         L.lg_infer_start.argtypes = [vp, pp, vp, vp, vp]
-        for name in ("bim_residual", "bim_residual_linear", "bim_bottom_pressure", "bim_jv", "bim_residual_timed", "bim_tune_residual", "precond_setup",
+        for name in ("bim_residual", "bim_residual_linear", "bim_residual_noalloc", "bim_bottom_pressure", "bim_jv", "bim_residual_timed", "bim_tune_residual", "precond_setup",
                      "precond_setup_ex", "precond_storage", "precond_apply", "precond_band", "jfnk_solve",
                      "bim_linear_start", "bim_linear_start_ex", "lg_create",
                      "lg_num_params", "lg_set_params", "lg_get_params", "lg_forward", "lg_train_step",
@@ -187,6 +190,12 @@ def residual_linear(dp: DeviceProblem, u: torch.Tensor, prec="fp64", out: Option
     return F
 
 
+def residual_noalloc(dp: DeviceProblem, u: torch.Tensor, F: torch.Tensor, prec="fp64", stream=None) -> torch.Tensor:
+    """bim_residual_noalloc: F(u) into the caller's F with the library's fixed device scratch."""
+    _check(lib().bim_residual_noalloc(dp.ref(), _dptr(u), _dptr(F), _PREC[prec], _stream(stream)))
+    return F
+
+
 def bottom_pressure(dp: DeviceProblem, u: torch.Tensor, stream=None):
     """bim_bottom_pressure: (pressure at the bottom nodes [M][N], force (Fx, Fy, Fz)) as device tensors."""
     h = dp.host
@@ -194,6 +203,10 @@ def bottom_pressure(dp: DeviceProblem, u: torch.Tensor, stream=None):
     force = torch.empty(3, dtype=torch.float64, device=u.device)
     _check(lib().bim_bottom_pressure(dp.ref(), _dptr(u), pres.data_ptr(), force.data_ptr(), _stream(stream)))
     return pres, force
+
+
+def residual_noalloc_max_bytes() -> int:
+    return int(lib().bim_residual_noalloc_max_bytes())
 
 
 def residual_batched(dps, us, prec="fp64", outs=None, stream=None):

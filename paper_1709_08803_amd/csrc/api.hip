@@ -162,6 +162,76 @@ int bim_residual_timed(const bim_problem *prob, const double *u, double *F, int 
     return BIM_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free residual
+namespace bim {
+
+// Fixed device scratch of the allocation-free residual: every call on a GPU
+// carves its workspace out of that GPU's copy of this array.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+// Device address of `scratch` per device, looked up once per device with that
+// device current (the array's name is a host-side stand-in in host code).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_addr[kMaxDevices] = {};
+
+int scratch_address(void **out) {
+    int dev = 0;
+    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return fail(BIM_EINVAL, "device index beyond the allocation-free residual's table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        if ((rc = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress"))) return rc;
+        if (!ptr) return fail(BIM_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return BIM_OK;
+}
+
+}  // namespace
+}  // namespace bim
+
+extern "C" {
+
+size_t bim_residual_noalloc_max_bytes(void) { return kNoAllocBytes; }
+
+int bim_residual_noalloc(const bim_problem *prob, const double *u, double *F, int prec, void *stream) {
+    g_last_error.clear();
+    int rc = validate(prob);
+    if (rc) return rc;
+    if (!u || !F) return fail(BIM_EINVAL, "u and F must be device pointers");
+    if (u == F) return fail(BIM_EINVAL, "F must not alias u");
+    if (prec != BIM_FP64 && prec != BIM_FP32C) return fail(BIM_EINVAL, "unknown precision");
+    const Dims d(prob);
+    PairLaunch pl = pair_launch_for(prob, prec);
+    if (residual_work_bytes(d, pl) > kNoAllocBytes) {
+        // the workspace is linear in the chunk count: keep the launch's variant
+        // and use the most source chunks whose partial sums still fit
+        const size_t one = residual_work_bytes(d, pair_launch(d, pl.tpl, pl.unroll, 1));
+        const size_t per_chunk = sizeof(double) * 2 * 2 * (size_t)d.ntg;
+        if (one > kNoAllocBytes)
+            return fail(BIM_EINVAL, "mesh too large for the allocation-free residual's " +
+                                        std::to_string(kNoAllocBytes >> 20) + " MiB scratch");
+        const long fit = 1 + (long)((kNoAllocBytes - one) / per_chunk);
+        pl = pair_launch(d, pl.tpl, pl.unroll, (int)std::min<long>(fit, pl.chunks));
+        while (pl.chunks > 1 && residual_work_bytes(d, pl) > kNoAllocBytes)
+            pl = pair_launch(d, pl.tpl, pl.unroll, pl.chunks - 1);
+    }
+    void *base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    ResidualWork w;
+    residual_work_carve(base, d, pl, &w);
+    return residual_enqueue(prob, u, F, prec, pl, w, (hipStream_t)stream, nullptr, 0);
+}
+
 int bim_jv(const bim_problem *prob, const double *u, const double *Fu, const double *v, double h, double *Jv,
            int prec, void *stream) {
     g_last_error.clear();
