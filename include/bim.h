@@ -359,11 +359,20 @@ int bim_residual_batched(const bim_problem *probs, int count, const double *cons
  * problems advance in lockstep rounds in which every unfinished problem needs
  * one residual evaluation, and the all-pairs sums of all of them run in one
  * persistent launch (bim_residual_batched).  A problem that fails does not stop
- * the others.
+ * the others.  A round is a fixed sequence of launches whose shapes do not
+ * depend on the round (op lists with one slot per problem, residual launches
+ * sized for every problem, inactive slots doing nothing); the host writes the
+ * round's descriptors into pinned memory and, with opts->use_graphs (the
+ * default), replays one HIP graph captured at the first round -- the copy of
+ * the descriptors, every GMRES, preconditioner and residual kernel, and the copy
+ * of the small results back -- so each round is one graph launch.  Graph replay
+ * and eager launches (use_graphs = 0) give identical results.
  *   probs: host array; Ps: host array of preconditioners (or NULL entries /
- *   a NULL array to build them internally); us: host array of device vectors
- *   (start in, last iterate out); opts: NULL for defaults (restart <= 30);
- *   reps: host array of `count` reports (may be NULL).
+ *   a NULL array to build them internally); no preconditioner may appear twice
+ *   (each problem writes its preconditioner's apply scratch); us: host array of
+ *   distinct device vectors (start in, last iterate out); opts: NULL for
+ *   defaults (restart <= 30); reps: host array of `count` reports (may be NULL).
+ *   Duplicate preconditioners or vectors: BIM_EINVAL.
  * Returns the most negative status among the problems, else the largest soft
  * status, else BIM_OK.
  */

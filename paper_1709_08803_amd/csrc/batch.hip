@@ -27,20 +27,25 @@ __device__ double bsum256(double v) {
     return r;
 }
 
-// part[row * kBRedBlocks + bx]; row = blockIdx.z (multidot) or 0 (dot)
+// part[row * kBRedBlocks + bx] for rows 0 .. nv-1 (multidot) or row 0 (dot):
+// each workgroup takes its grid-stride slice of every row in turn
 __global__ __launch_bounds__(kT) void k_bdot_part(const BOp *__restrict__ ops, int multi) {
     const BOp o = ops[blockIdx.y];
-    const int row = multi ? (int)blockIdx.z : 0;
-    if (row >= (multi ? o.nv : 1)) return;
-    const double *a = multi ? o.a + (size_t)row * o.ld : o.a;
-    double v = 0.0;
-    for (long e = (long)blockIdx.x * kT + threadIdx.x; e < o.n; e += (long)kBRedBlocks * kT) v = fma(a[e], o.b[e], v);
-    v = bsum256(v);
-    if (threadIdx.x == 0) o.part[(size_t)row * kBRedBlocks + blockIdx.x] = v;
+    if (o.n == 0) return;  // empty slot of a padded op list
+    const int rows = multi ? o.nv : 1;
+    for (int row = 0; row < rows; ++row) {
+        const double *a = multi ? o.a + (size_t)row * o.ld : o.a;
+        double v = 0.0;
+        for (long e = (long)blockIdx.x * kT + threadIdx.x; e < o.n; e += (long)kBRedBlocks * kT)
+            v = fma(a[e], o.b[e], v);
+        v = bsum256(v);
+        if (threadIdx.x == 0) o.part[(size_t)row * kBRedBlocks + blockIdx.x] = v;
+    }
 }
 
 __global__ __launch_bounds__(kT) void k_bdot_sum(const BOp *__restrict__ ops, int multi, int take_sqrt) {
     const BOp o = ops[blockIdx.y];
+    if (o.n == 0) return;
     const int row = blockIdx.x;
     if (row >= (multi ? o.nv : 1)) return;
     double v = (threadIdx.x < kBRedBlocks) ? o.part[(size_t)row * kBRedBlocks + threadIdx.x] : 0.0;
@@ -77,6 +82,7 @@ __global__ __launch_bounds__(kT) void k_belem(const BOp *__restrict__ ops, int k
 __global__ __launch_bounds__(kT) void k_bmax_part(const BOp *__restrict__ ops) {
     __shared__ double sh[kT];
     const BOp o = ops[blockIdx.y];
+    if (o.n == 0) return;  // uniform across the workgroup: no barrier is skipped by part of it
     double v = 0.0;
     for (long e = (long)blockIdx.x * kT + threadIdx.x; e < o.n; e += (long)kBRedBlocks * kT) {
         const double x = fabs(o.a[e]);
@@ -98,6 +104,7 @@ __global__ void k_bmax_sum(const BOp *__restrict__ ops, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const BOp o = ops[i];
+    if (o.n == 0) return;
     double v = 0.0;
     for (int b = 0; b < kBRedBlocks; ++b) {
         const double y = o.part[b];
@@ -110,6 +117,7 @@ __global__ void k_bshift(const BOp *__restrict__ ops, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const BOp o = ops[i];
+    if (!o.sc) return;  // empty slot (shift ops carry no vector length)
     if (o.alpha > 0.0) {
         o.sc[2] = o.alpha;
     } else {
@@ -217,6 +225,7 @@ __global__ __launch_bounds__(256) void k_bgemv(const BGemv *__restrict__ ops) {
 
 __global__ void k_bgather(const BOp *__restrict__ ops) {
     const BOp o = ops[blockIdx.x];
+    if (!o.c) return;  // empty slot
     for (int t = threadIdx.x; t < 8 + o.nv; t += blockDim.x) o.c[t] = (t < 8) ? o.a[t] : o.b[t - 8];
 }
 
@@ -228,14 +237,14 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 int b_dot(const BOp *ops, int count, bool take_sqrt, hipStream_t s) {
     if (count <= 0) return BIM_OK;
-    hipLaunchKernelGGL(k_bdot_part, dim3(kBRedBlocks, count, 1), dim3(kT), 0, s, ops, 0);
+    hipLaunchKernelGGL(k_bdot_part, dim3(kBRedBlocks, count), dim3(kT), 0, s, ops, 0);
     hipLaunchKernelGGL(k_bdot_sum, dim3(1, count), dim3(kT), 0, s, ops, 0, take_sqrt ? 1 : 0);
     return hip_check(hipGetLastError(), "batched dot launch");
 }
 
 int b_multidot(const BOp *ops, int count, int max_nv, hipStream_t s) {
     if (count <= 0 || max_nv <= 0) return BIM_OK;
-    hipLaunchKernelGGL(k_bdot_part, dim3(kBRedBlocks, count, max_nv), dim3(kT), 0, s, ops, 1);
+    hipLaunchKernelGGL(k_bdot_part, dim3(kBRedBlocks, count), dim3(kT), 0, s, ops, 1);
     hipLaunchKernelGGL(k_bdot_sum, dim3(max_nv, count), dim3(kT), 0, s, ops, 1, 0);
     return hip_check(hipGetLastError(), "batched multidot launch");
 }

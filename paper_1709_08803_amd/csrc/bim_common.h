@@ -94,6 +94,8 @@ struct PairDesc {
     double y1, dx, dy;
     int tiles_per_bnd, row_groups, target_tiles, chunks;
     long item0;  // index of this problem's first work item in the batch
+    long batch_items;  // work items of the whole batch (the same in every descriptor of a batch)
+    int active;        // 0: the problem takes no part in this evaluation (no work items, no rows)
     // node-level kernels
     const double *u;
     double *F;
@@ -134,5 +136,25 @@ int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
 int residual_batched_enqueue(const bim_problem *probs, int count, const double *const *u, double *const *F,
                              int prec, const PairLaunch *pls, const ResidualWork *ws, PairDesc *descs_dev,
                              int max_blocks, hipStream_t s, hipEvent_t *ev_pair = nullptr);
+
+// The batched residual split into a host part and a launch of fixed shape, so
+// that one captured graph serves every evaluation of a batch whatever subset of
+// its problems takes part (the descriptors are rewritten before each replay):
+//   residual_batched_fill writes the descriptors of all `count` problems into
+//   host memory (u[i], F[i] of an inactive problem may be NULL) and returns
+//   the total number of work items of the active ones;
+//   residual_batched_launch enqueues the four kernels over the descriptors
+//   already in device memory, with grids sized for all problems active.
+struct BatchShape {
+    int tpl, unroll;
+    int b_int, b_rec, b_fin;  // node-level workgroups of all problems
+    int blocks;               // persistent all-pairs grid
+};
+BatchShape residual_batched_shape(const bim_problem *probs, int count, const PairLaunch *pls, int max_blocks);
+int residual_batched_fill(const bim_problem *probs, int count, const int *active, const double *const *u,
+                          double *const *F, int prec, const PairLaunch *pls, const ResidualWork *ws,
+                          PairDesc *descs_host, long *total_items);
+int residual_batched_launch(const PairDesc *descs_dev, int count, int prec, const BatchShape &shape, hipStream_t s,
+                            hipEvent_t *ev_pair = nullptr);
 
 }  // namespace bim

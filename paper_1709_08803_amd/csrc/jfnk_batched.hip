@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,14 @@ namespace {
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 enum Phase { PH_BASE, PH_INNER, PH_ARNOLDI, PH_RESTART, PH_LINESEARCH, PH_DONE };
+// Op lists of a round, in launch order (one slot per problem in each).
+enum Slice {
+    S_COMB, S_ACCU, S_ACCF, S_GRHS, S_GZ, S_GR, S_GB, S_GV,          // pre-work
+    S_LS, S_SHU, S_SHZ, S_SHIFT, S_AXPY,                               // inputs of the evaluations
+    S_QUO, S_MD1, S_OR1, S_MD2, S_OR2, S_WN, S_VN, S_RSR, S_RSB, S_RSV,  // Arnoldi and restart post-work
+    S_NF2, S_NFI, S_GATHER, S_COUNT                                    // norms, results to the host
+};
+constexpr int kPcStages = 7;  // banded products of one preconditioner apply (plus its dense product)
 enum Pending { PD_NONE = 0, PD_GMRES_START = 1, PD_COMBINE = 2, PD_ACCEPT = 4 };
 
 
@@ -38,7 +47,7 @@ struct Inst {
     const Precond *pc;
     PairLaunch pl;
     ResidualWork rw;
-    double *u, *F, *Fin, *delta, *rhs, *V, *Z, *w, *ut, *Ft, *r, *hdev, *scal, *ydev, *part;
+    double *u, *F, *Fin, *delta, *rhs, *V, *Z, *w, *ut, *Ft, *r, *hdev, *scal, *part;
     int phase = PH_BASE;
     int pending = PD_NONE;
     int j = 0, cyc = 0, bt = 0, newton = 0;
@@ -114,14 +123,21 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         const size_t vb = al256(sizeof(double) * d.nvec);
         bytes += vb * ((size_t)(m + 1) + m + 9);
         bytes += al256(sizeof(double) * (size_t)kBRedBlocks * (m + 1)) + al256(sizeof(double) * 3 * (m + 1)) +
-                 al256(sizeof(double) * 8) + al256(sizeof(double) * (m + 1));
+                 al256(sizeof(double) * 8);
     }
-    const size_t desc_off = bytes;
-    bytes += 2 * al256(sizeof(PairDesc) * count);
-    const size_t ops_off = bytes;
-    const int kOpSlots = 24;
-    bytes += al256(sizeof(BOp) * (size_t)count * kOpSlots) + al256(sizeof(BBand) * (size_t)count * 8) +
-             al256(sizeof(BGemv) * count);
+    // the round block: every descriptor of a round (op lists padded to one slot
+    // per problem, preconditioner stages, pair descriptors of both precision
+    // groups, GMRES combination coefficients), laid out identically in pinned
+    // host memory and in device memory and moved by one copy per round
+    const size_t rb_ops = 0;
+    const size_t rb_bands = rb_ops + al256(sizeof(BOp) * (size_t)S_COUNT * count);
+    const size_t rb_gemv = rb_bands + al256(sizeof(BBand) * (size_t)kPcStages * count);
+    const size_t rb_d64 = rb_gemv + al256(sizeof(BGemv) * count);
+    const size_t rb_d32 = rb_d64 + al256(sizeof(PairDesc) * count);
+    const size_t rb_y = rb_d32 + al256(sizeof(PairDesc) * count);
+    const size_t rb_bytes = rb_y + al256(sizeof(double) * (size_t)count * m);
+    const size_t round_off = bytes;
+    bytes += rb_bytes;
     const int kSmall = 8 + 3 * (m + 1);  // per problem: scal[8] and the Hessenberg column buffers
     const size_t stage_off = bytes;
     bytes += al256(sizeof(double) * (size_t)count * kSmall);
@@ -135,14 +151,17 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         }
     } mg{mem, s};
     double *hstage = nullptr;
+    char *hround = nullptr;
     if ((rc = hip_check(hipHostMalloc((void **)&hstage, sizeof(double) * (size_t)count * kSmall), "hipHostMalloc")))
         return rc;
     struct HostGuard {
-        double *p;
+        void *p;
         ~HostGuard() {
             if (p) (void)hipHostFree(p);
         }
     } hg{hstage};
+    if ((rc = hip_check(hipHostMalloc((void **)&hround, rb_bytes), "hipHostMalloc"))) return rc;
+    HostGuard hg2{hround};
     for (int i = 0; i < count; ++i) {
         Inst &q = I[i];
         const Dims d(q.p);
@@ -168,7 +187,6 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         q.part = take(sizeof(double) * (size_t)kBRedBlocks * (m + 1));
         q.hdev = take(sizeof(double) * 3 * (m + 1));
         q.scal = take(sizeof(double) * 8);
-        q.ydev = take(sizeof(double) * (m + 1));
         q.u = us[i];
         q.H.assign((size_t)(m + 1) * m, 0.0);
         q.cs.assign(m, 0.0);
@@ -176,30 +194,134 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         q.g.assign(m + 1, 0.0);
         q.y.assign(m, 0.0);
     }
-    PairDesc *desc64 = (PairDesc *)((char *)mem + desc_off);
-    PairDesc *desc32 = (PairDesc *)((char *)mem + desc_off + al256(sizeof(PairDesc) * count));
-    BOp *opdev = (BOp *)((char *)mem + ops_off);
-    BBand *banddev = (BBand *)((char *)mem + ops_off + al256(sizeof(BOp) * (size_t)count * kOpSlots));
-    BGemv *gemvdev = (BGemv *)((char *)banddev + al256(sizeof(BBand) * (size_t)count * 8));
+    char *dround = (char *)mem + round_off;
     double *stage = (double *)((char *)mem + stage_off);
-
-    // host-side op list builder: every batched launch gets its own slice of opdev
-    std::vector<BOp> hops;
-    std::vector<std::pair<size_t, int>> slices;  // (first, count)
-    auto push_ops = [&](const std::vector<BOp> &v) {
-        slices.push_back({hops.size(), (int)v.size()});
-        hops.insert(hops.end(), v.begin(), v.end());
-        return (int)slices.size() - 1;
-    };
+    BOp *const hops = (BOp *)(hround + rb_ops);
+    BBand *const hbands = (BBand *)(hround + rb_bands);
+    BGemv *const hgemv = (BGemv *)(hround + rb_gemv);
+    PairDesc *const hd64 = (PairDesc *)(hround + rb_d64);
+    PairDesc *const hd32 = (PairDesc *)(hround + rb_d32);
+    double *const hy = (double *)(hround + rb_y);
+    BOp *const dops = (BOp *)(dround + rb_ops);
+    BBand *const dbands = (BBand *)(dround + rb_bands);
+    BGemv *const dgemv = (BGemv *)(dround + rb_gemv);
+    const PairDesc *const dd64 = (const PairDesc *)(dround + rb_d64);
+    const PairDesc *const dd32 = (const PairDesc *)(dround + rb_d32);
+    const double *const dy = (const double *)(dround + rb_y);
     const double eps64 = (o->fd_eps > 0) ? o->fd_eps : std::ldexp(1.0, -52);
     const double eps32 = (o->fd_eps > 0) ? o->fd_eps : std::ldexp(1.0, -23);
     const int maxh = (int)(sizeof(I[0].R.history) / sizeof(I[0].R.history[0]));
-    int rounds = 0;
+    int rounds = 0, graph_captures = 0;
+
+    // fixed launch shapes of a round, sized for every problem taking part
+    std::vector<PairLaunch> pls(count);
+    std::vector<ResidualWork> rws(count);
+    for (int i = 0; i < count; ++i) {
+        pls[i] = I[i].pl;
+        rws[i] = I[i].rw;
+    }
+    const BatchShape shape = residual_batched_shape(probs, count, pls.data(), 0);
+    const bool has32 = o->inner_prec == BIM_FP32C;
+    int max_groups = 0, max_rows = 0;
+    bool has_pc = false;
+    for (int i = 0; i < count; ++i)
+        if (I[i].pc) {
+            has_pc = true;
+            max_groups = std::max(max_groups, I[i].pc->M * ((I[i].pc->s + 3) / 4));
+            max_rows = std::max(max_rows, (int)I[i].pc->n);
+        }
+    auto OPS = [&](int slice) { return dops + (size_t)slice * count; };
+
+    // The device work of one round, in a fixed sequence of launches whose shapes
+    // do not depend on the round: every op list has one slot per problem (empty
+    // slots do nothing) and the residuals cover all problems (inactive ones do
+    // nothing).  With use_graphs it is captured once and replayed every round.
+    auto enqueue_round = [&]() -> int {
+        int q;
+        if ((q = hip_check(hipMemcpyAsync(dround, hround, rb_bytes, hipMemcpyHostToDevice, s), "copy"))) return q;
+        // pre-work: pending GMRES combinations, accepted steps, GMRES starts
+        if ((q = b_combine(OPS(S_COMB), count, s))) return q;
+        if ((q = b_axpby(OPS(S_ACCU), count, s))) return q;
+        if ((q = b_axpby(OPS(S_ACCF), count, s))) return q;
+        if ((q = b_axpby(OPS(S_GRHS), count, s))) return q;
+        if ((q = b_axpby(OPS(S_GZ), count, s))) return q;
+        if ((q = b_axpby(OPS(S_GR), count, s))) return q;
+        if ((q = b_dot(OPS(S_GB), count, true, s))) return q;
+        if ((q = b_scale_inv(OPS(S_GV), count, s))) return q;
+        // preconditioner applies, stage by stage in the order of precond_apply_enqueue:
+        // five banded products, the dense Schur product, two banded products
+        if (has_pc) {
+            for (int stg = 0; stg < 5; ++stg)
+                if ((q = b_bandmv(dbands + (size_t)stg * count, count, max_groups, s))) return q;
+            if ((q = b_gemv(dgemv, count, max_rows, s))) return q;
+            for (int stg = 5; stg < kPcStages; ++stg)
+                if ((q = b_bandmv(dbands + (size_t)stg * count, count, max_groups, s))) return q;
+        }
+        if ((q = b_axpby(OPS(S_LS), count, s))) return q;  // unpreconditioned copies and line-search points
+        if ((q = b_dot(OPS(S_SHU), count, true, s))) return q;
+        if ((q = b_dot(OPS(S_SHZ), count, true, s))) return q;
+        if ((q = b_shift(OPS(S_SHIFT), count, s))) return q;
+        if ((q = b_axpy_dev(OPS(S_AXPY), count, s))) return q;
+        // residuals: one persistent all-pairs launch per precision group
+        if ((q = residual_batched_launch(dd64, count, BIM_FP64, shape, s))) return q;
+        if (has32 && (q = residual_batched_launch(dd32, count, BIM_FP32C, shape, s))) return q;
+        // post-work: difference quotients, two CGS passes, norms, restarts, residual norms
+        if ((q = b_quotient(OPS(S_QUO), count, s))) return q;
+        if ((q = b_multidot(OPS(S_MD1), count, m, s))) return q;
+        if ((q = b_orth(OPS(S_OR1), count, s))) return q;
+        if ((q = b_multidot(OPS(S_MD2), count, m, s))) return q;
+        if ((q = b_orth(OPS(S_OR2), count, s))) return q;
+        if ((q = b_dot(OPS(S_WN), count, true, s))) return q;
+        if ((q = b_scale_inv(OPS(S_VN), count, s))) return q;
+        if ((q = b_axpby(OPS(S_RSR), count, s))) return q;
+        if ((q = b_dot(OPS(S_RSB), count, true, s))) return q;
+        if ((q = b_scale_inv(OPS(S_RSV), count, s))) return q;
+        if ((q = b_dot(OPS(S_NF2), count, true, s))) return q;
+        if ((q = b_maxabs(OPS(S_NFI), count, s))) return q;
+        // small results of every problem -> one pinned host copy
+        if ((q = b_gather(OPS(S_GATHER), count, s))) return q;
+        return hip_check(hipMemcpyAsync(hstage, stage, sizeof(double) * (size_t)count * kSmall,
+                                        hipMemcpyDeviceToHost, s), "copy");
+    };
+    hipGraphExec_t round_graph = nullptr;
+    struct GraphGuard {
+        hipGraphExec_t *g;
+        ~GraphGuard() {
+            if (*g) (void)hipGraphExecDestroy(*g);
+        }
+    } gg{&round_graph};
+    auto run_round = [&]() -> int {
+        int q;
+        if (!o->use_graphs) {
+            if ((q = enqueue_round())) return q;
+        } else {
+            if (!round_graph) {
+                if ((q = hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")))
+                    return q;
+                const int q_work = enqueue_round();
+                hipGraph_t g = nullptr;
+                q = hip_check(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
+                if (q_work || q) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return q_work ? q_work : q;
+                }
+                q = hip_check(hipGraphInstantiate(&round_graph, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+                (void)hipGraphDestroy(g);
+                if (q) return q;
+                ++graph_captures;
+            }
+            if ((q = hip_check(hipGraphLaunch(round_graph, s), "hipGraphLaunch"))) return q;
+        }
+        return hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    };
 
     auto finish_inst = [&](Inst &q, int status) {
         q.phase = PH_DONE;
         q.R.status = status;
     };
+    std::vector<int> on64(count), on32(count);
+    std::vector<const double *> in64(count), in32(count);
+    std::vector<double *> out64(count), out32(count);
 
     for (;;) {
         // ---------------- gather this round's work
@@ -208,45 +330,44 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
             if (I[i].phase != PH_DONE) act.push_back(i);
         if (act.empty()) break;
         ++rounds;
-        hops.clear();
-        slices.clear();
-        std::vector<BBand> hband;
-        std::vector<BGemv> hgemv;
+        std::memset(hround, 0, rb_bytes);  // every slot empty
+        auto put = [&](int slice, int i, const BOp &op) { hops[(size_t)slice * count + i] = op; };
+        std::fill(on64.begin(), on64.end(), 0);
+        std::fill(on32.begin(), on32.end(), 0);
+        std::fill(in64.begin(), in64.end(), nullptr);
+        std::fill(in32.begin(), in32.end(), nullptr);
+        std::fill(out64.begin(), out64.end(), nullptr);
+        std::fill(out32.begin(), out32.end(), nullptr);
         // pending actions decided last round
-        std::vector<BOp> combine, acc_u, acc_F, gm_zero, gm_rhs, gm_copy_r, gm_beta, gm_v0;
         for (int i : act) {
             Inst &q = I[i];
-            if (q.pending & PD_COMBINE) combine.push_back({q.Z, nullptr, q.delta, q.ydev, nullptr, nullptr, q.n, q.n, q.j + 1, 0, 0});
+            if (q.pending & PD_COMBINE) {
+                std::copy(q.y.begin(), q.y.begin() + (q.j + 1), hy + (size_t)i * m);
+                put(S_COMB, i, {q.Z, nullptr, q.delta, dy + (size_t)i * m, nullptr, nullptr, q.n, q.n, q.j + 1, 0, 0});
+            }
             if (q.pending & PD_ACCEPT) {
-                acc_u.push_back({q.ut, nullptr, q.u, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, 0.0});
-                acc_F.push_back({q.Ft, nullptr, q.F, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, 0.0});
+                put(S_ACCU, i, {q.ut, nullptr, q.u, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, 0.0});
+                put(S_ACCF, i, {q.Ft, nullptr, q.F, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, 0.0});
             }
             if (q.pending & PD_GMRES_START) {
-                gm_rhs.push_back({q.F, nullptr, q.rhs, nullptr, nullptr, nullptr, q.n, 0, 0, -1.0, 0.0});
-                gm_zero.push_back({q.F, nullptr, q.delta, nullptr, nullptr, nullptr, q.n, 0, 0, 0.0, 0.0});
-                gm_copy_r.push_back({q.F, nullptr, q.r, nullptr, nullptr, nullptr, q.n, 0, 0, -1.0, 0.0});
-                gm_beta.push_back({q.r, q.r, nullptr, nullptr, q.scal + 3, q.part, q.n, 0, 0, 0, 0});
-                gm_v0.push_back({q.r, nullptr, q.V, q.scal + 3, nullptr, nullptr, q.n, 0, 0, 0, 0});
+                put(S_GRHS, i, {q.F, nullptr, q.rhs, nullptr, nullptr, nullptr, q.n, 0, 0, -1.0, 0.0});
+                put(S_GZ, i, {q.F, nullptr, q.delta, nullptr, nullptr, nullptr, q.n, 0, 0, 0.0, 0.0});
+                put(S_GR, i, {q.F, nullptr, q.r, nullptr, nullptr, nullptr, q.n, 0, 0, -1.0, 0.0});
+                put(S_GB, i, {q.r, q.r, nullptr, nullptr, q.scal + 3, q.part, q.n, 0, 0, 0, 0});
+                put(S_GV, i, {q.r, nullptr, q.V, q.scal + 3, nullptr, nullptr, q.n, 0, 0, 0, 0});
             }
         }
-        const int sl_comb = push_ops(combine), sl_accu = push_ops(acc_u), sl_accF = push_ops(acc_F);
-        const int sl_grhs = push_ops(gm_rhs), sl_gz = push_ops(gm_zero), sl_gr = push_ops(gm_copy_r),
-                  sl_gb = push_ops(gm_beta), sl_gv = push_ops(gm_v0);
         // evaluation requests
-        std::vector<int> eval64, eval32;  // problem indices
-        std::vector<const double *> in64, in32;
-        std::vector<double *> out64, out32;
-        std::vector<BOp> sh_u, sh_z, sh_shift, sh_axpy, ls_axpby;
         std::vector<int> arn, rst, lsr, bas;
         for (int i : act) {
             Inst &q = I[i];
             const bool inner64 = q.inner64;
             switch (q.phase) {
                 case PH_BASE:
-                    eval64.push_back(i); in64.push_back(q.u); out64.push_back(q.F); bas.push_back(i);
+                    on64[i] = 1; in64[i] = q.u; out64[i] = q.F; bas.push_back(i);
                     break;
                 case PH_INNER:
-                    eval32.push_back(i); in32.push_back(q.u); out32.push_back(q.Fin);
+                    on32[i] = 1; in32[i] = q.u; out32[i] = q.Fin;
                     break;
                 case PH_ARNOLDI:
                 case PH_RESTART: {
@@ -262,174 +383,82 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
                             const int M = pc->M, ss = pc->s, h = pc->h;
                             const int f = pc->storage == BIM_STORE_FP32;
                             auto arr = [&](int which) { return precond_array(pc, which); };
-                            hband.push_back({arr(0), r1, nullptr, a1, M, 0, ss, 1.0, 0.0, f});   // Dinv11
-                            hband.push_back({arr(5), a1, r3, t3, M, h, ss, -1.0, 1.0, f});       // B31
-                            hband.push_back({arr(1), t3, nullptr, a3, M, 0, ss, 1.0, 0.0, f});   // Dinv22
-                            hband.push_back({arr(3), a1, r2, t2, M, h, ss, -1.0, 1.0, f});       // B21
-                            hband.push_back({arr(4), a3, t2, t2, M, h, ss, -1.0, 1.0, f});       // B23
-                            hgemv.push_back({arr(7), t2, nullptr, z2, nn, (int)nn, (int)nn, 1.0, 0.0, f});  // S^-1
-                            hband.push_back({arr(6), z2, a3, z3, M, h, ss, -1.0, 1.0, f});       // G
-                            hband.push_back({arr(2), z2, a1, z1, M, 0, ss, -1.0, 1.0, f});       // E
+                            BBand *b = hbands + i;
+                            const size_t st = count;
+                            b[0 * st] = {arr(0), r1, nullptr, a1, M, 0, ss, 1.0, 0.0, f};   // Dinv11
+                            b[1 * st] = {arr(5), a1, r3, t3, M, h, ss, -1.0, 1.0, f};       // B31
+                            b[2 * st] = {arr(1), t3, nullptr, a3, M, 0, ss, 1.0, 0.0, f};   // Dinv22
+                            b[3 * st] = {arr(3), a1, r2, t2, M, h, ss, -1.0, 1.0, f};       // B21
+                            b[4 * st] = {arr(4), a3, t2, t2, M, h, ss, -1.0, 1.0, f};       // B23
+                            hgemv[i] = {arr(7), t2, nullptr, z2, nn, (int)nn, (int)nn, 1.0, 0.0, f};  // S^-1
+                            b[5 * st] = {arr(6), z2, a3, z3, M, h, ss, -1.0, 1.0, f};       // G
+                            b[6 * st] = {arr(2), z2, a1, z1, M, 0, ss, -1.0, 1.0, f};       // E
                         } else {
-                            ls_axpby.push_back({v, nullptr, z, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, 0.0});
+                            put(S_LS, i, {v, nullptr, z, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, 0.0});
                         }
                         arn.push_back(i);
                     } else {
                         rst.push_back(i);
                     }
-                    sh_u.push_back({q.u, q.u, nullptr, nullptr, q.scal + 0, q.part, q.n, 0, 0, 0, 0});
-                    sh_z.push_back({z, z, nullptr, nullptr, q.scal + 1, q.part + kBRedBlocks, q.n, 0, 0, 0, 0});
-                    sh_shift.push_back({nullptr, nullptr, nullptr, nullptr, q.scal, nullptr, 0, 0, 0, 0.0,
-                                        inner64 ? eps64 : eps32});
-                    sh_axpy.push_back({q.u, z, q.ut, q.scal + 2, nullptr, nullptr, q.n, 0, 0, 0, 0});
-                    if (inner64) { eval64.push_back(i); in64.push_back(q.ut); out64.push_back(q.Ft); }
-                    else { eval32.push_back(i); in32.push_back(q.ut); out32.push_back(q.Ft); }
+                    put(S_SHU, i, {q.u, q.u, nullptr, nullptr, q.scal + 0, q.part, q.n, 0, 0, 0, 0});
+                    put(S_SHZ, i, {z, z, nullptr, nullptr, q.scal + 1, q.part + kBRedBlocks, q.n, 0, 0, 0, 0});
+                    put(S_SHIFT, i, {nullptr, nullptr, nullptr, nullptr, q.scal, nullptr, 0, 0, 0, 0.0,
+                                     inner64 ? eps64 : eps32});
+                    put(S_AXPY, i, {q.u, z, q.ut, q.scal + 2, nullptr, nullptr, q.n, 0, 0, 0, 0});
+                    if (inner64) { on64[i] = 1; in64[i] = q.ut; out64[i] = q.Ft; }
+                    else { on32[i] = 1; in32[i] = q.ut; out32[i] = q.Ft; }
                     break;
                 }
                 case PH_LINESEARCH:
-                    ls_axpby.push_back({q.u, q.delta, q.ut, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, q.mu});
-                    eval64.push_back(i); in64.push_back(q.ut); out64.push_back(q.Ft); lsr.push_back(i);
+                    put(S_LS, i, {q.u, q.delta, q.ut, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, q.mu});
+                    on64[i] = 1; in64[i] = q.ut; out64[i] = q.Ft; lsr.push_back(i);
                     break;
             }
         }
-        const int sl_shu = push_ops(sh_u), sl_shz = push_ops(sh_z), sl_shift = push_ops(sh_shift),
-                  sl_axpy = push_ops(sh_axpy), sl_ls = push_ops(ls_axpby);
         // post-work descriptors
-        std::vector<BOp> quo, md1, or1, md2, or2, wn, vn, rs_r, rs_b, rs_v, nF2, nFi;
-        int max_nv = 1;
         for (int i : arn) {
             Inst &q = I[i];
             const double *Fb = q.inner64 ? q.F : q.Fin;
-            quo.push_back({q.Ft, Fb, q.w, q.scal + 2, nullptr, nullptr, q.n, 0, 0, 0, 0});
-            md1.push_back({q.V, q.w, nullptr, nullptr, q.hdev, q.part, q.n, q.n, q.j + 1, 0, 0});
-            or1.push_back({q.V, nullptr, q.w, q.hdev, nullptr, nullptr, q.n, q.n, q.j + 1, 0, 0});
-            md2.push_back({q.V, q.w, nullptr, nullptr, q.hdev + m + 1, q.part, q.n, q.n, q.j + 1, 0, 0});
-            or2.push_back({q.V, nullptr, q.w, q.hdev + m + 1, nullptr, nullptr, q.n, q.n, q.j + 1, 0, 0});
-            wn.push_back({q.w, q.w, nullptr, nullptr, q.hdev + 2 * (m + 1), q.part, q.n, 0, 0, 0, 0});
-            vn.push_back({q.w, nullptr, q.V + (size_t)(q.j + 1) * q.n, q.hdev + 2 * (m + 1), nullptr, nullptr, q.n, 0, 0, 0, 0});
-            max_nv = std::max(max_nv, q.j + 1);
+            put(S_QUO, i, {q.Ft, Fb, q.w, q.scal + 2, nullptr, nullptr, q.n, 0, 0, 0, 0});
+            put(S_MD1, i, {q.V, q.w, nullptr, nullptr, q.hdev, q.part, q.n, q.n, q.j + 1, 0, 0});
+            put(S_OR1, i, {q.V, nullptr, q.w, q.hdev, nullptr, nullptr, q.n, q.n, q.j + 1, 0, 0});
+            put(S_MD2, i, {q.V, q.w, nullptr, nullptr, q.hdev + m + 1, q.part, q.n, q.n, q.j + 1, 0, 0});
+            put(S_OR2, i, {q.V, nullptr, q.w, q.hdev + m + 1, nullptr, nullptr, q.n, q.n, q.j + 1, 0, 0});
+            put(S_WN, i, {q.w, q.w, nullptr, nullptr, q.hdev + 2 * (m + 1), q.part, q.n, 0, 0, 0, 0});
+            put(S_VN, i, {q.w, nullptr, q.V + (size_t)(q.j + 1) * q.n, q.hdev + 2 * (m + 1), nullptr, nullptr, q.n, 0, 0, 0, 0});
         }
         for (int i : rst) {
             Inst &q = I[i];
             const double *Fb = q.inner64 ? q.F : q.Fin;
-            quo.push_back({q.Ft, Fb, q.w, q.scal + 2, nullptr, nullptr, q.n, 0, 0, 0, 0});
-            rs_r.push_back({q.rhs, q.w, q.r, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, -1.0});
-            rs_b.push_back({q.r, q.r, nullptr, nullptr, q.scal + 3, q.part, q.n, 0, 0, 0, 0});
-            rs_v.push_back({q.r, nullptr, q.V, q.scal + 3, nullptr, nullptr, q.n, 0, 0, 0, 0});
+            put(S_QUO, i, {q.Ft, Fb, q.w, q.scal + 2, nullptr, nullptr, q.n, 0, 0, 0, 0});
+            put(S_RSR, i, {q.rhs, q.w, q.r, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, -1.0});
+            put(S_RSB, i, {q.r, q.r, nullptr, nullptr, q.scal + 3, q.part, q.n, 0, 0, 0, 0});
+            put(S_RSV, i, {q.r, nullptr, q.V, q.scal + 3, nullptr, nullptr, q.n, 0, 0, 0, 0});
         }
         for (int i : bas) {
             Inst &q = I[i];
-            nF2.push_back({q.F, q.F, nullptr, nullptr, q.scal + 4, q.part, q.n, 0, 0, 0, 0});
-            nFi.push_back({q.F, nullptr, nullptr, nullptr, q.scal + 5, q.part + 2 * kBRedBlocks, q.n, 0, 0, 0, 0});
+            put(S_NF2, i, {q.F, q.F, nullptr, nullptr, q.scal + 4, q.part, q.n, 0, 0, 0, 0});
+            put(S_NFI, i, {q.F, nullptr, nullptr, nullptr, q.scal + 5, q.part + 2 * kBRedBlocks, q.n, 0, 0, 0, 0});
         }
         for (int i : lsr) {
             Inst &q = I[i];
-            nF2.push_back({q.Ft, q.Ft, nullptr, nullptr, q.scal + 4, q.part, q.n, 0, 0, 0, 0});
-            nFi.push_back({q.Ft, nullptr, nullptr, nullptr, q.scal + 5, q.part + 2 * kBRedBlocks, q.n, 0, 0, 0, 0});
+            put(S_NF2, i, {q.Ft, q.Ft, nullptr, nullptr, q.scal + 4, q.part, q.n, 0, 0, 0, 0});
+            put(S_NFI, i, {q.Ft, nullptr, nullptr, nullptr, q.scal + 5, q.part + 2 * kBRedBlocks, q.n, 0, 0, 0, 0});
         }
-        const int sl_quo = push_ops(quo), sl_md1 = push_ops(md1), sl_or1 = push_ops(or1), sl_md2 = push_ops(md2),
-                  sl_or2 = push_ops(or2), sl_wn = push_ops(wn), sl_vn = push_ops(vn), sl_rsr = push_ops(rs_r),
-                  sl_rsb = push_ops(rs_b), sl_rsv = push_ops(rs_v), sl_nF2 = push_ops(nF2), sl_nFi = push_ops(nFi);
-        if (hops.size() > (size_t)count * kOpSlots) return fail(BIM_EINVAL, "internal: batched op buffer too small");
-        if ((rc = hip_check(hipMemcpyAsync(opdev, hops.data(), sizeof(BOp) * hops.size(), hipMemcpyHostToDevice, s),
-                            "copy")))
+        for (int i : act)
+            put(S_GATHER, i, {I[i].scal, I[i].hdev, stage + (size_t)i * kSmall, nullptr, nullptr, nullptr, 0, 0,
+                              3 * (m + 1), 0, 0});
+        long tot = 0;
+        if (!has32)
+            for (int i = 0; i < count; ++i)
+                if (on32[i]) return fail(BIM_EINVAL, "internal: FP32C evaluation in an FP64 batch");
+        if ((rc = residual_batched_fill(probs, count, on64.data(), in64.data(), out64.data(), BIM_FP64, pls.data(),
+                                        rws.data(), hd64, &tot)))
             return rc;
-        if (!hgemv.empty() &&
-            (rc = hip_check(hipMemcpyAsync(gemvdev, hgemv.data(), sizeof(BGemv) * hgemv.size(), hipMemcpyHostToDevice, s),
-                            "copy")))
+        if (has32 && (rc = residual_batched_fill(probs, count, on32.data(), in32.data(), out32.data(), BIM_FP32C,
+                                                 pls.data(), rws.data(), hd32, &tot)))
             return rc;
-        auto S = [&](int k) { return opdev + slices[k].first; };
-        auto C = [&](int k) { return slices[k].second; };
-        // y coefficients for the combines
-        for (int i : act) {
-            Inst &q = I[i];
-            if (q.pending & PD_COMBINE)
-                if ((rc = hip_check(hipMemcpyAsync(q.ydev, q.y.data(), sizeof(double) * (q.j + 1), hipMemcpyHostToDevice, s), "copy")))
-                    return rc;
-        }
-        // ---------------- pre-work
-        if ((rc = b_combine(S(sl_comb), C(sl_comb), s))) return rc;
-        if ((rc = b_axpby(S(sl_accu), C(sl_accu), s))) return rc;
-        if ((rc = b_axpby(S(sl_accF), C(sl_accF), s))) return rc;
-        if ((rc = b_axpby(S(sl_grhs), C(sl_grhs), s))) return rc;
-        if ((rc = b_axpby(S(sl_gz), C(sl_gz), s))) return rc;
-        if ((rc = b_axpby(S(sl_gr), C(sl_gr), s))) return rc;
-        if ((rc = b_dot(S(sl_gb), C(sl_gb), true, s))) return rc;
-        if ((rc = b_scale_inv(S(sl_gv), C(sl_gv), s))) return rc;
-        // preconditioner applies, in the order of precond_apply_enqueue: hband holds 7 banded
-        // products per problem (5 before the dense Schur product, 2 after); gather them stage by stage
-        if (!hgemv.empty()) {
-            const int napp = (int)hgemv.size(), per = 7;
-            int max_rows = 0, max_groups = 0;
-            for (int a = 0; a < napp; ++a) max_rows = std::max(max_rows, hgemv[a].rows);
-            for (const BBand &bb : hband) max_groups = std::max(max_groups, bb.M * ((bb.s + 3) / 4));
-            std::vector<BBand> gathered;
-            gathered.reserve((size_t)napp * per);
-            for (int stg = 0; stg < per; ++stg)
-                for (int a = 0; a < napp; ++a) gathered.push_back(hband[(size_t)a * per + stg]);
-            if ((rc = hip_check(hipMemcpyAsync(banddev, gathered.data(), sizeof(BBand) * gathered.size(),
-                                               hipMemcpyHostToDevice, s), "copy")))
-                return rc;
-            for (int stg = 0; stg < 5; ++stg)
-                if ((rc = b_bandmv(banddev + (size_t)stg * napp, napp, max_groups, s))) return rc;
-            if ((rc = b_gemv(gemvdev, napp, max_rows, s))) return rc;
-            for (int stg = 5; stg < per; ++stg)
-                if ((rc = b_bandmv(banddev + (size_t)stg * napp, napp, max_groups, s))) return rc;
-        }
-        if ((rc = b_axpby(S(sl_ls), C(sl_ls), s))) return rc;  // unpreconditioned copies and line-search points
-        if ((rc = b_dot(S(sl_shu), C(sl_shu), true, s))) return rc;
-        if ((rc = b_dot(S(sl_shz), C(sl_shz), true, s))) return rc;
-        if ((rc = b_shift(S(sl_shift), C(sl_shift), s))) return rc;
-        if ((rc = b_axpy_dev(S(sl_axpy), C(sl_axpy), s))) return rc;
-        // ---------------- batched residuals (one persistent all-pairs launch per precision)
-        auto run_eval = [&](const std::vector<int> &idx, const std::vector<const double *> &in,
-                            const std::vector<double *> &out, int prec, PairDesc *descs) -> int {
-            if (idx.empty()) return BIM_OK;
-            std::vector<bim_problem> pp;
-            std::vector<PairLaunch> pls;
-            std::vector<ResidualWork> ws;
-            for (int i : idx) {
-                pp.push_back(*I[i].p);
-                pls.push_back(I[i].pl);
-                ws.push_back(I[i].rw);
-            }
-            return residual_batched_enqueue(pp.data(), (int)idx.size(), in.data(), out.data(), prec, pls.data(),
-                                            ws.data(), descs, 0, s);
-        };
-        // FP64 and FP32C groups use separate workspaces? They never share a problem in one round.
-        if ((rc = run_eval(eval64, in64, out64, BIM_FP64, desc64))) return rc;
-        if ((rc = run_eval(eval32, in32, out32, BIM_FP32C, desc32))) return rc;
-        // ---------------- post-work
-        if ((rc = b_quotient(S(sl_quo), C(sl_quo), s))) return rc;
-        if ((rc = b_multidot(S(sl_md1), C(sl_md1), max_nv, s))) return rc;
-        if ((rc = b_orth(S(sl_or1), C(sl_or1), s))) return rc;
-        if ((rc = b_multidot(S(sl_md2), C(sl_md2), max_nv, s))) return rc;
-        if ((rc = b_orth(S(sl_or2), C(sl_or2), s))) return rc;
-        if ((rc = b_dot(S(sl_wn), C(sl_wn), true, s))) return rc;
-        if ((rc = b_scale_inv(S(sl_vn), C(sl_vn), s))) return rc;
-        if ((rc = b_axpby(S(sl_rsr), C(sl_rsr), s))) return rc;
-        if ((rc = b_dot(S(sl_rsb), C(sl_rsb), true, s))) return rc;
-        if ((rc = b_scale_inv(S(sl_rsv), C(sl_rsv), s))) return rc;
-        if ((rc = b_dot(S(sl_nF2), C(sl_nF2), true, s))) return rc;
-        if ((rc = b_maxabs(S(sl_nFi), C(sl_nFi), s))) return rc;
-        // small results of every problem -> one pinned host copy
-        {
-            std::vector<BOp> gat;
-            for (int i : act)
-                gat.push_back({I[i].scal, I[i].hdev, stage + (size_t)i * kSmall, nullptr, nullptr, nullptr, 0, 0,
-                               3 * (m + 1), 0, 0});
-            BOp *gdev = opdev + hops.size();
-            if (hops.size() + gat.size() > (size_t)count * kOpSlots)
-                return fail(BIM_EINVAL, "internal: batched op buffer too small");
-            if ((rc = hip_check(hipMemcpyAsync(gdev, gat.data(), sizeof(BOp) * gat.size(), hipMemcpyHostToDevice, s),
-                                "copy")))
-                return rc;
-            if ((rc = b_gather(gdev, (int)gat.size(), s))) return rc;
-            if ((rc = hip_check(hipMemcpyAsync(hstage, stage, sizeof(double) * (size_t)count * kSmall,
-                                               hipMemcpyDeviceToHost, s), "copy")))
-                return rc;
-            if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
-        }
+        if ((rc = run_round())) return rc;
         // ---------------- host decisions
         for (int i : act) {
             Inst &q = I[i];
@@ -575,15 +604,19 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
     }
     // make sure every accepted step was applied (the last round's pending copies)
     {
-        std::vector<BOp> acc_u;
+        BOp *acc = hops + (size_t)S_ACCU * count;
+        std::memset(acc, 0, sizeof(BOp) * count);
+        bool any = false;
         for (int i = 0; i < count; ++i)
-            if (I[i].pending & PD_ACCEPT)
-                acc_u.push_back({I[i].ut, nullptr, I[i].u, nullptr, nullptr, nullptr, I[i].n, 0, 0, 1.0, 0.0});
-        if (!acc_u.empty()) {
-            if ((rc = hip_check(hipMemcpyAsync(opdev, acc_u.data(), sizeof(BOp) * acc_u.size(), hipMemcpyHostToDevice, s),
+            if (I[i].pending & PD_ACCEPT) {
+                acc[i] = {I[i].ut, nullptr, I[i].u, nullptr, nullptr, nullptr, I[i].n, 0, 0, 1.0, 0.0};
+                any = true;
+            }
+        if (any) {
+            if ((rc = hip_check(hipMemcpyAsync(OPS(S_ACCU), acc, sizeof(BOp) * count, hipMemcpyHostToDevice, s),
                                 "copy")))
                 return rc;
-            if ((rc = b_axpby(opdev, (int)acc_u.size(), s))) return rc;
+            if ((rc = b_axpby(OPS(S_ACCU), count, s))) return rc;
         }
         if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
     }
@@ -597,6 +630,7 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
     }
     const int worst = worst_err < 0 ? worst_err : worst_soft;
     (void)rounds;
+    (void)graph_captures;
     return worst;
 }
 
@@ -612,6 +646,12 @@ extern "C" int jfnk_solve_batched(const bim_problem *probs, int count, bim_preco
     for (int i = 0; i < count; ++i) {
         if ((rc = validate(&probs[i]))) return rc;
         if (!us[i]) return fail(BIM_EINVAL, "u[i] must be a device pointer");
+        // each problem owns its iterate and its preconditioner's apply scratch:
+        // a shared one would be written by two problems in one launch
+        for (int k = 0; k < i; ++k) {
+            if (us[k] == us[i]) return fail(BIM_EINVAL, "u[i] must be distinct vectors");
+            if (Ps && Ps[i] && Ps[k] == Ps[i]) return fail(BIM_EINVAL, "a preconditioner appears twice in Ps");
+        }
     }
     bim_jfnk_opts o;
     jfnk_default_opts(&o);

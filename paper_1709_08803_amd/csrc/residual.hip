@@ -88,6 +88,7 @@ __device__ __forceinline__ void integrate_body(const PairDesc &D, int idx) {
 __global__ __launch_bounds__(64) void k_integrate(PairDesc D) { integrate_body(D, blockIdx.x); }
 __global__ __launch_bounds__(64) void k_integrate_batched(const PairDesc *__restrict__ descs, int count) {
     const PairDesc &D = descs[find_problem<0>(descs, count, blockIdx.x)];
+    if (!D.active) return;
     integrate_body(D, blockIdx.x - D.blk_int);
 }
 
@@ -218,6 +219,7 @@ __global__ __launch_bounds__(256) void k_records(PairDesc D) { records_body<T>(D
 template <typename T>
 __global__ __launch_bounds__(256) void k_records_batched(const PairDesc *__restrict__ descs, int count) {
     const PairDesc &D = descs[find_problem<1>(descs, count, blockIdx.x)];
+    if (!D.active) return;  // uniform over the workgroup
     records_body<T>(D, blockIdx.x - D.blk_rec);
 }
 
@@ -596,11 +598,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMinWaves<T
 }
 
 // Many problems in one persistent launch: the work items (target tile, source
-// chunk) of all problems form one list; every wave walks it with a fixed stride,
-// so the schedule (and each problem's fixed-order reduction) is deterministic.
+// chunk) of all active problems form one list; every wave walks it with a fixed
+// stride, so the schedule (and each problem's fixed-order reduction) is
+// deterministic.  An inactive problem owns no items (its item0 equals the next
+// problem's), so the walk never selects it.
 template <typename T, bool COMP, int TPL, int UNROLL>
-__global__ __launch_bounds__(256) void k_allpairs_batched(const PairDesc *__restrict__ descs, int count,
-                                                          long total_items) {
+__global__ __launch_bounds__(256) void k_allpairs_batched(const PairDesc *__restrict__ descs, int count) {
+    const long total_items = descs[0].batch_items;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long nwaves = (long)gridDim.x * 4;
@@ -756,6 +760,7 @@ __device__ __forceinline__ void finalize_body(const PairDesc &D, int b) {
 __global__ __launch_bounds__(256) void k_finalize(PairDesc D) { finalize_body(D, blockIdx.x); }
 __global__ __launch_bounds__(256) void k_finalize_batched(const PairDesc *__restrict__ descs, int count) {
     const PairDesc &D = descs[find_problem<2>(descs, count, blockIdx.x)];
+    if (!D.active) return;  // uniform over the workgroup
     finalize_body(D, blockIdx.x - D.blk_fin);
 }
 
@@ -812,6 +817,8 @@ PairDesc make_desc(const bim_problem *p, const Dims &d, const PairLaunch &pl, co
     D.target_tiles = pl.target_tiles;
     D.chunks = pl.chunks;
     D.item0 = 0;
+    D.batch_items = 0;
+    D.active = 1;
     D.u = u;
     D.F = F;
     D.nodes = w.nodes;
@@ -887,12 +894,25 @@ int residual_enqueue(const bim_problem *p, const double *u, double *F, int prec,
 }
 
 
-int residual_batched_enqueue(const bim_problem *probs, int count, const double *const *u, double *const *F,
-                             int prec, const PairLaunch *pls, const ResidualWork *ws, PairDesc *descs_dev,
-                             int max_blocks, hipStream_t s, hipEvent_t *ev_pair) {
-    if (count <= 0) return BIM_OK;
+BatchShape residual_batched_shape(const bim_problem *probs, int count, const PairLaunch *pls, int max_blocks) {
+    BatchShape sh{pls[0].tpl, pls[0].unroll, 0, 0, 0, 1};
+    long total = 0;
+    for (int i = 0; i < count; ++i) {
+        const Dims d(&probs[i]);
+        sh.b_int += 3 * d.M;
+        sh.b_rec += record_blocks(d.N, d.M);
+        sh.b_fin += finalize_blocks(d.N, d.M);
+        total += (long)pls[i].target_tiles * pls[i].chunks;
+    }
+    const long want = (total + 3) / 4;
+    sh.blocks = (int)std::max(1L, std::min(want, (long)(max_blocks > 0 ? max_blocks : 2048)));
+    return sh;
+}
+
+int residual_batched_fill(const bim_problem *probs, int count, const int *active, const double *const *u,
+                          double *const *F, int prec, const PairLaunch *pls, const ResidualWork *ws,
+                          PairDesc *descs, long *total_items) {
     const int tpl = pls[0].tpl, unroll = pls[0].unroll;
-    std::vector<PairDesc> descs(count);
     long total = 0;
     int b_int = 0, b_rec = 0, b_fin = 0;
     for (int i = 0; i < count; ++i) {
@@ -900,10 +920,13 @@ int residual_batched_enqueue(const bim_problem *probs, int count, const double *
         const Dims d(p);
         const PairLaunch &pl = pls[i];
         if (pl.tpl != tpl || pl.unroll != unroll) return fail(BIM_EINVAL, "batched launch needs one kernel variant");
+        const int on = active ? active[i] : 1;
+        if (on && (!u[i] || !F[i])) return fail(BIM_EINVAL, "an active problem needs u and F");
         PairDesc &D = descs[i];
-        D = make_desc(p, d, pl, ws[i], u[i], F[i], prec, 0);
+        D = make_desc(p, d, pl, ws[i], on ? u[i] : nullptr, on ? F[i] : nullptr, prec, 0);
+        D.active = on;
         D.item0 = total;
-        total += (long)pl.target_tiles * pl.chunks;
+        if (on) total += (long)pl.target_tiles * pl.chunks;
         D.blk_int = b_int;
         D.blk_rec = b_rec;
         D.blk_fin = b_fin;
@@ -911,19 +934,23 @@ int residual_batched_enqueue(const bim_problem *probs, int count, const double *
         b_rec += record_blocks(d.N, d.M);
         b_fin += finalize_blocks(d.N, d.M);
     }
-    BIM_HIP(hipMemcpyAsync(descs_dev, descs.data(), sizeof(PairDesc) * count, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_integrate_batched, dim3(b_int), dim3(64), 0, s, descs_dev, count);
+    for (int i = 0; i < count; ++i) descs[i].batch_items = total;
+    *total_items = total;
+    return BIM_OK;
+}
+
+int residual_batched_launch(const PairDesc *descs_dev, int count, int prec, const BatchShape &sh, hipStream_t s,
+                            hipEvent_t *ev_pair) {
+    if (count <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_integrate_batched, dim3(sh.b_int), dim3(64), 0, s, descs_dev, count);
     if (prec == BIM_FP64)
-        hipLaunchKernelGGL(k_records_batched<double>, dim3(b_rec), dim3(256), 0, s, descs_dev, count);
+        hipLaunchKernelGGL(k_records_batched<double>, dim3(sh.b_rec), dim3(256), 0, s, descs_dev, count);
     else
-        hipLaunchKernelGGL(k_records_batched<float>, dim3(b_rec), dim3(256), 0, s, descs_dev, count);
-    const long want = (total + 3) / 4;
-    const int blocks = (int)std::max(1L, std::min(want, (long)(max_blocks > 0 ? max_blocks : 2048)));
+        hipLaunchKernelGGL(k_records_batched<float>, dim3(sh.b_rec), dim3(256), 0, s, descs_dev, count);
     if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[0], s));
-#define BIM_LAUNCH_BATCH(T, COMP, TPL, UNR)                                                                   \
-    hipLaunchKernelGGL((k_allpairs_batched<T, COMP, TPL, UNR>), dim3(blocks), dim3(256), 0, s, descs_dev, count, \
-                       total)
-    const int vsel = (tpl == 2 ? 3 : 0) + (unroll == 2 ? 0 : unroll == 4 ? 1 : 2);
+#define BIM_LAUNCH_BATCH(T, COMP, TPL, UNR) \
+    hipLaunchKernelGGL((k_allpairs_batched<T, COMP, TPL, UNR>), dim3(sh.blocks), dim3(256), 0, s, descs_dev, count)
+    const int vsel = (sh.tpl == 2 ? 3 : 0) + (sh.unroll == 2 ? 0 : sh.unroll == 4 ? 1 : 2);
     if (prec == BIM_FP64) {
         switch (vsel) {
             case 0: BIM_LAUNCH_BATCH(double, false, 1, 2); break;
@@ -945,8 +972,21 @@ int residual_batched_enqueue(const bim_problem *probs, int count, const double *
     }
 #undef BIM_LAUNCH_BATCH
     if (ev_pair) BIM_HIP(hipEventRecord(ev_pair[1], s));
-    hipLaunchKernelGGL(k_finalize_batched, dim3(b_fin), dim3(256), 0, s, descs_dev, count);
+    hipLaunchKernelGGL(k_finalize_batched, dim3(sh.b_fin), dim3(256), 0, s, descs_dev, count);
     return hip_check(hipGetLastError(), "batched residual launch");
+}
+
+int residual_batched_enqueue(const bim_problem *probs, int count, const double *const *u, double *const *F,
+                             int prec, const PairLaunch *pls, const ResidualWork *ws, PairDesc *descs_dev,
+                             int max_blocks, hipStream_t s, hipEvent_t *ev_pair) {
+    if (count <= 0) return BIM_OK;
+    std::vector<PairDesc> descs(count);
+    long total = 0;
+    int rc = residual_batched_fill(probs, count, nullptr, u, F, prec, pls, ws, descs.data(), &total);
+    if (rc) return rc;
+    BIM_HIP(hipMemcpyAsync(descs_dev, descs.data(), sizeof(PairDesc) * count, hipMemcpyHostToDevice, s));
+    return residual_batched_launch(descs_dev, count, prec, residual_batched_shape(probs, count, pls, max_blocks), s,
+                                   ev_pair);
 }
 
 }  // namespace bim

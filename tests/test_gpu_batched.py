@@ -121,3 +121,42 @@ def test_batched_solve_with_fp32_stored_preconditioners(bim):
         if rb["status"] == 0:
             assert (ubi - us_).abs().max().item() <= 1e-8
             assert np.abs(R.residual(p, ubi.cpu().numpy())).max() < 1e-9
+
+
+def test_batched_graph_replay_equals_eager_execution(bim):
+    # one captured round graph replayed every round against the same rounds
+    # launched eagerly: identical iterates and decisions, bit for bit; the
+    # batch includes a 121 x 41 mesh and runs the sweep configuration (FP32C
+    # inner sums, FP32-stored preconditioners)
+    from paper_1709_08803_amd import workloads as W2
+    probs = W2.sweep_instances(5, seed=11, n_choices=[31, 46, 61, 121])
+    probs.append(W2.make_problem(121, 41, -30.0, 30.0, 0.0, 20.0, 1.3, [W2.Bump(0.15, 1.2, 1.2)], name="gauss-121x41"))
+    dps = [bim.DeviceProblem(p) for p in probs]
+    starts = [bim.linear_start(dp, prec="fp32c", rtol=1e-4) for dp in dps]
+    opts = dict(ftol=1e-10, inner_prec="fp32c", precond_storage="fp32", max_newton=10, stall_steps=4)
+    ug = [u.clone() for u in starts]
+    ue = [u.clone() for u in starts]
+    rc_g, rep_g = bim.solve_batched(dps, ug, check=False, use_graphs=1, **opts)
+    rc_e, rep_e = bim.solve_batched(dps, ue, check=False, use_graphs=0, **opts)
+    assert rc_g == rc_e
+    for p, a, b, ra, rb in zip(probs, ug, ue, rep_g, rep_e):
+        print(p.name, ra["status"], ra["newton_iters"], ra["gmres_iters"], rb["newton_iters"], rb["gmres_iters"])
+        assert torch.equal(a, b)
+        for k in ("status", "newton_iters", "gmres_iters", "residual_evals", "jv_evals", "backtracks"):
+            assert ra[k] == rb[k], k
+        assert ra["history"] == rb["history"]
+    big = len(probs) - 1
+    assert rep_g[big]["status"] == 0
+    assert np.abs(R.residual(probs[big], ug[big].cpu().numpy())).max() <= 1e-10
+
+
+def test_batched_solve_rejects_shared_preconditioner_or_vector(bim):
+    probs = W.sweep_instances(2, seed=3, n_choices=[31])
+    dps = [bim.DeviceProblem(p) for p in probs]
+    P = bim.Preconditioner(dps[0])
+    us = [bim.linear_start(dp) for dp in dps]
+    with pytest.raises(bim.BimError):
+        bim.solve_batched(dps, us, Ps=[P, P])
+    with pytest.raises(bim.BimError):
+        bim.solve_batched(dps, [us[0], us[0]])
+    P.close()
