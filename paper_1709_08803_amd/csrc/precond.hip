@@ -76,10 +76,13 @@ __global__ void k_diag_blocks(double *D11, double *D12, double *D22, int N, doub
 }
 
 // Per collocation point (k, l): sum over every node and image of w K5, and the
-// exact integral of K5 over the truncated (mirrored) rectangle.
+// exact integral of K5 over the truncated (mirrored) rectangle.  The corners'
+// offsets from the point are formed from mesh indices, so the offset to an edge
+// through the point is exactly zero (its antiderivative term is then dropped);
+// a difference of separately rounded coordinates can leave a few ulp there, and
+// the logarithm of the near-zero argument that goes with it is not finite.
 __global__ __launch_bounds__(64) void k_k5_rowsum(double *rowsum, double *I5, int N, int M, double x1, double dx,
-                                                  double y1, double dy, int nimg, double xlo, double xhi,
-                                                  double ylo, double yhi) {
+                                                  double y1, double dy, int nimg) {
     const int t = blockIdx.x;  // l (N-1) + k
     const int l = t / (N - 1), k = t - l * (N - 1);
     const int lane = threadIdx.x;
@@ -104,7 +107,10 @@ __global__ __launch_bounds__(64) void k_k5_rowsum(double *rowsum, double *I5, in
             if (s != 0.0) g += s * log(2.0 * tt + 2.0 * q);
             return g;
         };
-        const double s1 = xlo - xs, s2 = xhi - xs, t1 = ylo - ys, t2 = yhi - ys;
+        // rectangle [x_1, x_N] x [y_lo, y_M], y_lo = -y_M on a half domain (y_1 = 0), else y_1
+        const double s1 = -(k + 0.5) * dx, s2 = (N - 1.5 - k) * dx;
+        const double t1 = (nimg == 2) ? -(double)(M - 1 + l) * dy : -(double)l * dy;
+        const double t2 = (double)(M - 1 - l) * dy;
         I5[t] = G(s2, t2) - G(s1, t2) - G(s2, t1) + G(s1, t1);
     }
 }
@@ -341,8 +347,6 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         ops.push_back({0, items.size(), (int)batch.size(), m_, n_, k_, lda, ldb, ldc, al, be});
         items.insert(items.end(), batch.begin(), batch.end());
     };
-    const double xN = p->x1 + (N - 1) * p->dx, yM = p->y1 + (M - 1) * p->dy;
-    const double ylo = p->half_domain ? -yM : p->y1;
 
 #define RUN(x)                   \
     do {                         \
@@ -367,7 +371,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     for (double *b : {pc->B21, pc->B23, pc->B31})
         RUN(hip_check(hipMemsetAsync(b, 0, sizeof(double) * band_elems(M, h, s), st), "memset"));
     hipLaunchKernelGGL(k_k5_rowsum, dim3(d.ntg), dim3(64), 0, st, rowsum, I5, N, M, p->x1, p->dx, p->y1, p->dy,
-                       d.nimg, p->x1, xN, ylo, yM);
+                       d.nimg);
     hipLaunchKernelGGL(k_band_rows, dim3(M * (2 * h + 1) * (N - 1)), dim3(64), 0, st, pc->B21, pc->B23, pc->B31,
                        rowsum, I5, N, M, h, p->x1, p->dx, p->y1, p->dy, d.nimg);
     RUN(hip_check(hipGetLastError(), "band assembly launch"));

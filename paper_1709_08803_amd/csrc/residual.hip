@@ -670,14 +670,15 @@ __device__ __forceinline__ void finalize_bie(const PairDesc &D, int b, double (*
         acc += v.x;
         acc2 += v.y;
     }
-    // corner w of the rectangle [xlo, xhi] x [ylo, yhi] relative to the target
+    // corner w of the rectangle [x_1, x_N] x [y_lo, y_M] relative to the target,
+    // from mesh indices: the offset to an edge through the target is exactly zero
+    // (y_lo = -y_M on a half domain, where y_1 = 0; y_1 on a full one)
     const double *tg = D.tg64;
-    const double xs = tg[0 * T2 + t], ys = tg[1 * T2 + t];
     const double A = tg[4 * T2 + t], B = tg[5 * T2 + t], C = tg[6 * T2 + t];
-    const double xN = D.x1 + (N - 1) * D.dx, yM = D.y1 + (M - 1) * D.dy;
-    const double ylo = D.half ? -yM : D.y1;
-    const double sc = (w & 1) ? D.x1 - xs : xN - xs;
-    const double tc = (w & 2) ? ylo - ys : yM - ys;
+    const int tl = (t % ntg) / (N - 1), tk = (t % ntg) - tl * (N - 1);
+    const double sc = (w & 1) ? -(tk + 0.5) * D.dx : (N - 1.5 - tk) * D.dx;
+    const double tc = (w & 2) ? (D.half ? -(double)(M - 1 + tl) * D.dy : -(double)tl * D.dy)
+                              : (double)(M - 1 - tl) * D.dy;
     const double corner = s2_antideriv(A, B, C, sc, tc);
     if (w > 0) {
         red[w - 1][0][lane] = acc;

@@ -75,9 +75,17 @@ def run(count: int = 64, seed: int = 0, inner: str = "fp32c", ftol: float = 1e-1
                                                             inner_prec=inner, max_newton=max_newton,
                                                             stall_steps=stall_steps))
     conv = [r["status"] == 0 for r in reps]
+    # the same lockstep rounds launched eagerly instead of replaying the round graph
+    ue = [u.clone() for u in ulin]
+    (rc_e, reps_e), t_eager = _sync_time(lambda: B.solve_batched(dps, ue, Ps, check=False, ftol=ftol,
+                                                                 inner_prec=inner, max_newton=max_newton,
+                                                                 stall_steps=stall_steps, use_graphs=0))
+    graph_same = all(torch.equal(a, b) for a, b in zip(ub, ue)) and \
+        all(a["newton_iters"] == b["newton_iters"] and a["status"] == b["status"] for a, b in zip(reps, reps_e))
     res["sweep"] = {"inner": inner, "precond_storage": storage, "linear_start_rtol": lrtol,
                     "precond_setup_s": t_setup, "linear_starts_s": t_lin,
-                    "batched_solve_s": t_solve, "converged": int(sum(conv)),
+                    "batched_solve_s": t_solve, "batched_solve_eager_s": t_eager,
+                    "graph_replay_equals_eager": bool(graph_same), "converged": int(sum(conv)),
                     "newton_total": int(sum(r["newton_iters"] for r in reps)),
                     "gmres_total": int(sum(r["gmres_iters"] for r in reps)),
                     "per_instance": [{"name": p.name, "F": round(p.froude, 4), "status": r["status"],

@@ -143,3 +143,28 @@ def test_fp32_storage_small_meshes_match_oracle(bim, name, mk, hb, tol):
     print(name, "fp32 storage rel err", err)
     assert 0 < err <= tol  # rounded (not bit-equal to FP64), and close
     P.close()
+
+
+def test_precond_full_domain_with_offset_edges(bim):
+    # Full domains whose y_1 is not 0: the offset of the closed-form S2 (K5)
+    # integral to the edge y_M through the last row of collocation points must be
+    # exactly zero; formed from separately rounded coordinates it can be a few ulp,
+    # which made that row's entries non-finite and the last pivot block singular
+    # (the 91 x 91 mesh of the paper's two-bump domain did).  P z = r by the
+    # oracle's banded product.
+    import math
+    d = 0.5 * math.sqrt(2.0)
+    for N, M, (xlo, xhi, ylo, yhi) in ((91, 91, (-7.0, 53.0, -30.0, 30.0)), (121, 81, (-30.0, 30.0, -20.0, 20.0))):
+        p = W.make_problem(N, M, xlo, xhi, ylo, yhi, 0.6,
+                           [W.Bump(0.2, d, d, cx=10.0, cy=10.0), W.Bump(0.2, d, d, cx=0.0, cy=-10.0)],
+                           half_domain=False)
+        print(f"case full {N}x{M}", flush=True)
+        dp = bim.DeviceProblem(p)
+        P = bim.Preconditioner(dp)
+        r = np.random.default_rng(7).standard_normal(p.n_unknowns)
+        z = P.apply(torch.as_tensor(r, device="cuda"))
+        torch.cuda.synchronize()
+        res = Lin.banded_matvec(p, z.cpu().numpy(), P.band) - r
+        print(f"full {N}x{M} |Pz - r| / |r|", np.abs(res).max() / np.abs(r).max())
+        assert np.abs(res).max() <= 1e-9 * np.abs(r).max()
+        P.close()

@@ -34,6 +34,10 @@ CASES = [
     ("full-31x13", lambda: W.make_problem(31, 13, -10, 10, -6, 6, 1.2, [W.Bump(0.2, 1.0, 1.0, cy=1.5)],
                                           half_domain=False), 4),
     ("min-3x3", lambda: W.make_problem(3, 3, -1, 1, 0, 1, 0.8, [W.Bump(0.1, 1.0, 1.0)]), 5),
+    # a full domain whose y_1 = -30 is not 0 (edge rows through the rectangle's corners)
+    ("full-61x61-offset", lambda: W.make_problem(61, 61, -7, 53, -30, 30, 0.6,
+                                                 [W.Bump(0.2, 0.71, 0.71, cx=10.0, cy=10.0),
+                                                  W.Bump(0.2, 0.71, 0.71, cx=0.0, cy=-10.0)], half_domain=False), 6),
 ]
 
 
