@@ -10,15 +10,21 @@ pair-interactions per second (collocation point x source node x y-image).
 The default warm-up is 100 evaluations (about 70 ms): a GPU that comes out of
 idle runs its first tens of milliseconds of work at lower clocks (measured on
 this workload: 0.720 ms per evaluation over the 50 evaluations after a
-5-evaluation warm-up from idle, 0.670 ms once warm).
+5-evaluation warm-up from idle, 0.670 ms once warm).  With the solver legs (the
+default) the GPU is busy for seconds before the warm-up starts.
 
 Also reported: the FP32-compensated evaluation, the all-pairs kernel's
 roofline fraction from HIP events on the launch stream, the time to a converged
 solve (preconditioner setup, linear start and JFNK with FP64 or FP32-compensated
 inner sums and an FP64- or FP32-stored preconditioner, with the distance between
 the solutions and, where a stored oracle solution of the same problem exists, to
-it), and the CPU oracle timed on a bounded sample of the same workload on this
-host's cores.
+it) at F = 0.6, 0.7 and 1.4, at F = 0.7 on the domain extended upstream to
+x_1 = -40, and on a full domain with two offset bumps; the 64-instance batched
+sweep (one persistent all-pairs launch per lockstep round, each round one
+replayed HIP graph); and the CPU oracle timed on a bounded sample of the same
+workload on this host's cores.  The solver legs run before the timed residual
+steps (their GPU work brings the clocks up; the timed region is the K steps
+alone).
 """
 import argparse
 import json
@@ -80,12 +86,15 @@ def measured_traffic():
 
 
 
-def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15):
-    """Wall time from the mesh to ||F||_inf <= ftol on the 181 x 61 problem at one F.
+def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15, problem=None, golden=None):
+    """Wall time from the mesh to ||F||_inf <= ftol on the 181 x 61 problem at one F
+    (or on `problem`, compared with the stored oracle solution `golden`).
 
     Each preconditioner storage (FP64, FP32) has its own setup and linear start;
-    a leg's total is its storage's setup and linear start plus its solve."""
-    p = W.working(froude)
+    a leg's total is its storage's setup and linear start plus its solve.  A leg
+    that does not converge is reported with its status and final ||F||_inf only:
+    no speedup and no distance to another solution is formed from it."""
+    p = problem if problem is not None else W.working(froude)
     dp = B.DeviceProblem(p)
     nb = (p.N + 1) * p.M
     res = {"froude": froude}
@@ -146,26 +155,47 @@ def time_to_solution(B, W, np, torch, froude, ftol=1e-10, max_newton=15):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             sols[leg] = u.cpu().numpy()
-            res[leg] = {"precond_storage": storage, "status": rep["status"], "solve_ms": dt * 1e3,
+            res[leg] = {"precond_storage": storage, "status": rep["status"], "converged": rep["status"] == 0,
+                        "solve_ms": dt * 1e3,
                         "total_ms": (dt + t_setup + t_lin) * 1e3, "newton": rep["newton_iters"],
                         "gmres": rep["gmres_iters"], "jv_evals": rep["jv_evals"],
                         "residual_evals": rep["residual_evals"], "fnorm_inf": rep["fnorm_inf"]}
         P.close()
-    d = sols["fp32c"] - sols["fp64"]
-    res["fp32c_vs_fp64"] = {"max_dzeta_x": float(np.abs(d[:nb]).max()),
-                            "max_dphi_x": float(np.abs(d[nb:2 * nb]).max())}
+    if res["fp64"]["converged"] and res["fp32c"]["converged"]:
+        d = sols["fp32c"] - sols["fp64"]
+        res["fp32c_vs_fp64"] = {"max_dzeta_x": float(np.abs(d[:nb]).max()),
+                                "max_dphi_x": float(np.abs(d[nb:2 * nb]).max())}
     for leg in legs:
-        if leg != "fp64" and res["fp64"]["status"] == 0 and res[leg]["status"] == 0:
+        if leg != "fp64" and res["fp64"]["converged"] and res[leg]["converged"]:
             res[f"speedup_{leg}"] = res["fp64"]["solve_ms"] / res[leg]["solve_ms"]
             res[f"speedup_{leg}_total"] = res["fp64"]["total_ms"] / res[leg]["total_ms"]
-    gold = os.path.join(HERE, "tests", "golden", f"working_181x61_F{froude}.npz")
-    if os.path.exists(gold):
+    gold = golden if problem is not None else os.path.join(HERE, "tests", "golden", f"working_181x61_F{froude}.npz")
+    if gold and os.path.exists(gold):
         ref = np.load(gold)["u"]
         zr, pr = node_values(p, ref, 0), node_values(p, ref, 1)
         for leg, u in sols.items():
-            res[leg]["max_dzeta_vs_oracle"] = float(np.abs(node_values(p, u, 0) - zr).max())
-            res[leg]["max_dphi_vs_oracle"] = float(np.abs(node_values(p, u, 1) - pr).max())
+            if res[leg]["converged"]:
+                res[leg]["max_dzeta_vs_oracle"] = float(np.abs(node_values(p, u, 0) - zr).max())
+                res[leg]["max_dphi_vs_oracle"] = float(np.abs(node_values(p, u, 1) - pr).max())
     return res
+
+
+def extended_domain(W):
+    """The 181 x 61 working problem at F = 0.7 with the domain extended upstream to
+    x_1 = -40 at the same spacing (211 x 61): on x in [-30, 30] Newton stalls where
+    the discrete Jacobian becomes singular, on this domain it converges."""
+    return W.make_problem(211, 61, -40.0, 30.0, 0.0, 20.0, 0.7, [W.Bump(0.2, 1.0, 1.0)], name="working-211x61-x1=-40")
+
+
+def two_bump_full_domain(W, N=151):
+    """The paper's asymmetric two-bump problem (bumps of eq. (bottom) with height
+    0.2 and delta = 0.5 at (10, 10) and (0, -10); F = 0.6; x in [-7, 53],
+    y in [-30, 30]) on a full N x N mesh."""
+    import math
+    d = 0.5 * math.sqrt(2.0)
+    return W.make_problem(N, N, -7.0, 53.0, -30.0, 30.0, 0.6,
+                          [W.Bump(0.2, d, d, cx=10.0, cy=10.0), W.Bump(0.2, d, d, cx=0.0, cy=-10.0)],
+                          half_domain=False, name=f"two-bumps-full-{N}x{N}")
 
 
 def node_values(p, u, f):
@@ -184,7 +214,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution leg")
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution legs")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 64-instance batched sweep")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="first run a plain elementwise copy of MB megabytes (reads MB, writes MB), "
                          "the reference for scaling hardware byte counters")
@@ -208,6 +239,27 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # solver legs first: they are reported as well, and the seconds of GPU work
+    # they take bring the GPU to its steady clocks before the residual is timed
+    extra = {}
+    if not args.no_solve:
+        extra["time_to_solution"] = [time_to_solution(B, W, np, torch, f) for f in (0.6, 0.7, 1.4)]
+        gold = os.path.join(HERE, "tests", "golden", "working_211x61_F0.7.npz")
+        extra["time_to_solution_extended_domain"] = dict(
+            workload="F = 0.7 on x in [-40, 30], y in [0, 20] (211 x 61, same spacing and bump)",
+            **time_to_solution(B, W, np, torch, 0.7, problem=extended_domain(W), golden=gold))
+        pf = two_bump_full_domain(W)
+        extra["time_to_solution_full_domain"] = dict(
+            workload="two offset bumps (10, 10), (0, -10), height 0.2, delta 0.5, F = 0.6, full domain "
+                     "x in [-7, 53], y in [-30, 30], 151 x 151",
+            pairs_per_eval=pf.pairs_per_eval(), **time_to_solution(B, W, np, torch, 0.6, problem=pf))
+    if not args.no_sweep:
+        from paper_1709_08803_amd import sweep as SW
+        sw = SW.run(64, 0, "fp32c")
+        sw["sweep"]["per_instance"] = [[r["name"], r["F"], r["status"], r["newton"], r["gmres"]]
+                                       for r in sw["sweep"]["per_instance"]]
+        extra["sweep"] = sw
+
     p = W.working(0.7)
     dp = B.DeviceProblem(p)
     u_host = W.perturbed_state(p, 11)
@@ -226,7 +278,8 @@ def main():
     ms_step = dt / args.steps * 1e3
     value = pairs * args.steps / dt
 
-    # dominant kernel: all-pairs sums, HIP events on the launch stream
+    # dominant kernel: all-pairs sums, HIP events on the launch stream, right
+    # after the timed steps
     k64, t64 = B.residual_timed(dp, u, "fp64", iters=max(5, args.steps // 2))
     k32, t32 = B.residual_timed(dp, u, "fp32c", iters=max(5, args.steps // 2))
     ach64 = pairs * FLOP_PER_PAIR / (k64 * 1e-3) / 1e12
@@ -258,8 +311,7 @@ def main():
         "fp64_eval_ms_events": t64,
         "residual_evals_per_s": 1e3 / ms_step,
     }
-    if not args.no_solve:
-        out["time_to_solution"] = [time_to_solution(B, W, np, torch, f) for f in (0.6, 0.7, 1.4)]
+    out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, u_host)
     print(json.dumps(out))

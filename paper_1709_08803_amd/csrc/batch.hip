@@ -27,20 +27,17 @@ __device__ double bsum256(double v) {
     return r;
 }
 
-// part[row * kBRedBlocks + bx] for rows 0 .. nv-1 (multidot) or row 0 (dot):
-// each workgroup takes its grid-stride slice of every row in turn
+// part[row * kBRedBlocks + bx]; row = blockIdx.z (multidot) or 0 (dot)
 __global__ __launch_bounds__(kT) void k_bdot_part(const BOp *__restrict__ ops, int multi) {
     const BOp o = ops[blockIdx.y];
     if (o.n == 0) return;  // empty slot of a padded op list
-    const int rows = multi ? o.nv : 1;
-    for (int row = 0; row < rows; ++row) {
-        const double *a = multi ? o.a + (size_t)row * o.ld : o.a;
-        double v = 0.0;
-        for (long e = (long)blockIdx.x * kT + threadIdx.x; e < o.n; e += (long)kBRedBlocks * kT)
-            v = fma(a[e], o.b[e], v);
-        v = bsum256(v);
-        if (threadIdx.x == 0) o.part[(size_t)row * kBRedBlocks + blockIdx.x] = v;
-    }
+    const int row = multi ? (int)blockIdx.z : 0;
+    if (row >= (multi ? o.nv : 1)) return;
+    const double *a = multi ? o.a + (size_t)row * o.ld : o.a;
+    double v = 0.0;
+    for (long e = (long)blockIdx.x * kT + threadIdx.x; e < o.n; e += (long)kBRedBlocks * kT) v = fma(a[e], o.b[e], v);
+    v = bsum256(v);
+    if (threadIdx.x == 0) o.part[(size_t)row * kBRedBlocks + blockIdx.x] = v;
 }
 
 __global__ __launch_bounds__(kT) void k_bdot_sum(const BOp *__restrict__ ops, int multi, int take_sqrt) {
@@ -244,7 +241,7 @@ int b_dot(const BOp *ops, int count, bool take_sqrt, hipStream_t s) {
 
 int b_multidot(const BOp *ops, int count, int max_nv, hipStream_t s) {
     if (count <= 0 || max_nv <= 0) return BIM_OK;
-    hipLaunchKernelGGL(k_bdot_part, dim3(kBRedBlocks, count), dim3(kT), 0, s, ops, 1);
+    hipLaunchKernelGGL(k_bdot_part, dim3(kBRedBlocks, count, max_nv), dim3(kT), 0, s, ops, 1);
     hipLaunchKernelGGL(k_bdot_sum, dim3(max_nv, count), dim3(kT), 0, s, ops, 1, 0);
     return hip_check(hipGetLastError(), "batched multidot launch");
 }

@@ -31,14 +31,15 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 // ------------------------------------------------------------------ rsqrt
 // FP32: the hardware reciprocal square root (about 1 ulp).
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-// FP64: the hardware estimate (relative error ~5e-8) refined by one step of the
-// second-order Newton-Raphson/Householder correction y (1 + e/2 + 3e^2/8),
-// e = 1 - x y^2, whose truncation error 5e^3/16 lies below FP64 rounding.
+// FP64: the hardware estimate y refined by one Newton-Raphson step
+// y (1 + e/2), e = 1 - x y^2, whose truncation error is (3/8) e^2 relative: of
+// order 1e-15 for an estimate good to ~5e-8, far below the parity bound of the
+// sums (1e-12 of the sum of |terms|), at one FMA per rsqrt less than the
+// second-order step y (1 + e/2 + 3e^2/8) (the sums are bound by VALU issue).
 __device__ __forceinline__ double rsq(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    double e = fma(-h, y, 1.0);
-    return fma(y * e, fma(0.375, e, 0.5), y);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
 // ------------------------------------------------------------------ batched lookup
