@@ -8,11 +8,16 @@ the slice-banded J~ (Section 4.2).  Stops at ||F||_inf <= 1e-11.
 
 Output: tests/golden/working_181x61_F<F>.npz with the full unknown vector u
 (FP64, 3 (N+1) M entries in the order of Section 3.1), the Newton history and
-the band half-width used.  Needs about 20 GB of host memory and a few minutes
-per Froude number on 8 cores.
+the band half-width used.  A run that does not converge writes its record
+instead -- tests/golden/oracle_newton_181x61_F<F>.json: the Newton history of
+||F||_inf, the GMRES iterations, the line-search outcome and the largest
+surface elevation of the last iterate.  Needs about 20 GB of host memory and a
+few minutes per Froude number on 8 cores.
 
     python tests/golden/make_working_solutions.py 1.4 [0.7 ...]
+    python tests/golden/make_working_solutions.py --extended 0.7   (x_1 = -40, 211 x 61)
 """
+import json
 import os
 import sys
 import time
@@ -39,8 +44,14 @@ class _LU:
         return sla.lu_solve(self.lu, r)
 
 
-def solve(froude: float, ftol: float = 1e-11):
-    p = W.working(froude)
+def extended(froude: float):
+    """The working problem with the domain extended upstream to x_1 = -40 (211 x 61, same spacing)."""
+    return W.make_problem(211, 61, -40.0, 30.0, 0.0, 20.0, froude, [W.Bump(0.2, 1.0, 1.0)])
+
+
+def solve(froude: float, ftol: float = 1e-11, ext: bool = False):
+    p = extended(froude) if ext else W.working(froude)
+    tag = f"{p.N}x{p.M}"
     t0 = time.time()
     J = Lin.jacobian(p)
     f0 = Lin.forcing(p)
@@ -58,13 +69,28 @@ def solve(froude: float, ftol: float = 1e-11):
     print(f"F={froude}: converged={res.converged} newton={res.newton_iters} gmres={res.gmres_iters} "
           f"history={['%.2e' % h for h in res.history]} ({time.time() - t0:.0f} s)", flush=True)
     if not res.converged:
-        raise SystemExit(f"the oracle did not converge at F={froude}")
-    out = os.path.join(HERE, f"working_181x61_F{froude}.npz")
+        from oracle import residual as R
+        zeta = R.reconstruct(p, res.u).zeta
+        rec = dict(problem=f"{tag} half domain, x in [{p.x1:g}, 30], y in [0, 20], bump 0.2 exp(-(x^2+y^2))",
+                   froude=froude, converged=False, ftol=ftol, band=BAND, newton_iters=res.newton_iters,
+                   gmres_iters=res.gmres_iters, history_inf=[float(h) for h in res.history],
+                   outcome="line search failed" if res.newton_iters < 30 else "Newton step limit",
+                   final_inf=float(res.history[-1]), max_abs_zeta=float(abs(zeta).max()),
+                   limiting_height=froude * froude / 2)
+        out = os.path.join(HERE, f"oracle_newton_{tag}_F{froude}.json")
+        with open(out, "w") as f:
+            json.dump(rec, f, indent=1)
+        print("did not converge; wrote", out, flush=True)
+        return
+    out = os.path.join(HERE, f"working_{tag}_F{froude}.npz")
     np.savez_compressed(out, u=res.u, history=np.array(res.history), band=BAND, ftol=ftol,
                         newton_iters=res.newton_iters, gmres_iters=res.gmres_iters)
     print("wrote", out, flush=True)
 
 
 if __name__ == "__main__":
-    for a in sys.argv[1:] or ["1.4"]:
-        solve(float(a))
+    args = sys.argv[1:] or ["1.4"]
+    ext = "--extended" in args
+    for a in args:
+        if a != "--extended":
+            solve(float(a), ext=ext)
