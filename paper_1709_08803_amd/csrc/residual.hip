@@ -31,13 +31,17 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 // ------------------------------------------------------------------ rsqrt
 // FP32: the hardware reciprocal square root (about 1 ulp).
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-// FP64: the hardware estimate y refined by one Newton-Raphson step
-// y (1 + e/2), e = 1 - x y^2, whose truncation error is (3/8) e^2 relative: of
-// order 1e-15 for an estimate good to ~5e-8, far below the parity bound of the
-// sums (1e-12 of the sum of |terms|), at one FMA per rsqrt less than the
-// second-order step y (1 + e/2 + 3e^2/8) (the sums are bound by VALU issue).
+// FP64: an estimate y refined by one Newton-Raphson step y (1 + e/2),
+// e = 1 - x y^2, whose truncation error is (3/8) e^2 relative.  The estimate is
+// the FP32 reciprocal square root of x rounded to FP32 (relative error ~1e-7,
+// so the refined value is good to ~2e-14, far below the parity bound of the
+// sums, 1e-12 of the sum of |terms|): on gfx950 the two conversions and
+// v_rsq_f32 issue in ~10 cycles per wave against ~17 for v_rsq_f64, and one
+// first-order step costs one FMA less than the second-order one the FP64
+// estimate would otherwise get (the sums are bound by VALU issue).  x is a
+// squared distance or a positive quadratic form well inside the FP32 range.
 __device__ __forceinline__ double rsq(double x) {
-    const double y = __builtin_amdgcn_rsq(x);
+    const double y = (double)__builtin_amdgcn_rsqf((float)x);
     const double e = fma(-x * y, y, 1.0);
     return fma(0.5 * y, e, y);
 }
