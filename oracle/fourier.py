@@ -28,10 +28,13 @@ def dispersion_root(F: float) -> float:
 
 
 def linear_surface_fft(F: float, bump_fn, half_length: float = 160.0, h: float = 0.25,
-                       mu: float = 0.02):
+                       mu: float = 0.02, tau: float = 0.0):
     """Return (x, y, zeta) on a periodic box [-L, L)^2 with spacing h.
 
-    bump_fn(X, Y) -> beta + 1 on the grid.
+    bump_fn(X, Y) -> beta + 1 on the grid.  tau: surface tension (Section 6);
+    the linear dynamic condition phi_x + zeta / F^2 - tau lap(zeta) = 1 makes
+    1/F^2 into 1/F^2 + tau kappa^2 for each Fourier mode, so kappa tanh(kappa)
+    in the denominator gains the factor 1 + tau F^2 kappa^2.
     """
     n = int(round(2 * half_length / h))
     x = -half_length + h * np.arange(n)
@@ -45,7 +48,7 @@ def linear_surface_fft(F: float, bump_fn, half_length: float = 160.0, h: float =
     with np.errstate(invalid="ignore", divide="ignore"):
         th = np.where(kap > 0, np.tanh(kap), 0.0)
         sech = 1.0 / np.cosh(np.minimum(kap, 700.0))
-        zh = sig * sig * F * F * bh * sech / (sig * sig * F * F + kap * th)
+        zh = sig * sig * F * F * bh * sech / (sig * sig * F * F + kap * th * (1.0 + tau * F * F * kap * kap))
     zh[0, 0] = F * F / (F * F - 1.0) * bh[0, 0]
     z = np.real(np.fft.ifft2(zh))
     return x, x, z

@@ -17,6 +17,14 @@ numpy/scipy matrices; meant for small meshes.
     slice pairs |m - l| <= h_b (Appendix A: "b blocks of size (N+1) x (N+1) in
     each row"; Reading: the band is centred, h_b = max(1, round(M/20)), i.e.
     b = 2 h_b + 1 ~ M/10 as in Table 1).
+  * Surface tension (Section 6, tau != 0): the linearised dynamic row gains
+    -tau (zeta_xx* + zeta_yy*) (the linear part of -tau K), which adds entries
+    near the diagonal of block (1,1) -- within the slice, and coupling each
+    slice to its neighbours through zeta_yy.  Reading: P keeps block (1,1)
+    slice-block-diagonal, every slice with the interior slice's block (own-row
+    coefficient -2/dy^2 of the second y-difference), so that P11 stays the same
+    block on every slice; the couplings to neighbouring slices are left to the
+    Krylov solver.
   * P^-1 r by a dense LU solve of P (the definition); the block LU of
     Appendix A is one way of computing the same vector.
   * The linear start u_lin = u0 - J~^-1 F_lin(u0), u0 the uniform stream
@@ -63,6 +71,44 @@ def reconstruction_maps(p):
     Dt = np.kron(eyeM, Avg @ Dn)
     assert Pn.shape == (N * M, nb)
     return Pn, Dx, Pt, Dt
+
+
+def Pt_slice(p):
+    """Node values -> half-mesh values of one slice: [(N-1)][(N+1)] (the per-slice block of Pt)."""
+    N, dx = p.N, p.dx
+    Tn = np.zeros((N, N + 1))
+    Tn[:, 0] = 1.0
+    for i in range(1, N):
+        Tn[i, 1:] = Tn[i - 1, 1:]
+        Tn[i, 1 + i - 1] += 0.5 * dx
+        Tn[i, 1 + i] += 0.5 * dx
+    Avg = 0.5 * (np.eye(N - 1, N) + np.eye(N - 1, N, 1))
+    return Avg @ Tn
+
+
+def half_mesh_xx_map(p):
+    """zeta_x unknowns -> zeta_xx at the half-mesh points, (zeta_x,k+1 - zeta_x,k) / dx, all slices."""
+    N, M, dx = p.N, p.M, p.dx
+    D = np.zeros((N - 1, N + 1))
+    for k in range(N - 1):
+        D[k, 1 + k] = -1.0 / dx
+        D[k, 2 + k] = 1.0 / dx
+    return np.kron(np.eye(M), D)
+
+
+def second_y_difference(p):
+    """[M][M] matrix of the node second y-differences of the residual's reading
+    (oracle.residual.d2_dy2): interior, mirrored symmetry row, one-sided edges."""
+    M, dy = p.M, p.dy
+    Y = np.zeros((M, M))
+    for j in range(1, M - 1):
+        Y[j, j - 1:j + 2] = (1.0, -2.0, 1.0)
+    Y[M - 1, M - 4:] = (-1.0, 4.0, -5.0, 2.0)
+    if p.half_domain:
+        Y[0, 0:2] = (-2.0, 2.0)
+    else:
+        Y[0, 0:4] = (2.0, -5.0, 4.0, -1.0)
+    return Y / (dy * dy)
 
 
 # ----------------------------------------------------------------------------- kernel matrices
@@ -134,9 +180,12 @@ def jacobian(p, K=None) -> np.ndarray:
     for blk, cols in ((0, Z), (1, Ph), (2, Ps)):
         J[blk * nb + rad0, cols] = A0
         J[blk * nb + rad1, cols] = A1
-    # F1 = phi*_x + zeta*/F^2 - 1
+    # F1 = phi*_x + zeta*/F^2 - 1 (- tau (zeta*_xx + zeta*_yy) with surface tension)
     J[col, Z] = Pt / (F * F)
     J[col, Ph] = Dt
+    tau = getattr(p, "tau", 0.0)
+    if tau != 0.0:
+        J[col, Z] -= tau * (half_mesh_xx_map(p) + np.kron(second_y_difference(p), Pt_slice(p)))
     # F2 = K5 (zeta_x - zeta*_x) + zeta*_x I5 + K6 (psi - x) - beta terms - 2 pi (phi* - x*)
     J[nb + col, Z] = K5 @ Dx - (K5.sum(axis=1) - I5)[:, None] * Dt
     J[nb + col, Ph] = -TWO_PI * Pt
@@ -187,7 +236,8 @@ def slice_of_index(p, idx: np.ndarray) -> np.ndarray:
 
 
 def banded(p, J: np.ndarray, hb: int) -> np.ndarray:
-    """P: J~ with the dense blocks (2,1), (2,3), (3,1), (3,2) cut to slice band |m - l| <= hb."""
+    """P: J~ with the dense blocks (2,1), (2,3), (3,1), (3,2) cut to slice band |m - l| <= hb;
+    with surface tension, block (1,1) is the interior slice's diagonal block on every slice."""
     nb = (p.N + 1) * p.M
     P = J.copy()
     sl = slice_of_index(p, np.arange(nb))
@@ -195,6 +245,10 @@ def banded(p, J: np.ndarray, hb: int) -> np.ndarray:
     for (bi, bj) in ((1, 0), (1, 2), (2, 0), (2, 1)):
         blk = P[bi * nb:(bi + 1) * nb, bj * nb:(bj + 1) * nb]
         blk[far] = 0.0
+    if getattr(p, "tau", 0.0) != 0.0:
+        s = p.N + 1
+        inner = J[s:2 * s, s:2 * s].copy()  # slice 1: interior stencil (M >= 4)
+        P[:nb, :nb] = np.kron(np.eye(p.M), inner)
     return P
 
 
@@ -235,6 +289,10 @@ def banded_matvec(p, z: np.ndarray, hb: int) -> np.ndarray:
     phx_s = R.half_mesh(nf.phi_x)
     psi_s = R.half_mesh(nf.psi)
     F1 = phx_s + zeta_s / (F * F)
+    tau = getattr(p, "tau", 0.0)
+    if tau != 0.0:  # P's block (1,1): in-slice part with the interior own-row coefficient
+        zxx_s = (nf.zeta_x[:, 1:] - nf.zeta_x[:, :-1]) / dx
+        F1 = F1 - tau * (zxx_s - 2.0 / (p.dy * p.dy) * zeta_s)
     F2 = -TWO_PI * phi_s
     F7 = -TWO_PI * psi_s
     images = (1.0, -1.0) if p.half_domain else (1.0,)

@@ -16,7 +16,8 @@ F(u) is built in these steps:
   4. the boundary-integral rows on the free surface (F2) and on the bottom (F7)
      from the trapezoidal sums of K1, K2 with the S2 subtraction and the closed
      form of the S2 integral (Section 2.2 and Section 3.1);
-  5. the dynamic condition (F1, eq. (new_finite_dynamic)) at the same points;
+  5. the dynamic condition (F1, eq. (new_finite_dynamic)) at the same points,
+     with the surface-tension term of Section 6 when the problem's tau is not 0;
   6. the six radiation rows per slice (eqs. (scullen1)-(scullen6), discretised
      as in Appendix B);
   7. assembly in the row order printed in Appendix B.
@@ -83,6 +84,25 @@ def d_dy(f: np.ndarray, dy: float, half: bool) -> np.ndarray:
         g[0] = 0.0
     else:
         g[0] = (-3.0 * f[0] + 4.0 * f[1] - f[2]) / (2.0 * dy)
+    return g
+
+
+def d2_dy2(f: np.ndarray, dy: float, half: bool) -> np.ndarray:
+    """Second y-derivative of a node field [M][N] (used by the surface-tension term).
+
+    Reading (the paper only names the curvature term): second differences
+    inside; on a half domain the field is even in y, so on y = 0 the mirror
+    value f_2 stands for f_0; on an outer edge the one-sided second-order
+    four-point stencil (2 f_M - 5 f_{M-1} + 4 f_{M-2} - f_{M-3}) / dy^2 (and its
+    mirror on y_1 of a full domain).  Needs M >= 4.
+    """
+    g = np.empty_like(f)
+    g[1:-1] = (f[2:] - 2.0 * f[1:-1] + f[:-2]) / (dy * dy)
+    g[-1] = (2.0 * f[-1] - 5.0 * f[-2] + 4.0 * f[-3] - f[-4]) / (dy * dy)
+    if half:
+        g[0] = 2.0 * (f[1] - f[0]) / (dy * dy)
+    else:
+        g[0] = (2.0 * f[0] - 5.0 * f[1] + 4.0 * f[2] - f[3]) / (dy * dy)
     return g
 
 
@@ -250,14 +270,37 @@ def subset(tg: TargetSet, idx: np.ndarray) -> TargetSet:
 
 
 # ----------------------------------------------------------------------------- step 5
+def curvature(p, nf: NodeFields) -> np.ndarray:
+    """Twice the mean curvature of z = zeta at the half-mesh points,
+    K = div(grad zeta / sqrt(1 + |grad zeta|^2))
+      = [(1 + zy^2) zxx - 2 zx zy zxy + (1 + zx^2) zyy] / (1 + zx^2 + zy^2)^(3/2)
+    (Section 6: surface tension times mean curvature enters Bernoulli's equation).
+    Reading: zx*, zy* are the half-mesh means used by the dynamic condition; zxx*
+    and zxy* the differences of the node zeta_x and zeta_y across the half-mesh
+    cell, (g_{k+1} - g_k) / dx; zyy* the half-mesh mean of the node second
+    y-differences (d2_dy2)."""
+    zx, zy = half_mesh(nf.zeta_x), half_mesh(nf.zeta_y)
+    zxx = (nf.zeta_x[:, 1:] - nf.zeta_x[:, :-1]) / p.dx
+    zxy = (nf.zeta_y[:, 1:] - nf.zeta_y[:, :-1]) / p.dx
+    zyy = half_mesh(d2_dy2(nf.zeta, p.dy, p.half_domain))
+    q = 1.0 + zx * zx + zy * zy
+    return ((1.0 + zy * zy) * zxx - 2.0 * zx * zy * zxy + (1.0 + zx * zx) * zyy) / (q * np.sqrt(q))
+
+
 def dynamic_rows(p, nf: NodeFields) -> np.ndarray:
-    """F1 at the half-mesh points: eq. (new_finite_dynamic) written as a residual."""
+    """F1 at the half-mesh points: eq. (new_finite_dynamic) written as a residual,
+    with the surface-tension term -tau K when tau != 0 (Section 6; tau = T / (rho U^2 H),
+    the pressure jump T K across the surface)."""
     zx, zy = half_mesh(nf.zeta_x), half_mesh(nf.zeta_y)
     px, py = half_mesh(nf.phi_x), half_mesh(nf.phi_y)
     z = half_mesh(nf.zeta)
     kin = 0.5 * ((1.0 + zx * zx) * py * py + (1.0 + zy * zy) * px * px - 2.0 * zx * zy * px * py) \
         / (1.0 + zx * zx + zy * zy)
-    return kin + z / (p.froude * p.froude) - 0.5
+    F1 = kin + z / (p.froude * p.froude) - 0.5
+    tau = getattr(p, "tau", 0.0)
+    if tau != 0.0:
+        F1 = F1 - tau * curvature(p, nf)
+    return F1
 
 
 # ----------------------------------------------------------------------------- step 6

@@ -31,6 +31,7 @@ class Problem:
     half_domain = True means the data are even in y about y = 0 and only
     y >= 0 is stored (y1 must be 0); the mirror half is implied.
     beta, beta_x, beta_y are node arrays [M][N] of the bottom z = beta(x, y).
+    tau is the surface-tension parameter T / (rho U^2 H) (0: gravity waves only).
     """
     N: int
     M: int
@@ -45,6 +46,7 @@ class Problem:
     half_domain: bool = True
     n_decay: float = RADIATION_DECAY
     name: str = ""
+    tau: float = 0.0
 
     @property
     def n_unknowns(self) -> int:
@@ -112,7 +114,7 @@ def topography(bumps: Sequence[Bump], x: np.ndarray, y: np.ndarray,
 
 def make_problem(N: int, M: int, xlo: float, xhi: float, ylo: float, yhi: float,
                  froude: float, bumps: Sequence[Bump], half_domain: bool = True,
-                 name: str = "") -> Problem:
+                 name: str = "", tau: float = 0.0) -> Problem:
     dx = (xhi - xlo) / (N - 1)
     dy = (yhi - ylo) / (M - 1)
     if half_domain and ylo != 0.0:
@@ -121,7 +123,7 @@ def make_problem(N: int, M: int, xlo: float, xhi: float, ylo: float, yhi: float,
     y = ylo + dy * np.arange(M)
     b, bx, by = topography(bumps, x, y, mirror=half_domain)
     return Problem(N=N, M=M, x1=xlo, dx=dx, y1=ylo, dy=dy, froude=froude,
-                   beta=b, beta_x=bx, beta_y=by, half_domain=half_domain, name=name)
+                   beta=b, beta_x=bx, beta_y=by, half_domain=half_domain, name=name, tau=tau)
 
 
 # ---------------------------------------------------------------- named workloads
