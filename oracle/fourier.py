@@ -11,6 +11,12 @@
   replaced by i k1 + mu with a small mu > 0, which damps waves downstream and
   removes them upstream; the transform is taken on a large periodic box.
   beta^ is the discrete transform of beta + 1 on the same box.
+* exact_solution / exact_solution_point: eq. (exactsoln) itself, and its
+  x-derivative, by adaptive quadrature (scipy.integrate.quad; the principal
+  value with the Cauchy weight), for topographies that are sums of the
+  Gaussian bumps of eq. (bottom).  Pins: tests/test_oracle_exact_pins.py
+  (the FFT solution extrapolated to mu -> 0, decay upstream, differences of
+  zeta against zeta_x, symmetry in y).
 """
 from __future__ import annotations
 
@@ -52,3 +58,132 @@ def linear_surface_fft(F: float, bump_fn, half_length: float = 160.0, h: float =
     zh[0, 0] = F * F / (F * F - 1.0) * bh[0, 0]
     z = np.real(np.fft.ifft2(zh))
     return x, x, z
+
+
+def gaussian_transform(eps: float, w: float):
+    """Fourier transform of beta + 1 = eps exp(-(x^2 + y^2) / w^2) in polar form,
+    beta~(k, psi) = eps pi w^2 exp(-k^2 w^2 / 4) (real and isotropic)."""
+    return lambda k, psi: eps * math.pi * w * w * math.exp(-k * k * w * w / 4.0)
+
+
+def bump_transform(eps: float, delta: float):
+    """beta~ of one bump of eq. (bottom) centred at the origin,
+    eps exp(-(x^2 + y^2) / (2 delta^2)): eps 2 pi delta^2 exp(-k^2 delta^2 / 2)."""
+    return gaussian_transform(eps, math.sqrt(2.0) * delta)
+
+
+def bump_kmax(delta: float, decay: float = 45.0) -> float:
+    """k beyond which k^2 sech(k) beta~(k) of a bump of width delta is below
+    exp(-decay) of its scale: the root of k + k^2 delta^2 / 2 = decay."""
+    a = 0.5 * delta * delta
+    return (-1.0 + math.sqrt(1.0 + 4.0 * a * decay)) / (2.0 * a)
+
+
+def pole(F: float, psi: float) -> float:
+    """k_1(psi): the positive root of k F^2 - sec^2(psi) tanh(k), or 0 if there is none."""
+    sec2 = 1.0 / math.cos(psi) ** 2
+    if F * F >= sec2:
+        return 0.0
+    g = lambda k: k * F * F - sec2 * math.tanh(k)
+    hi = sec2 / (F * F) + 1.0
+    return optimize.brentq(g, 1e-12, hi, xtol=1e-15, rtol=1e-15)
+
+
+def _sech(k: float) -> float:
+    e = math.exp(-k)
+    return 2.0 * e / (1.0 + e * e)
+
+
+def pole_residue(F: float, beta_t, psi: float, k1: float) -> float:
+    """R(psi) = k_1^2 sech(k_1) beta~(k_1, psi) / (F^2 - sec^2(psi) sech^2(k_1)): the
+    residue at k = k_1 of the k-integrand of eq. (exactsoln) without its cosine
+    (the denominator is the k-derivative of k F^2 - sec^2(psi) tanh k there);
+    0 where there is no pole (k1 = 0)."""
+    if k1 <= 0.0:
+        return 0.0
+    sec2 = 1.0 / math.cos(psi) ** 2
+    return k1 * k1 * _sech(k1) * beta_t(k1, psi) / (F * F - sec2 * _sech(k1) ** 2)
+
+
+def exact_solution_point(F: float, beta_t, x: float, y: float, kmax: float = 14.0, order: int = 0) -> float:
+    """zeta(x, y) (order 0) or zeta_x(x, y) (order 1) of eq. (exactsoln)
+    (Section 4.1), by adaptive quadrature, for a topography whose transform
+    beta~(k, psi) is real and even in psi (symmetric about x = 0 and y = 0).
+
+    Reading of the path below the pole: the k-integral of the first term is its
+    principal value plus pi R sin(k_1 X), X = |x| cos(psi) + y sin(psi), with
+    R = k_1^2 sech(k_1) beta~(k_1) / (F^2 - sec^2(psi) sech^2(k_1)) the residue
+    of the integrand's pole (the denominator is the k-derivative of
+    k F^2 - sec^2(psi) tanh k at k_1).  That is the half-residue an indentation
+    below the pole adds to the real part of exp(-i k X); its sign is the one for
+    which zeta vanishes far upstream (the principal value alone, or the other
+    sign, leaves a wave there).  The second term is the downstream wave H(x) as
+    printed.  zeta_x differentiates both under the integral signs
+    (d|x|/dx = sign(x), with sign(0) = 0 and H(0) = 1/2, the mean of the
+    one-sided derivatives, which agree since zeta is smooth).
+    kmax: truncation of the k-integrals (beta~ decays like a Gaussian).
+    """
+    from scipy import integrate
+
+    F2 = F * F
+    sgn = (x > 0) - (x < 0)
+    psi0 = 0.0 if F < 1.0 else math.acos(1.0 / F)
+
+    def residue(psi, k1):
+        return pole_residue(F, beta_t, psi, k1)
+
+    def inner(psi):
+        c, s = math.cos(psi), math.sin(psi)
+        sec2 = 1.0 / (c * c)
+        X = abs(x) * c + y * s
+        if order == 0:
+            num = lambda k: k * k * _sech(k) * beta_t(k, psi) * math.cos(k * X)
+        else:
+            num = lambda k: -k * c * sgn * k * k * _sech(k) * beta_t(k, psi) * math.sin(k * X)
+        g = lambda k: k * F2 - sec2 * math.tanh(k)
+        k1 = pole(F, psi)
+        lim = max(200, int(6 * kmax * (abs(X) + 1)))
+        if k1 <= 0.0 or k1 >= kmax:
+            v, _ = integrate.quad(lambda k: num(k) / g(k) if k > 0 else 0.0, 0.0, kmax, limit=lim,
+                                  epsabs=1e-13, epsrel=1e-11)
+            return v
+        # principal value: Cauchy weight 1 / (k - k1) times the regular factor num (k - k1) / g
+        def reg(k):
+            d = k - k1
+            if k <= 0.0:
+                return 0.0  # num ~ k^2 and g ~ k (F^2 - sec^2 psi) near k = 0
+            if abs(d) < 1e-7:
+                return num(k) / (F2 - sec2 * _sech(k1) ** 2)
+            return num(k) * d / g(k)
+        v, _ = integrate.quad(reg, 0.0, kmax, weight="cauchy", wvar=k1, limit=lim, epsabs=1e-13, epsrel=1e-11)
+        if order == 0:
+            return v + math.pi * residue(psi, k1) * math.sin(k1 * X)
+        return v + math.pi * residue(psi, k1) * k1 * c * sgn * math.cos(k1 * X)
+
+    pts = [-psi0, psi0] if psi0 > 0.0 else None
+    first, _ = integrate.quad(inner, -math.pi / 2, math.pi / 2, points=pts, limit=400, epsabs=1e-12, epsrel=1e-10)
+    out = F2 / (2.0 * math.pi ** 2) * first
+    if x >= 0.0:
+        def wave(psi):
+            c, s = math.cos(psi), math.sin(psi)
+            k1 = pole(F, psi)
+            if order == 0:
+                return residue(psi, k1) * math.sin(k1 * x * c) * math.cos(k1 * y * s)
+            return residue(psi, k1) * k1 * c * math.cos(k1 * x * c) * math.cos(k1 * y * s)
+        w, _ = integrate.quad(wave, psi0, math.pi / 2, limit=400, epsabs=1e-12, epsrel=1e-10)
+        out -= (0.5 if x == 0.0 else 1.0) * 2.0 * F2 / math.pi * w
+    return out
+
+
+def exact_solution(F: float, bumps, xs, ys, order: int = 0) -> np.ndarray:
+    """zeta (order 0) or zeta_x (order 1) of eq. (exactsoln) at the points
+    (xs[i], ys[i]) for beta + 1 a sum of bumps of eq. (bottom), bumps =
+    [(eps, delta, b1, b2), ...]: the linear problem is linear in beta + 1, so the
+    solution is the sum of each bump's solution, shifted to its centre."""
+    out = np.zeros(len(xs))
+    for eps, delta, b1, b2 in bumps:
+        bt = bump_transform(eps, delta)
+        km = bump_kmax(delta)
+        for i, (x, y) in enumerate(zip(xs, ys)):
+            out[i] += exact_solution_point(F, bt, float(x) - b1, float(y) - b2, kmax=km, order=order)
+    return out
