@@ -94,6 +94,16 @@ def _sech(k: float) -> float:
     return 2.0 * e / (1.0 + e * e)
 
 
+def _k_minus_tanh(k: float) -> float:
+    """k - tanh(k) without cancellation at small k: the Taylor series of tanh
+    (k^3/3 - 2k^5/15 + 17k^7/315 - 62k^9/2835 + 1382k^11/155925 - ...) below 0.1."""
+    if k >= 0.1:
+        return k - math.tanh(k)
+    k2 = k * k
+    return k * k2 * (1.0 / 3 - k2 * (2.0 / 15 - k2 * (17.0 / 315 - k2 * (62.0 / 2835 - k2 * (1382.0 / 155925
+                     - k2 * 21844.0 / 6081075)))))
+
+
 def pole_residue(F: float, beta_t, psi: float, k1: float) -> float:
     """R(psi) = k_1^2 sech(k_1) beta~(k_1, psi) / (F^2 - sec^2(psi) sech^2(k_1)): the
     residue at k = k_1 of the k-integrand of eq. (exactsoln) without its cosine
@@ -140,22 +150,39 @@ def exact_solution_point(F: float, beta_t, x: float, y: float, kmax: float = 14.
             num = lambda k: k * k * _sech(k) * beta_t(k, psi) * math.cos(k * X)
         else:
             num = lambda k: -k * c * sgn * k * k * _sech(k) * beta_t(k, psi) * math.sin(k * X)
-        g = lambda k: k * F2 - sec2 * math.tanh(k)
+        # g = k F^2 - sec^2(psi) tanh k, written as k (F^2 - sec^2 psi) + sec^2 psi (k - tanh k):
+        # near psi_0 (F > 1) both of k F^2 and sec^2 tanh k are much larger than g
+        g = lambda k: k * (F2 - sec2) + sec2 * _k_minus_tanh(k)
         k1 = pole(F, psi)
         lim = max(200, int(6 * kmax * (abs(X) + 1)))
         if k1 <= 0.0 or k1 >= kmax:
-            v, _ = integrate.quad(lambda k: num(k) / g(k) if k > 0 else 0.0, 0.0, kmax, limit=lim,
-                                  epsabs=1e-13, epsrel=1e-11)
+            # no pole; for F > 1 just below psi_0, g / k nearly vanishes at k = 0 and the
+            # integrand varies on the scale sqrt(3 (F^2 - sec^2 psi) / sec^2 psi)
+            sig = math.sqrt(max(3.0 * (F2 - sec2) / sec2, 0.0))
+            brk = [sig * 2.0 ** j for j in range(40) if 0.0 < sig * 2.0 ** j < kmax] or None
+            v, _ = integrate.quad(lambda k: num(k) / g(k) if k > 0 else 0.0, 0.0, kmax, points=brk,
+                                  limit=lim, epsabs=1e-13, epsrel=1e-11)
             return v
-        # principal value: Cauchy weight 1 / (k - k1) times the regular factor num (k - k1) / g
+        # principal value: Cauchy weight 1 / (k - k1) times the regular factor num (k - k1) / g,
+        # with g / (k - k1) = F^2 - sec^2 (tanh k - tanh k1) / (k - k1) and
+        # tanh k - tanh k1 = tanh(k - k1) (1 - tanh k tanh k1) (no cancellation at the pole)
+        t1 = math.tanh(k1)
+
         def reg(k):
             d = k - k1
             if k <= 0.0:
                 return 0.0  # num ~ k^2 and g ~ k (F^2 - sec^2 psi) near k = 0
-            if abs(d) < 1e-7:
-                return num(k) / (F2 - sec2 * _sech(k1) ** 2)
-            return num(k) * d / g(k)
-        v, _ = integrate.quad(reg, 0.0, kmax, weight="cauchy", wvar=k1, limit=lim, epsabs=1e-13, epsrel=1e-11)
+            q = F2 - sec2 * (1.0 - math.tanh(k) * t1) * (math.tanh(d) / d if d != 0.0 else 1.0)
+            return num(k) / q
+        # the principal value over [0, 2 k1] (symmetric about the pole) and the plain
+        # integral beyond, split where the integrand's scale k1 ends
+        k2 = min(2.0 * k1, kmax)
+        v, _ = integrate.quad(reg, 0.0, k2, weight="cauchy", wvar=k1, limit=lim, epsabs=1e-13, epsrel=1e-11)
+        if k2 < kmax:
+            brk = [k1 * 2.0 ** j for j in range(2, 40) if k1 * 2.0 ** j < kmax] or None
+            w, _ = integrate.quad(lambda k: num(k) / g(k), k2, kmax, points=brk, limit=lim,
+                                  epsabs=1e-13, epsrel=1e-11)
+            v += w
         if order == 0:
             return v + math.pi * residue(psi, k1) * math.sin(k1 * X)
         return v + math.pi * residue(psi, k1) * k1 * c * sgn * math.cos(k1 * X)

@@ -97,3 +97,23 @@ def test_planted_residue_mistakes_fail_the_pins(monkeypatch, plant):
         monkeypatch.setattr(Fo, "pole_residue", lambda *a: -true(*a))
     assert not _upstream_pin_holds(0.7)[0]
     assert not _fft_pin_holds(*FFT_CASES[0])[0]
+
+
+def test_k_minus_tanh_series():
+    # the series branch below 0.1 against the direct difference where that is still accurate,
+    # and against its leading term k^3/3 where the direct difference has lost every digit
+    for k in (0.05, 0.07, 0.0999):
+        assert abs(Fo._k_minus_tanh(k) - (k - math.tanh(k))) <= 1e-12 * (k - math.tanh(k))
+    for k in (1e-5, 1e-3):
+        assert abs(Fo._k_minus_tanh(k) - k ** 3 / 3) <= 0.41 * k ** 5
+    assert Fo._k_minus_tanh(0.1) == 0.1 - math.tanh(0.1)
+
+
+@pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")
+def test_exact_supercritical_stable_under_k_truncation():
+    # F > 1: the principal value next to small poles (psi just above psi_0) is formed without
+    # cancellation, so the result does not move when the k-range is extended
+    bt = Fo.bump_transform(EPS, 3.0)
+    a = Fo.exact_solution_point(3.0, bt, 10.0, 0.0, kmax=Fo.bump_kmax(3.0))
+    b = Fo.exact_solution_point(3.0, bt, 10.0, 0.0, kmax=5.0)
+    assert abs(a - b) <= 1e-9 * EPS
