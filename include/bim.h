@@ -61,7 +61,14 @@ enum { BIM_STORE_FP64 = 0, BIM_STORE_FP32 = 1 };
  *   half_domain = 0: the full truncated mesh (the paper's y1 = -yM, or any y1).
  *   n_decay: the upstream decay rate n of the radiation condition (0.05 in the paper).
  *   beta, beta_x, beta_y: device node arrays of the bottom and its slopes.
- * Requirements: N >= 3, M >= 3, dx > 0, dy > 0, froude > 0.
+ *   tau: surface-tension parameter T / (rho U^2 H) (Section 6); 0 for the
+ *        gravity-wave problem of the paper.  With tau != 0 the dynamic condition
+ *        gains -tau K, K twice the mean curvature of the free surface
+ *        (div(grad zeta / sqrt(1 + |grad zeta|^2))), and the linearised one
+ *        -tau (zeta_xx + zeta_yy); second y-differences are central inside,
+ *        mirrored on the symmetry line of a half domain and one-sided
+ *        (four points) on an outer edge, so M >= 4 is required.
+ * Requirements: N >= 3, M >= 3, dx > 0, dy > 0, froude > 0, tau finite.
  */
 typedef struct bim_problem {
     int32_t N, M;
@@ -70,6 +77,7 @@ typedef struct bim_problem {
     double n_decay;
     double froude;
     const double *beta, *beta_x, *beta_y;
+    double tau;
 } bim_problem;
 
 /*

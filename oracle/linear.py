@@ -14,17 +14,23 @@ numpy/scipy matrices; meant for small meshes.
     entries printed in Appendix B are used only as test values; several of
     them are misprinted (see the tests).
   * P: J~ with its four dense blocks (2,1), (2,3), (3,1), (3,2) kept only for
-    slice pairs |m - l| <= h_b (Appendix A: "b blocks of size (N+1) x (N+1) in
-    each row"; Reading: the band is centred, h_b = max(1, round(M/20)), i.e.
+    slice pairs |m - l| <= h_b (Appendix A: a band of b blocks of size
+    (N+1) x (N+1) in each block row; Reading: the band is centred, h_b = max(1, round(M/20)), i.e.
     b = 2 h_b + 1 ~ M/10 as in Table 1).
   * Surface tension (Section 6, tau != 0): the linearised dynamic row gains
     -tau (zeta_xx* + zeta_yy*) (the linear part of -tau K), which adds entries
     near the diagonal of block (1,1) -- within the slice, and coupling each
-    slice to its neighbours through zeta_yy.  Reading: P keeps block (1,1)
-    slice-block-diagonal, every slice with the interior slice's block (own-row
-    coefficient -2/dy^2 of the second y-difference), so that P11 stays the same
-    block on every slice; the couplings to neighbouring slices are left to the
-    Krylov solver.
+    slice to its neighbours through zeta_yy.  Reading (the paper leaves surface
+    tension to future work and gives no preconditioner for it): P is the
+    preconditioner of the problem without surface tension, the whole tension
+    term being left to the Krylov solver.  Any part of -tau zeta_xx* kept in
+    block (1,1) turns the slice block, lower triangular in x (the radiation rows
+    F5, F6 fix the upstream end and each dynamic row the next slope), into a
+    recurrence with a growing mode -- capillary waves travel upstream -- whose
+    inverse overflows (31 x 11, F = 1.4, tau = 0.1: max |(P11 slice)^-1| ~ 1e24,
+    so a factorisation that eliminates block 1 first breaks down).  Without it
+    GMRES needs more iterations (to 1e-10 on the linear system at that mesh:
+    298 against 176 with the in-slice zeta_xx* kept, 37 without tension).
   * P^-1 r by a dense LU solve of P (the definition); the block LU of
     Appendix A is one way of computing the same vector.
   * The linear start u_lin = u0 - J~^-1 F_lin(u0), u0 the uniform stream
@@ -237,7 +243,7 @@ def slice_of_index(p, idx: np.ndarray) -> np.ndarray:
 
 def banded(p, J: np.ndarray, hb: int) -> np.ndarray:
     """P: J~ with the dense blocks (2,1), (2,3), (3,1), (3,2) cut to slice band |m - l| <= hb;
-    with surface tension, block (1,1) is the interior slice's diagonal block on every slice."""
+    with surface tension, block (1,1) is that of the problem without it."""
     nb = (p.N + 1) * p.M
     P = J.copy()
     sl = slice_of_index(p, np.arange(nb))
@@ -245,10 +251,10 @@ def banded(p, J: np.ndarray, hb: int) -> np.ndarray:
     for (bi, bj) in ((1, 0), (1, 2), (2, 0), (2, 1)):
         blk = P[bi * nb:(bi + 1) * nb, bj * nb:(bj + 1) * nb]
         blk[far] = 0.0
-    if getattr(p, "tau", 0.0) != 0.0:
-        s = p.N + 1
-        inner = J[s:2 * s, s:2 * s].copy()  # slice 1: interior stencil (M >= 4)
-        P[:nb, :nb] = np.kron(np.eye(p.M), inner)
+    tau = getattr(p, "tau", 0.0)
+    if tau != 0.0:  # block (1,1) of the problem without surface tension
+        _, _, _, col = _row_positions(p)
+        P[col, :nb] += tau * (half_mesh_xx_map(p) + np.kron(second_y_difference(p), Pt_slice(p)))
     return P
 
 
@@ -289,10 +295,6 @@ def banded_matvec(p, z: np.ndarray, hb: int) -> np.ndarray:
     phx_s = R.half_mesh(nf.phi_x)
     psi_s = R.half_mesh(nf.psi)
     F1 = phx_s + zeta_s / (F * F)
-    tau = getattr(p, "tau", 0.0)
-    if tau != 0.0:  # P's block (1,1): in-slice part with the interior own-row coefficient
-        zxx_s = (nf.zeta_x[:, 1:] - nf.zeta_x[:, :-1]) / dx
-        F1 = F1 - tau * (zxx_s - 2.0 / (p.dy * p.dy) * zeta_s)
     F2 = -TWO_PI * phi_s
     F7 = -TWO_PI * psi_s
     images = (1.0, -1.0) if p.half_domain else (1.0,)

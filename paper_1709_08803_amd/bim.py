@@ -38,7 +38,8 @@ class _Problem(ctypes.Structure):
                 ("y1", ctypes.c_double), ("dy", ctypes.c_double),
                 ("half_domain", ctypes.c_int32), ("n_decay", ctypes.c_double),
                 ("froude", ctypes.c_double),
-                ("beta", ctypes.c_void_p), ("beta_x", ctypes.c_void_p), ("beta_y", ctypes.c_void_p)]
+                ("beta", ctypes.c_void_p), ("beta_x", ctypes.c_void_p), ("beta_y", ctypes.c_void_p),
+                ("tau", ctypes.c_double)]
 
 
 def lib():
@@ -165,7 +166,7 @@ class DeviceProblem:
         self.beta, self.beta_x, self.beta_y = t(p.beta), t(p.beta_x), t(p.beta_y)
         self.struct = _Problem(p.N, p.M, p.x1, p.dx, p.y1, p.dy, 1 if p.half_domain else 0,
                                p.n_decay, p.froude, self.beta.data_ptr(), self.beta_x.data_ptr(),
-                               self.beta_y.data_ptr())
+                               self.beta_y.data_ptr(), float(getattr(p, "tau", 0.0)))
 
     @property
     def n(self) -> int:

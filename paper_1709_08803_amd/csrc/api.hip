@@ -39,6 +39,8 @@ int validate(const bim_problem *p) {
         return fail(BIM_EINVAL, "non-finite mesh origin or decay rate");
     if (p->half_domain && p->y1 != 0.0) return fail(BIM_EINVAL, "a half domain must start at y1 = 0");
     if (!p->beta || !p->beta_x || !p->beta_y) return fail(BIM_EINVAL, "bottom arrays must be device pointers");
+    if (!std::isfinite(p->tau)) return fail(BIM_EINVAL, "surface tension must be finite");
+    if (p->tau != 0.0 && p->M < 4) return fail(BIM_EINVAL, "surface tension needs M >= 4 (one-sided second y-differences)");
     return BIM_OK;
 }
 

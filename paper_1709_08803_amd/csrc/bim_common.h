@@ -102,7 +102,7 @@ struct PairDesc {
     double *nodes, *ydiv;
     float *tg32;
     const double *beta, *beta_x, *beta_y;
-    double x1, n_decay, froude;
+    double x1, n_decay, froude, tau;
     int half, linear;
     int blk_int, blk_rec, blk_fin;  // first workgroup of this problem in each batched node-level launch
 };

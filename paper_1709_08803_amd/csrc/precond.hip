@@ -66,6 +66,11 @@ __global__ void k_diag_blocks(double *D11, double *D12, double *D22, int N, doub
     } else {
         const int k = r - 2;
         const double pt = (c == 0) ? 1.0 : dx * tau(k, c - 1);  // d f*_k / d u-slice
+        // With surface tension the block stays that of the problem without it: the
+        // in-slice -tau zeta*_xx would turn this lower-triangular block into a
+        // recurrence with a growing (upstream capillary) mode, whose inverse -- which
+        // the elimination below starts from -- overflows.  The Krylov solver takes
+        // the whole tension term.
         d11 = pt / (froude * froude);
         d22 = -kTwoPi * pt;
         if (c == 1 + k || c == 2 + k) d12 = 0.5;

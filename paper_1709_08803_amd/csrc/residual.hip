@@ -706,6 +706,17 @@ __device__ __forceinline__ void finalize_bie(const PairDesc &D, int b, double (*
 
 // Dynamic rows (block 0, columns >= 2) and radiation rows (columns 0, 1 of the
 // three blocks); r enumerates block 0 and then the radiation pairs of blocks 1, 2.
+// Second y-difference of the node field g (zeta: block 0 of the node array) at
+// (l, i): central inside; on the symmetry line of a half domain the mirror node
+// stands for row -1; one-sided four-point stencils on an outer edge (M >= 4).
+__device__ __forceinline__ double y_second_diff(const double *g, int l, int i, int N, int M, double dy, int half) {
+    const double c = 1.0 / (dy * dy);
+    auto at = [&](int j) { return g[(size_t)j * N + i]; };
+    if (l > 0 && l < M - 1) return c * (at(l + 1) - 2.0 * at(l) + at(l - 1));
+    if (l == M - 1) return c * (2.0 * at(M - 1) - 5.0 * at(M - 2) + 4.0 * at(M - 3) - at(M - 4));
+    return half ? c * 2.0 * (at(1) - at(0)) : c * (2.0 * at(0) - 5.0 * at(1) + 4.0 * at(2) - at(3));
+}
+
 __device__ __forceinline__ void finalize_rows(const PairDesc &D, int r) {
     const int N = D.N, M = D.M;
     const int nblk = (N + 1) * M;
@@ -754,7 +765,23 @@ __device__ __forceinline__ void finalize_rows(const PairDesc &D, int r) {
                        (1.0 + a * a + b * b);
     const double fr2 = D.froude * D.froude;
     // linear mode: eq. (linear_dynamic2), phi*_x + zeta*/F^2 - 1
-    D.F[row] = D.linear ? p + z / fr2 - 1.0 : kin + z / fr2 - 0.5;
+    double f1 = D.linear ? p + z / fr2 - 1.0 : kin + z / fr2 - 0.5;
+    if (D.tau != 0.0) {
+        // surface tension (Section 6): -tau K, K = div(grad zeta / |(1, grad zeta)|) from the
+        // half-mesh slopes, the cell differences of zeta_x and zeta_y and the mean of the
+        // node second y-differences; linear mode: -tau (zeta_xx + zeta_yy)
+        const double zxx = (zx[k + 1] - zx[k]) / dx;
+        const double zyy = 0.5 * (y_second_diff(nodes, l, k, N, M, D.dy, D.half) +
+                                  y_second_diff(nodes, l, k + 1, N, M, D.dy, D.half));
+        if (D.linear) {
+            f1 -= D.tau * (zxx + zyy);
+        } else {
+            const double zxy = (ydiv[n1] - ydiv[n0]) / dx;
+            const double qq = 1.0 + a * a + b * b;
+            f1 -= D.tau * ((1.0 + b * b) * zxx - 2.0 * a * b * zxy + (1.0 + a * a) * zyy) / (qq * sqrt(qq));
+        }
+    }
+    D.F[row] = f1;
 }
 
 __device__ __forceinline__ void finalize_body(const PairDesc &D, int b) {
@@ -836,6 +863,7 @@ PairDesc make_desc(const bim_problem *p, const Dims &d, const PairLaunch &pl, co
     D.x1 = p->x1;
     D.n_decay = p->n_decay;
     D.froude = p->froude;
+    D.tau = p->tau;
     D.half = p->half_domain ? 1 : 0;
     D.linear = linear;
     return D;

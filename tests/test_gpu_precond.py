@@ -26,6 +26,9 @@ CASES = [
     ("61x21-default", lambda: W.working(0.7, N=61, M=21), -1),
     ("ragged-45x9-h3", lambda: W.make_problem(45, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 3),
     ("full-31x13", lambda: W.make_problem(31, 13, -10, 10, -6, 6, 1.2, [], half_domain=False), 1),
+    # surface tension: P is the preconditioner of the problem without it
+    ("tension-31x11-h2", lambda: W.make_problem(31, 11, -16, 16, 0, 10, 1.4, [W.Bump(0.1, 1.0, 1.0)], tau=0.1), 2),
+    ("tension-full-31x13", lambda: W.make_problem(31, 13, -10, 10, -6, 6, 1.2, [], half_domain=False, tau=0.05), 1),
     # pivot blocks of s = N + 1 = 192, the largest the register inversion holds
     ("max-block-191x5-h1", lambda: W.make_problem(191, 5, -20, 20, 0, 1, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 1),
     # s = 193: the augmented-matrix Gauss-Jordan kernel for blocks beyond that

@@ -38,6 +38,10 @@ CASES = [
     ("full-61x61-offset", lambda: W.make_problem(61, 61, -7, 53, -30, 30, 0.6,
                                                  [W.Bump(0.2, 0.71, 0.71, cx=10.0, cy=10.0),
                                                   W.Bump(0.2, 0.71, 0.71, cx=0.0, cy=-10.0)], half_domain=False), 6),
+    # surface tension (Section 6): the curvature term of the dynamic rows
+    ("tension-31x11", lambda: W.make_problem(31, 11, -16, 16, 0, 10, 1.4, [W.Bump(0.1, 1.0, 1.0)], tau=0.1), 7),
+    ("tension-full-31x13", lambda: W.make_problem(31, 13, -10, 10, -6, 6, 1.2, [W.Bump(0.2, 1.0, 1.0, cy=1.5)],
+                                                  half_domain=False, tau=0.05), 8),
 ]
 
 

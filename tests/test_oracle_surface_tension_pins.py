@@ -115,3 +115,20 @@ def test_tau_change_of_discrete_linear_solution_converges_to_fourier():
 def test_fourier_pin_rejects_the_opposite_sign_of_the_tension_term():
     (e1, c1), (e2, c2) = _tau_change(-0.1)
     assert c2 < 0.0 and e2 > 1.0
+
+
+def test_preconditioner_with_tension_is_the_gravity_wave_one():
+    # P leaves the whole tension term to the Krylov solver: with tau it is P of the same
+    # problem without tau.  The reason: keeping -tau zeta*_xx in the slice block of (1,1)
+    # makes that lower-triangular block a recurrence with a growing mode.
+    mk = lambda tau: W.make_problem(31, 11, -16, 16, 0, 10, 1.4, [W.Bump(0.1, 1.0, 1.0)], tau=tau)
+    p, p0 = mk(0.1), mk(0.0)
+    hb = Lin.band_halfwidth(p.M)
+    P, P0 = Lin.banded(p, Lin.jacobian(p), hb), Lin.banded(p0, Lin.jacobian(p0), hb)
+    assert np.abs(P - P0).max() <= 1e-13 * np.abs(P0).max()
+    s = p.N + 1
+    slice0 = Lin.jacobian(p0)[s:2 * s, s:2 * s]
+    with_xx = slice0.copy()
+    with_xx[2:, :] -= p.tau * Lin.half_mesh_xx_map(p)[: p.N - 1, : s]
+    assert np.abs(np.linalg.inv(slice0)).max() < 1e4
+    assert np.abs(np.linalg.inv(with_xx)).max() > 1e15
