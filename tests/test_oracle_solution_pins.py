@@ -7,7 +7,7 @@
   (Section 3.2).
 * The spectrum of the nonlinear Jacobian at a flat-surface start, right
   preconditioned by the linear Jacobian J~, clusters tightly around 1, and
-  less tightly with the banded preconditioner P (Section 3.3 and its figure of
+  less tightly with the banded preconditioner P (Section 4.2 and its figure of
   eigenvalues: F = 0.6, bump height 0.1, delta = 0.5, 31 x 31 full mesh,
   dx = dy = 0.8).  The nonlinear Jacobian is formed by finite differences of
   the nonlinear residual, J~ from the linear system of Appendix B: two
