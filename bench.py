@@ -21,10 +21,12 @@ the solutions and, where a stored oracle solution of the same problem exists, to
 it) at F = 0.6, 0.7 and 1.4, at F = 0.7 on the domain extended upstream to
 x_1 = -40, and on a full domain with two offset bumps; the 64-instance batched
 sweep (one persistent all-pairs launch per lockstep round, each round one
-replayed HIP graph); and the CPU oracle timed on a bounded sample of the same
-workload on this host's cores.  The solver legs run before the timed residual
-steps (their GPU work brings the clocks up; the timed region is the K steps
-alone).
+replayed HIP graph); the exact linear solution of eq. (exactsoln) on the
+paper's 281 x 281 linear-solution meshes (its node contraction against the FP64
+matrix peak) and Newton from the start it gives; and the CPU oracle timed on a
+bounded sample of the same workload on this host's cores.  The solver legs run
+before the timed residual steps (their GPU work brings the clocks up; the timed
+region is the K steps alone).
 """
 import argparse
 import json
@@ -198,6 +200,76 @@ def two_bump_full_domain(W, N=151):
                           half_domain=False, name=f"two-bumps-full-{N}x{N}")
 
 
+PEAK_FP64_MATRIX = 78.6   # TFLOP/s, MI355X dense FP64 MFMA
+
+
+def exact_linear_legs(B, W, np, torch, reps=3):
+    """Exact linear solution of eq. (exactsoln) on the meshes of the paper's linear
+    solutions (Figs. 4(a,b), 5(a,b), 8(a,b): 281 x 281), zeta and zeta_x, with the
+    contraction kernel's time from HIP events on its stream; and Newton from the
+    start it gives against the discrete linear start on the 181 x 61 problem."""
+    import math
+    k06 = 1.0 / 0.36
+    for _ in range(100):  # root of k F^2 = tanh k at F = 0.6 (wavelength 2 pi / k): Newton from
+        # k = 1 / F^2, where k F^2 - tanh k > 0, decreases monotonically to it (convex for k > 0)
+        k06 -= (0.36 * k06 - math.tanh(k06)) / (0.36 - 1.0 / math.cosh(k06) ** 2)
+    lam = 2.0 * math.pi / k06
+    meshes = [("fig4-281x281-F0.6", 0.6, [(0.1, 0.5, 0.0, 0.0)], 281, 281, -7.0, 17.0, -12.0, 12.0),
+              ("fig5-281x281-F3", 3.0, [(0.1, 3.0, 0.0, 0.0)], 281, 281, -21.0, 51.0, -36.0, 36.0),
+              ("fig8-inline-281x281-F0.6", 0.6, [(0.1, 0.5, 0.0, 0.0), (0.1, 0.5, 4 * lam, 0.0)], 281, 281,
+               -7.0, 53.0, -30.0, 30.0)]
+    out = {"meshes": []}
+    for name, F, bumps, N, M, xlo, xhi, ylo, yhi in meshes:
+        dx, dy = (xhi - xlo) / (N - 1), (yhi - ylo) / (M - 1)
+        best = None
+        for _ in range(reps):
+            z, zx, info = B.exact_linear(F, bumps, N, M, xlo, dx, ylo, dy, config={"timing": 1})
+            if best is None or info["contract_ms"] < best["contract_ms"]:
+                best = info
+        flop = 4.0 * N * M * best["nodes"] * len(bumps)  # 2 outputs x one FMA per (target, node)
+        ach = flop / (best["contract_ms"] * 1e-3) / 1e12
+        out["meshes"].append({"name": name, "froude": F, "bumps": bumps, "mesh": f"{N}x{M}",
+                              "nodes": best["nodes"], "psi_nodes": best["psi_nodes"], "kcut": best["kcut"],
+                              "total_ms": best["total_ms"], "contract_ms": best["contract_ms"],
+                              "contract_tflops": ach, "contract_frac_fp64_matrix_peak": ach / PEAK_FP64_MATRIX,
+                              "max_abs_zeta": float(z.abs().max())})
+    # Newton from the exact linear solution's start against the discrete linear start
+    starts = []
+    for F in (1.4, 0.6):
+        p = W.working(F)
+        dp = B.DeviceProblem(p)
+        P = B.Preconditioner(dp, storage="fp64")
+        row = {"froude": F}
+        for kind in ("linear", "exact"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if kind == "linear":
+                u = B.linear_start(dp, P, rtol=1e-8, prec="fp64")
+            else:
+                z, zx, _ = B.exact_linear(F, [(0.2, 1.0 / math.sqrt(2.0), 0.0, 0.0)], p.N, p.M, p.x1, p.dx,
+                                          p.y1, p.dy)
+                u = B.exact_start(dp, z, zx)
+            torch.cuda.synchronize()
+            t_start = time.perf_counter() - t0
+            F0 = B.residual(dp, u, "fp64")
+            f0 = float(F0.abs().max())
+            t0 = time.perf_counter()
+            rep = B.solve(dp, u, P, ftol=1e-10, check=False, max_newton=15, inner_prec="fp64")
+            torch.cuda.synchronize()
+            row[kind] = {"start_ms": t_start * 1e3, "fnorm_inf_start": f0, "status": rep["status"],
+                         "newton": rep["newton_iters"], "gmres": rep["gmres_iters"],
+                         "solve_ms": (time.perf_counter() - t0) * 1e3}
+            row[kind + "_u"] = u.cpu().numpy()
+        if row["linear"]["status"] == 0 and row["exact"]["status"] == 0:
+            nb = (p.N + 1) * p.M
+            row["max_dzeta_x_between_solutions"] = float(np.abs(row["linear_u"][:nb] - row["exact_u"][:nb]).max())
+        del row["linear_u"], row["exact_u"]
+        P.close()
+        starts.append(row)
+    out["newton_from_exact_start_181x61"] = starts
+    return out
+
+
 def node_values(p, u, f):
     """f-th field at the nodes from u (trapezoidal x-integration of f_x from f_1)."""
     import numpy as np
@@ -216,6 +288,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution legs")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 64-instance batched sweep")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact linear solution legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="first run a plain elementwise copy of MB megabytes (reads MB, writes MB), "
                          "the reference for scaling hardware byte counters")
@@ -259,6 +332,8 @@ def main():
         sw["sweep"]["per_instance"] = [[r["name"], r["F"], r["status"], r["newton"], r["gmres"]]
                                        for r in sw["sweep"]["per_instance"]]
         extra["sweep"] = sw
+    if not args.no_exact:
+        extra["exact_linear"] = exact_linear_legs(B, W, np, torch)
 
     p = W.working(0.7)
     dp = B.DeviceProblem(p)

@@ -352,6 +352,74 @@ int bim_linear_start_ex(const bim_problem *prob, const bim_precond *P, double *u
 int bim_bottom_pressure(const bim_problem *prob, const double *u, double *pres, double *force, void *stream);
 
 /*
+ * Exact solution of the linear problem (Section 4.1, eq. (exactsoln)) for a
+ * topography that is a sum of Gaussian bumps of eq. (bottom),
+ *   beta + 1 = sum_b eps_b exp(-((x - b1_b)^2 + (y - b2_b)^2) / (2 delta_b^2)),
+ * evaluated on the mesh x_i = x1 + i dx (i < N), y_j = y1 + j dy (j < M).
+ * Each bump's solution is eq. (exactsoln) with its transform
+ * eps 2 pi delta^2 exp(-k^2 delta^2 / 2), shifted to its centre; the linear
+ * problem being linear in beta + 1, they add.  The k-path below the pole k_1 is
+ * the principal value plus the half-residue pi R sin(k_1 X) (the sign for which
+ * zeta vanishes upstream); the downstream wave H(x) is as printed.
+ * Quadrature: 16-point Gauss-Legendre panels in psi over (0, pi/2) (each node
+ * standing for +-psi) and in k over [0, K], K the root of
+ * k + k^2 delta^2 / 2 = decay for the widest transform; the pole at the centre
+ * of a symmetric panel; panels hold at most periods_per_panel periods of the
+ * oscillation at the mesh's largest |x - b1| + |y - b2|; geometric grading
+ * next to small poles and toward psi_0 = arccos(1/F) (F > 1).  Accuracy about
+ * 1e-15 (F < 1) to 1e-11 (F > 1) of eps with the defaults.  All node values and
+ * sums on the GPU (FP64; the contraction over nodes on the matrix cores); the
+ * host lays out the panel edges.
+ *   bumps: host array of nbumps (1..16); zeta: device [M][N] output (x
+ *   fastest); zeta_x: device [M][N] output of d zeta / dx, or NULL.
+ *   config: host, may be NULL (defaults); info: host, may be NULL.
+ * Errors: BIM_EDOMAIN for F not finite and positive, |F - 1| < 1e-3 (the linear
+ * solution is singular at F = 1), or a bump with delta <= 0 or non-finite
+ * values; BIM_EINVAL for bad sizes or pointers.  Uses stream-ordered scratch
+ * (node table, 8 (2 + nbumps) bytes per node, and per-chunk partial tiles of
+ * 64 KiB) and synchronises `stream` before it returns.
+ */
+typedef struct bim_bump {
+    double eps;    /* height (negative: a crater) */
+    double delta;  /* width, > 0 */
+    double b1, b2; /* centre */
+} bim_bump;
+
+typedef struct bim_exact_config {
+    double periods_per_panel; /* <= 0: 4 */
+    double decay;             /* <= 0: 36 (k-cutoff where the transform is exp(-decay) of its scale) */
+    double psi_width_max;     /* <= 0: 0.1 */
+    double grade_start;       /* <= 0: 1e-10 (first graded psi panel next to psi_0) */
+    int32_t workgroups;       /* <= 0: about 2048 for the contraction */
+    int32_t timing;           /* 1: time the contraction kernel and the whole call with HIP events */
+} bim_exact_config;
+
+typedef struct bim_exact_info {
+    int64_t nodes;      /* quadrature nodes (padded to 16 per kind) */
+    int32_t psi_nodes;  /* psi nodes over (0, pi/2) */
+    int32_t chunks;     /* node chunks of the contraction */
+    int32_t tiles;      /* 64 x 64 target tiles */
+    double kcut, hk;    /* k cutoff and k-panel width bound */
+    double contract_ms; /* with timing: the contraction kernel */
+    double total_ms;    /* with timing: the whole evaluation */
+} bim_exact_info;
+
+int bim_exact_linear(double froude, const bim_bump *bumps, int nbumps, int N, int M, double x1, double dx,
+                     double y1, double dy, double *zeta, double *zeta_x, const bim_exact_config *config,
+                     bim_exact_info *info, void *stream);
+
+/*
+ * A start for Newton from the exact linear solution on the problem's mesh (the
+ * mesh of bim_exact_linear's zeta, zeta_x): zeta_1 and zeta_x from it; phi_x =
+ * 1 - zeta / F^2 (the linear dynamic condition, eq. (linear_dynamic)) and phi_1
+ * from the radiation row F3; the bottom potential that of the uniform stream
+ * (psi_1 = x1, psi_x = 1).
+ *   zeta, zeta_x: device [M][N]; u_out: device [3(N+1)M].
+ */
+int bim_exact_start(const bim_problem *prob, const double *zeta, const double *zeta_x, double *u_out,
+                    void *stream);
+
+/*
  * F_i = F(u_i) for `count` problems (possibly of different mesh sizes) whose
  * all-pairs sums run in one persistent launch: the work items of all problems
  * form one list that every wave walks with a fixed stride, so each F_i is

@@ -42,6 +42,24 @@ class _Problem(ctypes.Structure):
                 ("tau", ctypes.c_double)]
 
 
+class Bump(ctypes.Structure):
+    """bim_bump: eps exp(-((x - b1)^2 + (y - b2)^2) / (2 delta^2)), eq. (bottom)."""
+    _fields_ = [("eps", ctypes.c_double), ("delta", ctypes.c_double), ("b1", ctypes.c_double),
+                ("b2", ctypes.c_double)]
+
+
+class ExactConfig(ctypes.Structure):
+    _fields_ = [("periods_per_panel", ctypes.c_double), ("decay", ctypes.c_double),
+                ("psi_width_max", ctypes.c_double), ("grade_start", ctypes.c_double),
+                ("workgroups", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+class ExactInfo(ctypes.Structure):
+    _fields_ = [("nodes", ctypes.c_int64), ("psi_nodes", ctypes.c_int32), ("chunks", ctypes.c_int32),
+                ("tiles", ctypes.c_int32), ("kcut", ctypes.c_double), ("hk", ctypes.c_double),
+                ("contract_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -54,6 +72,9 @@ def lib():
         L.bim_residual_linear.argtypes = [pp, vp, vp, i32, vp]
         L.bim_residual_noalloc.argtypes = [pp, vp, vp, i32, vp]
         L.bim_bottom_pressure.argtypes = [pp, vp, vp, vp, vp]
+        L.bim_exact_linear.argtypes = [dbl, ctypes.POINTER(Bump), i32, i32, i32, dbl, dbl, dbl, dbl, vp, vp,
+                                       ctypes.POINTER(ExactConfig), ctypes.POINTER(ExactInfo), vp]
+        L.bim_exact_start.argtypes = [pp, vp, vp, vp, vp]
         L.bim_residual_noalloc_max_bytes.argtypes = []
         L.bim_residual_noalloc_max_bytes.restype = ctypes.c_size_t
         L.bim_jv.argtypes = [pp, vp, vp, vp, dbl, vp, i32, vp]
@@ -204,6 +225,33 @@ def bottom_pressure(dp: DeviceProblem, u: torch.Tensor, stream=None):
     force = torch.empty(3, dtype=torch.float64, device=u.device)
     _check(lib().bim_bottom_pressure(dp.ref(), _dptr(u), pres.data_ptr(), force.data_ptr(), _stream(stream)))
     return pres, force
+
+
+def exact_linear(froude: float, bumps, N: int, M: int, x1: float, dx: float, y1: float, dy: float,
+                 derivative: bool = True, config: Optional[dict] = None, device="cuda", stream=None):
+    """bim_exact_linear: (zeta [M][N], zeta_x [M][N] or None, info dict) of eq. (exactsoln) for
+    bumps = [(eps, delta, b1, b2), ...] on the mesh x1 + i dx, y1 + j dy."""
+    arr = (Bump * len(bumps))(*[Bump(*map(float, b)) for b in bumps])
+    zeta = torch.empty((M, N), dtype=torch.float64, device=device)
+    zx = torch.empty((M, N), dtype=torch.float64, device=device) if derivative else None
+    cfg = ExactConfig(**(config or {}))
+    info = ExactInfo()
+    _check(lib().bim_exact_linear(float(froude), arr, len(bumps), int(N), int(M), float(x1), float(dx), float(y1),
+                                  float(dy), zeta.data_ptr(), zx.data_ptr() if zx is not None else None,
+                                  ctypes.byref(cfg), ctypes.byref(info), _stream(stream)))
+    return zeta, zx, {f: getattr(info, f) for f, _ in ExactInfo._fields_}
+
+
+def exact_start(dp: DeviceProblem, zeta: torch.Tensor, zeta_x: torch.Tensor, out: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """bim_exact_start: an unknown vector from the exact linear solution on dp's mesh."""
+    h = dp.host
+    if tuple(zeta.shape) != (h.M, h.N) or tuple(zeta_x.shape) != (h.M, h.N):
+        raise ValueError("zeta and zeta_x must be [M][N] on the problem's mesh")
+    u = out if out is not None else torch.empty(dp.n, dtype=torch.float64, device=dp.device)
+    _check(lib().bim_exact_start(dp.ref(), _dptr(zeta), _dptr(zeta_x), _dptr(u),
+                                 _stream(stream)))
+    return u
 
 
 def residual_noalloc_max_bytes() -> int:

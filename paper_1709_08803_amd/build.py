@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbim.so")
-SOURCES = ["api.hip", "batch.hip", "dense.hip", "jfnk.hip", "jfnk_batched.hip", "learned.hip", "precond.hip", "pressure.hip", "residual.hip", "tune.hip", "vec.hip"]
+SOURCES = ["api.hip", "batch.hip", "dense.hip", "exact.hip", "jfnk.hip", "jfnk_batched.hip", "learned.hip", "precond.hip", "pressure.hip", "residual.hip", "tune.hip", "vec.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1,0 +1,136 @@
+"""GPU exact linear solution (eq. (exactsoln), Section 4.1) through the C ABI
+against the oracle's adaptive quadrature: sampled nodes of the paper's 281 x 281
+linear solutions and of the working problem (values written by
+tests/golden/make_exact_linear.py from oracle/ only), every node the oracle can
+afford on a ragged mesh of several 64 x 64 tiles, and the degenerate cases."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fourier as Fo
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::scipy.integrate.IntegrationWarning")]
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_exact_linear.json")
+
+
+@pytest.fixture(scope="module")
+def bim():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_1709_08803_amd import bim as B
+    B.lib()
+    return B
+
+
+def _cases():
+    with open(GOLDEN) as f:
+        return json.load(f)["cases"]
+
+
+# The quadrature is accurate to ~1e-15 of eps for F < 1 and ~1e-11 for F > 1
+# (graded panels at psi_0); the oracle's adaptive quadrature to ~1e-10 of its
+# values.  Bound: 1e-9 of max |zeta| (resp. |zeta_x|) over the samples.
+TOL = 1e-9
+
+
+@pytest.mark.parametrize("c", _cases(), ids=[c["name"] for c in _cases()])
+def test_exact_linear_matches_oracle_at_sampled_nodes(bim, c):
+    z, zx, info = bim.exact_linear(c["froude"], c["bumps"], c["N"], c["M"], c["x1"], c["dx"], c["y1"], c["dy"])
+    torch.cuda.synchronize()
+    i, j = np.array(c["i"]), np.array(c["j"])
+    zg, zxg = z.cpu().numpy()[j, i], zx.cpu().numpy()[j, i]
+    ez = np.abs(zg - np.array(c["zeta"])).max() / np.abs(c["zeta"]).max()
+    ex = np.abs(zxg - np.array(c["zeta_x"])).max() / np.abs(c["zeta_x"]).max()
+    print(f"{c['name']}: nodes {info['nodes']} psi {info['psi_nodes']} rel err zeta {ez:.2e} zeta_x {ex:.2e}")
+    assert ez <= TOL and ex <= TOL
+    assert torch.isfinite(z).all() and torch.isfinite(zx).all()
+
+
+def test_exact_linear_every_affordable_node_ragged_tiles(bim):
+    # 70 x 67 nodes: 2 x 2 tiles of 64 with ragged tails; the oracle evaluates a
+    # seeded sample of nodes from every tile (including both tails) plus the bump centre
+    F, bumps = 0.7, [(0.05, 0.6, 1.3, -0.9)]
+    N, M, x1, dx, y1, dy = 70, 67, -6.0, 0.25, -8.0, 0.25
+    z, zx, _ = bim.exact_linear(F, bumps, N, M, x1, dx, y1, dy)
+    rng = np.random.default_rng(11)
+    pts = {(0, 0), (N - 1, M - 1), (63, 63), (64, 64), (69, 0), (0, 66), (int(round((1.3 - x1) / dx)), 28)}
+    for ti in (0, 1):
+        for tj in (0, 1):
+            while sum(1 for (a, b) in pts if a // 64 == ti and b // 64 == tj) < 6:
+                pts.add((int(rng.integers(64 * ti, min(N, 64 * ti + 64))), int(rng.integers(64 * tj, min(M, 64 * tj + 64)))))
+    pts = sorted(pts)
+    xs = [x1 + a * dx for a, _ in pts]
+    ys = [y1 + b * dy for _, b in pts]
+    ref = Fo.exact_solution(F, bumps, xs, ys, 0)
+    refx = Fo.exact_solution(F, bumps, xs, ys, 1)
+    zz, zzx = z.cpu().numpy(), zx.cpu().numpy()
+    g = np.array([zz[b, a] for a, b in pts])
+    gx = np.array([zzx[b, a] for a, b in pts])
+    assert np.abs(g - ref).max() <= TOL * np.abs(ref).max()
+    assert np.abs(gx - refx).max() <= TOL * np.abs(refx).max()
+
+
+def test_exact_linear_degenerate_meshes_and_bump_centre(bim):
+    # one row, one column, one node, each exactly on the bump centre (|x - b1| = 0, H(0) = 1/2)
+    F, bumps = 0.6, [(0.1, 0.5, 0.0, 0.0)]
+    ref0 = Fo.exact_solution(F, bumps, [0.0], [0.0], 0)[0]
+    refx0 = Fo.exact_solution(F, bumps, [0.0], [0.0], 1)[0]
+    for N, M, x1, y1 in ((1, 1, 0.0, 0.0), (5, 1, -1.0, 0.0), (1, 7, 0.0, -1.5)):
+        z, zx, _ = bim.exact_linear(F, bumps, N, M, x1, 0.5, y1, 0.5)
+        zz, zzx = z.cpu().numpy(), zx.cpu().numpy()
+        jc, ic = int(round(-y1 / 0.5)), int(round(-x1 / 0.5))
+        assert abs(zz[jc, ic] - ref0) <= TOL * abs(ref0)
+        assert abs(zzx[jc, ic] - refx0) <= TOL * max(abs(refx0), abs(ref0))
+
+
+def test_exact_linear_is_linear_in_the_bumps_and_deterministic(bim):
+    F, N, M, x1, dx, y1, dy = 0.8, 90, 40, -10.0, 0.3, 0.0, 0.3
+    b1, b2 = (0.1, 0.7, 0.0, 2.0), (-0.05, 1.1, 3.0, -1.0)
+    za, zxa, _ = bim.exact_linear(F, [b1], N, M, x1, dx, y1, dy)
+    zb, zxb, _ = bim.exact_linear(F, [b2], N, M, x1, dx, y1, dy)
+    zab, zxab, _ = bim.exact_linear(F, [b1, b2], N, M, x1, dx, y1, dy)
+    zab2, _, _ = bim.exact_linear(F, [b1, b2], N, M, x1, dx, y1, dy)
+    assert torch.equal(zab, zab2)
+    scale = float((za.abs().max() + zb.abs().max()))
+    assert float((zab - za - zb).abs().max()) <= 1e-13 * scale
+    assert float((zxab - zxa - zxb).abs().max()) <= 1e-13 * float(zxa.abs().max() + zxb.abs().max())
+    # a crater of the opposite height is the mirror image
+    zc, _, _ = bim.exact_linear(F, [(-0.1, 0.7, 0.0, 2.0)], N, M, x1, dx, y1, dy)
+    assert float((zc + za).abs().max()) <= 1e-15 * float(za.abs().max())
+    # without zeta_x
+    zo, none, _ = bim.exact_linear(F, [b1], N, M, x1, dx, y1, dy, derivative=False)
+    assert none is None and torch.equal(zo, za)
+
+
+def test_exact_linear_rejects_bad_input(bim):
+    good = [(0.1, 0.5, 0.0, 0.0)]
+    for F, bumps in ((1.0, good), (1.0005, good), (0.0, good), (float("nan"), good), (0.6, []),
+                     (0.6, [(0.1, 0.0, 0.0, 0.0)]), (0.6, [(0.1, -1.0, 0.0, 0.0)]),
+                     (0.6, [(float("inf"), 0.5, 0.0, 0.0)]), (0.6, good * 17)):
+        with pytest.raises(bim.BimError):
+            bim.exact_linear(F, bumps, 8, 8, -1.0, 0.25, -1.0, 0.25)
+    with pytest.raises(bim.BimError):
+        bim.exact_linear(0.6, good, 8, 8, -1.0, 0.0, -1.0, 0.25)
+
+
+def test_exact_start_assembles_the_linear_unknowns(bim):
+    from paper_1709_08803_amd import workloads as W
+    from oracle import residual as R
+    p = W.working(0.7, N=61, M=21)
+    dp = bim.DeviceProblem(p)
+    z, zx, _ = bim.exact_linear(p.froude, [(0.2, 1 / math.sqrt(2.0), 0.0, 0.0)], p.N, p.M, p.x1, p.dx, p.y1, p.dy)
+    u = bim.exact_start(dp, z, zx).cpu().numpy()
+    nf = R.reconstruct(p, u)
+    s = p.N + 1
+    zc, zxc = z.cpu().numpy(), zx.cpu().numpy()
+    assert np.array_equal(nf.zeta_x, zxc) and np.array_equal(nf.zeta[:, 0], zc[:, 0])
+    assert np.allclose(nf.phi_x, 1.0 - zc / p.froude ** 2, rtol=0, atol=1e-15)
+    assert np.all(u[2 * s * p.M:].reshape(p.M, s)[:, 1:] == 1.0)
+    # F3: x1 (phi_x,1 - 1) + n (phi_1 - x1) = 0
+    phx1, phi1 = nf.phi_x[:, 0], nf.phi[:, 0]
+    assert np.abs(p.x1 * (phx1 - 1.0) + p.n_decay * (phi1 - p.x1)).max() <= 1e-13
