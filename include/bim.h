@@ -44,7 +44,10 @@ enum {
     BIM_ENOMEM = -3,   /* device allocation failed */
     BIM_EDOMAIN = -4,  /* non-finite input, or a value outside the method's domain */
     BIM_NOT_CONVERGED = 1,
-    BIM_LINESEARCH_FAIL = 2
+    BIM_LINESEARCH_FAIL = 2,
+    BIM_UNPHYSICAL = 3  /* solver: the last iterate rises above the limiting height F^2/2
+                           (Bernoulli's equation with a stagnant crest; not checked with surface
+                           tension) or the surface reaches the bottom (zeta - beta <= 0) */
 };
 
 /* Precision of the all-pairs boundary-integral sums (the rest is always FP64). */
@@ -293,6 +296,8 @@ typedef struct bim_jfnk_report {
     double time_ms;               /* wall time of the call, preconditioner setup included */
     double precond_ms;            /* preconditioner setup time (0 if one was passed) */
     double history[64];
+    double max_zeta;              /* largest node elevation of the last iterate */
+    double min_depth;             /* smallest zeta - beta over the nodes of the last iterate */
 } bim_jfnk_report;
 
 void jfnk_default_opts(bim_jfnk_opts *opts);
@@ -309,7 +314,9 @@ void jfnk_default_opts(bim_jfnk_opts *opts);
  * Synchronises `stream` repeatedly (the host takes the Newton and Krylov
  * decisions).  Returns BIM_OK when ||F||_inf <= ftol, BIM_NOT_CONVERGED after
  * max_newton steps (or on the stall stop), BIM_LINESEARCH_FAIL when no step
- * length decreases ||F||, BIM_EDOMAIN on a non-finite residual.
+ * length decreases ||F||, BIM_EDOMAIN on a non-finite residual, and
+ * BIM_UNPHYSICAL (in place of any of the first three) when the last iterate
+ * rises above F^2/2 or reaches the bottom (rep->max_zeta, rep->min_depth).
  */
 int jfnk_solve(const bim_problem *prob, const bim_precond *P, double *u, const bim_jfnk_opts *opts,
                bim_jfnk_report *rep, void *stream);

@@ -164,7 +164,8 @@ class JfnkReport(ctypes.Structure):
                 ("residual_evals", ctypes.c_int32), ("inner_residual_evals", ctypes.c_int32),
                 ("jv_evals", ctypes.c_int32), ("backtracks", ctypes.c_int32), ("fnorm_inf", ctypes.c_double),
                 ("fnorm0_inf", ctypes.c_double), ("gmres_relres_last", ctypes.c_double), ("time_ms", ctypes.c_double),
-                ("precond_ms", ctypes.c_double), ("history", ctypes.c_double * 64)]
+                ("precond_ms", ctypes.c_double), ("history", ctypes.c_double * 64),
+                ("max_zeta", ctypes.c_double), ("min_depth", ctypes.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "history"}

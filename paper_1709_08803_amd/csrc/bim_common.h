@@ -25,6 +25,13 @@ int hip_check(hipError_t e, const char *what);
 // Validates a problem description; returns BIM_OK or BIM_EINVAL with a message.
 int validate(const bim_problem *p);
 
+// Largest node elevation max zeta and smallest depth min (zeta - beta) of the
+// iterate u into out[0..1] (device); rows: device scratch of 2 M doubles.
+int surface_extent_enqueue(const bim_problem *p, const double *u, double *rows, double *out, hipStream_t s);
+// BIM_UNPHYSICAL when max_zeta exceeds the limiting height F^2 / 2 (checked
+// without surface tension only) or min_depth <= 0, else BIM_OK.
+int physical_status(const bim_problem *p, double max_zeta, double min_depth);
+
 // Sizes derived from (N, M).
 struct Dims {
     int N, M, nimg;

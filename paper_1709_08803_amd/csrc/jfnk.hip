@@ -20,6 +20,76 @@ namespace bim {
 
 namespace {
 
+// Largest node elevation of the surface and smallest depth zeta - beta on each
+// mesh row of the iterate u: zeta at the nodes is zeta_1 plus the trapezoidal
+// x-integral of zeta_x (one wave per row, 64-wide scans).
+__global__ __launch_bounds__(64) void k_surface_extent_rows(const double *__restrict__ u,
+                                                            const double *__restrict__ beta, int N, int M,
+                                                            double dx, double *__restrict__ rows) {
+    const int j = blockIdx.x, lane = threadIdx.x;
+    const double *s = u + (size_t)j * (N + 1);  // [zeta_1, zeta_x(1..N)]
+    const double hdx = 0.5 * dx;
+    double run = s[0], zmax = -INFINITY, dmin = INFINITY;
+    for (int base = 0; base < N; base += 64) {
+        const int i = base + lane;
+        double inc = (i > 0 && i < N) ? hdx * (s[i] + s[i + 1]) : 0.0;
+        for (int d = 1; d < 64; d <<= 1) {
+            const double t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        if (i < N) {
+            const double z = run + inc;
+            zmax = fmax(zmax, z);
+            dmin = fmin(dmin, z - beta[(size_t)j * N + i]);
+        }
+        run += __shfl(inc, 63, 64);
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        zmax = fmax(zmax, __shfl_xor(zmax, d, 64));
+        dmin = fmin(dmin, __shfl_xor(dmin, d, 64));
+    }
+    if (lane == 0) {
+        rows[j] = zmax;
+        rows[M + j] = dmin;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_surface_extent_reduce(const double *__restrict__ rows, int M,
+                                                              double *__restrict__ out) {
+    const int lane = threadIdx.x;
+    double zmax = -INFINITY, dmin = INFINITY;
+    for (int j = lane; j < M; j += 64) {
+        zmax = fmax(zmax, rows[j]);
+        dmin = fmin(dmin, rows[M + j]);
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        zmax = fmax(zmax, __shfl_xor(zmax, d, 64));
+        dmin = fmin(dmin, __shfl_xor(dmin, d, 64));
+    }
+    if (lane == 0) {
+        out[0] = zmax;
+        out[1] = dmin;
+    }
+}
+
+}  // namespace
+
+int surface_extent_enqueue(const bim_problem *p, const double *u, double *rows, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_surface_extent_rows, dim3(p->M), dim3(64), 0, s, u, p->beta, p->N, p->M, p->dx, rows);
+    hipLaunchKernelGGL(k_surface_extent_reduce, dim3(1), dim3(64), 0, s, rows, p->M, out);
+    return hip_check(hipGetLastError(), "surface extent launch");
+}
+
+int physical_status(const bim_problem *p, double max_zeta, double min_depth) {
+    // Bernoulli on the surface: zeta / F^2 = 1/2 - |grad Phi|^2 / 2 <= 1/2 without surface
+    // tension, so no steady surface rises above F^2 / 2; the fluid depth zeta - beta must
+    // stay positive
+    const bool crest = p->tau == 0.0 && max_zeta > 0.5 * p->froude * p->froude * (1.0 + 1e-12);
+    return (crest || !(min_depth > 0.0)) ? BIM_UNPHYSICAL : BIM_OK;
+}
+
+namespace {
+
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct Workspace {
@@ -308,6 +378,20 @@ int solve_impl(const bim_problem *p, const bim_precond *P, double *u_io, const b
     bim_jfnk_report R{};
     R.precond_ms = precond_ms;
     auto finish = [&](int status) {
+        if (!linear_start_only && status >= BIM_OK && (size_t)2 * d.M <= (size_t)reduce_parts() * (m + 1)) {
+            // the extent of the last iterate (the caller's u)
+            if (surface_extent_enqueue(p, u_io, K.part, K.scal + 6, s) == BIM_OK &&
+                hip_check(hipMemcpyAsync(hhost, K.scal + 6, sizeof(double) * 2, hipMemcpyDeviceToHost, s),
+                          "copy") == BIM_OK &&
+                hip_check(hipStreamSynchronize(s), "sync") == BIM_OK) {
+                R.max_zeta = hhost[0];
+                R.min_depth = hhost[1];
+                if (physical_status(p, R.max_zeta, R.min_depth) != BIM_OK) {
+                    status = fail(BIM_UNPHYSICAL, "the iterate rises above the limiting height F^2/2 or "
+                                                  "reaches the bottom");
+                }
+            }
+        }
         R.status = status;
         R.jv_evals = K.jv_evals;
         R.time_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

@@ -620,6 +620,22 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         }
         if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
     }
+    // the extent of every instance's last iterate (largest elevation, smallest depth)
+    std::vector<double> ext(2 * (size_t)count, 0.0);
+    for (int i = 0; i < count; ++i)
+        if (I[i].R.status >= BIM_OK && (size_t)2 * I[i].p->M <= (size_t)kBRedBlocks * (m + 1)) {
+            if ((rc = surface_extent_enqueue(I[i].p, I[i].u, I[i].part, I[i].scal + 6, s))) return rc;
+            if ((rc = hip_check(hipMemcpyAsync(&ext[2 * (size_t)i], I[i].scal + 6, sizeof(double) * 2,
+                                               hipMemcpyDeviceToHost, s), "copy")))
+                return rc;
+        }
+    if ((rc = hip_check(hipStreamSynchronize(s), "hipStreamSynchronize"))) return rc;
+    for (int i = 0; i < count; ++i)
+        if (I[i].R.status >= BIM_OK && (size_t)2 * I[i].p->M <= (size_t)kBRedBlocks * (m + 1)) {
+            I[i].R.max_zeta = ext[2 * (size_t)i];
+            I[i].R.min_depth = ext[2 * (size_t)i + 1];
+            if (physical_status(I[i].p, I[i].R.max_zeta, I[i].R.min_depth) != BIM_OK) I[i].R.status = BIM_UNPHYSICAL;
+        }
     const double tot = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     int worst_err = 0, worst_soft = 0;
     for (int i = 0; i < count; ++i) {

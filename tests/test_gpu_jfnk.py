@@ -63,6 +63,9 @@ def test_converged_solution_matches_oracle(bim, F, inner, tol):
     assert dz <= tol and dphi <= 10 * tol
     # the oracle agrees that the GPU solution solves the discrete system
     assert np.abs(R.residual(p, uh)).max() < 1e-10
+    # the reported extent of the solution: its largest elevation and smallest depth
+    assert abs(rep["max_zeta"] - z_ref.zeta.max()) <= 1e-8
+    assert abs(rep["min_depth"] - (z_ref.zeta - p.beta).min()) <= 1e-8
 
 
 def test_solver_reports_nonconvergence_and_bad_input(bim):
@@ -75,6 +78,30 @@ def test_solver_reports_nonconvergence_and_bad_input(bim):
     bad[5] = float("nan")
     rep = bim.solve(dp, bad, check=False)
     assert rep["status"] == -4  # BIM_EDOMAIN
+
+
+def test_solver_flags_unphysical_iterates(bim):
+    # iterates above the limiting height F^2 / 2, or reaching the bottom, are reported as
+    # BIM_UNPHYSICAL (3) with their extent, in place of the convergence status
+    p = W.tiny(0.7)
+    dp = bim.DeviceProblem(p)
+    u = bim.linear_start(dp)
+    s = p.N + 1
+    for shift, what in ((p.froude ** 2, "crest"), (-2.0, "bottom")):
+        v = u.clone()
+        v.view(3, p.M, s)[0, :, 0] += shift  # zeta_1 of every row: the whole surface moves
+        rep = bim.solve(dp, v, max_newton=0, check=False)
+        print(what, rep["status"], rep["max_zeta"], rep["min_depth"])
+        assert rep["status"] == 3
+        if what == "crest":
+            assert rep["max_zeta"] > 0.5 * p.froude ** 2
+        else:
+            assert rep["min_depth"] <= 0.0
+    # the batched solver reports the same per instance
+    v = u.clone()
+    v.view(3, p.M, s)[0, :, 0] += p.froude ** 2
+    rc, reps = bim.solve_batched([dp, dp], [u.clone(), v], max_newton=0, check=False)
+    assert [r["status"] for r in reps] == [1, 3] and rc == 3
 
 
 def test_unpreconditioned_gmres_needs_more_iterations(bim):
