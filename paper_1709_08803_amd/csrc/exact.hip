@@ -120,10 +120,24 @@ __device__ inline double bump_tr(const Bumps &bs, int b, double k) {
     return bs.eps[b] * 2.0 * kPi * d2 * exp(-0.5 * k * k * d2);
 }
 
+// The rotation factors of one node: cos and sin of a dx and of b dy (stepping the
+// operands' phases from one mesh row or column to the next).
+__device__ __forceinline__ void rot_factors(double a, double b, double dx, double dy, long q, double *__restrict__ rot,
+                                            long qpad) {
+    double s1, c1, s2, c2;
+    sincos(a * dx, &s1, &c1);
+    sincos(b * dy, &s2, &c2);
+    rot[q] = c1;
+    rot[qpad + q] = s1;
+    rot[2 * qpad + q] = c2;
+    rot[3 * qpad + q] = s2;
+}
+
 __global__ __launch_bounds__(64) void k_exact_nodes(const PsiNode *__restrict__ pn, GL16 gl, Bumps bs, double F,
                                                     double K, double hk, long q1off, long q2off, long qpad,
-                                                    double *__restrict__ na, double *__restrict__ nb,
-                                                    double *__restrict__ nw) {
+                                                    double dx, double dy, double *__restrict__ na,
+                                                    double *__restrict__ nb, double *__restrict__ nw,
+                                                    double *__restrict__ rot) {
     const PsiNode P = pn[blockIdx.x];
     const double c = cos(P.psi), s = sin(P.psi), sec2 = 1.0 / (c * c), F2 = F * F;
     const bool pole = P.type == 0;
@@ -179,6 +193,7 @@ __global__ __launch_bounds__(64) void k_exact_nodes(const PsiNode *__restrict__ 
         const long q = P.off + t;
         na[q] = k * c;
         nb[q] = k * s;
+        rot_factors(k * c, k * s, dx, dy, q, rot, qpad);
         for (int b = 0; b < bs.n; ++b) nw[b * qpad + q] = base * bump_tr(bs, b, k);
     }
     if (pole && threadIdx.x == 0) {
@@ -187,6 +202,8 @@ __global__ __launch_bounds__(64) void k_exact_nodes(const PsiNode *__restrict__ 
         const long q1 = q1off + P.pole, q2 = q2off + P.pole;
         na[q1] = na[q2] = k1 * c;
         nb[q1] = nb[q2] = k1 * s;
+        rot_factors(k1 * c, k1 * s, dx, dy, q1, rot, qpad);
+        rot_factors(k1 * c, k1 * s, dx, dy, q2, rot, qpad);
         for (int b = 0; b < bs.n; ++b) {
             const double bt = bump_tr(bs, b, k1);
             nw[b * qpad + q1] = scale * kPi * R * bt;
@@ -203,13 +220,94 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // MFMA operand layout (v_mfma_f64_16x16x4): lane l holds A[l % 16][l / 16]
 // and B[l / 16][l % 16]; the result block holds D[l / 16 + 4 r][l % 16] in
 // element r of lane l (rows interleaved, unlike the FP32 16x16x4 form).
+// Software pipeline, one barrier per step: while the matrix cores multiply
+// step st out of one LDS buffer, the waves generate step st + 1 into the other
+// from node data loaded during step st - 1.
+// Operand generation: thread t takes node gq = t / 16 of the step and the four
+// consecutive rows (and columns) 4 (t % 16) .. + 3 of the tile: one sincos at the
+// first row, then three rotations by exp(+-i a dx) (the sign of the step of |xi|),
+// the same for the columns with exp(i b dy); rows on both sides of the bump
+// centre (|xi| not monotone) take a sincos each.
+struct NodeData {
+    double a, b, w, ca, sa, cb, sb;
+};
+
+__device__ __forceinline__ void load_node(const double *__restrict__ na, const double *__restrict__ nb,
+                                          const double *__restrict__ nw, const double *__restrict__ rot, long qpad,
+                                          long sq, long st, int gq, NodeData &nd) {
+    const int bump = (int)(st / sq);
+    const long q = (st - (long)bump * sq) * kStep + gq;
+    nd.a = na[q];
+    nd.b = nb[q];
+    nd.w = nw[(long)bump * qpad + q];
+    nd.ca = rot[q];
+    nd.sa = rot[qpad + q];
+    nd.cb = rot[2 * qpad + q];
+    nd.sb = rot[3 * qpad + q];
+}
+
+__device__ __forceinline__ void gen_step(const NodeData &nd, const Bumps &bs, long sq, long st, long q1off,
+                                         long q2off, double x0, double y0, double dx, double dy, int gq, int r0,
+                                         double (*sL)[kLds], double (*sLx)[kLds], double (*sR)[kLds]) {
+    const int b = (int)(st / sq);
+    const long q0 = (st - (long)b * sq) * kStep;
+    const int kind = q0 < q1off ? 0 : (q0 < q2off ? 1 : 2);
+    const double xi0 = x0 - bs.b1[b], eta0 = y0 - bs.b2[b];
+    const double a = nd.a, w = nd.w;
+    double sn[4], cs[4];
+    if (xi0 >= 0.0 || xi0 + 3.0 * dx <= 0.0) {
+        // |xi| = |xi0| +- r dx on all four rows
+        const double dir = xi0 >= 0.0 ? 1.0 : -1.0;
+        const double sa = dir * nd.sa;
+        sincos(a * fabs(xi0), &sn[0], &cs[0]);
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            cs[r] = cs[r - 1] * nd.ca - sn[r - 1] * sa;
+            sn[r] = sn[r - 1] * nd.ca + cs[r - 1] * sa;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sincos(a * fabs(xi0 + r * dx), &sn[r], &cs[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double xi = xi0 + r * dx;
+        const double sg = (xi > 0.0) ? 1.0 : (xi < 0.0 ? -1.0 : 0.0);
+        double f, fx;
+        if (kind == 0) {
+            f = cs[r];
+            fx = -a * sg * sn[r];
+        } else if (kind == 1) {
+            f = sn[r];
+            fx = a * sg * cs[r];
+        } else {  // a |xi| = a xi wherever H(xi) != 0
+            const double H = (xi > 0.0) ? 1.0 : (xi == 0.0 ? 0.5 : 0.0);
+            f = -H * sn[r];
+            fx = -H * a * cs[r];
+        }
+        sL[gq][r0 + r] = w * f;
+        sLx[gq][r0 + r] = w * fx;
+    }
+    double sy, cy;
+    sincos(nd.b * eta0, &sy, &cy);
+    sR[gq][r0] = cy;
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const double c2 = cy * nd.cb - sy * nd.sb;
+        sy = sy * nd.cb + cy * nd.sb;
+        cy = c2;
+        sR[gq][r0 + r] = cy;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_exact_contract(const double *__restrict__ na,
                                                         const double *__restrict__ nb,
-                                                        const double *__restrict__ nw, long qpad, long q1off,
+                                                        const double *__restrict__ nw,
+                                                        const double *__restrict__ rot, long qpad, long q1off,
                                                         long q2off, Bumps bs, double x1, double dx, double y1,
                                                         double dy, int tiles_i, long steps_total,
                                                         long steps_per_chunk, double *__restrict__ part) {
-    __shared__ double sL[kStep][kLds], sLx[kStep][kLds], sR[kStep][kLds];
+    __shared__ double sL[2][kStep][kLds], sLx[2][kStep][kLds], sR[2][kStep][kLds];
     const int tile = blockIdx.x, chunk = blockIdx.y;
     const int ti = tile % tiles_i, tj = tile / tiles_i;
     const int t = threadIdx.x, lane = t & 63;
@@ -222,58 +320,47 @@ __global__ __launch_bounds__(256) void k_exact_contract(const double *__restrict
     const long sq = qpad / kStep;  // steps per bump
     const long s0 = (long)chunk * steps_per_chunk;
     const long s1 = s0 + steps_per_chunk < steps_total ? s0 + steps_per_chunk : steps_total;
-    const int gq = wave * 4;  // this wave generates nodes gq .. gq + 3 of each step
-    const double xg = x1 + (double)(ti * kTile + lane) * dx;
-    const double yg = y1 + (double)(tj * kTile + lane) * dy;
-    for (long st = s0; st < s1; ++st) {
-        const int b = (int)(st / sq);
-        const long q0 = (st - (long)b * sq) * kStep;
-        const double xi = xg - bs.b1[b], eta = yg - bs.b2[b];
-        const double ax = fabs(xi);
-        const double sg = (xi > 0.0) ? 1.0 : (xi < 0.0 ? -1.0 : 0.0);
-        const double H = (xi > 0.0) ? 1.0 : (xi == 0.0 ? 0.5 : 0.0);
-        const int kind = q0 < q1off ? 0 : (q0 < q2off ? 1 : 2);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const long q = q0 + gq + u;
-            const double a = na[q], bq = nb[q], w = nw[(long)b * qpad + q];
-            double sn, cs;
-            sincos(a * ax, &sn, &cs);
-            double f, fx;
-            if (kind == 0) {
-                f = cs;
-                fx = -a * sg * sn;
-            } else if (kind == 1) {
-                f = sn;
-                fx = a * sg * cs;
-            } else {  // a |xi| = a xi wherever H(xi) != 0
-                f = -H * sn;
-                fx = -H * a * cs;
-            }
-            sL[gq + u][lane] = w * f;
-            sLx[gq + u][lane] = w * fx;
-            sR[gq + u][lane] = cos(bq * eta);
-        }
+    const int gq = t >> 4, r0 = 4 * (t & 15);  // generation: node gq, rows / columns r0 .. r0 + 3
+    const double x0 = x1 + (double)(ti * kTile + r0) * dx;
+    const double y0 = y1 + (double)(tj * kTile + r0) * dy;
+    if (s0 < s1) {
+        NodeData nd;
+        load_node(na, nb, nw, rot, qpad, sq, s0, gq, nd);
+        gen_step(nd, bs, sq, s0, q1off, q2off, x0, y0, dx, dy, gq, r0, sL[0], sLx[0], sR[0]);
+        if (s0 + 1 < s1) load_node(na, nb, nw, rot, qpad, sq, s0 + 1, gq, nd);
         __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < kStep / 4; ++ks) {
-            const int kk = 4 * ks + (lane >> 4), r16 = lane & 15;
-            double A0[2], A1[2], B[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                A0[h] = sL[kk][32 * ih + 16 * h + r16];
-                A1[h] = sLx[kk][32 * ih + 16 * h + r16];
-                B[h] = sR[kk][32 * jh + 16 * h + r16];
+        int cur = 0;
+        for (long st = s0; st < s1; ++st) {
+            if (st + 1 < s1) {
+                gen_step(nd, bs, sq, st + 1, q1off, q2off, x0, y0, dx, dy, gq, r0, sL[cur ^ 1], sLx[cur ^ 1],
+                         sR[cur ^ 1]);
+                if (st + 2 < s1) load_node(na, nb, nw, rot, qpad, sq, st + 2, gq, nd);
             }
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+            for (int ks = 0; ks < kStep / 4; ++ks) {
+                const int kk = 4 * ks + (lane >> 4), r16 = lane & 15;
+                double A0[2], A1[2], B[2];
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    acc[0][bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(A0[bi], B[bj], acc[0][bi][bj], 0, 0, 0);
-                    acc[1][bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(A1[bi], B[bj], acc[1][bi][bj], 0, 0, 0);
+                for (int h = 0; h < 2; ++h) {
+                    A0[h] = sL[cur][kk][32 * ih + 16 * h + r16];
+                    A1[h] = sLx[cur][kk][32 * ih + 16 * h + r16];
+                    B[h] = sR[cur][kk][32 * jh + 16 * h + r16];
                 }
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj) {
+                        acc[0][bi][bj] =
+                            __builtin_amdgcn_mfma_f64_16x16x4f64(A0[bi], B[bj], acc[0][bi][bj], 0, 0, 0);
+                        acc[1][bi][bj] =
+                            __builtin_amdgcn_mfma_f64_16x16x4f64(A1[bi], B[bj], acc[1][bi][bj], 0, 0, 0);
+                    }
+            }
+            // one barrier: buffer cur ^ 1 is complete for the next step, and every
+            // wave is done reading buffer cur before it is overwritten at st + 2
+            __syncthreads();
+            cur ^= 1;
         }
-        __syncthreads();
     }
     // partial tile, [out][j local][i local]
     double *pt = part + ((long)chunk * gridDim.x + tile) * 2 * kTile * kTile;
@@ -546,26 +633,27 @@ extern "C" int bim_exact_linear(double froude, const bim_bump *bumps, int nbumps
     const size_t npsi = L.psi.size();
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t b_psi = al(sizeof(PsiNode) * npsi), b_n = al(sizeof(double) * L.qpad),
-                 b_w = al(sizeof(double) * L.qpad * nbumps),
+                 b_w = al(sizeof(double) * L.qpad * nbumps), b_rot = al(sizeof(double) * 4 * L.qpad),
                  b_part = al(sizeof(double) * (size_t)chunks * tiles * 2 * kTile * kTile);
     hipStream_t s = (hipStream_t)stream;
     char *ws = nullptr;
-    if ((rc = hip_check(hipMallocAsync((void **)&ws, b_psi + 2 * b_n + b_w + b_part, s), "hipMallocAsync")))
+    if ((rc = hip_check(hipMallocAsync((void **)&ws, b_psi + 2 * b_n + b_w + b_rot + b_part, s), "hipMallocAsync")))
         return rc;
     PsiNode *d_psi = (PsiNode *)ws;
     double *na = (double *)(ws + b_psi), *nb_ = (double *)(ws + b_psi + b_n), *nw = (double *)(ws + b_psi + 2 * b_n);
-    double *part = (double *)(ws + b_psi + 2 * b_n + b_w);
+    double *rot = (double *)(ws + b_psi + 2 * b_n + b_w);
+    double *part = (double *)(ws + b_psi + 2 * b_n + b_w + b_rot);
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     rc = [&]() -> int {
         if (cfg.timing)
             for (auto &e : ev) BIM_HIP(hipEventCreate(&e));
         if (cfg.timing) BIM_HIP(hipEventRecord(ev[0], s));
         BIM_HIP(hipMemcpyAsync(d_psi, L.psi.data(), sizeof(PsiNode) * npsi, hipMemcpyHostToDevice, s));
-        BIM_HIP(hipMemsetAsync(na, 0, 2 * b_n + b_w, s));  // padding nodes: a = b = W = 0
+        BIM_HIP(hipMemsetAsync(na, 0, 2 * b_n + b_w + b_rot, s));  // padding nodes: a = b = W = 0
         hipLaunchKernelGGL(k_exact_nodes, dim3((unsigned)npsi), dim3(64), 0, s, d_psi, gauss_legendre16(), bs,
-                           froude, L.K, L.hk, L.q1off, L.q2off, L.qpad, na, nb_, nw);
+                           froude, L.K, L.hk, L.q1off, L.q2off, L.qpad, dx, dy, na, nb_, nw, rot);
         if (cfg.timing) BIM_HIP(hipEventRecord(ev[1], s));
-        hipLaunchKernelGGL(k_exact_contract, dim3(tiles, (unsigned)chunks), dim3(256), 0, s, na, nb_, nw, L.qpad,
+        hipLaunchKernelGGL(k_exact_contract, dim3(tiles, (unsigned)chunks), dim3(256), 0, s, na, nb_, nw, rot, L.qpad,
                            L.q1off, L.q2off, bs, x1, dx, y1, dy, tiles_i, steps_total, spc, part);
         if (cfg.timing) BIM_HIP(hipEventRecord(ev[2], s));
         const long outs = 2L * N * M;
