@@ -14,6 +14,13 @@ struct GemmItemT {
 };
 using GemmItem = GemmItemT<double>;
 using GemmItemF = GemmItemT<float>;
+// One product over nkb K-blocks at fixed strides: C = alpha sum_b A_b B_b + beta C.
+struct GemmKItem {
+    const double *A;
+    const double *B;
+    double *C;
+    long nkb;
+};
 // One matrix of a batched inversion: Ainv = A^-1 (s x s, row-major).
 struct InvItem {
     const double *A;
@@ -25,6 +32,10 @@ struct InvItem {
 // items_dev: device array of `batch` items; all share m, n, k and leading dims.
 int gemm_enqueue(const GemmItem *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
                  double alpha, double beta, hipStream_t s);
+// C = alpha sum_{b < nkb} (A + b sA)(B + b sB) + beta C per item (every A_b
+// m x k with leading dim lda, B_b k x n with ldb); nkb may differ per item.
+int gemm_kblocks_enqueue(const GemmKItem *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
+                         long sA, long sB, double alpha, double beta, hipStream_t s);
 // The same product in FP32 (FP32 operands, FP32 accumulation on the matrix
 // cores) for 128 < m <= 192 only (BIM_EINVAL otherwise).
 int gemm_f32_enqueue(const GemmItemF *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,

@@ -130,6 +130,106 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
             }
 }
 
+// C = alpha sum_{b < it.nkb} A_b B_b + beta C, with A_b = A + b sA and
+// B_b = B + b sB (each m x k, k x n, row-major): one product of K = nkb k whose
+// K-blocks lie at fixed strides, as a block row of a slice-banded matrix times
+// a block column of another.  The same 64 x 64 tiles and MFMA layout as k_gemm;
+// the accumulator stays in registers over all nkb blocks, so C is read and
+// written once instead of once per block.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_kblocks(
+    const GemmKItem *__restrict__ items, int m, int n, int k, int lda, int ldb, int ldc, long sA, long sB,
+    double alpha, double beta) {
+    const GemmKItem it = items[blockIdx.z];
+    const GlobalPtr<const double> A = (GlobalPtr<const double>)it.A;
+    const GlobalPtr<const double> B = (GlobalPtr<const double>)it.B;
+    const GlobalPtr<double> C = (GlobalPtr<double>)it.C;
+    const int K = it.nkb * k;
+    __shared__ double As[TM][TK + 1];
+    __shared__ double Bs[TK][TN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+    const int li = lane & 15, lk = lane >> 4;
+    double ra[8], rb[8];
+    // global K index g -> block g / k, column g % k; loads at clamped indices as in
+    // k_gemm, the rows of B past K zeroed when staged
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + q * 256;
+            const int ar = e >> 5, ac = e & 31;
+            const int ga = min(k0 + ac, K - 1), ba = ga / k;
+            ra[q] = A[(size_t)ba * sA + (size_t)min(row0 + ar, m - 1) * lda + (ga - ba * k)];
+            const int br = e >> 6, bc = e & 63;
+            const int gb = min(k0 + br, K - 1), bb = gb / k;
+            rb[q] = B[(size_t)bb * sB + (size_t)(gb - bb * k) * ldb + min(col0 + bc, n - 1)];
+        }
+    };
+    auto store = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + q * 256;
+            As[e >> 5][e & 31] = ra[q];
+            Bs[e >> 6][e & 63] = (k0 + (e >> 6) < K) ? rb[q] : 0.0;
+        }
+    };
+    double4_t acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) acc[t][u] = double4_t{0.0, 0.0, 0.0, 0.0};
+    if (K > 0) {
+        load(0);
+        store(0);
+    }
+    const bool rmw = beta != 0.0;
+    double cv[2][2][4];
+    if (rmw) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int gr = row0 + wm + 16 * t + lk + 4 * v, gc = col0 + wn + 16 * u + li;
+                    cv[t][u][v] = C[(size_t)min(gr, m - 1) * ldc + min(gc, n - 1)];
+                }
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < K; k0 += TK) {
+        const bool more = k0 + TK < K;
+        if (more) load(k0 + TK);
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 4) {
+            double a[2], b[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                a[t] = As[wm + 16 * t + li][kk + lk];
+                b[t] = Bs[kk + lk][wn + 16 * t + li];
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int u = 0; u < 2; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
+        }
+        __syncthreads();
+        if (more) {
+            store(k0 + TK);
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gr = row0 + wm + 16 * t + lk + 4 * v, gc = col0 + wn + 16 * u + li;
+                if (gr < m && gc < n)
+                    C[(size_t)gr * ldc + gc] = rmw ? fma(alpha, acc[t][u][v], beta * cv[t][u][v]) : alpha * acc[t][u][v];
+            }
+}
+
 // The same product for 128 < m <= 192 (the preconditioner's block rows, m = s):
 // one workgroup holds all m rows of a TN-column panel, so that the workgroup
 // count cdiv(n, TN) can be matched to the 256 compute units (a 64 x 64 tiling
@@ -729,6 +829,15 @@ int gemm_enqueue(const GemmItem *items_dev, int batch, int m, int n, int k, int 
             hipLaunchKernelGGL((k_gemm_tall<64, NW>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
                                alpha, beta);
     }
+    return hip_check(hipGetLastError(), "gemm launch");
+}
+
+int gemm_kblocks_enqueue(const GemmKItem *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
+                         long sA, long sB, double alpha, double beta, hipStream_t s) {
+    if (batch <= 0 || m <= 0 || n <= 0) return BIM_OK;
+    if (batch > 65535) return fail(BIM_EINVAL, "gemm batch too large");
+    dim3 grid(cdiv(n, TN), cdiv(m, TM), batch);
+    hipLaunchKernelGGL(k_gemm_kblocks, grid, dim3(256), 0, s, items_dev, m, n, k, lda, ldb, ldc, sA, sB, alpha, beta);
     return hip_check(hipGetLastError(), "gemm launch");
 }
 

@@ -309,6 +309,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                           (size_t)M * (w2 * w2 + w2 + 2) + 3 * (size_t)M + 16;
     addt(sizeof(GemmItem) * nitems);
     addt(sizeof(InvItem) * (M + 4));
+    addt(sizeof(GemmKItem) * (size_t)M * (2 * w2 + 1));
     void *tbase = nullptr;
     rc = hip_check(hipMallocAsync(&tbase, tmp, st), "hipMallocAsync(preconditioner setup)");
     if (rc) {
@@ -335,6 +336,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     int *info = ta.take<int>(M + 2);
     GemmItem *items_dev = ta.take<GemmItem>(nitems);
     InvItem *inv_dev = ta.take<InvItem>(M + 4);
+    GemmKItem *kitems_dev = ta.take<GemmKItem>((size_t)M * (2 * w2 + 1));
 
     std::vector<GemmItem> items;
     items.reserve(nitems);
@@ -404,18 +406,18 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         gemm(b1, s, s, s, s, s, s, -1.0, 1.0);  // T := T - B31 E   (T pre-filled with B23)
         gemm(b2, s, s, s, s, s, s, 1.0, 0.0);   // G := Dinv22 T
         gemm(bS1, s, s, s, s, s, s, -1.0, 1.0); // S := S - B21 E   (S pre-filled with D22 on the diagonal)
-        for (int dq = -h; dq <= h; ++dq) {
-            std::vector<GemmItem> bq;
-            for (int l = 0; l < M; ++l) {
-                const int q = l + dq;
-                if (q < 0 || q >= M) continue;
-                for (int m = std::max(0, q - h); m <= std::min(M - 1, q + h); ++m)
-                    bq.push_back({band_blk(pc->B23, h, s, l, q), band_blk(pc->G, h, s, q, m),
-                                  band_blk(S, w2, s, l, m)});
-            }
-            gemm(bq, s, s, s, s, s, s, -1.0, 1.0);
-        }
     }
+    // S[l][m] -= sum_q B23[l][q] G[q][m] over q in [max(0, l-h, m-h), min(M-1, l+h, m+h)]: one
+    // product per output block with the q-blocks as K (consecutive q: the next block of row l of
+    // B23, s^2 further; the same column m of G one band row down, 2h s^2 further)
+    std::vector<GemmKItem> kitems;
+    for (int l = 0; l < M; ++l)
+        for (int m = std::max(0, l - w2); m <= std::min(M - 1, l + w2); ++m) {
+            const int q0 = std::max(0, std::max(l - h, m - h)), q1 = std::min(M - 1, std::min(l + h, m + h));
+            if (q0 <= q1)
+                kitems.push_back({band_blk(pc->B23, h, s, l, q0), band_blk(pc->G, h, s, q0, m), band_blk(S, w2, s, l, m),
+                                  (long)(q1 - q0 + 1)});
+        }
     // block LU of S (band 2h): per step l, L[q][l] = S[q][l] Uinv[l] (into Lrow), then
     // S[q][m] -= L[q][l] S[l][m] for q, m in l+1..l+2h
     std::vector<size_t> lu_ops_first(M), lu_ops_count(M);
@@ -444,6 +446,9 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                   "copy"));
     RUN(hip_check(hipMemcpyAsync(inv_dev, invs.data(), sizeof(InvItem) * invs.size(), hipMemcpyHostToDevice, st),
                   "copy"));
+    RUN(hip_check(hipMemcpyAsync(kitems_dev, kitems.data(), sizeof(GemmKItem) * kitems.size(), hipMemcpyHostToDevice,
+                                 st),
+                  "copy"));
     {
         auto run_op = [&](const Op &o) {
             return gemm_enqueue(items_dev + o.first, o.count, o.m, o.nn, o.k, o.lda, o.ldb, o.ldc, o.alpha, o.beta,
@@ -459,6 +464,8 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         const long bs = (long)s * s, brow = (long)(2 * w2 + 1) * bs;  // one block; one block row of S
         RUN(copy_blocks_enqueue(D22, 0, 0, s, band_blk(S, w2, s, 0, 0), brow, 0, s, s, s, M, 1, M, st));
         for (size_t q = 1; q < lu_ops_first[0]; ++q) RUN(run_op(ops[q]));
+        RUN(gemm_kblocks_enqueue(kitems_dev, (int)kitems.size(), s, s, s, s, s, s, (long)s * s, (long)2 * h * s * s,
+                                 -1.0, 1.0, st));
         // zero L/U row buffers (short rows at the ends stay zero)
         RUN(hip_check(hipMemsetAsync(Lrow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));
         RUN(hip_check(hipMemsetAsync(Urow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));

@@ -79,11 +79,15 @@ def test_precond_rejects_bad_band(bim):
         bim.Preconditioner(dp, p.M)
 
 
-def test_fp32_storage_is_the_fp64_operator_rounded(bim):
-    """FP32 storage: the same factored operator rounded to FP32 (half the bytes);
-    at 181 x 61 its apply still solves the banded system P z = r of the oracle's
-    banded product, next to the FP64 one, to FP32 rounding amplified by the
-    conditioning of the Schur complement."""
+def test_fp32_storage_operator_solves_the_banded_system(bim):
+    """FP32 storage (half the bytes): the block elimination and block LU of P in
+    FP64, then, for pivot blocks of 128 < s <= 192, both substitutions that form
+    the dense Schur inverse S^-1 in FP32 on FP32 copies of the FP64 factors, and
+    the other arrays the apply reads rounded to FP32.  So it is not the FP64
+    operator rounded: part of the factorisation runs in FP32.  At 181 x 61 its
+    apply still solves the banded system P z = r of the oracle's banded product,
+    next to the FP64 one, to FP32 rounding amplified by the conditioning of the
+    Schur complement (the FP32 substitutions add ~1e-6, far below that)."""
     p = W.working(0.7)
     dp = bim.DeviceProblem(p)
     r = np.random.default_rng(6).standard_normal(p.n_unknowns)
