@@ -42,6 +42,26 @@ int gemm_f32_enqueue(const GemmItemF *items_dev, int batch, int m, int n, int k,
                      double alpha, double beta, hipStream_t s);
 // work: device scratch of batch * s * 2s doubles; info[b] = 0 or (1 + column of a zero pivot).
 int invert_enqueue(const InvItem *items_dev, int batch, int s_dim, double *work, int *info, hipStream_t s);
+
+// Inversion of one s x s block with 192 < s <= 384 as a 2 x 2 block matrix:
+// the leading 192 x 192 block A11 and the Schur complement A22 - A21 A11^-1 A12
+// by the register Gauss-Jordan kernel (partial pivoting within each), the rest
+// by MFMA products:  B22 = (A22 - A21 T)^-1 with T = A11^-1 A12,
+// B21 = -B22 A21 A11^-1, B12 = -T B22, B11 = A11^-1 - T B21.  (No pivoting
+// across the split: A11 must be invertible on its own, as the blocks of the
+// preconditioner's elimination are.)  The plan is built on the host, copied to
+// device memory, then enqueued; inversions of one stream run in order and may
+// share `scratch`.
+struct SplitInv {
+    InvItem inv11, invS;
+    GemmItem T, Sc, W, B21, B12, B11;
+};
+bool split_invert_applies(int s_dim);
+// scratch: device, at least split_invert_scratch(s) doubles (T, W and the Schur complement)
+size_t split_invert_scratch(int s_dim);
+void split_invert_plan(const InvItem &item, int s_dim, double *scratch, SplitInv *plan);
+// plan_dev: a device copy of plan; info: two ints (zero-pivot flags of the two inversions)
+int split_invert_enqueue(const SplitInv &plan, const SplitInv *plan_dev, int s_dim, int *info, hipStream_t s);
 // y = alpha A x + beta c (dense, rows x cols, row-major with leading dim lda); c may equal y.
 // A in FP64 or FP32 (products and sums in FP64).
 int gemv_enqueue(const double *A, long lda, const double *x, const double *c, double *y, int rows, int cols,

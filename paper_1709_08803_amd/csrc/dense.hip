@@ -851,6 +851,50 @@ int invert_enqueue(const InvItem *items_dev, int batch, int s_dim, double *work,
     return hip_check(hipGetLastError(), "invert launch");
 }
 
+constexpr int kSplitS1 = kRegMaxS;
+
+bool split_invert_applies(int s_dim) { return s_dim > kRegMaxS && s_dim <= 2 * kRegMaxS; }
+
+size_t split_invert_scratch(int s_dim) {
+    const size_t r = (size_t)std::max(0, s_dim - kSplitS1);
+    return 2 * (size_t)kSplitS1 * r + r * r;
+}
+
+void split_invert_plan(const InvItem &it, int s_dim, double *scratch, SplitInv *P) {
+    const int s1 = kSplitS1, r = s_dim - s1;
+    const double *A = it.A;
+    const long lda = it.lda, ldx = it.ldinv;
+    double *X = it.Ainv;
+    double *T = scratch, *W = scratch + (size_t)s1 * r, *Sc = W + (size_t)r * s1;
+    double *X22 = X + (size_t)s1 * ldx + s1, *X21 = X + (size_t)s1 * ldx, *X12 = X + s1;
+    P->inv11 = {A, lda, X, ldx};                  // A11^-1 into the leading block of X
+    P->T = {X, A + s1, T};                        // T = A11^-1 A12           (s1 x r)
+    P->Sc = {A + (size_t)s1 * lda, T, Sc};        // Sc = A22 - A21 T         (r x r; Sc holds A22)
+    P->invS = {Sc, r, X22, ldx};                  // B22 = Sc^-1
+    P->W = {A + (size_t)s1 * lda, X, W};          // W = A21 A11^-1           (r x s1)
+    P->B21 = {X22, W, X21};                       // B21 = -B22 W
+    P->B12 = {T, X22, X12};                       // B12 = -T B22
+    P->B11 = {T, X21, X};                         // B11 = A11^-1 - T B21
+}
+
+int split_invert_enqueue(const SplitInv &P, const SplitInv *D, int s_dim, int *info, hipStream_t st) {
+    if (!split_invert_applies(s_dim)) return fail(BIM_EINVAL, "split inversion needs 192 < s <= 384");
+    const int s1 = kSplitS1, r = s_dim - s1;
+    const int lda = (int)P.inv11.lda, ldx = (int)P.inv11.ldinv;
+    int rc;
+    hipLaunchKernelGGL(k_invert_reg, dim3(1), dim3(kRegThreads), 0, st, &D->inv11, s1, info);
+    if ((rc = gemm_enqueue(&D->T, 1, s1, r, s1, ldx, lda, r, 1.0, 0.0, st))) return rc;
+    if ((rc = copy2d_enqueue(P.inv11.A + (size_t)s1 * lda + s1, lda, const_cast<double *>(P.invS.A), r, r, r, st)))
+        return rc;
+    if ((rc = gemm_enqueue(&D->Sc, 1, r, r, s1, lda, r, r, -1.0, 1.0, st))) return rc;
+    hipLaunchKernelGGL(k_invert_reg, dim3(1), dim3(kRegThreads), 0, st, &D->invS, r, info + 1);
+    if ((rc = gemm_enqueue(&D->W, 1, r, s1, s1, lda, ldx, s1, 1.0, 0.0, st))) return rc;
+    if ((rc = gemm_enqueue(&D->B21, 1, r, s1, r, ldx, s1, ldx, -1.0, 0.0, st))) return rc;
+    if ((rc = gemm_enqueue(&D->B12, 1, s1, r, r, r, ldx, ldx, -1.0, 0.0, st))) return rc;
+    if ((rc = gemm_enqueue(&D->B11, 1, s1, s1, r, r, ldx, ldx, -1.0, 1.0, st))) return rc;
+    return hip_check(hipGetLastError(), "split inversion launch");
+}
+
 namespace {
 template <typename TA>
 int gemv_launch(const TA *A, long lda, const double *x, const double *c, double *y, int rows, int cols,

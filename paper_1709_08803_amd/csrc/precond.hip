@@ -304,7 +304,8 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     if (storage == BIM_STORE_FP32) addt(sizeof(float) * (size_t)M * s * w2 * s);  // L rows in FP32
     addt(sizeof(double) * (size_t)s * n);           // one block row of S^-1 (temp)
     addt(sizeof(double) * (size_t)4 * s * 2 * s);   // inversion work
-    addt(sizeof(int) * (M + 2));                    // info
+    addt(sizeof(int) * 3 * (M + 2));                // info (2 more per block for split inversions)
+    addt(sizeof(SplitInv) * (M + 2));               // split-inversion plans (192 < s <= 384)
     const size_t nitems = 64 + (size_t)M * (2 * h + 1) * 4 + (size_t)M * (2 * w2 + 1) * (2 * h + 3) +
                           (size_t)M * (w2 * w2 + w2 + 2) + 3 * (size_t)M + 16;
     addt(sizeof(GemmItem) * nitems);
@@ -333,7 +334,9 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     float *L32 = (storage == BIM_STORE_FP32) ? ta.take<float>((size_t)M * s * w2 * s) : nullptr;
     double *rowtmp = ta.take<double>((size_t)s * n);
     double *invwork = ta.take<double>((size_t)4 * s * 2 * s);
-    int *info = ta.take<int>(M + 2);
+    int *info = ta.take<int>(3 * (M + 2));
+    SplitInv *plans_dev = ta.take<SplitInv>(M + 2);
+
     GemmItem *items_dev = ta.take<GemmItem>(nitems);
     InvItem *inv_dev = ta.take<InvItem>(M + 4);
     GemmKItem *kitems_dev = ta.take<GemmKItem>((size_t)M * (2 * w2 + 1));
@@ -341,6 +344,25 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     std::vector<GemmItem> items;
     items.reserve(nitems);
     std::vector<InvItem> invs;
+    const bool split = split_invert_applies(s);
+    std::vector<SplitInv> plans;
+    // inversions first .. first + count - 1 of `invs` (their items already on the device)
+    auto invert_range = [&](int first, int count) -> int {
+        if (!split) return invert_enqueue(inv_dev + first, count, s, invwork, info + first, st);
+        for (int i = first; i < first + count; ++i)
+            if (int q = split_invert_enqueue(plans[i], plans_dev + i, s, info + (M + 2) + 2 * i, st)) return q;
+        return BIM_OK;
+    };
+    // plans of invs[first ..] (sharing the inversion scratch), copied to the device
+    auto plan_range = [&](int first) -> int {
+        if (!split) return BIM_OK;
+        if (split_invert_scratch(s) > (size_t)4 * s * 2 * s) return fail(BIM_EINVAL, "split inversion scratch");
+        plans.resize(invs.size());
+        for (size_t i = first; i < invs.size(); ++i) split_invert_plan(invs[i], s, invwork, &plans[i]);
+        return hip_check(hipMemcpyAsync(plans_dev + first, plans.data() + first, sizeof(SplitInv) * (invs.size() - first),
+                                        hipMemcpyHostToDevice, st),
+                         "copy");
+    };
     struct Op {
         int kind;  // 0 gemm, 1 invert, 2 copy rows
         size_t first;
@@ -368,7 +390,8 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     invs.push_back({D11, s, Dinv11, s});
     invs.push_back({D22, s, Dinv22, s});
     RUN(hip_check(hipMemcpyAsync(inv_dev, invs.data(), sizeof(InvItem) * 2, hipMemcpyHostToDevice, st), "copy"));
-    RUN(invert_enqueue(inv_dev, 2, s, invwork, info, st));
+    RUN(plan_range(0));
+    RUN(invert_range(0, 2));
     hipLaunchKernelGGL(k_replicate, dim3(cdiv((long)M * s * s, 256)), dim3(256), 0, st, Dinv11, pc->Dinv11, M,
                        (long)s * s);
     hipLaunchKernelGGL(k_replicate, dim3(cdiv((long)M * s * s, 256)), dim3(256), 0, st, Dinv22, pc->Dinv22, M,
@@ -446,6 +469,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                   "copy"));
     RUN(hip_check(hipMemcpyAsync(inv_dev, invs.data(), sizeof(InvItem) * invs.size(), hipMemcpyHostToDevice, st),
                   "copy"));
+    RUN(plan_range(2));
     RUN(hip_check(hipMemcpyAsync(kitems_dev, kitems.data(), sizeof(GemmKItem) * kitems.size(), hipMemcpyHostToDevice,
                                  st),
                   "copy"));
@@ -470,7 +494,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         RUN(hip_check(hipMemsetAsync(Lrow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));
         RUN(hip_check(hipMemsetAsync(Urow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));
         for (int l = 0; l < M; ++l) {
-            RUN(invert_enqueue(inv_dev + 2 + l, 1, s, invwork, info + 2 + l, st));
+            RUN(invert_range(2 + l, 1));
             for (size_t q = 0; q < lu_ops_count[l]; ++q) RUN(run_op(ops[lu_ops_first[l] + q]));
         }
         // U rows: U[l][m] for m = l+1..l+2h packed as [l][s][2h s] (block j = m - l - 1,
@@ -568,12 +592,14 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
             }
         }
         // a zero pivot in any inverted block makes P singular in this factorisation
-        std::vector<int> hinfo(2 + M, 0);
-        RUN(hip_check(hipMemcpyAsync(hinfo.data(), info, sizeof(int) * (2 + M), hipMemcpyDeviceToHost, st),
+        std::vector<int> hinfo(3 * (2 + M), 0);
+        RUN(hip_check(hipMemcpyAsync(hinfo.data(), info, sizeof(int) * 3 * (2 + M), hipMemcpyDeviceToHost, st),
                       "copy"));
         RUN(hip_check(hipStreamSynchronize(st), "hipStreamSynchronize"));
-        for (int q = 0; q < 2 + M; ++q)
-            if (hinfo[q]) return fail(BIM_EDOMAIN, "preconditioner: singular diagonal block " + std::to_string(q));
+        for (int q = 0; q < 2 + M; ++q) {
+            const bool bad = split ? (hinfo[(M + 2) + 2 * q] || hinfo[(M + 2) + 2 * q + 1]) : hinfo[q] != 0;
+            if (bad) return fail(BIM_EDOMAIN, "preconditioner: singular diagonal block " + std::to_string(q));
+        }
     }
     return BIM_OK;
     }();

@@ -31,8 +31,13 @@ CASES = [
     ("tension-full-31x13", lambda: W.make_problem(31, 13, -10, 10, -6, 6, 1.2, [], half_domain=False, tau=0.05), 1),
     # pivot blocks of s = N + 1 = 192, the largest the register inversion holds
     ("max-block-191x5-h1", lambda: W.make_problem(191, 5, -20, 20, 0, 1, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 1),
-    # s = 193: the augmented-matrix Gauss-Jordan kernel for blocks beyond that
-    ("big-block-192x5-h1", lambda: W.make_problem(192, 5, -20, 20, 0, 1, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 1),
+    # s = 193, 212, 300: blocks beyond the register kernel, inverted as 2 x 2 block matrices
+    # (the leading 192 block and the Schur complement in registers, the rest on the matrix cores)
+    ("split-block-192x5-h1", lambda: W.make_problem(192, 5, -20, 20, 0, 1, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 1),
+    ("split-block-211x5-h1", lambda: W.make_problem(211, 5, -40, 30, 0, 1, 0.7, [W.Bump(0.2, 1.0, 1.0)]), 1),
+    ("split-block-299x5-h2", lambda: W.make_problem(299, 5, -30, 30, 0, 2, 1.2, [W.Bump(0.2, 1.0, 1.0)]), 2),
+    # s = 385: the augmented-matrix Gauss-Jordan kernel beyond that
+    ("big-block-384x5-h1", lambda: W.make_problem(384, 5, -40, 40, 0, 1, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 1),
 ]
 
 
@@ -52,7 +57,9 @@ def test_precond_apply_matches_oracle_solve(bim, name, mk, hb):
         torch.cuda.synchronize()
         err = np.abs(z.cpu().numpy() - z_ref).max() / np.abs(z_ref).max()
         print(name, "precond rel err", err)
-        assert err <= 1e-10
+        # the diagonal blocks' conditioning grows with N (their trapezoidal x-integration
+        # recurrences): 1e-9 for the 385-wide blocks, 1e-10 up to 300
+        assert err <= (1e-10 if p.N + 1 <= 300 else 1e-9)
     P.close()
 
 
