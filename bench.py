@@ -23,8 +23,10 @@ x_1 = -40, and on a full domain with two offset bumps; the 64-instance batched
 sweep (one persistent all-pairs launch per lockstep round, each round one
 replayed HIP graph); the exact linear solution of eq. (exactsoln) on the
 paper's 281 x 281 linear-solution meshes (its node contraction against the FP64
-matrix peak) and Newton from the start it gives; and the CPU oracle timed on a
-bounded sample of the same workload on this host's cores.  The solver legs run
+matrix peak) and Newton from the start it gives; the learned start at 121 x 41
+(trained in the run on a few hundred sweep problems) against the linear start;
+and the CPU oracle timed on a bounded sample of the same workload on this
+host's cores.  The solver legs run
 before the timed residual steps (their GPU work brings the clocks up; the timed
 region is the K steps alone).
 """
@@ -203,7 +205,7 @@ def two_bump_full_domain(W, N=151):
 PEAK_FP64_MATRIX = 78.6   # TFLOP/s, MI355X dense FP64 MFMA
 
 
-def exact_linear_legs(B, W, np, torch, reps=3):
+def exact_linear_legs(B, W, np, torch, reps=3, starts=True):
     """Exact linear solution of eq. (exactsoln) on the meshes of the paper's linear
     solutions (Figs. 4(a,b), 5(a,b), 8(a,b): 281 x 281), zeta and zeta_x, with the
     contraction kernel's time from HIP events on its stream; and Newton from the
@@ -233,6 +235,8 @@ def exact_linear_legs(B, W, np, torch, reps=3):
                               "total_ms": best["total_ms"], "contract_ms": best["contract_ms"],
                               "contract_tflops": ach, "contract_frac_fp64_matrix_peak": ach / PEAK_FP64_MATRIX,
                               "max_abs_zeta": float(z.abs().max())})
+    if not starts:
+        return out
     # Newton from the exact linear solution's start against the discrete linear start
     starts = []
     for F in (1.4, 0.6):
@@ -270,6 +274,17 @@ def exact_linear_legs(B, W, np, torch, reps=3):
     return out
 
 
+def learned_leg(n_train=384, n_test=16, epochs=100, hidden=512):
+    """The learned start at 121 x 41 (M = (N-1)/3 + 1): a network trained in this
+    run on n_train problems of the seeded sweep (their converged FP64 solutions
+    from the batched solver), then Newton from the learned start against Newton
+    from the discrete linear start on n_test held-out problems (a learned attempt
+    that has not converged in 8 steps falls back to the linear start, its cost
+    charged to the learned side).  Reported whether it gains or loses."""
+    from paper_1709_08803_amd import learned_start as LS
+    return LS.experiment(121, n_train, n_test, epochs, hidden=hidden, log=lambda m: None)
+
+
 def node_values(p, u, f):
     """f-th field at the nodes from u (trapezoidal x-integration of f_x from f_1)."""
     import numpy as np
@@ -289,6 +304,7 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-solution legs")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 64-instance batched sweep")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact linear solution legs")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-start leg (trains a network, ~1 min)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="first run a plain elementwise copy of MB megabytes (reads MB, writes MB), "
                          "the reference for scaling hardware byte counters")
@@ -315,25 +331,39 @@ def main():
     # solver legs first: they are reported as well, and the seconds of GPU work
     # they take bring the GPU to its steady clocks before the residual is timed
     extra = {}
+    t_start = time.perf_counter()
+
+    def progress(what):  # one line per finished leg on stderr (the JSON line stays alone on stdout)
+        print(f"[bench] {what} done at {time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
     if not args.no_solve:
-        extra["time_to_solution"] = [time_to_solution(B, W, np, torch, f) for f in (0.6, 0.7, 1.4)]
+        extra["time_to_solution"] = []
+        for f in (0.6, 0.7, 1.4):
+            extra["time_to_solution"].append(time_to_solution(B, W, np, torch, f))
+            progress(f"time to solution at F = {f}")
         gold = os.path.join(HERE, "tests", "golden", "working_211x61_F0.7.npz")
         extra["time_to_solution_extended_domain"] = dict(
             workload="F = 0.7 on x in [-40, 30], y in [0, 20] (211 x 61, same spacing and bump)",
             **time_to_solution(B, W, np, torch, 0.7, problem=extended_domain(W), golden=gold))
+        progress("extended domain")
         pf = two_bump_full_domain(W)
         extra["time_to_solution_full_domain"] = dict(
             workload="two offset bumps (10, 10), (0, -10), height 0.2, delta 0.5, F = 0.6, full domain "
                      "x in [-7, 53], y in [-30, 30], 151 x 151",
             pairs_per_eval=pf.pairs_per_eval(), **time_to_solution(B, W, np, torch, 0.6, problem=pf))
+        progress("full domain")
     if not args.no_sweep:
         from paper_1709_08803_amd import sweep as SW
         sw = SW.run(64, 0, "fp32c")
         sw["sweep"]["per_instance"] = [[r["name"], r["F"], r["status"], r["newton"], r["gmres"]]
                                        for r in sw["sweep"]["per_instance"]]
         extra["sweep"] = sw
+        progress("sweep")
     if not args.no_exact:
-        extra["exact_linear"] = exact_linear_legs(B, W, np, torch)
+        extra["exact_linear"] = exact_linear_legs(B, W, np, torch, starts=not args.no_solve)
+        progress("exact linear solution")
+    if not args.no_solve and not args.no_learned:
+        extra["learned_start_121x41"] = learned_leg()
+        progress("learned start")
 
     p = W.working(0.7)
     dp = B.DeviceProblem(p)
@@ -387,8 +417,10 @@ def main():
         "residual_evals_per_s": 1e3 / ms_step,
     }
     out.update(extra)
+    progress("timed residual steps")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, u_host)
+        progress("CPU baseline")
     print(json.dumps(out))
 
 
