@@ -159,6 +159,29 @@ def test_full_size_solution_matches_stored_oracle_solution(bim, inner, tol, stor
     P.close()
 
 
+@pytest.mark.parametrize("inner,tol,storage,lin", [("fp64", 1e-9, "fp64", "fp64"), ("fp32c", 1e-8, "fp32", "fp32c")],
+                         ids=["fp64", "mixed-fp32-storage"])
+def test_froude_07_on_the_domain_extended_upstream_matches_the_oracle(bim, inner, tol, storage, lin):
+    # F = 0.7 has no solution on x in [-30, 30] at 181 x 61 (a fold of the truncated
+    # problem); on x in [-40, 30] at the same spacing (211 x 61, pivot blocks of 212 for
+    # the split inversion) it converges, to the oracle's stored solution
+    p = W.make_problem(211, 61, -40.0, 30.0, 0.0, 20.0, 0.7, [W.Bump(0.2, 1.0, 1.0)])
+    ref = np.load(f"{GOLDEN}/working_211x61_F0.7.npz")["u"]
+    dp = bim.DeviceProblem(p)
+    P = bim.Preconditioner(dp, storage=storage)
+    u = bim.linear_start(dp, P, rtol=1e-4 if lin == "fp32c" else 0.0, prec=lin)
+    rep = bim.solve(dp, u, P, ftol=1e-11, inner_prec=inner)
+    print(inner, {k: rep[k] for k in ("status", "newton_iters", "gmres_iters", "fnorm_inf", "time_ms")})
+    assert rep["status"] == 0
+    uh = u.cpu().numpy()
+    z_gpu, z_ref = R.reconstruct(p, uh), R.reconstruct(p, ref)
+    dz = np.abs(z_gpu.zeta - z_ref.zeta).max()
+    dphi = np.abs(z_gpu.phi - z_ref.phi).max()
+    print("max |dzeta|", dz, "max |dphi|", dphi)
+    assert dz <= tol and dphi <= 10 * tol
+    P.close()
+
+
 def test_stall_stop_ends_a_stagnating_solve(bim):
     # F = 0.7 on the 181 x 61 working domain stagnates near ||F|| = 3.7e-3 (in the
     # oracle as here); with stall_steps = 3 the solve stops as soon as ||F||_inf
