@@ -383,8 +383,8 @@ int bim_bottom_pressure(const bim_problem *prob, const double *u, double *pres, 
  * Errors: BIM_EDOMAIN for F not finite and positive, |F - 1| < 1e-3 (the linear
  * solution is singular at F = 1), or a bump with delta <= 0 or non-finite
  * values; BIM_EINVAL for bad sizes or pointers.  Uses stream-ordered scratch
- * (node table, 8 (2 + nbumps) bytes per node, and per-chunk partial tiles of
- * 64 KiB) and synchronises `stream` before it returns.
+ * (node table, 8 (6 + nbumps) bytes per node, and per-chunk partial tiles of
+ * 2 x 64 x tile_cols doubles) and synchronises `stream` before it returns.
  */
 typedef struct bim_bump {
     double eps;    /* height (negative: a crater) */
@@ -399,16 +399,18 @@ typedef struct bim_exact_config {
     double grade_start;       /* <= 0: 1e-10 (first graded psi panel next to psi_0) */
     int32_t workgroups;       /* <= 0: about 2048 for the contraction */
     int32_t timing;           /* 1: time the contraction kernel and the whole call with HIP events */
+    int32_t tile_cols;        /* targets along y per workgroup tile: 64, 96 or 128; <= 0: chosen for M */
 } bim_exact_config;
 
 typedef struct bim_exact_info {
     int64_t nodes;      /* quadrature nodes (padded to 16 per kind) */
     int32_t psi_nodes;  /* psi nodes over (0, pi/2) */
     int32_t chunks;     /* node chunks of the contraction */
-    int32_t tiles;      /* 64 x 64 target tiles */
+    int32_t tiles;      /* 64 x tile_cols target tiles */
     double kcut, hk;    /* k cutoff and k-panel width bound */
     double contract_ms; /* with timing: the contraction kernel */
     double total_ms;    /* with timing: the whole evaluation */
+    int32_t tile_cols;  /* the tile width used */
 } bim_exact_info;
 
 int bim_exact_linear(double froude, const bim_bump *bumps, int nbumps, int N, int M, double x1, double dx,

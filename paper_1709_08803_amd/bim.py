@@ -51,13 +51,13 @@ class Bump(ctypes.Structure):
 class ExactConfig(ctypes.Structure):
     _fields_ = [("periods_per_panel", ctypes.c_double), ("decay", ctypes.c_double),
                 ("psi_width_max", ctypes.c_double), ("grade_start", ctypes.c_double),
-                ("workgroups", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("workgroups", ctypes.c_int32), ("timing", ctypes.c_int32), ("tile_cols", ctypes.c_int32)]
 
 
 class ExactInfo(ctypes.Structure):
     _fields_ = [("nodes", ctypes.c_int64), ("psi_nodes", ctypes.c_int32), ("chunks", ctypes.c_int32),
                 ("tiles", ctypes.c_int32), ("kcut", ctypes.c_double), ("hk", ctypes.c_double),
-                ("contract_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("contract_ms", ctypes.c_double), ("total_ms", ctypes.c_double), ("tile_cols", ctypes.c_int32)]
 
 
 def lib():

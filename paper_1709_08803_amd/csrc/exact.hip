@@ -58,9 +58,7 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kGL = 16;          // Gauss-Legendre nodes per panel
-constexpr int kTile = 64;        // targets per tile side (64 x 64 per workgroup)
 constexpr int kStep = 16;        // nodes per LDS stage
-constexpr int kLds = kTile + 2;  // LDS row stride (doubles)
 constexpr int kMaxBumps = 16;
 
 struct GL16 {
@@ -246,9 +244,26 @@ __device__ __forceinline__ void load_node(const double *__restrict__ na, const d
     nd.sb = rot[3 * qpad + q];
 }
 
+// LDS row strides (doubles) of the operand buffers: 64 + 16 and JT + 16 (JT = 96:
+// 112), so that the four node rows an MFMA operand read touches fall on
+// alternate halves of the 64 banks (row strides of 32 mod 64 dwords).
+template <int W>
+struct LdsStride {
+    static constexpr int value = W + 16;
+};
+
+// Generation of one step's operands: thread t takes node gq = t / 16 and the
+// four rows 4 g .. 4 g + 3 (g = t % 16) of L and the JT / 16 columns
+// (JT / 16) g .. of R: one sincos at the first row (column), then rotations by
+// exp(+-i a dx) (the sign of the step of |xi|) and exp(i b dy); rows on both
+// sides of the bump centre (|xi| not monotone) take a sincos each.
+template <int JT>
 __device__ __forceinline__ void gen_step(const NodeData &nd, const Bumps &bs, long sq, long st, long q1off,
-                                         long q2off, double x0, double y0, double dx, double dy, int gq, int r0,
-                                         double (*sL)[kLds], double (*sLx)[kLds], double (*sR)[kLds]) {
+                                         long q2off, double x0, double y0, double dx, double dy, int gq, int g,
+                                         double (*sL)[LdsStride<64>::value], double (*sLx)[LdsStride<64>::value],
+                                         double (*sR)[LdsStride<JT>::value]) {
+    constexpr int RJ = JT / 16;
+    const int r0 = 4 * g, c0 = RJ * g;
     const int b = (int)(st / sq);
     const long q0 = (st - (long)b * sq) * kStep;
     const int kind = q0 < q1off ? 0 : (q0 < q2off ? 1 : 2);
@@ -290,66 +305,80 @@ __device__ __forceinline__ void gen_step(const NodeData &nd, const Bumps &bs, lo
     }
     double sy, cy;
     sincos(nd.b * eta0, &sy, &cy);
-    sR[gq][r0] = cy;
+    sR[gq][c0] = cy;
 #pragma unroll
-    for (int r = 1; r < 4; ++r) {
+    for (int r = 1; r < RJ; ++r) {
         const double c2 = cy * nd.cb - sy * nd.sb;
         sy = sy * nd.cb + cy * nd.sb;
         cy = c2;
-        sR[gq][r0 + r] = cy;
+        sR[gq][c0 + r] = cy;
     }
 }
 
-__global__ __launch_bounds__(256) void k_exact_contract(const double *__restrict__ na,
-                                                        const double *__restrict__ nb,
-                                                        const double *__restrict__ nw,
-                                                        const double *__restrict__ rot, long qpad, long q1off,
-                                                        long q2off, Bumps bs, double x1, double dx, double y1,
-                                                        double dy, int tiles_i, long steps_total,
-                                                        long steps_per_chunk, double *__restrict__ part) {
-    __shared__ double sL[2][kStep][kLds], sLx[2][kStep][kLds], sR[2][kStep][kLds];
+// One workgroup: a 64 x JT tile of targets (i along x, j along y) and a range of
+// node steps (16 nodes of one bump each).  Wave w owns the 32 x JT/2 part
+// (i half w & 1, j half w >> 1) as 2 x JT/32 blocks of 16 x 16 for each output.
+// MFMA operand layout (v_mfma_f64_16x16x4): lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; the result block holds D[l / 16 + 4 r][l % 16] in
+// element r of lane l (rows interleaved, unlike the FP32 16x16x4 form).
+// Software pipeline, one barrier per step: while the matrix cores multiply
+// step st out of one LDS buffer, the waves generate step st + 1 into the other
+// from node data loaded during step st - 1.  A wider tile (JT = 96, 128) spends
+// more matrix work per generated operand (the rows' L is shared by more
+// columns), at the price of more padding on meshes that are not a multiple of JT.
+// Two waves per SIMD are requested (registers capped at 256, the accumulators in
+// ordinary VGPRs): with one, the operand generation of a wave cannot overlap the
+// matrix work of another.
+template <int JT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_exact_contract(
+    const double *__restrict__ na, const double *__restrict__ nb, const double *__restrict__ nw,
+    const double *__restrict__ rot, long qpad, long q1off, long q2off, Bumps bs, double x1, double dx, double y1,
+    double dy, int tiles_i, long steps_total, long steps_per_chunk, double *__restrict__ part) {
+    constexpr int SI = LdsStride<64>::value, SJ = LdsStride<JT>::value, BJ = JT / 32;
+    __shared__ double sL[2][kStep][SI], sLx[2][kStep][SI], sR[2][kStep][SJ];
     const int tile = blockIdx.x, chunk = blockIdx.y;
     const int ti = tile % tiles_i, tj = tile / tiles_i;
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int ih = wave & 1, jh = wave >> 1;
-    d4 acc[2][2][2];
+    d4 acc[2][2][BJ];
     for (int o = 0; o < 2; ++o)
         for (int bi = 0; bi < 2; ++bi)
-            for (int bj = 0; bj < 2; ++bj) acc[o][bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int bj = 0; bj < BJ; ++bj) acc[o][bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
     const long sq = qpad / kStep;  // steps per bump
     const long s0 = (long)chunk * steps_per_chunk;
     const long s1 = s0 + steps_per_chunk < steps_total ? s0 + steps_per_chunk : steps_total;
-    const int gq = t >> 4, r0 = 4 * (t & 15);  // generation: node gq, rows / columns r0 .. r0 + 3
-    const double x0 = x1 + (double)(ti * kTile + r0) * dx;
-    const double y0 = y1 + (double)(tj * kTile + r0) * dy;
+    const int gq = t >> 4, g = t & 15;  // generation: node gq, row group g
+    const double x0 = x1 + (double)(ti * 64 + 4 * g) * dx;
+    const double y0 = y1 + (double)(tj * JT + (JT / 16) * g) * dy;
     if (s0 < s1) {
         NodeData nd;
         load_node(na, nb, nw, rot, qpad, sq, s0, gq, nd);
-        gen_step(nd, bs, sq, s0, q1off, q2off, x0, y0, dx, dy, gq, r0, sL[0], sLx[0], sR[0]);
+        gen_step<JT>(nd, bs, sq, s0, q1off, q2off, x0, y0, dx, dy, gq, g, sL[0], sLx[0], sR[0]);
         if (s0 + 1 < s1) load_node(na, nb, nw, rot, qpad, sq, s0 + 1, gq, nd);
         __syncthreads();
         int cur = 0;
         for (long st = s0; st < s1; ++st) {
             if (st + 1 < s1) {
-                gen_step(nd, bs, sq, st + 1, q1off, q2off, x0, y0, dx, dy, gq, r0, sL[cur ^ 1], sLx[cur ^ 1],
-                         sR[cur ^ 1]);
+                gen_step<JT>(nd, bs, sq, st + 1, q1off, q2off, x0, y0, dx, dy, gq, g, sL[cur ^ 1], sLx[cur ^ 1],
+                             sR[cur ^ 1]);
                 if (st + 2 < s1) load_node(na, nb, nw, rot, qpad, sq, st + 2, gq, nd);
             }
 #pragma unroll
             for (int ks = 0; ks < kStep / 4; ++ks) {
                 const int kk = 4 * ks + (lane >> 4), r16 = lane & 15;
-                double A0[2], A1[2], B[2];
+                double A0[2], A1[2], B[BJ];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     A0[h] = sL[cur][kk][32 * ih + 16 * h + r16];
                     A1[h] = sLx[cur][kk][32 * ih + 16 * h + r16];
-                    B[h] = sR[cur][kk][32 * jh + 16 * h + r16];
                 }
+#pragma unroll
+                for (int h = 0; h < BJ; ++h) B[h] = sR[cur][kk][(JT / 2) * jh + 16 * h + r16];
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                    for (int bj = 0; bj < 2; ++bj) {
+                    for (int bj = 0; bj < BJ; ++bj) {
                         acc[0][bi][bj] =
                             __builtin_amdgcn_mfma_f64_16x16x4f64(A0[bi], B[bj], acc[0][bi][bj], 0, 0, 0);
                         acc[1][bi][bj] =
@@ -363,23 +392,23 @@ __global__ __launch_bounds__(256) void k_exact_contract(const double *__restrict
         }
     }
     // partial tile, [out][j local][i local]
-    double *pt = part + ((long)chunk * gridDim.x + tile) * 2 * kTile * kTile;
+    double *pt = part + ((long)chunk * gridDim.x + tile) * 2 * 64 * JT;
 #pragma unroll
     for (int o = 0; o < 2; ++o)
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
+            for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int il = 32 * ih + 16 * bi + (lane >> 4) + 4 * r;
-                    const int jl = 32 * jh + 16 * bj + (lane & 15);
-                    pt[(long)o * kTile * kTile + jl * kTile + il] = acc[o][bi][bj][r];
+                    const int jl = (JT / 2) * jh + 16 * bj + (lane & 15);
+                    pt[(long)o * 64 * JT + jl * 64 + il] = acc[o][bi][bj][r];
                 }
 }
 
 __global__ __launch_bounds__(256) void k_exact_reduce(const double *__restrict__ part, int chunks, int tiles,
-                                                      int tiles_i, int N, int M, double *__restrict__ zeta,
+                                                      int tiles_i, int jt, int N, int M, double *__restrict__ zeta,
                                                       double *__restrict__ zeta_x) {
     const long nm = (long)N * M;
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -388,10 +417,11 @@ __global__ __launch_bounds__(256) void k_exact_reduce(const double *__restrict__
     if (o == 1 && !zeta_x) return;
     const long r = e - o * nm;
     const int j = (int)(r / N), i = (int)(r % N);
-    const int tile = i / kTile + (j / kTile) * tiles_i;
-    const long loc = (long)o * kTile * kTile + (j % kTile) * kTile + (i % kTile);
+    const int tile = i / 64 + (j / jt) * tiles_i;
+    const long tsz = 2L * 64 * jt;
+    const long loc = (long)o * 64 * jt + (j % jt) * 64 + (i % 64);
     double sum = 0.0;
-    for (int c = 0; c < chunks; ++c) sum += part[((long)c * tiles + tile) * 2 * kTile * kTile + loc];
+    for (int c = 0; c < chunks; ++c) sum += part[((long)c * tiles + tile) * tsz + loc];
     (o ? zeta_x : zeta)[r] = sum;
 }
 
@@ -583,6 +613,7 @@ bim_exact_config resolve(const bim_exact_config *c) {
     r.grade_start = (c && c->grade_start > 0) ? c->grade_start : 1e-10;
     r.workgroups = (c && c->workgroups > 0) ? c->workgroups : 2048;
     r.timing = (c && c->timing) ? 1 : 0;
+    r.tile_cols = c ? c->tile_cols : 0;
     return r;
 }
 
@@ -610,6 +641,8 @@ extern "C" int bim_exact_linear(double froude, const bim_bump *bumps, int nbumps
         return fail(BIM_EINVAL, "exact linear solution: x1, y1 finite and dx, dy > 0 required");
     if (!zeta) return fail(BIM_EINVAL, "exact linear solution: zeta must be a device pointer");
     const bim_exact_config cfg = resolve(config);
+    if (!(cfg.tile_cols <= 0 || cfg.tile_cols == 64 || cfg.tile_cols == 96 || cfg.tile_cols == 128))
+        return fail(BIM_EINVAL, "exact linear solution: tile_cols must be 64, 96 or 128 (or <= 0)");
     if (!(cfg.periods_per_panel <= 64.0 && cfg.decay <= 700.0 && cfg.psi_width_max <= 1.0 && cfg.grade_start < 1e-2))
         return fail(BIM_EINVAL, "exact linear solution: config outside periods_per_panel <= 64, decay <= 700, "
                                 "psi_width_max <= 1, grade_start < 1e-2");
@@ -624,7 +657,21 @@ extern "C" int bim_exact_linear(double froude, const bim_bump *bumps, int nbumps
         bs.b1[b] = bumps[b].b1;
         bs.b2[b] = bumps[b].b2;
     }
-    const int tiles_i = (N + kTile - 1) / kTile, tiles_j = (M + kTile - 1) / kTile, tiles = tiles_i * tiles_j;
+    // tile width along y: the one of 64, 96, 128 with the least padded work per
+    // generated operand (padded columns x (1 + 64 / JT): the rows' operands are
+    // shared by JT columns), unless the config fixes it
+    int jt = cfg.tile_cols;
+    if (jt <= 0) {
+        double best = 1e300;
+        for (int c : {64, 96, 128}) {
+            const double cost = (double)((M + c - 1) / c) * c * (1.0 + 64.0 / c);
+            if (cost < best - 1e-9) {
+                best = cost;
+                jt = c;
+            }
+        }
+    }
+    const int tiles_i = (N + 63) / 64, tiles_j = (M + jt - 1) / jt, tiles = tiles_i * tiles_j;
     const long steps_total = (long)nbumps * (L.qpad / kStep);
     long chunks = std::max(1L, std::min(steps_total, (long)(cfg.workgroups + tiles - 1) / tiles));
     const long spc = (steps_total + chunks - 1) / chunks;
@@ -634,7 +681,7 @@ extern "C" int bim_exact_linear(double froude, const bim_bump *bumps, int nbumps
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t b_psi = al(sizeof(PsiNode) * npsi), b_n = al(sizeof(double) * L.qpad),
                  b_w = al(sizeof(double) * L.qpad * nbumps), b_rot = al(sizeof(double) * 4 * L.qpad),
-                 b_part = al(sizeof(double) * (size_t)chunks * tiles * 2 * kTile * kTile);
+                 b_part = al(sizeof(double) * (size_t)chunks * tiles * 2 * 64 * jt);
     hipStream_t s = (hipStream_t)stream;
     char *ws = nullptr;
     if ((rc = hip_check(hipMallocAsync((void **)&ws, b_psi + 2 * b_n + b_w + b_rot + b_part, s), "hipMallocAsync")))
@@ -653,12 +700,20 @@ extern "C" int bim_exact_linear(double froude, const bim_bump *bumps, int nbumps
         hipLaunchKernelGGL(k_exact_nodes, dim3((unsigned)npsi), dim3(64), 0, s, d_psi, gauss_legendre16(), bs,
                            froude, L.K, L.hk, L.q1off, L.q2off, L.qpad, dx, dy, na, nb_, nw, rot);
         if (cfg.timing) BIM_HIP(hipEventRecord(ev[1], s));
-        hipLaunchKernelGGL(k_exact_contract, dim3(tiles, (unsigned)chunks), dim3(256), 0, s, na, nb_, nw, rot, L.qpad,
-                           L.q1off, L.q2off, bs, x1, dx, y1, dy, tiles_i, steps_total, spc, part);
+        const dim3 cgrid(tiles, (unsigned)chunks);
+        if (jt == 128)
+            hipLaunchKernelGGL(k_exact_contract<128>, cgrid, dim3(256), 0, s, na, nb_, nw, rot, L.qpad, L.q1off,
+                               L.q2off, bs, x1, dx, y1, dy, tiles_i, steps_total, spc, part);
+        else if (jt == 96)
+            hipLaunchKernelGGL(k_exact_contract<96>, cgrid, dim3(256), 0, s, na, nb_, nw, rot, L.qpad, L.q1off,
+                               L.q2off, bs, x1, dx, y1, dy, tiles_i, steps_total, spc, part);
+        else
+            hipLaunchKernelGGL(k_exact_contract<64>, cgrid, dim3(256), 0, s, na, nb_, nw, rot, L.qpad, L.q1off,
+                               L.q2off, bs, x1, dx, y1, dy, tiles_i, steps_total, spc, part);
         if (cfg.timing) BIM_HIP(hipEventRecord(ev[2], s));
         const long outs = 2L * N * M;
         hipLaunchKernelGGL(k_exact_reduce, dim3((unsigned)((outs + 255) / 256)), dim3(256), 0, s, part, (int)chunks,
-                           tiles, tiles_i, N, M, zeta, zeta_x);
+                           tiles, tiles_i, jt, N, M, zeta, zeta_x);
         BIM_HIP(hipGetLastError());
         if (cfg.timing) BIM_HIP(hipEventRecord(ev[3], s));
         // the host node table must outlive its copy
@@ -677,6 +732,7 @@ extern "C" int bim_exact_linear(double froude, const bim_bump *bumps, int nbumps
     const int rf = hip_check(hipFreeAsync(ws, s), "hipFreeAsync");
     if (info) {
         if (!cfg.timing) info->contract_ms = info->total_ms = 0.0;
+        info->tile_cols = jt;
         info->nodes = L.qpad;
         info->psi_nodes = (int)npsi;
         info->kcut = L.K;

@@ -52,11 +52,16 @@ def test_exact_linear_matches_oracle_at_sampled_nodes(bim, c):
 
 
 def test_exact_linear_every_affordable_node_ragged_tiles(bim):
-    # 70 x 67 nodes: 2 x 2 tiles of 64 with ragged tails; the oracle evaluates a
-    # seeded sample of nodes from every tile (including both tails) plus the bump centre
+    # 70 x 67 nodes: 2 x 2 tiles of 64 x 64 (1 x 1 of 64 x 96, 64 x 128) with ragged
+    # tails; the oracle evaluates a seeded sample of nodes from every 64 x 64 tile
+    # (including both tails) plus the bump centre; every tile width must agree
     F, bumps = 0.7, [(0.05, 0.6, 1.3, -0.9)]
     N, M, x1, dx, y1, dy = 70, 67, -6.0, 0.25, -8.0, 0.25
-    z, zx, _ = bim.exact_linear(F, bumps, N, M, x1, dx, y1, dy)
+    outs = [bim.exact_linear(F, bumps, N, M, x1, dx, y1, dy, config={"tile_cols": jt}) for jt in (64, 96, 128)]
+    assert [o[2]["tile_cols"] for o in outs] == [64, 96, 128]
+    for o in outs[1:]:
+        assert float((o[0] - outs[0][0]).abs().max()) <= 1e-13 * float(outs[0][0].abs().max())  # chunking differs
+    z, zx, _ = outs[2]
     rng = np.random.default_rng(11)
     pts = {(0, 0), (N - 1, M - 1), (63, 63), (64, 64), (69, 0), (0, 66), (int(round((1.3 - x1) / dx)), 28)}
     for ti in (0, 1):
@@ -116,6 +121,8 @@ def test_exact_linear_rejects_bad_input(bim):
             bim.exact_linear(F, bumps, 8, 8, -1.0, 0.25, -1.0, 0.25)
     with pytest.raises(bim.BimError):
         bim.exact_linear(0.6, good, 8, 8, -1.0, 0.0, -1.0, 0.25)
+    with pytest.raises(bim.BimError):
+        bim.exact_linear(0.6, good, 8, 8, -1.0, 0.25, -1.0, 0.25, config={"tile_cols": 80})
 
 
 def test_exact_start_assembles_the_linear_unknowns(bim):
