@@ -202,9 +202,10 @@ int bim_tune_residual(const bim_problem *prob, const double *u, int prec, void *
  * blocks kept only within a band of slices |m - l| <= band_halfwidth
  * ("b blocks of size (N+1) x (N+1) in each row", b = 2 band_halfwidth + 1).
  * P depends only on the mesh and F (not on u or the bottom).
- *   band_halfwidth < 0 selects max(1, round(M / 6)) (b ~ M/3 blocks: wider than
- *   the b ~ M/10 of Table 1, because GMRES iterations per Newton step fall
- *   several-fold for a modest rise in setup and apply cost).
+ *   band_halfwidth < 0 selects max(1, min(10, round(M / 6))) (b ~ M/3 blocks up
+ *   to 21: wider than the b ~ M/10 of Table 1, because GMRES iterations per
+ *   Newton step fall several-fold for a modest rise in setup and apply cost;
+ *   beyond 10 slices the setup grows faster than the solve shrinks).
  * precond_setup factors P on the device and returns a library-owned handle
  * (free with precond_destroy).  It synchronises `stream`.  Device memory used:
  * precond_bytes().  Requires N + 1 <= 1024.  Returns BIM_EDOMAIN if a block

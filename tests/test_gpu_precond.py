@@ -46,8 +46,8 @@ def test_precond_apply_matches_oracle_solve(bim, name, mk, hb):
     p = mk()
     dp = bim.DeviceProblem(p)
     P = bim.Preconditioner(dp, hb)
-    if hb < 0:  # the library's default band: max(1, round(M / 6)) slices
-        assert P.band == max(1, round(p.M / 6))
+    if hb < 0:  # the library's default band: max(1, min(10, round(M / 6))) slices
+        assert P.band == max(1, min(10, round(p.M / 6)))
     pc_ref = Lin.Preconditioner(p, hb=P.band)
     rng = np.random.default_rng(5)
     for trial in range(2):
