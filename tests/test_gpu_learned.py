@@ -141,6 +141,43 @@ def test_trained_network_reduces_newton_iterations(bim):
     assert s["max_dx_between_solutions"] <= 1e-8
 
 
+@pytest.mark.timeout(600)
+def test_learned_start_solutions_at_121x41_match_the_oracle(bim):
+    # The learned-start configuration (121 x 41, the sweep distribution): a network
+    # trained on the GPU on the method's own solutions of seeded sweep problems; on
+    # held-out problems of the experiment's test set, Newton from the learned start
+    # (falling back to the linear start after 8 steps, as the experiment does) must
+    # reach the FP64 oracle's own converged solution (tests/golden/
+    # make_learned_heldout.py, oracle/ only).
+    import os
+    from oracle import residual as R
+    from paper_1709_08803_amd import learned_start as LS
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "learned_heldout_121x41.npz"))
+    net = bim.LearnedNet(121, 41, seed=0, max_batch=32, D3=256)
+    data = LS.generate(W.sweep_instances(96, seed=1, fixed_n=121), net, batch=32, log=None)
+    assert len(data) >= 32
+    LS.train(net, data, epochs=40, batch=32, log=None)
+    probs = W.sweep_instances(8, seed=2, fixed_n=121)
+    for i, F, uref in zip(g["index"], g["froude"], g["u"]):
+        p = probs[int(i)]
+        assert p.froude == F
+        dp = bim.DeviceProblem(p)
+        P = bim.Preconditioner(dp)
+        u = net.infer_start(dp, P)
+        rep = bim.solve(dp, u, P, ftol=1e-11, max_newton=8, check=False)
+        fallback = rep["status"] != 0
+        if fallback:
+            u = bim.linear_start(dp, P)
+            rep = bim.solve(dp, u, P, ftol=1e-11)
+        P.close()
+        uh = u.cpu().numpy()
+        z, zr = R.reconstruct(p, uh), R.reconstruct(p, uref)
+        dz = np.abs(z.zeta - zr.zeta).max()
+        print(f"held-out {int(i)} F = {F:.3f}: Newton {rep['newton_iters']} fallback {fallback} max|dzeta| {dz:.2e}")
+        assert rep["status"] == 0 and dz <= 1e-9
+        assert np.abs(R.residual(p, uh)).max() <= 1e-10  # a root of the oracle's discrete system
+
+
 # The kernels keep inputs, weights, activations and the gradients fed to products
 # in bf16 (8 significant bits, unit roundoff u = 2^-8 relative to the spacing),
 # with FP32 accumulation.  Against the plain FP64 network (no rounding at all)
