@@ -61,18 +61,21 @@ struct BBand {
 };
 // max_groups: the largest M ceil(s / 4) over the ops (waves needed by the largest problem)
 int b_bandmv(const BBand *ops, int count, int max_groups, hipStream_t s);
-// One dense product y = alpha A x + beta c (rows x cols, row stride lda).
-// A holds FP64 elements, or FP32 ones when f32 != 0.
+// One product y = alpha A' x + beta c of one problem, A' the strictly lower
+// (part 1) or strictly upper (part 2) slice-block part of a dense n x n A
+// (M slices of s, row stride n).  A holds FP64 elements, or FP32 ones when
+// f32 != 0.  c may equal x; y must not alias x.
 struct BGemv {
     const void *A;
     const double *x;
     const double *c;
     double *y;
-    long lda;
-    int rows, cols;
+    long n;
+    int M, s, part;
     double alpha, beta;
     int f32;
 };
-int b_gemv(const BGemv *ops, int count, int max_rows, hipStream_t s);
+// max_groups: the largest M ceil(s / 4) over the ops
+int b_gemv_tri(const BGemv *ops, int count, int max_groups, hipStream_t s);
 
 }  // namespace bim

@@ -199,25 +199,28 @@ __global__ __launch_bounds__(256) void k_bbandmv(const BBand *__restrict__ ops) 
 }
 
 template <typename TA>
-__device__ __forceinline__ void bgemv_rows(const BGemv &o, int row0, int lane, double (&acc)[kBGR]) {
+__device__ __forceinline__ void bgemv_tri_rows(const BGemv &o, int l, int r0, int lane, double (&acc)[kBGR]) {
     const TA *A = (const TA *)o.A;
-    const bool vec = (o.lda % 2 == 0) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) && ((uintptr_t)o.x % 16 == 0);
+    const long c0 = (o.part == 1) ? 0 : (long)(l + 1) * o.s, c1 = (o.part == 1) ? (long)l * o.s : o.n;
+    const bool vec = (o.s % 2 == 0) && (o.n % 2 == 0) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) &&
+                     ((uintptr_t)o.x % 16 == 0);
     const TA *row[kBGR];
 #pragma unroll
-    for (int r = 0; r < kBGR; ++r) row[r] = A + (size_t)min(row0 + r, o.rows - 1) * o.lda;
-    brows_dot<TA>(row, o.x, o.cols, vec, lane, acc);
+    for (int r = 0; r < kBGR; ++r) row[r] = A + ((size_t)l * o.s + min(r0 + r, o.s - 1)) * o.n + c0;
+    brows_dot<TA>(row, o.x + c0, (int)(c1 - c0), vec, lane, acc);
 }
 
-__global__ __launch_bounds__(256) void k_bgemv(const BGemv *__restrict__ ops) {
+__global__ __launch_bounds__(256) void k_bgemv_tri(const BGemv *__restrict__ ops) {
     const BGemv o = ops[blockIdx.y];
+    const int gps = (o.s + kBGR - 1) / kBGR;  // row groups per slice
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int row0 = wave * kBGR;
-    if (row0 >= o.rows) return;
+    if (wave >= o.M * gps) return;
+    const int l = wave / gps, r0 = (wave - l * gps) * kBGR;
     double acc[kBGR] = {};
-    if (o.f32) bgemv_rows<float>(o, row0, lane, acc);
-    else bgemv_rows<double>(o, row0, lane, acc);
-    brows_store(acc, lane, min(kBGR, o.rows - row0), o.y, o.c, row0, o.alpha, o.beta);
+    if (o.f32) bgemv_tri_rows<float>(o, l, r0, lane, acc);
+    else bgemv_tri_rows<double>(o, l, r0, lane, acc);
+    brows_store(acc, lane, min(kBGR, o.s - r0), o.y, o.c, l * o.s + r0, o.alpha, o.beta);
 }
 
 __global__ void k_bgather(const BOp *__restrict__ ops) {
@@ -293,9 +296,9 @@ int b_bandmv(const BBand *ops, int count, int max_groups, hipStream_t s) {
     return hip_check(hipGetLastError(), "batched bandmv launch");
 }
 
-int b_gemv(const BGemv *ops, int count, int max_rows, hipStream_t s) {
+int b_gemv_tri(const BGemv *ops, int count, int max_groups, hipStream_t s) {
     if (count <= 0) return BIM_OK;
-    hipLaunchKernelGGL(k_bgemv, dim3(cdiv(cdiv(max_rows, kBGR), 4), count), dim3(256), 0, s, ops);
+    hipLaunchKernelGGL(k_bgemv_tri, dim3(cdiv(max_groups, 4), count), dim3(256), 0, s, ops);
     return hip_check(hipGetLastError(), "batched gemv launch");
 }
 

@@ -21,6 +21,20 @@ struct GemmKItem {
     double *C;
     long nkb;
 };
+// One product of a block-triangular launch (blocks s x s): for each output
+// column block cb = cb0 .. cb0 + ncb - 1,
+//   C[:, cb] = alpha sum_{j = klo .. khi-1} A[:, j] B[j, cb],
+//   klo = max(0, cb - lo_off), khi = min(nk, cb - hi_off)
+// (A: s x (nk s); B: nk block rows; C: s rows; zero where klo >= khi).
+template <typename T>
+struct GemmTriItemT {
+    const T *A;
+    const T *B;
+    T *C;
+    int nk, cb0, ncb, lo_off, hi_off;
+};
+using GemmTriItem = GemmTriItemT<double>;
+using GemmTriItemF = GemmTriItemT<float>;
 // One matrix of a batched inversion: Ainv = A^-1 (s x s, row-major).
 struct InvItem {
     const double *A;
@@ -40,6 +54,21 @@ int gemm_kblocks_enqueue(const GemmKItem *items_dev, int batch, int m, int n, in
 // cores) for 128 < m <= 192 only (BIM_EINVAL otherwise).
 int gemm_f32_enqueue(const GemmItemF *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
                      double alpha, double beta, hipStream_t s);
+// Block-triangular products of `batch` items (FP64 or FP32 matrix cores, any
+// block size s); max_ncb: the largest ncb; kmax: the largest khi - klo of any
+// column block; work: the sum of khi - klo over all items' column blocks (the
+// two choose the panel width).
+int gemm_tri_enqueue(const GemmTriItem *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
+                     int ldb, int ldc, double alpha, hipStream_t s_);
+int gemm_tri_enqueue(const GemmTriItemF *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
+                     int ldb, int ldc, double alpha, hipStream_t s_);
+// y = alpha A' x + beta c, A' the strictly lower (part 1) or strictly upper
+// (part 2) block part of the dense n x n A with M x M blocks of s; c may equal x
+// (read per row), y must not alias x.
+int gemv_tri_enqueue(const double *A, long n, int M, int s, int part, const double *x, const double *c, double *y,
+                     double alpha, double beta, hipStream_t st);
+int gemv_tri_enqueue(const float *A, long n, int M, int s, int part, const double *x, const double *c, double *y,
+                     double alpha, double beta, hipStream_t st);
 // work: device scratch of batch * s * 2s doubles; info[b] = 0 or (1 + column of a zero pivot).
 int invert_enqueue(const InvItem *items_dev, int batch, int s_dim, double *work, int *info, hipStream_t s);
 

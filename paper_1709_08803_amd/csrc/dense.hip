@@ -362,6 +362,117 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItemT<T> *__res
             }
 }
 
+// Block-triangular product of the substitutions that invert unit block-
+// triangular factors (blocks s x s): per item, for each output column block
+// cb = cb0 .. cb0 + ncb - 1,
+//   C[:, cb] = alpha sum_{j = klo .. khi-1} A[:, j] B[j, cb],
+//   klo = max(0, cb - lo_off), khi = min(nk, cb - hi_off),
+// with A an s x (nk s) row of blocks (leading dim lda), B nk block rows of
+// leading dim ldb, C s rows of leading dim ldc (C = 0 where klo >= khi).  The
+// K range of a column block leaves out the operand blocks that are zero by
+// the triangular structure, which lets two factors' inverses share one array:
+// the blocks of B outside the range may hold the other factor.  Workgroups as
+// in k_gemm_tall: 192-row panels (blockIdx.y) of TN columns, ppb panels per
+// column block (a panel never straddles two column blocks), blockIdx.z the item.
+template <int TN, int NW, typename T = double>
+__global__ __launch_bounds__(64 * NW) void k_gemm_tri(const GemmTriItemT<T> *__restrict__ items, int s, int ppb,
+                                                      int lda, int ldb, int ldc, double alpha) {
+    constexpr int NT = 64 * NW, NB = TN / 16, RB = 12 / NW;
+    constexpr int QA = kTallM * kTallK / NT, QB = (kTallK * TN + NT - 1) / NT;
+    static_assert(QA * NT == kTallM * kTallK && RB * NW == 12, "tall tile shape");
+    typedef Mfma16<T> MF;
+    const GemmTriItemT<T> it = items[blockIdx.z];
+    const int cbi = blockIdx.x / ppb, pan = blockIdx.x - cbi * ppb;
+    if (cbi >= it.ncb) return;
+    const int cb = it.cb0 + cbi;
+    const int klo = max(0, cb - it.lo_off), khi = min(it.nk, cb - it.hi_off);
+    const int row0 = blockIdx.y * kTallM, m = min(kTallM, s - row0);
+    const int col0 = cb * s + pan * TN, cend = (cb + 1) * s;
+    if (col0 >= cend) return;
+    const int k = max(0, khi - klo) * s;
+    const GlobalPtr<const T> A = (GlobalPtr<const T>)(it.A + (size_t)row0 * lda + (size_t)klo * s);
+    const GlobalPtr<const T> B = (GlobalPtr<const T>)(it.B + (size_t)klo * s * ldb);
+    const GlobalPtr<T> C = (GlobalPtr<T>)(it.C + (size_t)row0 * ldc);
+    __shared__ T As[2][kTallM][kTallK + 1];
+    __shared__ T Bs[2][kTallK][TN + 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave * 16 * RB;
+    const int li = lane & 15, lk = lane >> 4;
+    // loads at clamped indices (rows past m, columns past the block's end), B
+    // rows past k zeroed when staged
+    T ra[QA], rb[QB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + q * NT;
+            const int ar = e >> 5, ac = e & 31;
+            ra[q] = A[(size_t)min(ar, m - 1) * lda + min(k0 + ac, k - 1)];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = min(tid + q * NT, kTallK * TN - 1);
+            const int br = e / TN, bc = e - br * TN;
+            rb[q] = B[(size_t)min(k0 + br, k - 1) * ldb + min(col0 + bc, cend - 1)];
+        }
+    };
+    auto store = [&](int buf, int k0) {
+#pragma unroll
+        for (int q = 0; q < QA; ++q) {
+            const int e = tid + q * NT;
+            As[buf][e >> 5][e & 31] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+            const int e = tid + q * NT;
+            if (e < kTallK * TN) {
+                const int br = e / TN;
+                Bs[buf][br][e - br * TN] = (k0 + br < k) ? rb[q] : (T)0;
+            }
+        }
+    };
+    typename MF::acc acc[RB][NB];
+#pragma unroll
+    for (int t = 0; t < RB; ++t)
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[t][u] = typename MF::acc{0, 0, 0, 0};
+    if (k > 0) {
+        load(0);
+        store(0, 0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < k; k0 += kTallK) {
+        const bool more = k0 + kTallK < k;
+        if (more) load(k0 + kTallK);
+#pragma unroll
+        for (int kk = 0; kk < kTallK; kk += 4) {
+            T a[RB], b[NB];
+#pragma unroll
+            for (int t = 0; t < RB; ++t) a[t] = As[buf][wm + 16 * t + li][kk + lk];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) b[u] = Bs[buf][kk + lk][16 * u + li];
+#pragma unroll
+            for (int t = 0; t < RB; ++t)
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    acc[t][u] = MF::step(a[t], b[u], acc[t][u]);
+        }
+        if (more) store(buf ^ 1, k0 + kTallK);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int t = 0; t < RB; ++t)
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gr = wm + 16 * t + MF::row(lk, v), gc = col0 + 16 * u + li;
+                if (gr < m && gc < cend) C[(size_t)gr * ldc + gc] = (T)alpha * acc[t][u][v];
+            }
+}
+
 // In-place Gauss-Jordan inversion of one s x s block (s <= 192) per 1024-thread
 // workgroup, with the matrix held in registers: wave ty (= tid / 64, uniform in
 // the wave) owns rows ty + 16 i (i < 12) and lane tx columns tx + 64 j (j < 3).
@@ -690,6 +801,60 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const TA *__restrict__ A, lon
     }
 }
 
+// y = alpha A' x + beta c for the strictly lower (part 1) or strictly upper
+// (part 2) slice-block part A' of a dense n x n A (M slices of s): row block l
+// reads columns [0, l s) or [(l+1) s, n).  Each wave owns GR rows of one slice;
+// with even s and aligned operands it reads two elements per lane per row.
+template <typename TA>
+__global__ __launch_bounds__(256) void k_gemv_tri(const TA *__restrict__ A, long n, int M, int s, int part,
+                                                  bool vec, const double *__restrict__ x, const double *c,
+                                                  double *y, double alpha, double beta) {
+    typedef double double2_t __attribute__((ext_vector_type(2)));
+    typedef TA ta2_t __attribute__((ext_vector_type(2)));
+    const int gps = (s + GR - 1) / GR;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= M * gps) return;
+    const int l = wave / gps, r0 = (wave - l * gps) * GR;
+    const long c0 = (part == 1) ? 0 : (long)(l + 1) * s, c1 = (part == 1) ? (long)l * s : n;
+    const long len = c1 - c0;
+    const TA *arow[GR];
+#pragma unroll
+    for (int r = 0; r < GR; ++r) arow[r] = A + ((size_t)l * s + min(r0 + r, s - 1)) * n + c0;
+    const double *xs = x + c0;
+    double acc[GR] = {};
+    if (vec) {
+        for (long q = lane; q < (len >> 1); q += 64) {
+            const double2_t xv = *reinterpret_cast<const double2_t *>(xs + 2 * q);
+#pragma unroll
+            for (int r = 0; r < GR; ++r) {
+                const ta2_t a = *reinterpret_cast<const ta2_t *>(arow[r] + 2 * q);
+                acc[r] = fma((double)a[0], xv[0], acc[r]);
+                acc[r] = fma((double)a[1], xv[1], acc[r]);
+            }
+        }
+        if ((len & 1) && lane == 0)
+#pragma unroll
+            for (int r = 0; r < GR; ++r) acc[r] = fma((double)arow[r][len - 1], xs[len - 1], acc[r]);
+    } else {
+        for (long j = lane; j < len; j += 64) {
+            const double xv = xs[j];
+#pragma unroll
+            for (int r = 0; r < GR; ++r) acc[r] = fma((double)arow[r][j], xv, acc[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < GR; ++r)
+        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, 64);
+    if (lane < GR && r0 + lane < s) {
+        double v = acc[0];
+#pragma unroll
+        for (int r = 1; r < GR; ++r) v = (lane == r) ? acc[r] : v;
+        const long row = (long)l * s + r0 + lane;
+        y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
+    }
+}
+
 // y_l = alpha sum_{m in band} B[l][m] x_m + beta c_l for slice-block-banded B
 // (blocks s x s, half-width w, elements of type TA): one wave per row of y.
 template <typename TA>
@@ -974,6 +1139,73 @@ int gemm_f32_enqueue(const GemmItemF *items_dev, int batch, int m, int n, int k,
         hipLaunchKernelGGL((k_gemm_tall<64, NW, float>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
                            alpha, beta);
     return hip_check(hipGetLastError(), "gemm launch");
+}
+
+namespace {
+// Panel width of a block-triangular product launch: the time goes as the larger
+// of the deepest workgroup (kmax K blocks of one TN-wide panel) and the total
+// panel work spread over 256 compute units; 32-wide panels issue fewer MFMAs
+// per LDS read and count 15% more.
+int tri_panel_width(int s, long kmax, long work) {
+    int best = 64;
+    double best_cost = -1.0;
+    for (int tn : {64, 48, 32}) {
+        const double ppb = cdiv(s, tn), rp = cdiv(s, kTallM);
+        const double cost = std::max((double)kmax * tn, rp * (double)work * ppb * tn / 256.0) * (tn == 32 ? 1.15 : 1.0);
+        if (best_cost < 0.0 || cost < best_cost) {
+            best_cost = cost;
+            best = tn;
+        }
+    }
+    return best;
+}
+
+template <typename T>
+int gemm_tri_launch(const GemmTriItemT<T> *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
+                    int ldb, int ldc, double alpha, hipStream_t st) {
+    if (batch <= 0 || max_ncb <= 0 || s <= 0) return BIM_OK;
+    if (batch > 65535) return fail(BIM_EINVAL, "gemm batch too large");
+    const int tn = tri_panel_width(s, kmax, work), ppb = cdiv(s, tn);
+    if ((long)max_ncb * ppb > 0x7fffffffL) return fail(BIM_EINVAL, "block-triangular product too wide");
+    dim3 grid(max_ncb * ppb, cdiv(s, kTallM), batch);
+    constexpr int NW = kTallWaves;
+    if (tn == 32)
+        hipLaunchKernelGGL((k_gemm_tri<32, NW, T>), grid, dim3(64 * NW), 0, st, items_dev, s, ppb, lda, ldb, ldc, alpha);
+    else if (tn == 48)
+        hipLaunchKernelGGL((k_gemm_tri<48, NW, T>), grid, dim3(64 * NW), 0, st, items_dev, s, ppb, lda, ldb, ldc, alpha);
+    else
+        hipLaunchKernelGGL((k_gemm_tri<64, NW, T>), grid, dim3(64 * NW), 0, st, items_dev, s, ppb, lda, ldb, ldc, alpha);
+    return hip_check(hipGetLastError(), "block-triangular gemm launch");
+}
+
+template <typename TA>
+int gemv_tri_launch(const TA *A, long n, int M, int s, int part, const double *x, const double *c, double *y,
+                    double alpha, double beta, hipStream_t st) {
+    if (M <= 0 || s <= 0) return BIM_OK;
+    if (part != 1 && part != 2) return fail(BIM_EINVAL, "gemv_tri: part must be 1 (lower) or 2 (upper)");
+    const bool vec = (s % 2 == 0) && (n % 2 == 0) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) && ((uintptr_t)x % 16 == 0);
+    const long waves = (long)M * ((s + GR - 1) / GR);
+    hipLaunchKernelGGL(k_gemv_tri<TA>, dim3(cdiv(waves, 4)), dim3(256), 0, st, A, n, M, s, part, vec, x, c, y, alpha,
+                       beta);
+    return hip_check(hipGetLastError(), "gemv_tri launch");
+}
+}  // namespace
+
+int gemm_tri_enqueue(const GemmTriItem *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
+                     int ldb, int ldc, double alpha, hipStream_t st) {
+    return gemm_tri_launch(items_dev, batch, s, max_ncb, kmax, work, lda, ldb, ldc, alpha, st);
+}
+int gemm_tri_enqueue(const GemmTriItemF *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
+                     int ldb, int ldc, double alpha, hipStream_t st) {
+    return gemm_tri_launch(items_dev, batch, s, max_ncb, kmax, work, lda, ldb, ldc, alpha, st);
+}
+int gemv_tri_enqueue(const double *A, long n, int M, int s, int part, const double *x, const double *c, double *y,
+                     double alpha, double beta, hipStream_t st) {
+    return gemv_tri_launch(A, n, M, s, part, x, c, y, alpha, beta, st);
+}
+int gemv_tri_enqueue(const float *A, long n, int M, int s, int part, const double *x, const double *c, double *y,
+                     double alpha, double beta, hipStream_t st) {
+    return gemv_tri_launch(A, n, M, s, part, x, c, y, alpha, beta, st);
 }
 
 int copy2d_enqueue(const double *src, long lds, double *dst, long ldd, int rows, int cols, hipStream_t s) {

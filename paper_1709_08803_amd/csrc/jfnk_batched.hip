@@ -37,7 +37,7 @@ enum Slice {
     S_QUO, S_MD1, S_OR1, S_MD2, S_OR2, S_WN, S_VN, S_RSR, S_RSB, S_RSV,  // Arnoldi and restart post-work
     S_NF2, S_NFI, S_GATHER, S_COUNT                                    // norms, results to the host
 };
-constexpr int kPcStages = 7;  // banded products of one preconditioner apply (plus its dense product)
+constexpr int kPcStages = 8;  // banded products of one preconditioner apply (plus its two triangular ones)
 enum Pending { PD_NONE = 0, PD_GMRES_START = 1, PD_COMBINE = 2, PD_ACCEPT = 4 };
 
 
@@ -132,7 +132,7 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
     const size_t rb_ops = 0;
     const size_t rb_bands = rb_ops + al256(sizeof(BOp) * (size_t)S_COUNT * count);
     const size_t rb_gemv = rb_bands + al256(sizeof(BBand) * (size_t)kPcStages * count);
-    const size_t rb_d64 = rb_gemv + al256(sizeof(BGemv) * count);
+    const size_t rb_d64 = rb_gemv + al256(sizeof(BGemv) * 2 * (size_t)count);
     const size_t rb_d32 = rb_d64 + al256(sizeof(PairDesc) * count);
     const size_t rb_y = rb_d32 + al256(sizeof(PairDesc) * count);
     const size_t rb_bytes = rb_y + al256(sizeof(double) * (size_t)count * m);
@@ -222,13 +222,12 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
     }
     const BatchShape shape = residual_batched_shape(probs, count, pls.data(), 0);
     const bool has32 = o->inner_prec == BIM_FP32C;
-    int max_groups = 0, max_rows = 0;
+    int max_groups = 0;
     bool has_pc = false;
     for (int i = 0; i < count; ++i)
         if (I[i].pc) {
             has_pc = true;
             max_groups = std::max(max_groups, I[i].pc->M * ((I[i].pc->s + 3) / 4));
-            max_rows = std::max(max_rows, (int)I[i].pc->n);
         }
     auto OPS = [&](int slice) { return dops + (size_t)slice * count; };
 
@@ -249,12 +248,15 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
         if ((q = b_dot(OPS(S_GB), count, true, s))) return q;
         if ((q = b_scale_inv(OPS(S_GV), count, s))) return q;
         // preconditioner applies, stage by stage in the order of precond_apply_enqueue:
-        // five banded products, the dense Schur product, two banded products
+        // five banded products, the Schur inverse (lower triangular product,
+        // block-diagonal product, upper triangular product), two banded products
         if (has_pc) {
             for (int stg = 0; stg < 5; ++stg)
                 if ((q = b_bandmv(dbands + (size_t)stg * count, count, max_groups, s))) return q;
-            if ((q = b_gemv(dgemv, count, max_rows, s))) return q;
-            for (int stg = 5; stg < kPcStages; ++stg)
+            if ((q = b_gemv_tri(dgemv, count, max_groups, s))) return q;
+            if ((q = b_bandmv(dbands + (size_t)5 * count, count, max_groups, s))) return q;
+            if ((q = b_gemv_tri(dgemv + count, count, max_groups, s))) return q;
+            for (int stg = 6; stg < kPcStages; ++stg)
                 if ((q = b_bandmv(dbands + (size_t)stg * count, count, max_groups, s))) return q;
         }
         if ((q = b_axpby(OPS(S_LS), count, s))) return q;  // unpreconditioned copies and line-search points
@@ -390,9 +392,11 @@ int solve_batched_impl(const bim_problem *probs, int count, bim_precond *const *
                             b[2 * st] = {arr(1), t3, nullptr, a3, M, 0, ss, 1.0, 0.0, f};   // Dinv22
                             b[3 * st] = {arr(3), a1, r2, t2, M, h, ss, -1.0, 1.0, f};       // B21
                             b[4 * st] = {arr(4), a3, t2, t2, M, h, ss, -1.0, 1.0, f};       // B23
-                            hgemv[i] = {arr(7), t2, nullptr, z2, nn, (int)nn, (int)nn, 1.0, 0.0, f};  // S^-1
-                            b[5 * st] = {arr(6), z2, a3, z3, M, h, ss, -1.0, 1.0, f};       // G
-                            b[6 * st] = {arr(2), z2, a1, z1, M, 0, ss, -1.0, 1.0, f};       // E
+                            hgemv[i] = {arr(7), t2, t2, t3, nn, M, ss, 1, 1.0, 1.0, f};           // L^-1
+                            b[5 * st] = {arr(8), t3, nullptr, t2, M, 0, ss, 1.0, 0.0, f};   // D^-1
+                            hgemv[st + i] = {arr(7), t2, t2, z2, nn, M, ss, 2, 1.0, 1.0, f};      // V^-1
+                            b[6 * st] = {arr(6), z2, a3, z3, M, h, ss, -1.0, 1.0, f};       // G
+                            b[7 * st] = {arr(2), z2, a1, z1, M, 0, ss, -1.0, 1.0, f};       // E
                         } else {
                             put(S_LS, i, {v, nullptr, z, nullptr, nullptr, nullptr, q.n, 0, 0, 1.0, 0.0});
                         }

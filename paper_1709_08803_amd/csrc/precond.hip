@@ -17,8 +17,11 @@
 //      a1 = P11^-1 r1,  a3 = P33^-1 (r3 - P31 a1)
 //      z2 = S^-1 (r2 - P21 a1 - P23 a3),  z3 = a3 - G z2,  z1 = a1 - E z2.
 // S is factored by a block LU without inter-block pivoting (its diagonal
-// blocks are inverted with partial pivoting) and its inverse is formed
-// explicitly, so that the apply is one dense GEMV plus banded products, all
+// blocks are inverted with partial pivoting), S = L D V with L, V unit block-
+// triangular and D the pivot blocks, and its inverse is kept explicitly as
+// V^-1 D^-1 L^-1: the two triangular inverses in one dense n x n array, D^-1 in
+// a block-diagonal one.  The apply is then two triangular GEMVs (together one
+// pass over the array), a block-diagonal product and banded products, all
 // bound by HBM bandwidth.
 #include <hip/hip_runtime.h>
 
@@ -210,14 +213,15 @@ static double *band_blk(double *band, int w, int s, int l, int m) {
     return band + ((size_t)l * (2 * w + 1) + (m - l + w)) * s * s;
 }
 
-// FP32 storage: the eight arrays the apply reads are rounded into a new, half-
+// FP32 storage: the nine arrays the apply reads are rounded into a new, half-
 // sized allocation (with the apply scratch), and the FP64 allocation is freed.
 static int precond_round_to_fp32(Precond *pc, hipStream_t st) {
     const int M = pc->M, s = pc->s, h = pc->h;
     const long n = pc->n;
-    const size_t cnt[8] = {band_elems(M, 0, s), band_elems(M, 0, s), band_elems(M, 0, s), band_elems(M, h, s),
-                           band_elems(M, h, s), band_elems(M, h, s), band_elems(M, h, s), (size_t)n * n};
-    double *src[8] = {pc->Dinv11, pc->Dinv22, pc->E, pc->B21, pc->B23, pc->B31, pc->G, pc->Sinv};
+    const size_t cnt[9] = {band_elems(M, 0, s), band_elems(M, 0, s), band_elems(M, 0, s), band_elems(M, h, s),
+                           band_elems(M, h, s), band_elems(M, h, s), band_elems(M, h, s), (size_t)n * n,
+                           band_elems(M, 0, s)};
+    double *src[9] = {pc->Dinv11, pc->Dinv22, pc->E, pc->B21, pc->B23, pc->B31, pc->G, pc->Sinv, pc->Uinv};
     size_t bytes = 0;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     for (size_t c : cnt) bytes += al(sizeof(float) * c);
@@ -226,9 +230,9 @@ static int precond_round_to_fp32(Precond *pc, hipStream_t st) {
     int rc = hip_check(hipMalloc(&mem, bytes), "hipMalloc(preconditioner, FP32)");
     if (rc) return rc;
     DevArena ar{(char *)mem, 0, bytes};
-    float **dst[8] = {&pc->f32.Dinv11, &pc->f32.Dinv22, &pc->f32.E, &pc->f32.B21,
-                      &pc->f32.B23,    &pc->f32.B31,    &pc->f32.G, &pc->f32.Sinv};
-    for (int q = 0; q < 8 && !rc; ++q) {
+    float **dst[9] = {&pc->f32.Dinv11, &pc->f32.Dinv22, &pc->f32.E,    &pc->f32.B21, &pc->f32.B23,
+                      &pc->f32.B31,    &pc->f32.G,      &pc->f32.Sinv, &pc->f32.Uinv};
+    for (int q = 0; q < 9 && !rc; ++q) {
         *dst[q] = ar.take<float>(cnt[q]);
         rc = to_float_enqueue(src[q], *dst[q], cnt[q], st);
     }
@@ -244,7 +248,7 @@ static int precond_round_to_fp32(Precond *pc, hipStream_t st) {
     pc->mem = mem;
     pc->bytes = bytes;
     pc->scratch = scratch;
-    pc->Dinv11 = pc->Dinv22 = pc->E = pc->B21 = pc->B23 = pc->B31 = pc->G = pc->Sinv = nullptr;
+    pc->Dinv11 = pc->Dinv22 = pc->E = pc->B21 = pc->B23 = pc->B31 = pc->G = pc->Sinv = pc->Uinv = nullptr;
     pc->storage = BIM_STORE_FP32;
     return BIM_OK;
 }
@@ -271,7 +275,8 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     add(band_elems(M, h, s));  // B23
     add(band_elems(M, h, s));  // B31
     add(band_elems(M, h, s));  // G
-    add((size_t)n * n);        // S^-1
+    add((size_t)n * n);        // L^-1 | I | V^-1
+    add(band_elems(M, 0, s));  // D^-1 (inverse pivot blocks)
     add((size_t)4 * n);        // apply scratch
     pc->bytes = pers;
     int rc = hip_check(hipMalloc(&pc->mem, pers), "hipMalloc(preconditioner)");
@@ -288,6 +293,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     pc->B31 = ar.take<double>(band_elems(M, h, s));
     pc->G = ar.take<double>(band_elems(M, h, s));
     pc->Sinv = ar.take<double>((size_t)n * n);
+    pc->Uinv = ar.take<double>(band_elems(M, 0, s));
     pc->scratch = ar.take<double>((size_t)4 * n);
 
     // setup-only scratch
@@ -298,17 +304,19 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     addt(sizeof(double) * 2 * d.ntg);               // rowsum5, I5
     addt(sizeof(double) * band_elems(M, h, s));     // T (band h)
     addt(sizeof(double) * band_elems(M, w2, s));    // S band 2h
-    addt(sizeof(double) * (size_t)M * s * s);       // Uinv
     addt(sizeof(double) * (size_t)M * s * w2 * s);  // L rows
     addt(sizeof(double) * (size_t)M * s * w2 * s);  // U rows
     if (storage == BIM_STORE_FP32) addt(sizeof(float) * (size_t)M * s * w2 * s);  // L rows in FP32
-    addt(sizeof(double) * (size_t)s * n);           // one block row of S^-1 (temp)
+    addt(sizeof(double) * (size_t)s * s);           // E (one block)
     addt(sizeof(double) * (size_t)4 * s * 2 * s);   // inversion work
     addt(sizeof(int) * 3 * (M + 2));                // info (2 more per block for split inversions)
     addt(sizeof(SplitInv) * (M + 2));               // split-inversion plans (192 < s <= 384)
     const size_t nitems = 64 + (size_t)M * (2 * h + 1) * 4 + (size_t)M * (2 * w2 + 1) * (2 * h + 3) +
-                          (size_t)M * (w2 * w2 + w2 + 2) + 3 * (size_t)M + 16;
+                          (size_t)M * (w2 * w2 + w2 + 2) + 16;
     addt(sizeof(GemmItem) * nitems);
+    addt(sizeof(GemmItem) * M);              // V rows
+    addt(sizeof(GemmTriItem) * 2 * M);       // triangular substitutions
+    addt(sizeof(GemmTriItemF) * 2 * M);      // the same in FP32
     addt(sizeof(InvItem) * (M + 4));
     addt(sizeof(GemmKItem) * (size_t)M * (2 * w2 + 1));
     void *tbase = nullptr;
@@ -328,11 +336,11 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     double *I5 = rowsum + d.ntg;
     double *T = ta.take<double>(band_elems(M, h, s));
     double *S = ta.take<double>(band_elems(M, w2, s));
-    double *Uinv = ta.take<double>((size_t)M * s * s);
+    double *const Uinv = pc->Uinv;
     double *Lrow = ta.take<double>((size_t)M * s * w2 * s);
     double *Urow = ta.take<double>((size_t)M * s * w2 * s);
     float *L32 = (storage == BIM_STORE_FP32) ? ta.take<float>((size_t)M * s * w2 * s) : nullptr;
-    double *rowtmp = ta.take<double>((size_t)s * n);
+    double *rowtmp = ta.take<double>((size_t)s * s);
     double *invwork = ta.take<double>((size_t)4 * s * 2 * s);
     int *info = ta.take<int>(3 * (M + 2));
     SplitInv *plans_dev = ta.take<SplitInv>(M + 2);
@@ -340,6 +348,9 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     GemmItem *items_dev = ta.take<GemmItem>(nitems);
     InvItem *inv_dev = ta.take<InvItem>(M + 4);
     GemmKItem *kitems_dev = ta.take<GemmKItem>((size_t)M * (2 * w2 + 1));
+    GemmItem *vitems_dev = ta.take<GemmItem>(M);
+    GemmTriItem *tri_dev = ta.take<GemmTriItem>((size_t)2 * M);
+    GemmTriItemF *tri32_dev = ta.take<GemmTriItemF>((size_t)2 * M);
 
     std::vector<GemmItem> items;
     items.reserve(nitems);
@@ -441,25 +452,21 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                 kitems.push_back({band_blk(pc->B23, h, s, l, q0), band_blk(pc->G, h, s, q0, m), band_blk(S, w2, s, l, m),
                                   (long)(q1 - q0 + 1)});
         }
-    // block LU of S (band 2h): per step l, L[q][l] = S[q][l] Uinv[l] (into Lrow), then
-    // S[q][m] -= L[q][l] S[l][m] for q, m in l+1..l+2h
-    std::vector<size_t> lu_ops_first(M), lu_ops_count(M);
+    // block LU of S (band 2h): per step l, L[q][l] = S[q][l] Uinv[l] (into Lrow, leading
+    // dim 2h s), then S[q][m] -= L[q][l] S[l][m] for q, m in l+1..l+2h
+    const size_t elim_end = ops.size();
+    std::vector<long> op_bl(M, -1), op_upd(M, -1);
     for (int l = 0; l < M; ++l) {
-        lu_ops_first[l] = ops.size();
+        const int hi = std::min(M - 1, l + w2);
+        auto Lblk = [&](int q) { return Lrow + ((size_t)q * s) * (w2 * s) + (size_t)(l - (q - w2)) * s; };
         std::vector<GemmItem> bl, bu;
-        for (int q = l + 1; q <= std::min(M - 1, l + w2); ++q) {
-            double *Lql = Lrow + ((size_t)q * s) * (w2 * s) + (size_t)(l - (q - w2)) * s;  // ld = w2 s
-            bl.push_back({band_blk(S, w2, s, q, l), Uinv + (size_t)l * s * s, Lql});
-        }
+        for (int q = l + 1; q <= hi; ++q) bl.push_back({band_blk(S, w2, s, q, l), Uinv + (size_t)l * s * s, Lblk(q)});
+        for (int q = l + 1; q <= hi; ++q)
+            for (int m = l + 1; m <= hi; ++m) bu.push_back({Lblk(q), band_blk(S, w2, s, l, m), band_blk(S, w2, s, q, m)});
+        if (!bl.empty()) op_bl[l] = (long)ops.size();
         gemm(bl, s, s, s, s, s, w2 * s, 1.0, 0.0);
-        for (int q = l + 1; q <= std::min(M - 1, l + w2); ++q)
-            for (int m = l + 1; m <= std::min(M - 1, l + w2); ++m) {
-                const double *Lql = Lrow + ((size_t)q * s) * (w2 * s) + (size_t)(l - (q - w2)) * s;
-                bu.push_back({Lql, band_blk(S, w2, s, l, m), band_blk(S, w2, s, q, m)});
-            }
-        // lda of L blocks is w2 s; other operands s: handled by a dedicated op (A stride differs)
+        if (!bu.empty()) op_upd[l] = (long)ops.size();
         gemm(bu, s, s, s, w2 * s, s, s, -1.0, 1.0);
-        lu_ops_count[l] = ops.size() - lu_ops_first[l];
     }
     for (int l = 0; l < M; ++l) invs.push_back({band_blk(S, w2, s, l, l), s, Uinv + (size_t)l * s * s, s});
 
@@ -474,12 +481,12 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                                  st),
                   "copy"));
     {
-        auto run_op = [&](const Op &o) {
+        auto run_op = [&](const Op &o, hipStream_t on) {
             return gemm_enqueue(items_dev + o.first, o.count, o.m, o.nn, o.k, o.lda, o.ldb, o.ldc, o.alpha, o.beta,
-                                st);
+                                on);
         };
         // E, replicated
-        RUN(run_op(ops[0]));
+        RUN(run_op(ops[0], st));
         hipLaunchKernelGGL(k_replicate, dim3(cdiv((long)M * s * s, 256)), dim3(256), 0, st, rowtmp, pc->E, M,
                            (long)s * s);
         // T := B23 ; S := 0 with D22 on the diagonal
@@ -487,7 +494,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         RUN(hip_check(hipMemsetAsync(S, 0, sizeof(double) * band_elems(M, w2, s), st), "memset"));
         const long bs = (long)s * s, brow = (long)(2 * w2 + 1) * bs;  // one block; one block row of S
         RUN(copy_blocks_enqueue(D22, 0, 0, s, band_blk(S, w2, s, 0, 0), brow, 0, s, s, s, M, 1, M, st));
-        for (size_t q = 1; q < lu_ops_first[0]; ++q) RUN(run_op(ops[q]));
+        for (size_t q = 1; q < elim_end; ++q) RUN(run_op(ops[q], st));
         RUN(gemm_kblocks_enqueue(kitems_dev, (int)kitems.size(), s, s, s, s, s, s, (long)s * s, (long)2 * h * s * s,
                                  -1.0, 1.0, st));
         // zero L/U row buffers (short rows at the ends stay zero)
@@ -495,101 +502,82 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         RUN(hip_check(hipMemsetAsync(Urow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));
         for (int l = 0; l < M; ++l) {
             RUN(invert_range(2 + l, 1));
-            for (size_t q = 0; q < lu_ops_count[l]; ++q) RUN(run_op(ops[lu_ops_first[l] + q]));
+            for (long o : {op_bl[l], op_upd[l]})
+                if (o >= 0) RUN(run_op(ops[o], st));
         }
         // U rows: U[l][m] for m = l+1..l+2h packed as [l][s][2h s] (block j = m - l - 1,
         // copied while l + j + 1 < M)
         RUN(copy_blocks_enqueue(S + (size_t)(w2 + 1) * bs, brow, bs, s, Urow, (long)s * w2 * s, s, (long)w2 * s, s, s,
                                 M, w2, M - 1, st));
-        // S^-1: forward with L (unit lower), backward with U (in FP32 when the
-        // operator is stored in FP32 and the block rows fit the FP32 panel kernel)
+        // S = L D V with D the pivot blocks and V = D^-1 U unit upper: the rows of V,
+        // V[l][m] = Uinv[l] U[l][m], into the memory of S (no longer read)
+        // (the host item arrays stay alive until the closing synchronisation)
+        double *Vrow = S;
+        std::vector<GemmItem> vi;
+        std::vector<GemmTriItemF> tf;
+        {
+            for (int l = 0; l < M; ++l)
+                vi.push_back({pc->Uinv + (size_t)l * s * s, Urow + (size_t)l * s * w2 * s, Vrow + (size_t)l * s * w2 * s});
+            RUN(hip_check(hipMemcpyAsync(vitems_dev, vi.data(), sizeof(GemmItem) * vi.size(), hipMemcpyHostToDevice, st),
+                          "copy"));
+            RUN(gemm_enqueue(vitems_dev, M, s, w2 * s, s, s, w2 * s, w2 * s, 1.0, 0.0, st));
+        }
+        // S^-1 = V^-1 D^-1 L^-1: L^-1 (unit lower) below the block diagonal of Sinv and
+        // V^-1 (unit upper) above it, identity blocks on it, both read by the
+        // substitutions and never written:
+        //   row block l of L^-1:  X[l][c] = -sum_{q = max(q0, c)}^{l-1} L[l][q] X[q][c],  c < l
+        //   row block l of V^-1:  Y[l][c] = -sum_{m = l+1}^{min(c, l+2h)} V[l][m] Y[m][c],  c > l
+        // (q0 = max(0, l - 2h)).  Step j computes row j of L^-1 and row M-1-j of V^-1 in
+        // one launch (both j column blocks wide, at most 2h K blocks deep); the two
+        // touch disjoint triangles.  In FP32 (FP32-stored operator and 128 < s <= 192)
+        // both run on FP32 copies of L and V into the FP32 Sinv.
         const bool bw32 = storage == BIM_STORE_FP32 && s > 128 && s <= 192;
         RUN(identity_enqueue(pc->Sinv, n, st));
-        std::vector<GemmItem> fw, bw1, bw2;
-        for (int l = 1; l < M; ++l) {
-            const int q0 = std::max(0, l - w2);
-            fw.push_back({Lrow + ((size_t)l * s) * (w2 * s) + (size_t)(q0 - (l - w2)) * s, pc->Sinv + (size_t)q0 * s * n,
-                          pc->Sinv + (size_t)l * s * n});
+        const int far = 1 << 29;  // an offset that leaves klo at 0 / khi at nk
+        std::vector<GemmTriItem> tri;
+        std::vector<long> kmax(M, 0), work(M, 0);
+        for (int j = 1; j < M; ++j) {
+            const int lf = j, q0 = std::max(0, lf - w2), nkf = lf - q0;
+            tri.push_back({Lrow + ((size_t)lf * s) * (w2 * s) + (size_t)(q0 - (lf - w2)) * s, pc->Sinv + (size_t)q0 * s * n,
+                           pc->Sinv + (size_t)lf * s * n, nkf, 0, lf, q0, -far});
+            const int lb = M - 1 - j, nkb = std::min(M - 1, lb + w2) - lb;
+            tri.push_back({Vrow + ((size_t)lb * s) * (w2 * s), pc->Sinv + (size_t)(lb + 1) * s * n,
+                           pc->Sinv + (size_t)lb * s * n, nkb, lb + 1, M - 1 - lb, far, lb});
+            kmax[j] = std::max(nkf, nkb);
+            for (int cb = 0; cb < lf; ++cb) work[j] += nkf - std::max(0, cb - q0);
+            for (int cb = lb + 1; cb < M; ++cb) work[j] += std::min(nkb, cb - lb);
         }
-        for (int l = M - 1; l >= 0; --l) {
-            bw1.push_back({Urow + ((size_t)l * s) * (w2 * s), pc->Sinv + (size_t)(l + 1) * s * n,
-                           pc->Sinv + (size_t)l * s * n});
-            bw2.push_back({Uinv + (size_t)l * s * s, pc->Sinv + (size_t)l * s * n, rowtmp});
-        }
-        const size_t base = items.size();
-        std::vector<GemmItem> all;
-        all.insert(all.end(), fw.begin(), fw.end());
-        all.insert(all.end(), bw1.begin(), bw1.end());
-        all.insert(all.end(), bw2.begin(), bw2.end());
-        (void)base;
-        GemmItem *sv_dev = items_dev + items.size();
-        if (items.size() + all.size() > nitems)
-            return fail(BIM_EINVAL, "internal: preconditioner item buffer too small");
-        RUN(hip_check(hipMemcpyAsync(sv_dev, all.data(), sizeof(GemmItem) * all.size(), hipMemcpyHostToDevice, st),
-                      "copy"));
         if (!bw32) {
-            for (int l = 1; l < M; ++l) {
-                const int q0 = std::max(0, l - w2);
-                // only columns of block rows < l can be nonzero in rows q < l of L^-1
-                RUN(gemm_enqueue(sv_dev + (l - 1), 1, s, l * s, (l - q0) * s, w2 * s, (int)n, (int)n, -1.0, 1.0,
-                                 st));
-            }
-        }
-        if (bw32) {
-            // FP32 storage: round the operator (S^-1 = I so far) to FP32 now and
-            // run both substitutions in FP32 on the matrix cores, into the FP32
-            // S^-1: the L rows are rounded into their own buffer, then the U rows
-            // and pivot inverses into the FP64 L rows' memory, which the rounding
-            // has read; rowtmp holds an FP32 block row.
+            if (!tri.empty())
+                RUN(hip_check(hipMemcpyAsync(tri_dev, tri.data(), sizeof(GemmTriItem) * tri.size(), hipMemcpyHostToDevice,
+                                             st),
+                              "copy"));
+            for (int j = 1; j < M; ++j)
+                RUN(gemm_tri_enqueue(tri_dev + 2 * (j - 1), 2, s, j, kmax[j], work[j], w2 * s, (int)n, (int)n, -1.0, st));
+        } else {
+            // round the operator (Sinv = I so far) to FP32 now, then L and V into
+            // their FP32 copies (V's into the memory of the FP64 U rows)
+            const double *Sinv64 = pc->Sinv;
             RUN(precond_round_to_fp32(pc, st));
             float *S32 = pc->f32.Sinv;
+            float *V32 = (float *)Urow;
             RUN(to_float_enqueue(Lrow, L32, (size_t)M * s * w2 * s, st));
-            float *U32 = (float *)Lrow;
-            float *Ui32 = U32 + (size_t)M * s * w2 * s;
-            float *row32 = (float *)rowtmp;
-            RUN(to_float_enqueue(Urow, U32, (size_t)M * s * w2 * s, st));
-            RUN(to_float_enqueue(Uinv, Ui32, (size_t)M * s * s, st));
-            std::vector<GemmItemF> bf;  // forward items (M - 1), then two per backward step
-            for (int l = 1; l < M; ++l) {
-                const int q0 = std::max(0, l - w2);
-                bf.push_back({L32 + ((size_t)l * s) * (w2 * s) + (size_t)(q0 - (l - w2)) * s,
-                              S32 + (size_t)q0 * s * n, S32 + (size_t)l * s * n});
+            RUN(to_float_enqueue(Vrow, V32, (size_t)M * s * w2 * s, st));
+            for (size_t i = 0; i < tri.size(); ++i) {
+                const GemmTriItem &t = tri[i];
+                const bool fwd = (i % 2) == 0;
+                const float *Ab = fwd ? L32 : V32;
+                const double *Ad = fwd ? Lrow : Vrow;
+                tf.push_back({Ab + (t.A - Ad), S32 + (t.B - Sinv64), S32 + (t.C - Sinv64), t.nk, t.cb0, t.ncb,
+                              t.lo_off, t.hi_off});
             }
-            for (int l = M - 1; l >= 0; --l) {
-                bf.push_back({U32 + ((size_t)l * s) * (w2 * s), S32 + (size_t)(l + 1) * s * n, S32 + (size_t)l * s * n});
-                bf.push_back({Ui32 + (size_t)l * s * s, S32 + (size_t)l * s * n, row32});
-            }
-            GemmItemF *bf_dev = (GemmItemF *)(sv_dev + all.size());
-            if (items.size() + all.size() + bf.size() > nitems)
-                return fail(BIM_EINVAL, "internal: preconditioner item buffer too small");
-            RUN(hip_check(hipMemcpyAsync(bf_dev, bf.data(), sizeof(GemmItemF) * bf.size(), hipMemcpyHostToDevice, st),
-                          "copy"));
-            for (int l = 1; l < M; ++l) {
-                const int q0 = std::max(0, l - w2);
-                RUN(gemm_f32_enqueue(bf_dev + (l - 1), 1, s, l * s, (l - q0) * s, w2 * s, (int)n, (int)n, -1.0, 1.0,
-                                     st));
-            }
-            bf_dev += M - 1;
-            for (int t = 0; t < M; ++t) {
-                const int l = M - 1 - t;
-                const int kk = std::min(M - 1, l + w2) - l;
-                if (kk > 0)
-                    RUN(gemm_f32_enqueue(bf_dev + 2 * t, 1, s, (int)n, kk * s, w2 * s, (int)n, (int)n, -1.0, 1.0, st));
-                RUN(gemm_f32_enqueue(bf_dev + 2 * t + 1, 1, s, (int)n, s, s, (int)n, (int)n, 1.0, 0.0, st));
-                RUN(hip_check(hipMemcpyAsync(S32 + (size_t)l * s * n, row32, sizeof(float) * (size_t)s * n,
-                                             hipMemcpyDeviceToDevice, st),
+            if (!tf.empty())
+                RUN(hip_check(hipMemcpyAsync(tri32_dev, tf.data(), sizeof(GemmTriItemF) * tf.size(),
+                                             hipMemcpyHostToDevice, st),
                               "copy"));
-            }
-        } else {
-            for (int t = 0; t < M; ++t) {
-                const int l = M - 1 - t;
-                const int kk = std::min(M - 1, l + w2) - l;  // number of blocks to the right
-                if (kk > 0)
-                    RUN(gemm_enqueue(sv_dev + (M - 1) + t, 1, s, (int)n, kk * s, w2 * s, (int)n, (int)n, -1.0, 1.0,
+            for (int j = 1; j < M; ++j)
+                RUN(gemm_tri_enqueue(tri32_dev + 2 * (j - 1), 2, s, j, kmax[j], work[j], w2 * s, (int)n, (int)n, -1.0,
                                      st));
-                RUN(gemm_enqueue(sv_dev + (M - 1) + M + t, 1, s, (int)n, s, s, (int)n, (int)n, 1.0, 0.0, st));
-                RUN(copy2d_enqueue(rowtmp, n, pc->Sinv + (size_t)l * s * n, n, s, (int)n, st));
-            }
         }
         // a zero pivot in any inverted block makes P singular in this factorisation
         std::vector<int> hinfo(3 * (2 + M), 0);
@@ -630,18 +618,22 @@ static int precond_apply_impl(const Precond *pc, const PrecondArrays<const T> &a
     if ((rc = bandmv_enqueue(a.Dinv22, M, 0, s, t3, nullptr, a3, 1.0, 0.0, st))) return rc;       // a3
     if ((rc = bandmv_enqueue(a.B21, M, h, s, a1, r2, t2, -1.0, 1.0, st))) return rc;              // r2 - P21 a1
     if ((rc = bandmv_enqueue(a.B23, M, h, s, a3, t2, t2, -1.0, 1.0, st))) return rc;              // - P23 a3
-    if ((rc = gemv_enqueue(a.Sinv, n, t2, nullptr, z2, (int)n, (int)n, 1.0, 0.0, st))) return rc; // z2
+    // z2 = V^-1 D^-1 L^-1 t2 (t3 is free once a3 is formed)
+    if ((rc = gemv_tri_enqueue(a.Sinv, n, M, s, 1, t2, t2, t3, 1.0, 1.0, st))) return rc;         // L^-1 t2
+    if ((rc = bandmv_enqueue(a.Uinv, M, 0, s, t3, nullptr, t2, 1.0, 0.0, st))) return rc;         // D^-1
+    if ((rc = gemv_tri_enqueue(a.Sinv, n, M, s, 2, t2, t2, z2, 1.0, 1.0, st))) return rc;         // V^-1
     if ((rc = bandmv_enqueue(a.G, M, h, s, z2, a3, z3, -1.0, 1.0, st))) return rc;                // z3
     return bandmv_enqueue(a.E, M, 0, s, z2, a1, z1, -1.0, 1.0, st);                               // z1
 }
 
 int precond_apply_enqueue(const Precond *pc, const double *r, double *z, hipStream_t st) {
     if (pc->storage == BIM_STORE_FP32) {
-        const PrecondArrays<const float> a{pc->f32.Dinv11, pc->f32.Dinv22, pc->f32.E, pc->f32.B21,
-                                           pc->f32.B23,    pc->f32.B31,    pc->f32.G, pc->f32.Sinv};
+        const PrecondArrays<const float> a{pc->f32.Dinv11, pc->f32.Dinv22, pc->f32.E,    pc->f32.B21, pc->f32.B23,
+                                           pc->f32.B31,    pc->f32.G,      pc->f32.Sinv, pc->f32.Uinv};
         return precond_apply_impl(pc, a, r, z, st);
     }
-    const PrecondArrays<const double> a{pc->Dinv11, pc->Dinv22, pc->E, pc->B21, pc->B23, pc->B31, pc->G, pc->Sinv};
+    const PrecondArrays<const double> a{pc->Dinv11, pc->Dinv22, pc->E,    pc->B21, pc->B23,
+                                        pc->B31,    pc->G,      pc->Sinv, pc->Uinv};
     return precond_apply_impl(pc, a, r, z, st);
 }
 
@@ -655,7 +647,9 @@ const void *precond_array(const Precond *pc, int which) {
         case 4: return f ? (const void *)pc->f32.B23 : (const void *)pc->B23;
         case 5: return f ? (const void *)pc->f32.B31 : (const void *)pc->B31;
         case 6: return f ? (const void *)pc->f32.G : (const void *)pc->G;
-        default: return f ? (const void *)pc->f32.Sinv : (const void *)pc->Sinv;
+        case 7: return f ? (const void *)pc->f32.Sinv : (const void *)pc->Sinv;
+        case 8: return f ? (const void *)pc->f32.Uinv : (const void *)pc->Uinv;
+        default: return nullptr;
     }
 }
 
