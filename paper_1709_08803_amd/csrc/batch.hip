@@ -198,29 +198,49 @@ __global__ __launch_bounds__(256) void k_bbandmv(const BBand *__restrict__ ops) 
     brows_store(acc, lane, min(kBGR, o.s - r0), o.y, o.c, l * o.s + r0, o.alpha, o.beta);
 }
 
+// Strictly lower / upper triangular products: as k_gemv_tri of the single-
+// problem path, one 256-thread workgroup per GR rows of one slice, the four
+// waves on the four quarters of the row range, partial sums added in LDS.
 template <typename TA>
-__device__ __forceinline__ void bgemv_tri_rows(const BGemv &o, int l, int r0, int lane, double (&acc)[kBGR]) {
+__device__ __forceinline__ void bgemv_tri_rows(const BGemv &o, int l, int r0, int wv, int lane,
+                                               double (&acc)[kBGR]) {
     const TA *A = (const TA *)o.A;
     const long c0 = (o.part == 1) ? 0 : (long)(l + 1) * o.s, c1 = (o.part == 1) ? (long)l * o.s : o.n;
+    const long len = c1 - c0;
     const bool vec = (o.s % 2 == 0) && (o.n % 2 == 0) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) &&
                      ((uintptr_t)o.x % 16 == 0);
+    const long ql = vec ? 2 * ((len / 2 + 3) / 4) : (len + 3) / 4;
+    const long q0 = min(len, (long)wv * ql), q1 = min(len, q0 + ql);
     const TA *row[kBGR];
 #pragma unroll
-    for (int r = 0; r < kBGR; ++r) row[r] = A + ((size_t)l * o.s + min(r0 + r, o.s - 1)) * o.n + c0;
-    brows_dot<TA>(row, o.x + c0, (int)(c1 - c0), vec, lane, acc);
+    for (int r = 0; r < kBGR; ++r) row[r] = A + ((size_t)l * o.s + min(r0 + r, o.s - 1)) * o.n + c0 + q0;
+    brows_dot<TA>(row, o.x + c0 + q0, (int)(q1 - q0), vec, lane, acc);
 }
 
 __global__ __launch_bounds__(256) void k_bgemv_tri(const BGemv *__restrict__ ops) {
+    __shared__ double partial[4][kBGR];
     const BGemv o = ops[blockIdx.y];
     const int gps = (o.s + kBGR - 1) / kBGR;  // row groups per slice
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (wave >= o.M * gps) return;
-    const int l = wave / gps, r0 = (wave - l * gps) * kBGR;
+    const int g = blockIdx.x;
+    if (g >= o.M * gps) return;  // uniform in the workgroup (also the empty slots, M = 0)
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lw = g / gps, r0 = (g - lw * gps) * kBGR;
+    const int l = (o.part == 1) ? o.M - 1 - lw : lw;  // the longest rows first
     double acc[kBGR] = {};
-    if (o.f32) bgemv_tri_rows<float>(o, l, r0, lane, acc);
-    else bgemv_tri_rows<double>(o, l, r0, lane, acc);
-    brows_store(acc, lane, min(kBGR, o.s - r0), o.y, o.c, l * o.s + r0, o.alpha, o.beta);
+    if (o.f32) bgemv_tri_rows<float>(o, l, r0, wv, lane, acc);
+    else bgemv_tri_rows<double>(o, l, r0, wv, lane, acc);
+#pragma unroll
+    for (int r = 0; r < kBGR; ++r)
+        for (int off = 32; off > 0; off >>= 1) acc[r] += __shfl_xor(acc[r], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int r = 0; r < kBGR; ++r) partial[wv][r] = acc[r];
+    __syncthreads();
+    if (wv == 0 && lane < kBGR && r0 + lane < o.s) {
+        const double v = ((partial[0][lane] + partial[1][lane]) + partial[2][lane]) + partial[3][lane];
+        const long row = (long)l * o.s + r0 + lane;
+        o.y[row] = (o.beta == 0.0) ? o.alpha * v : fma(o.alpha, v, o.beta * o.c[row]);
+    }
 }
 
 __global__ void k_bgather(const BOp *__restrict__ ops) {
@@ -298,7 +318,8 @@ int b_bandmv(const BBand *ops, int count, int max_groups, hipStream_t s) {
 
 int b_gemv_tri(const BGemv *ops, int count, int max_groups, hipStream_t s) {
     if (count <= 0) return BIM_OK;
-    hipLaunchKernelGGL(k_bgemv_tri, dim3(cdiv(max_groups, 4), count), dim3(256), 0, s, ops);
+    if (max_groups <= 0) return BIM_OK;
+    hipLaunchKernelGGL(k_bgemv_tri, dim3(max_groups, count), dim3(256), 0, s, ops);
     return hip_check(hipGetLastError(), "batched gemv launch");
 }
 

@@ -13,7 +13,6 @@ struct GemmItemT {
     T *C;
 };
 using GemmItem = GemmItemT<double>;
-using GemmItemF = GemmItemT<float>;
 // One product over nkb K-blocks at fixed strides: C = alpha sum_b A_b B_b + beta C.
 struct GemmKItem {
     const double *A;
@@ -26,12 +25,14 @@ struct GemmKItem {
 //   C[:, cb] = alpha sum_{j = klo .. khi-1} A[:, j] B[j, cb],
 //   klo = max(0, cb - lo_off), khi = min(nk, cb - hi_off)
 // (A: s x (nk s); B: nk block rows; C: s rows; zero where klo >= khi).
+// rev != 0: the column blocks are scheduled from the last to the first (for
+// items whose K range grows with cb, so that the deepest start first).
 template <typename T>
 struct GemmTriItemT {
     const T *A;
     const T *B;
     T *C;
-    int nk, cb0, ncb, lo_off, hi_off;
+    int nk, cb0, ncb, lo_off, hi_off, rev;
 };
 using GemmTriItem = GemmTriItemT<double>;
 using GemmTriItemF = GemmTriItemT<float>;
@@ -50,18 +51,12 @@ int gemm_enqueue(const GemmItem *items_dev, int batch, int m, int n, int k, int 
 // m x k with leading dim lda, B_b k x n with ldb); nkb may differ per item.
 int gemm_kblocks_enqueue(const GemmKItem *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
                          long sA, long sB, double alpha, double beta, hipStream_t s);
-// The same product in FP32 (FP32 operands, FP32 accumulation on the matrix
-// cores) for 128 < m <= 192 only (BIM_EINVAL otherwise).
-int gemm_f32_enqueue(const GemmItemF *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
-                     double alpha, double beta, hipStream_t s);
 // Block-triangular products of `batch` items (FP64 or FP32 matrix cores, any
-// block size s); max_ncb: the largest ncb; kmax: the largest khi - klo of any
-// column block; work: the sum of khi - klo over all items' column blocks (the
-// two choose the panel width).
-int gemm_tri_enqueue(const GemmTriItem *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
-                     int ldb, int ldc, double alpha, hipStream_t s_);
-int gemm_tri_enqueue(const GemmTriItemF *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
-                     int ldb, int ldc, double alpha, hipStream_t s_);
+// block size s); max_ncb: the largest ncb.
+int gemm_tri_enqueue(const GemmTriItem *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
+                     double alpha, hipStream_t st);
+int gemm_tri_enqueue(const GemmTriItemF *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
+                     double alpha, hipStream_t st);
 // y = alpha A' x + beta c, A' the strictly lower (part 1) or strictly upper
 // (part 2) block part of the dense n x n A with M x M blocks of s; c may equal x
 // (read per row), y must not alias x.
@@ -91,12 +86,6 @@ size_t split_invert_scratch(int s_dim);
 void split_invert_plan(const InvItem &item, int s_dim, double *scratch, SplitInv *plan);
 // plan_dev: a device copy of plan; info: two ints (zero-pivot flags of the two inversions)
 int split_invert_enqueue(const SplitInv &plan, const SplitInv *plan_dev, int s_dim, int *info, hipStream_t s);
-// y = alpha A x + beta c (dense, rows x cols, row-major with leading dim lda); c may equal y.
-// A in FP64 or FP32 (products and sums in FP64).
-int gemv_enqueue(const double *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
-                 double alpha, double beta, hipStream_t s);
-int gemv_enqueue(const float *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
-                 double alpha, double beta, hipStream_t s);
 // y = alpha B x + beta c for a slice-block-banded B stored [M][2w+1][s][s]; c may equal y.
 int bandmv_enqueue(const double *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
                    double alpha, double beta, hipStream_t s);

@@ -373,18 +373,23 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItemT<T> *__res
 // the triangular structure, which lets two factors' inverses share one array:
 // the blocks of B outside the range may hold the other factor.  Workgroups as
 // in k_gemm_tall: 192-row panels (blockIdx.y) of TN columns, ppb panels per
-// column block (a panel never straddles two column blocks), blockIdx.z the item.
+// column block (a panel never straddles two column blocks).  blockIdx.x walks
+// the items' column blocks together (item = blockIdx.x % batch), each item
+// from its deepest column block to its shallowest (`rev` reverses the column
+// order for items whose K range grows with cb): the long workgroups start first
+// and the short ones fill in after them (one workgroup per compute unit).
 template <int TN, int NW, typename T = double>
-__global__ __launch_bounds__(64 * NW) void k_gemm_tri(const GemmTriItemT<T> *__restrict__ items, int s, int ppb,
-                                                      int lda, int ldb, int ldc, double alpha) {
+__global__ __launch_bounds__(64 * NW) void k_gemm_tri(const GemmTriItemT<T> *__restrict__ items, int batch, int s,
+                                                      int ppb, int lda, int ldb, int ldc, double alpha) {
     constexpr int NT = 64 * NW, NB = TN / 16, RB = 12 / NW;
     constexpr int QA = kTallM * kTallK / NT, QB = (kTallK * TN + NT - 1) / NT;
     static_assert(QA * NT == kTallM * kTallK && RB * NW == 12, "tall tile shape");
     typedef Mfma16<T> MF;
-    const GemmTriItemT<T> it = items[blockIdx.z];
-    const int cbi = blockIdx.x / ppb, pan = blockIdx.x - cbi * ppb;
+    const int bx = blockIdx.x / batch;
+    const GemmTriItemT<T> it = items[blockIdx.x - bx * batch];
+    const int cbi = bx / ppb, pan = bx - cbi * ppb;
     if (cbi >= it.ncb) return;
-    const int cb = it.cb0 + cbi;
+    const int cb = it.cb0 + (it.rev ? it.ncb - 1 - cbi : cbi);
     const int klo = max(0, cb - it.lo_off), khi = min(it.nk, cb - it.hi_off);
     const int row0 = blockIdx.y * kTallM, m = min(kTallM, s - row0);
     const int col0 = cb * s + pan * TN, cend = (cb + 1) * s;
@@ -720,111 +725,42 @@ __global__ __launch_bounds__(kInvThreads) void k_invert(const InvItem *__restric
     }
 }
 
-// y[r] = alpha A[r, :] x + beta c[r] for a dense row-major n_rows x n_cols A
-// with elements of type TA (FP64, or FP32 for a preconditioner stored in FP32;
-// products and sums in FP64): one wave per row.
-template <typename TA>
-__global__ __launch_bounds__(256) void k_gemv(const TA *__restrict__ A, long lda, const double *__restrict__ x,
-                                              const double *c, double *y, int n_rows, int n_cols,
-                                              double alpha, double beta) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (row >= n_rows) return;
-    const TA *a = A + (size_t)row * lda;
-    double v = 0.0;
-    for (int j = lane; j < n_cols; j += 64) v = fma((double)a[j], x[j], v);
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
-}
-
-// Same product for rows aligned to two elements (even lda): each wave owns GR
-// rows and reads two elements per lane per row (16 bytes in FP64, 8 in FP32),
-// loading every x chunk once for its GR rows; two chunks per iteration keep
-// each wave's loads of 2 GR chunks in flight.
-constexpr int GR = 4;
-template <typename TA>
-__global__ __launch_bounds__(256) void k_gemv_rows(const TA *__restrict__ A, long lda,
-                                                   const double *__restrict__ x, const double *c, double *y,
-                                                   int n_rows, int n_cols, double alpha, double beta) {
-    typedef double double2_t __attribute__((ext_vector_type(2)));
-    typedef TA ta2_t __attribute__((ext_vector_type(2)));
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int row0 = wave * GR;
-    if (row0 >= n_rows) return;
-    const TA *arow[GR];
-#pragma unroll
-    for (int r = 0; r < GR; ++r) arow[r] = A + (size_t)min(row0 + r, n_rows - 1) * lda;
-    double acc[GR] = {};
-    const int pairs = n_cols >> 1;
-    int q = lane;
-    for (; q + 64 < pairs; q += 128) {
-        const double2_t x0 = *reinterpret_cast<const double2_t *>(x + 2 * q);
-        const double2_t x1 = *reinterpret_cast<const double2_t *>(x + 2 * (q + 64));
-        ta2_t a0[GR], a1[GR];
-#pragma unroll
-        for (int r = 0; r < GR; ++r) {
-            a0[r] = *reinterpret_cast<const ta2_t *>(arow[r] + 2 * q);
-            a1[r] = *reinterpret_cast<const ta2_t *>(arow[r] + 2 * (q + 64));
-        }
-#pragma unroll
-        for (int r = 0; r < GR; ++r) {
-            acc[r] = fma((double)a0[r][0], x0[0], acc[r]);
-            acc[r] = fma((double)a0[r][1], x0[1], acc[r]);
-            acc[r] = fma((double)a1[r][0], x1[0], acc[r]);
-            acc[r] = fma((double)a1[r][1], x1[1], acc[r]);
-        }
-    }
-    for (; q < pairs; q += 64) {
-        const double2_t x0 = *reinterpret_cast<const double2_t *>(x + 2 * q);
-#pragma unroll
-        for (int r = 0; r < GR; ++r) {
-            const ta2_t a0 = *reinterpret_cast<const ta2_t *>(arow[r] + 2 * q);
-            acc[r] = fma((double)a0[0], x0[0], acc[r]);
-            acc[r] = fma((double)a0[1], x0[1], acc[r]);
-        }
-    }
-    if ((n_cols & 1) && lane == 0) {
-        const int j = n_cols - 1;
-#pragma unroll
-        for (int r = 0; r < GR; ++r) acc[r] = fma((double)arow[r][j], x[j], acc[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < GR; ++r)
-        for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, 64);
-    if (lane < GR && row0 + lane < n_rows) {
-        double v = acc[0];
-#pragma unroll
-        for (int r = 1; r < GR; ++r) v = (lane == r) ? acc[r] : v;
-        const int row = row0 + lane;
-        y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
-    }
-}
+constexpr int GR = 4;  // rows per wave of the matrix-vector products
 
 // y = alpha A' x + beta c for the strictly lower (part 1) or strictly upper
 // (part 2) slice-block part A' of a dense n x n A (M slices of s): row block l
-// reads columns [0, l s) or [(l+1) s, n).  Each wave owns GR rows of one slice;
-// with even s and aligned operands it reads two elements per lane per row.
+// reads columns [0, l s) or [(l+1) s, n).  Each 256-thread workgroup owns GR
+// rows of one slice and its four waves split the row range in quarters (the
+// rows' lengths run from 0 to n - s, and a single wave over a whole row would
+// be the kernel's critical path); the four partial sums are added in LDS.
+// Workgroups are numbered from the longest rows (the last slices of the lower
+// part, the first of the upper).  With even s and aligned operands each lane
+// reads two elements per row.
 template <typename TA>
 __global__ __launch_bounds__(256) void k_gemv_tri(const TA *__restrict__ A, long n, int M, int s, int part,
                                                   bool vec, const double *__restrict__ x, const double *c,
                                                   double *y, double alpha, double beta) {
     typedef double double2_t __attribute__((ext_vector_type(2)));
     typedef TA ta2_t __attribute__((ext_vector_type(2)));
+    __shared__ double partial[4][GR];
     const int gps = (s + GR - 1) / GR;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (wave >= M * gps) return;
-    const int l = wave / gps, r0 = (wave - l * gps) * GR;
+    const int g = blockIdx.x;
+    if (g >= M * gps) return;
+    const int lw = g / gps, r0 = (g - lw * gps) * GR;
+    const int l = (part == 1) ? M - 1 - lw : lw;
     const long c0 = (part == 1) ? 0 : (long)(l + 1) * s, c1 = (part == 1) ? (long)l * s : n;
     const long len = c1 - c0;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // this wave's quarter [q0, q1) of the row range (an even length when vec)
+    const long ql = vec ? 2 * ((len / 2 + 3) / 4) : (len + 3) / 4;
+    const long q0 = min(len, (long)wv * ql), q1 = min(len, q0 + ql);
     const TA *arow[GR];
 #pragma unroll
     for (int r = 0; r < GR; ++r) arow[r] = A + ((size_t)l * s + min(r0 + r, s - 1)) * n + c0;
     const double *xs = x + c0;
     double acc[GR] = {};
     if (vec) {
-        for (long q = lane; q < (len >> 1); q += 64) {
+        for (long q = q0 / 2 + lane; q < q1 / 2; q += 64) {
             const double2_t xv = *reinterpret_cast<const double2_t *>(xs + 2 * q);
 #pragma unroll
             for (int r = 0; r < GR; ++r) {
@@ -833,11 +769,8 @@ __global__ __launch_bounds__(256) void k_gemv_tri(const TA *__restrict__ A, long
                 acc[r] = fma((double)a[1], xv[1], acc[r]);
             }
         }
-        if ((len & 1) && lane == 0)
-#pragma unroll
-            for (int r = 0; r < GR; ++r) acc[r] = fma((double)arow[r][len - 1], xs[len - 1], acc[r]);
     } else {
-        for (long j = lane; j < len; j += 64) {
+        for (long j = q0 + lane; j < q1; j += 64) {
             const double xv = xs[j];
 #pragma unroll
             for (int r = 0; r < GR; ++r) acc[r] = fma((double)arow[r][j], xv, acc[r]);
@@ -846,10 +779,12 @@ __global__ __launch_bounds__(256) void k_gemv_tri(const TA *__restrict__ A, long
 #pragma unroll
     for (int r = 0; r < GR; ++r)
         for (int o = 32; o > 0; o >>= 1) acc[r] += __shfl_xor(acc[r], o, 64);
-    if (lane < GR && r0 + lane < s) {
-        double v = acc[0];
+    if (lane == 0)
 #pragma unroll
-        for (int r = 1; r < GR; ++r) v = (lane == r) ? acc[r] : v;
+        for (int r = 0; r < GR; ++r) partial[wv][r] = acc[r];
+    __syncthreads();
+    if (wv == 0 && lane < GR && r0 + lane < s) {
+        const double v = ((partial[0][lane] + partial[1][lane]) + partial[2][lane]) + partial[3][lane];
         const long row = (long)l * s + r0 + lane;
         y[row] = (beta == 0.0) ? alpha * v : fma(alpha, v, beta * c[row]);
     }
@@ -1062,19 +997,6 @@ int split_invert_enqueue(const SplitInv &P, const SplitInv *D, int s_dim, int *i
 
 namespace {
 template <typename TA>
-int gemv_launch(const TA *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
-                double alpha, double beta, hipStream_t s) {
-    const bool aligned = (lda % 2 == 0) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) && ((uintptr_t)x % 16 == 0);
-    if (aligned)
-        hipLaunchKernelGGL(k_gemv_rows<TA>, dim3(cdiv(rows, 4 * GR)), dim3(256), 0, s, A, lda, x, c, y, rows, cols,
-                           alpha, beta);
-    else
-        hipLaunchKernelGGL(k_gemv<TA>, dim3(cdiv(rows, 4)), dim3(256), 0, s, A, lda, x, c, y, rows, cols, alpha,
-                           beta);
-    return hip_check(hipGetLastError(), "gemv launch");
-}
-
-template <typename TA>
 int bandmv_launch(const TA *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
                   double alpha, double beta, hipStream_t s) {
     const bool aligned = (s_dim % 2 == 0) && ((uintptr_t)band % (2 * sizeof(TA)) == 0) && ((uintptr_t)x % 16 == 0);
@@ -1087,15 +1009,6 @@ int bandmv_launch(const TA *band, int M, int w, int s_dim, const double *x, cons
     return hip_check(hipGetLastError(), "bandmv launch");
 }
 }  // namespace
-
-int gemv_enqueue(const double *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
-                 double alpha, double beta, hipStream_t s) {
-    return gemv_launch(A, lda, x, c, y, rows, cols, alpha, beta, s);
-}
-int gemv_enqueue(const float *A, long lda, const double *x, const double *c, double *y, int rows, int cols,
-                 double alpha, double beta, hipStream_t s) {
-    return gemv_launch(A, lda, x, c, y, rows, cols, alpha, beta, s);
-}
 
 int bandmv_enqueue(const double *band, int M, int w, int s_dim, const double *x, const double *c, double *y,
                    double alpha, double beta, hipStream_t s) {
@@ -1113,68 +1026,24 @@ int to_float_enqueue(const double *src, float *dst, size_t count, hipStream_t s)
     return hip_check(hipGetLastError(), "conversion launch");
 }
 
-int gemm_f32_enqueue(const GemmItemF *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
-                     double alpha, double beta, hipStream_t s) {
-    if (batch <= 0 || m <= 0 || n <= 0) return BIM_OK;
-    if (batch > 65535) return fail(BIM_EINVAL, "gemm batch too large");
-    if (m <= 128 || m > kTallM) return fail(BIM_EINVAL, "FP32 gemm needs 128 < m <= 192");
-    int tn = 64;
-    long best = -1;
-    for (int c : {64, 48, 32}) {  // fewest rounds of 256 workgroups times panel width
-        const long cost = (long)cdiv((long)cdiv(n, c) * batch, 256) * c;
-        if (best < 0 || cost < best) {
-            best = cost;
-            tn = c;
-        }
-    }
-    dim3 grid(cdiv(n, tn), 1, batch);
-    constexpr int NW = kTallWaves;
-    if (tn == 32)
-        hipLaunchKernelGGL((k_gemm_tall<32, NW, float>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
-                           alpha, beta);
-    else if (tn == 48)
-        hipLaunchKernelGGL((k_gemm_tall<48, NW, float>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
-                           alpha, beta);
-    else
-        hipLaunchKernelGGL((k_gemm_tall<64, NW, float>), grid, dim3(64 * NW), 0, s, items_dev, m, n, k, lda, ldb, ldc,
-                           alpha, beta);
-    return hip_check(hipGetLastError(), "gemm launch");
-}
-
 namespace {
-// Panel width of a block-triangular product launch: the time goes as the larger
-// of the deepest workgroup (kmax K blocks of one TN-wide panel) and the total
-// panel work spread over 256 compute units; 32-wide panels issue fewer MFMAs
-// per LDS read and count 15% more.
-int tri_panel_width(int s, long kmax, long work) {
-    int best = 64;
-    double best_cost = -1.0;
-    for (int tn : {64, 48, 32}) {
-        const double ppb = cdiv(s, tn), rp = cdiv(s, kTallM);
-        const double cost = std::max((double)kmax * tn, rp * (double)work * ppb * tn / 256.0) * (tn == 32 ? 1.15 : 1.0);
-        if (best_cost < 0.0 || cost < best_cost) {
-            best_cost = cost;
-            best = tn;
-        }
-    }
-    return best;
-}
+// Panel width of the block-triangular products: 32 (at 181 x 61 the setup took
+// 50.3 ms with 32-wide panels throughout, 51.7 with 48, 54.2 with 64, and 51.0
+// with a per-launch choice between them that weighed the deepest workgroup
+// against the total work: more, narrower panels balance the compute units
+// better than wider panels reuse their A operand).
+constexpr int kTriPanel = 32;
 
 template <typename T>
-int gemm_tri_launch(const GemmTriItemT<T> *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
-                    int ldb, int ldc, double alpha, hipStream_t st) {
+int gemm_tri_launch(const GemmTriItemT<T> *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
+                    double alpha, hipStream_t st) {
     if (batch <= 0 || max_ncb <= 0 || s <= 0) return BIM_OK;
     if (batch > 65535) return fail(BIM_EINVAL, "gemm batch too large");
-    const int tn = tri_panel_width(s, kmax, work), ppb = cdiv(s, tn);
-    if ((long)max_ncb * ppb > 0x7fffffffL) return fail(BIM_EINVAL, "block-triangular product too wide");
-    dim3 grid(max_ncb * ppb, cdiv(s, kTallM), batch);
-    constexpr int NW = kTallWaves;
-    if (tn == 32)
-        hipLaunchKernelGGL((k_gemm_tri<32, NW, T>), grid, dim3(64 * NW), 0, st, items_dev, s, ppb, lda, ldb, ldc, alpha);
-    else if (tn == 48)
-        hipLaunchKernelGGL((k_gemm_tri<48, NW, T>), grid, dim3(64 * NW), 0, st, items_dev, s, ppb, lda, ldb, ldc, alpha);
-    else
-        hipLaunchKernelGGL((k_gemm_tri<64, NW, T>), grid, dim3(64 * NW), 0, st, items_dev, s, ppb, lda, ldb, ldc, alpha);
+    const int ppb = cdiv(s, kTriPanel);
+    if ((long)max_ncb * ppb * batch > 0x7fffffffL) return fail(BIM_EINVAL, "block-triangular product too wide");
+    dim3 grid(max_ncb * ppb * batch, cdiv(s, kTallM), 1);
+    hipLaunchKernelGGL((k_gemm_tri<kTriPanel, kTallWaves, T>), grid, dim3(64 * kTallWaves), 0, st, items_dev, batch, s,
+                       ppb, lda, ldb, ldc, alpha);
     return hip_check(hipGetLastError(), "block-triangular gemm launch");
 }
 
@@ -1184,20 +1053,21 @@ int gemv_tri_launch(const TA *A, long n, int M, int s, int part, const double *x
     if (M <= 0 || s <= 0) return BIM_OK;
     if (part != 1 && part != 2) return fail(BIM_EINVAL, "gemv_tri: part must be 1 (lower) or 2 (upper)");
     const bool vec = (s % 2 == 0) && (n % 2 == 0) && ((uintptr_t)A % (2 * sizeof(TA)) == 0) && ((uintptr_t)x % 16 == 0);
-    const long waves = (long)M * ((s + GR - 1) / GR);
-    hipLaunchKernelGGL(k_gemv_tri<TA>, dim3(cdiv(waves, 4)), dim3(256), 0, st, A, n, M, s, part, vec, x, c, y, alpha,
-                       beta);
+    const long groups = (long)M * ((s + GR - 1) / GR);
+    if (groups > 0x7fffffffL) return fail(BIM_EINVAL, "gemv_tri: too many rows");
+    hipLaunchKernelGGL(k_gemv_tri<TA>, dim3((unsigned)groups), dim3(256), 0, st, A, n, M, s, part, vec, x, c, y,
+                       alpha, beta);
     return hip_check(hipGetLastError(), "gemv_tri launch");
 }
 }  // namespace
 
-int gemm_tri_enqueue(const GemmTriItem *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
-                     int ldb, int ldc, double alpha, hipStream_t st) {
-    return gemm_tri_launch(items_dev, batch, s, max_ncb, kmax, work, lda, ldb, ldc, alpha, st);
+int gemm_tri_enqueue(const GemmTriItem *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
+                     double alpha, hipStream_t st) {
+    return gemm_tri_launch(items_dev, batch, s, max_ncb, lda, ldb, ldc, alpha, st);
 }
-int gemm_tri_enqueue(const GemmTriItemF *items_dev, int batch, int s, int max_ncb, long kmax, long work, int lda,
-                     int ldb, int ldc, double alpha, hipStream_t st) {
-    return gemm_tri_launch(items_dev, batch, s, max_ncb, kmax, work, lda, ldb, ldc, alpha, st);
+int gemm_tri_enqueue(const GemmTriItemF *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
+                     double alpha, hipStream_t st) {
+    return gemm_tri_launch(items_dev, batch, s, max_ncb, lda, ldb, ldc, alpha, st);
 }
 int gemv_tri_enqueue(const double *A, long n, int M, int s, int part, const double *x, const double *c, double *y,
                      double alpha, double beta, hipStream_t st) {

@@ -535,17 +535,13 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         RUN(identity_enqueue(pc->Sinv, n, st));
         const int far = 1 << 29;  // an offset that leaves klo at 0 / khi at nk
         std::vector<GemmTriItem> tri;
-        std::vector<long> kmax(M, 0), work(M, 0);
         for (int j = 1; j < M; ++j) {
             const int lf = j, q0 = std::max(0, lf - w2), nkf = lf - q0;
             tri.push_back({Lrow + ((size_t)lf * s) * (w2 * s) + (size_t)(q0 - (lf - w2)) * s, pc->Sinv + (size_t)q0 * s * n,
-                           pc->Sinv + (size_t)lf * s * n, nkf, 0, lf, q0, -far});
+                           pc->Sinv + (size_t)lf * s * n, nkf, 0, lf, q0, -far, 0});
             const int lb = M - 1 - j, nkb = std::min(M - 1, lb + w2) - lb;
             tri.push_back({Vrow + ((size_t)lb * s) * (w2 * s), pc->Sinv + (size_t)(lb + 1) * s * n,
-                           pc->Sinv + (size_t)lb * s * n, nkb, lb + 1, M - 1 - lb, far, lb});
-            kmax[j] = std::max(nkf, nkb);
-            for (int cb = 0; cb < lf; ++cb) work[j] += nkf - std::max(0, cb - q0);
-            for (int cb = lb + 1; cb < M; ++cb) work[j] += std::min(nkb, cb - lb);
+                           pc->Sinv + (size_t)lb * s * n, nkb, lb + 1, M - 1 - lb, far, lb, 1});
         }
         if (!bw32) {
             if (!tri.empty())
@@ -553,7 +549,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                                              st),
                               "copy"));
             for (int j = 1; j < M; ++j)
-                RUN(gemm_tri_enqueue(tri_dev + 2 * (j - 1), 2, s, j, kmax[j], work[j], w2 * s, (int)n, (int)n, -1.0, st));
+                RUN(gemm_tri_enqueue(tri_dev + 2 * (j - 1), 2, s, j, w2 * s, (int)n, (int)n, -1.0, st));
         } else {
             // round the operator (Sinv = I so far) to FP32 now, then L and V into
             // their FP32 copies (V's into the memory of the FP64 U rows)
@@ -569,15 +565,14 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                 const float *Ab = fwd ? L32 : V32;
                 const double *Ad = fwd ? Lrow : Vrow;
                 tf.push_back({Ab + (t.A - Ad), S32 + (t.B - Sinv64), S32 + (t.C - Sinv64), t.nk, t.cb0, t.ncb,
-                              t.lo_off, t.hi_off});
+                              t.lo_off, t.hi_off, t.rev});
             }
             if (!tf.empty())
                 RUN(hip_check(hipMemcpyAsync(tri32_dev, tf.data(), sizeof(GemmTriItemF) * tf.size(),
                                              hipMemcpyHostToDevice, st),
                               "copy"));
             for (int j = 1; j < M; ++j)
-                RUN(gemm_tri_enqueue(tri32_dev + 2 * (j - 1), 2, s, j, kmax[j], work[j], w2 * s, (int)n, (int)n, -1.0,
-                                     st));
+                RUN(gemm_tri_enqueue(tri32_dev + 2 * (j - 1), 2, s, j, w2 * s, (int)n, (int)n, -1.0, st));
         }
         // a zero pivot in any inverted block makes P singular in this factorisation
         std::vector<int> hinfo(3 * (2 + M), 0);
