@@ -218,13 +218,17 @@ int precond_setup(const bim_problem *prob, int band_halfwidth, bim_precond **out
 /*
  * precond_setup with the storage of the factored operator: BIM_STORE_FP64 (as
  * precond_setup), or BIM_STORE_FP32: the arrays the apply reads (the banded
- * blocks, the replicated diagonal inverses and the dense Schur-complement
- * inverse) are rounded to FP32 after the FP64 factorisation, halving the
- * apply's memory traffic and precond_bytes().  The apply still forms its
- * products and sums in FP64.  P is then a fixed operator within ~1e-7 relative of
- * the FP64 one.  GMRES sees a slightly different but equally good
- * preconditioner; the Newton residual, and so the solution, is unchanged.
- * Returns BIM_EINVAL for any other storage value.
+ * blocks, the replicated diagonal inverses, the triangular inverses of the
+ * Schur complement's block LU and its inverse pivot blocks) are held in FP32,
+ * halving the apply's memory traffic and precond_bytes().  The block
+ * elimination and the block LU run in FP64; for 128 < N + 1 <= 192 the
+ * substitutions that form the triangular inverses run in FP32 on FP32 copies
+ * of the factors, otherwise the FP64 inverses are rounded.  The apply still
+ * forms its products and sums in FP64.  The rounding of the elements is
+ * amplified by the conditioning of the Schur complement: the apply differs
+ * from the FP64 one by ~1e-3 relative at 181 x 61.  GMRES sees a different but
+ * about equally good preconditioner; the Newton residual, and so the
+ * solution, is unchanged.  Returns BIM_EINVAL for any other storage value.
  */
 int precond_setup_ex(const bim_problem *prob, int band_halfwidth, int storage, bim_precond **out, void *stream);
 int precond_storage(const bim_precond *P);
