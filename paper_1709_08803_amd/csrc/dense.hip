@@ -35,9 +35,29 @@ using GlobalPtr = __attribute__((address_space(1))) T *;
 constexpr int TM = 64, TN = 64, TK = 32;
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
+// The tile (x, y) and item z of a workgroup, in an XCD-aware order.  The
+// hardware hands workgroup i (linear over x, y, z) to XCD i mod 8, and each XCD
+// has its own L2; workgroup i takes the logical tile base(i mod 8) + i / 8, so
+// that each XCD works through one contiguous range of tiles in x, y, z order:
+// the tiles of one product, and neighbouring products that share an operand
+// block, then meet in one L2 (a bijection for any tile count).
+struct Tile3 {
+    int x, y, z;
+};
+__device__ __forceinline__ Tile3 xcd_tile() {
+    constexpr unsigned kXcds = 8;
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned n = gx * gy * gridDim.z;
+    const unsigned id = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned per = n / kXcds, rem = n % kXcds, x = id % kXcds;
+    const unsigned t = x * per + min(x, rem) + id / kXcds;
+    return {(int)(t % gx), (int)((t / gx) % gy), (int)(t / (gx * gy))};
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm(
     const GemmItem *__restrict__ items, int m, int n, int k, int lda, int ldb, int ldc, double alpha, double beta) {
-    const GemmItem it = items[blockIdx.z];
+    const Tile3 tl = xcd_tile();
+    const GemmItem it = items[tl.z];
     const GlobalPtr<const double> A = (GlobalPtr<const double>)it.A;
     const GlobalPtr<const double> B = (GlobalPtr<const double>)it.B;
     const GlobalPtr<double> C = (GlobalPtr<double>)it.C;
@@ -45,7 +65,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     __shared__ double Bs[TK][TN + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+    const int row0 = tl.y * TM, col0 = tl.x * TN;
     const int li = lane & 15, lk = lane >> 4;
     // each thread stages 8 elements of A (rows e >> 5, cols e & 31) and 8 of B
     // (rows e >> 6, cols e & 63).  Loads are unconditional, at indices clamped
@@ -139,7 +159,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_kblocks(
     const GemmKItem *__restrict__ items, int m, int n, int k, int lda, int ldb, int ldc, long sA, long sB,
     double alpha, double beta) {
-    const GemmKItem it = items[blockIdx.z];
+    const Tile3 tl = xcd_tile();
+    const GemmKItem it = items[tl.z];
     const GlobalPtr<const double> A = (GlobalPtr<const double>)it.A;
     const GlobalPtr<const double> B = (GlobalPtr<const double>)it.B;
     const GlobalPtr<double> C = (GlobalPtr<double>)it.C;
@@ -148,7 +169,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     __shared__ double Bs[TK][TN + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+    const int row0 = tl.y * TM, col0 = tl.x * TN;
     const int li = lane & 15, lk = lane >> 4;
     double ra[8], rb[8];
     // global K index g -> block g / k, column g % k; loads at clamped indices as in
@@ -398,8 +419,12 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tri(const GemmTriItemT<T> *__r
     const GlobalPtr<const T> A = (GlobalPtr<const T>)(it.A + (size_t)row0 * lda + (size_t)klo * s);
     const GlobalPtr<const T> B = (GlobalPtr<const T>)(it.B + (size_t)klo * s * ldb);
     const GlobalPtr<T> C = (GlobalPtr<T>)(it.C + (size_t)row0 * ldc);
-    __shared__ T As[2][kTallM][kTallK + 1];
-    __shared__ T Bs[2][kTallK][TN + 1];
+    // row pads: one element in FP64; in FP32, strides of 4 and 16 mod 32 words,
+    // which spread a wave's 16 x 4 operand reads over distinct banks (a one-
+    // float pad put 14% of the cycles in LDS bank conflicts)
+    constexpr int PA = sizeof(T) == 4 ? 4 : 1, PB = sizeof(T) == 4 ? 16 : 1;
+    __shared__ T As[2][kTallM][kTallK + PA];
+    __shared__ T Bs[2][kTallK][TN + PB];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave * 16 * RB;

@@ -444,8 +444,14 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     // S[l][m] -= sum_q B23[l][q] G[q][m] over q in [max(0, l-h, m-h), min(M-1, l+h, m+h)]: one
     // product per output block with the q-blocks as K (consecutive q: the next block of row l of
     // B23, s^2 further; the same column m of G one band row down, 2h s^2 further)
+    // (rows l in the order 0, 8, 16, .., 1, 9, ..: the product's workgroups are
+    // split over the 8 XCDs in contiguous ranges, which then each hold a mix of
+    // edge rows, with fewer q-blocks, and interior rows)
     std::vector<GemmKItem> kitems;
-    for (int l = 0; l < M; ++l)
+    std::vector<int> lorder;
+    for (int r = 0; r < 8; ++r)
+        for (int l = r; l < M; l += 8) lorder.push_back(l);
+    for (int l : lorder)
         for (int m = std::max(0, l - w2); m <= std::min(M - 1, l + w2); ++m) {
             const int q0 = std::max(0, std::max(l - h, m - h)), q1 = std::min(M - 1, std::min(l + h, m + h));
             if (q0 <= q1)
