@@ -351,18 +351,36 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItemT<T> *__res
     for (int k0 = 0; k0 < k; k0 += kTallK) {
         const bool more = k0 + kTallK < k;
         if (more) load(k0 + kTallK);
+        // the LDS operands of step kk + 4 are read before the MFMAs of step kk
+        // (the scheduling barriers keep that order; left alone, the compiler read
+        // them after the MFMAs and waited for them)
+        T a[RB], b[NB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) a[t] = As[buf][wm + 16 * t + li][lk];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) b[u] = Bs[buf][lk][16 * u + li];
 #pragma unroll
         for (int kk = 0; kk < kTallK; kk += 4) {
-            T a[RB], b[NB];
+            T an[RB], bn[NB];
+            if (kk + 4 < kTallK) {
 #pragma unroll
-            for (int t = 0; t < RB; ++t) a[t] = As[buf][wm + 16 * t + li][kk + lk];
+                for (int t = 0; t < RB; ++t) an[t] = As[buf][wm + 16 * t + li][kk + 4 + lk];
 #pragma unroll
-            for (int u = 0; u < NB; ++u) b[u] = Bs[buf][kk + lk][16 * u + li];
+                for (int u = 0; u < NB; ++u) bn[u] = Bs[buf][kk + 4 + lk][16 * u + li];
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < RB; ++t)
 #pragma unroll
                 for (int u = 0; u < NB; ++u)
                     acc[t][u] = MF::step(a[t], b[u], acc[t][u]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (kk + 4 < kTallK) {
+#pragma unroll
+                for (int t = 0; t < RB; ++t) a[t] = an[t];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) b[u] = bn[u];
+            }
         }
         // the other buffer was last read in the previous step, before its barrier
         if (more) store(buf ^ 1, k0 + kTallK);
@@ -475,18 +493,36 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tri(const GemmTriItemT<T> *__r
     for (int k0 = 0; k0 < k; k0 += kTallK) {
         const bool more = k0 + kTallK < k;
         if (more) load(k0 + kTallK);
+        // the LDS operands of step kk + 4 are read before the MFMAs of step kk
+        // (the scheduling barriers keep that order; left alone, the compiler read
+        // them after the MFMAs and waited for them)
+        T a[RB], b[NB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) a[t] = As[buf][wm + 16 * t + li][lk];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) b[u] = Bs[buf][lk][16 * u + li];
 #pragma unroll
         for (int kk = 0; kk < kTallK; kk += 4) {
-            T a[RB], b[NB];
+            T an[RB], bn[NB];
+            if (kk + 4 < kTallK) {
 #pragma unroll
-            for (int t = 0; t < RB; ++t) a[t] = As[buf][wm + 16 * t + li][kk + lk];
+                for (int t = 0; t < RB; ++t) an[t] = As[buf][wm + 16 * t + li][kk + 4 + lk];
 #pragma unroll
-            for (int u = 0; u < NB; ++u) b[u] = Bs[buf][kk + lk][16 * u + li];
+                for (int u = 0; u < NB; ++u) bn[u] = Bs[buf][kk + 4 + lk][16 * u + li];
+            }
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < RB; ++t)
 #pragma unroll
                 for (int u = 0; u < NB; ++u)
                     acc[t][u] = MF::step(a[t], b[u], acc[t][u]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (kk + 4 < kTallK) {
+#pragma unroll
+                for (int t = 0; t < RB; ++t) a[t] = an[t];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) b[u] = bn[u];
+            }
         }
         if (more) store(buf ^ 1, k0 + kTallK);
         __syncthreads();
