@@ -315,7 +315,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                           (size_t)M * (w2 * w2 + w2 + 2) + 16;
     addt(sizeof(GemmItem) * nitems);
     addt(sizeof(GemmItem) * M);              // V rows
-    addt(sizeof(GemmTriItem) * 2 * M);       // triangular substitutions
+    addt(sizeof(GemmTriItem) * 2 * M + 256);  // triangular substitutions
     addt(sizeof(GemmTriItemF) * 2 * M);      // the same in FP32
     addt(sizeof(InvItem) * (M + 4));
     addt(sizeof(GemmKItem) * (size_t)M * (2 * w2 + 1));
@@ -349,7 +349,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     InvItem *inv_dev = ta.take<InvItem>(M + 4);
     GemmKItem *kitems_dev = ta.take<GemmKItem>((size_t)M * (2 * w2 + 1));
     GemmItem *vitems_dev = ta.take<GemmItem>(M);
-    GemmTriItem *tri_dev = ta.take<GemmTriItem>((size_t)2 * M);
+    GemmTriItem *tri_dev = ta.take<GemmTriItem>((size_t)2 * M + 2);
     GemmTriItemF *tri32_dev = ta.take<GemmTriItemF>((size_t)2 * M);
 
     std::vector<GemmItem> items;
@@ -394,6 +394,8 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         if (rc_) return rc_;     \
     } while (0)
 
+    hipStream_t aux = nullptr;  // the second stream (default priority) and its events
+    hipEvent_t ev_l = nullptr, ev_f = nullptr;
     rc = [&]() -> int {
     // 1. diagonal blocks and their inverses, E = D11^-1 D12
     hipLaunchKernelGGL(k_diag_blocks, dim3(cdiv((long)s * s, 256)), dim3(256), 0, st, D11, D12, D22, N, p->x1,
@@ -506,11 +508,41 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         // zero L/U row buffers (short rows at the ends stay zero)
         RUN(hip_check(hipMemsetAsync(Lrow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));
         RUN(hip_check(hipMemsetAsync(Urow, 0, sizeof(double) * (size_t)M * s * w2 * s, st), "memset"));
+        // The rows of L^-1 (see below) run on a second stream during the block LU:
+        // row j needs the L blocks of row j, all formed by step j - 1, and the
+        // rows of L^-1 above it, and it touches nothing the LU reads or writes.
+        // The pivot inversions leave all but one compute unit idle, and the
+        // forward rows fill them (setup 49.7 -> 47.9 ms at 181 x 61, FP64).  In
+        // FP32 (FP32-stored operator and 128 < s <= 192) both substitutions run
+        // after the LU, on FP32 copies.
+        const bool bw32 = storage == BIM_STORE_FP32 && s > 128 && s <= 192;
+        const int far = 1 << 29;  // an offset that leaves klo at 0 / khi at nk
+        std::vector<GemmTriItem> fwd;
+        if (!bw32) {
+            RUN(identity_enqueue(pc->Sinv, n, st));
+            for (int j = 1; j < M; ++j) {
+                const int lf = j, q0 = std::max(0, lf - w2), nkf = lf - q0;
+                fwd.push_back({Lrow + ((size_t)lf * s) * (w2 * s) + (size_t)(q0 - (lf - w2)) * s,
+                               pc->Sinv + (size_t)q0 * s * n, pc->Sinv + (size_t)lf * s * n, nkf, 0, lf, q0, -far, 0});
+            }
+            if (!fwd.empty())
+                RUN(hip_check(hipMemcpyAsync(tri_dev, fwd.data(), sizeof(GemmTriItem) * fwd.size(), hipMemcpyHostToDevice,
+                                             st), "copy"));
+            RUN(hip_check(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking), "hipStreamCreate"));
+            RUN(hip_check(hipEventCreateWithFlags(&ev_l, hipEventDisableTiming), "hipEventCreate"));
+            RUN(hip_check(hipEventCreateWithFlags(&ev_f, hipEventDisableTiming), "hipEventCreate"));
+        }
         for (int l = 0; l < M; ++l) {
             RUN(invert_range(2 + l, 1));
-            for (long o : {op_bl[l], op_upd[l]})
-                if (o >= 0) RUN(run_op(ops[o], st));
+            if (op_bl[l] >= 0) RUN(run_op(ops[op_bl[l]], st));
+            if (aux && l + 1 < M) {  // row l + 1 of L^-1
+                RUN(hip_check(hipEventRecord(ev_l, st), "hipEventRecord"));
+                RUN(hip_check(hipStreamWaitEvent(aux, ev_l, 0), "hipStreamWaitEvent"));
+                RUN(gemm_tri_enqueue(tri_dev + l, 1, s, l + 1, w2 * s, (int)n, (int)n, -1.0, aux));
+            }
+            if (op_upd[l] >= 0) RUN(run_op(ops[op_upd[l]], st));
         }
+        if (aux) RUN(hip_check(hipEventRecord(ev_f, aux), "hipEventRecord"));
         // U rows: U[l][m] for m = l+1..l+2h packed as [l][s][2h s] (block j = m - l - 1,
         // copied while l + j + 1 < M)
         RUN(copy_blocks_enqueue(S + (size_t)(w2 + 1) * bs, brow, bs, s, Urow, (long)s * w2 * s, s, (long)w2 * s, s, s,
@@ -533,13 +565,11 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         // substitutions and never written:
         //   row block l of L^-1:  X[l][c] = -sum_{q = max(q0, c)}^{l-1} L[l][q] X[q][c],  c < l
         //   row block l of V^-1:  Y[l][c] = -sum_{m = l+1}^{min(c, l+2h)} V[l][m] Y[m][c],  c > l
-        // (q0 = max(0, l - 2h)).  Step j computes row j of L^-1 and row M-1-j of V^-1 in
-        // one launch (both j column blocks wide, at most 2h K blocks deep); the two
-        // touch disjoint triangles.  In FP32 (FP32-stored operator and 128 < s <= 192)
-        // both run on FP32 copies of L and V into the FP32 Sinv.
-        const bool bw32 = storage == BIM_STORE_FP32 && s > 128 && s <= 192;
-        RUN(identity_enqueue(pc->Sinv, n, st));
-        const int far = 1 << 29;  // an offset that leaves klo at 0 / khi at nk
+        // (q0 = max(0, l - 2h)).  The two touch disjoint triangles.  In FP32, step j
+        // computes row j of L^-1 and row M-1-j of V^-1 in one launch (both j column
+        // blocks wide, at most 2h K blocks deep); otherwise the rows of L^-1 ran
+        // during the LU, and step j computes row M-1-j of V^-1 alone.
+        if (bw32) RUN(identity_enqueue(pc->Sinv, n, st));
         std::vector<GemmTriItem> tri;
         for (int j = 1; j < M; ++j) {
             const int lf = j, q0 = std::max(0, lf - w2), nkf = lf - q0;
@@ -550,12 +580,16 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                            pc->Sinv + (size_t)lb * s * n, nkb, lb + 1, M - 1 - lb, far, lb, 1});
         }
         if (!bw32) {
+            std::vector<GemmTriItem> bwd;
+            for (size_t i = 1; i < tri.size(); i += 2) bwd.push_back(tri[i]);
+            tri.swap(bwd);
             if (!tri.empty())
-                RUN(hip_check(hipMemcpyAsync(tri_dev, tri.data(), sizeof(GemmTriItem) * tri.size(), hipMemcpyHostToDevice,
+                RUN(hip_check(hipMemcpyAsync(tri_dev + M, tri.data(), sizeof(GemmTriItem) * tri.size(), hipMemcpyHostToDevice,
                                              st),
                               "copy"));
             for (int j = 1; j < M; ++j)
-                RUN(gemm_tri_enqueue(tri_dev + 2 * (j - 1), 2, s, j, w2 * s, (int)n, (int)n, -1.0, st));
+                RUN(gemm_tri_enqueue(tri_dev + M + (j - 1), 1, s, j, w2 * s, (int)n, (int)n, -1.0, st));
+            RUN(hip_check(hipStreamWaitEvent(st, ev_f, 0), "hipStreamWaitEvent"));
         } else {
             // round the operator (Sinv = I so far) to FP32 now, then L and V into
             // their FP32 copies (V's into the memory of the FP64 U rows)
@@ -593,6 +627,12 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     return BIM_OK;
     }();
 #undef RUN
+    if (aux) {
+        (void)hipStreamSynchronize(aux);  // (on success `st` has already waited for it)
+        (void)hipStreamDestroy(aux);
+    }
+    if (ev_l) (void)hipEventDestroy(ev_l);
+    if (ev_f) (void)hipEventDestroy(ev_f);
     (void)hipFreeAsync(tbase, st);
     if (!rc && storage == BIM_STORE_FP32 && pc->storage != BIM_STORE_FP32) rc = precond_round_to_fp32(pc, st);
     if (rc) {
