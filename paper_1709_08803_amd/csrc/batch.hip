@@ -176,12 +176,39 @@ __device__ __forceinline__ void bband_rows(const BBand &o, int l, int r0, int la
     const TA *band = (const TA *)o.band;
     const int m0 = max(0, l - o.w), m1 = min(o.M - 1, l + o.w);
     const bool vec = (o.s % 2 == 0) && ((uintptr_t)band % (2 * sizeof(TA)) == 0) && ((uintptr_t)o.x % 16 == 0);
+    if (vec) {
+        // as k_bandmv_rows: the element pairs of all band blocks as one range,
+        // 64 per step, in the same order (the same sums as one problem alone)
+        typedef TA ta2 __attribute__((ext_vector_type(2)));
+        const int s = o.s, pairs = s >> 1, total = (m1 - m0 + 1) * pairs;
+        int mb = lane / pairs, q = lane - mb * pairs;
+        const TA *rows = band + ((size_t)l * (2 * o.w + 1) + (m0 - l + o.w)) * s * s;
+        for (int g = lane; g < total; g += 64) {
+            const TA *blk = rows + (size_t)mb * s * s;
+            const bdouble2 xv = *reinterpret_cast<const bdouble2 *>(o.x + (size_t)(m0 + mb) * s + 2 * q);
+            ta2 a[kBGR];
+#pragma unroll
+            for (int r = 0; r < kBGR; ++r)
+                a[r] = *reinterpret_cast<const ta2 *>(blk + (size_t)min(r0 + r, s - 1) * s + 2 * q);
+#pragma unroll
+            for (int r = 0; r < kBGR; ++r) {
+                acc[r] = fma((double)a[r][0], xv[0], acc[r]);
+                acc[r] = fma((double)a[r][1], xv[1], acc[r]);
+            }
+            q += 64;
+            while (q >= pairs) {
+                q -= pairs;
+                ++mb;
+            }
+        }
+        return;
+    }
     for (int m = m0; m <= m1; ++m) {
         const TA *blk = band + ((size_t)l * (2 * o.w + 1) + (m - l + o.w)) * o.s * o.s;
         const TA *row[kBGR];
 #pragma unroll
         for (int r = 0; r < kBGR; ++r) row[r] = blk + (size_t)min(r0 + r, o.s - 1) * o.s;
-        brows_dot<TA>(row, o.x + (size_t)m * o.s, o.s, vec, lane, acc);
+        brows_dot<TA>(row, o.x + (size_t)m * o.s, o.s, false, lane, acc);
     }
 }
 

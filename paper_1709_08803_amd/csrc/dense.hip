@@ -888,21 +888,29 @@ __global__ __launch_bounds__(256) void k_bandmv_rows(const TA *__restrict__ band
     const int l = wave / gps, r0 = (wave - l * gps) * GR;
     const int m0 = max(0, l - w), m1 = min(M - 1, l + w);
     const int pairs = s >> 1;
+    // the element pairs of all band blocks of the rows as one range, 64 per step
+    // (a block row of s = 182 is 91 pairs: walked block by block, the second
+    // step of each left 37 of 64 lanes idle)
+    const int total = (m1 - m0 + 1) * pairs;
+    int mb = lane / pairs, q = lane - mb * pairs;  // this lane's block and pair
+    const TA *rows = band + ((size_t)l * (2 * w + 1) + (m0 - l + w)) * s * s;
     double acc[GR] = {};
-    for (int m = m0; m <= m1; ++m) {
-        const TA *blk = band + ((size_t)l * (2 * w + 1) + (m - l + w)) * s * s;
-        const double *xm = x + (size_t)m * s;
-        for (int q = lane; q < pairs; q += 64) {
-            const double2_t xv = *reinterpret_cast<const double2_t *>(xm + 2 * q);
-            ta2_t a[GR];
+    for (int g = lane; g < total; g += 64) {
+        const TA *blk = rows + (size_t)mb * s * s;
+        const double2_t xv = *reinterpret_cast<const double2_t *>(x + (size_t)(m0 + mb) * s + 2 * q);
+        ta2_t a[GR];
 #pragma unroll
-            for (int r = 0; r < GR; ++r)
-                a[r] = *reinterpret_cast<const ta2_t *>(blk + (size_t)min(r0 + r, s - 1) * s + 2 * q);
+        for (int r = 0; r < GR; ++r)
+            a[r] = *reinterpret_cast<const ta2_t *>(blk + (size_t)min(r0 + r, s - 1) * s + 2 * q);
 #pragma unroll
-            for (int r = 0; r < GR; ++r) {
-                acc[r] = fma((double)a[r][0], xv[0], acc[r]);
-                acc[r] = fma((double)a[r][1], xv[1], acc[r]);
-            }
+        for (int r = 0; r < GR; ++r) {
+            acc[r] = fma((double)a[r][0], xv[0], acc[r]);
+            acc[r] = fma((double)a[r][1], xv[1], acc[r]);
+        }
+        q += 64;
+        while (q >= pairs) {
+            q -= pairs;
+            ++mb;
         }
     }
 #pragma unroll
