@@ -207,7 +207,9 @@ int bim_tune_residual(const bim_problem *prob, const double *u, int prec, void *
  *   Newton step fall several-fold for a modest rise in setup and apply cost;
  *   beyond 10 slices the setup grows faster than the solve shrinks).
  * precond_setup factors P on the device and returns a library-owned handle
- * (free with precond_destroy).  It synchronises `stream`.  Device memory used:
+ * (free with precond_destroy).  It synchronises `stream`; part of the work runs
+ * on a second stream of its own (default priority), joined before it returns,
+ * so it must not be called under stream capture.  Device memory used:
  * precond_bytes().  Requires N + 1 <= 1024.  Returns BIM_EDOMAIN if a block
  * that must be inverted is singular.
  * precond_apply enqueues z = P^-1 r (device vectors of 3(N+1)M, z must not
