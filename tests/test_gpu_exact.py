@@ -141,3 +141,27 @@ def test_exact_start_assembles_the_linear_unknowns(bim):
     # F3: x1 (phi_x,1 - 1) + n (phi_1 - x1) = 0
     phx1, phi1 = nf.phi_x[:, 0], nf.phi[:, 0]
     assert np.abs(p.x1 * (phx1 - 1.0) + p.n_decay * (phi1 - p.x1)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("inner,storage,tol", [("fp64", "fp64", 1e-10), ("fp32c", "fp32", 1e-9)],
+                         ids=["fp64", "mixed-fp32-storage"])
+def test_newton_from_the_exact_start_reaches_the_stored_oracle_solution(bim, inner, storage, tol):
+    # 181 x 61, F = 1.4: Newton from the exact linear solution's start (plain FP64,
+    # and FP32C sums with the FP32-stored preconditioner) converges to the FP64
+    # oracle's stored solution of the discrete problem
+    import os
+    from paper_1709_08803_amd import workloads as W
+    from oracle import residual as R
+    p = W.working(1.4)
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "working_181x61_F1.4.npz"))["u"]
+    dp = bim.DeviceProblem(p)
+    z, zx, _ = bim.exact_linear(p.froude, [(0.2, 1 / math.sqrt(2.0), 0.0, 0.0)], p.N, p.M, p.x1, p.dx, p.y1, p.dy)
+    u = bim.exact_start(dp, z, zx)
+    P = bim.Preconditioner(dp, storage=storage)
+    rep = bim.solve(dp, u, P, ftol=1e-10, check=False, max_newton=15, inner_prec=inner)
+    P.close()
+    assert rep["status"] == 0
+    uh = u.cpu().numpy()
+    dz = np.abs(R.reconstruct(p, uh).zeta - R.reconstruct(p, ref).zeta).max()
+    print(f"exact start, {inner}: Newton {rep['newton_iters']} GMRES {rep['gmres_iters']} max|dzeta| {dz:.2e}")
+    assert dz <= tol
