@@ -315,7 +315,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
                           (size_t)M * (w2 * w2 + w2 + 2) + 16;
     addt(sizeof(GemmItem) * nitems);
     addt(sizeof(GemmItem) * M);              // V rows
-    addt(sizeof(GemmTriItem) * 2 * M + 256);  // triangular substitutions
+    addt(sizeof(GemmTriItem) * (2 * (size_t)M + 2));  // triangular substitutions (rows of L^-1 at 0, of V^-1 at M)
     addt(sizeof(GemmTriItemF) * 2 * M);      // the same in FP32
     addt(sizeof(InvItem) * (M + 4));
     addt(sizeof(GemmKItem) * (size_t)M * (2 * w2 + 1));
@@ -349,7 +349,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     InvItem *inv_dev = ta.take<InvItem>(M + 4);
     GemmKItem *kitems_dev = ta.take<GemmKItem>((size_t)M * (2 * w2 + 1));
     GemmItem *vitems_dev = ta.take<GemmItem>(M);
-    GemmTriItem *tri_dev = ta.take<GemmTriItem>((size_t)2 * M + 2);
+    GemmTriItem *tri_dev = ta.take<GemmTriItem>(2 * (size_t)M + 2);
     GemmTriItemF *tri32_dev = ta.take<GemmTriItemF>((size_t)2 * M);
 
     std::vector<GemmItem> items;
