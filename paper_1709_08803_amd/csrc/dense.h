@@ -52,11 +52,13 @@ int gemm_enqueue(const GemmItem *items_dev, int batch, int m, int n, int k, int 
 int gemm_kblocks_enqueue(const GemmKItem *items_dev, int batch, int m, int n, int k, int lda, int ldb, int ldc,
                          long sA, long sB, double alpha, double beta, hipStream_t s);
 // Block-triangular products of `batch` items (FP64 or FP32 matrix cores, any
-// block size s); max_ncb: the largest ncb.
+// block size s); max_ncb: the largest ncb.  max_groups > 0 caps the workgroups
+// per row panel (they then walk the column tiles with a stride), which leaves
+// compute units free for other streams; 0: one workgroup per tile.
 int gemm_tri_enqueue(const GemmTriItem *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
-                     double alpha, hipStream_t st);
+                     double alpha, hipStream_t st, int max_groups = 0);
 int gemm_tri_enqueue(const GemmTriItemF *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
-                     double alpha, hipStream_t st);
+                     double alpha, hipStream_t st, int max_groups = 0);
 // y = alpha A' x + beta c, A' the strictly lower (part 1) or strictly upper
 // (part 2) block part of the dense n x n A with M x M blocks of s; c may equal x
 // (read per row), y must not alias x.

@@ -419,20 +419,24 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tall(const GemmItemT<T> *__res
 // and the short ones fill in after them (one workgroup per compute unit).
 template <int TN, int NW, typename T = double>
 __global__ __launch_bounds__(64 * NW) void k_gemm_tri(const GemmTriItemT<T> *__restrict__ items, int batch, int s,
-                                                      int ppb, int lda, int ldb, int ldc, double alpha) {
+                                                      int ppb, int lda, int ldb, int ldc, double alpha, int ntiles) {
     constexpr int NT = 64 * NW, NB = TN / 16, RB = 12 / NW;
     constexpr int QA = kTallM * kTallK / NT, QB = (kTallK * TN + NT - 1) / NT;
     static_assert(QA * NT == kTallM * kTallK && RB * NW == 12, "tall tile shape");
     typedef Mfma16<T> MF;
-    const int bx = blockIdx.x / batch;
-    const GemmTriItemT<T> it = items[blockIdx.x - bx * batch];
+    // a grid narrower than the ntiles column tiles walks them with a stride
+    // (every early exit below is uniform over the workgroup, and each tile's
+    // last LDS reads are behind its K loop's final barrier)
+    for (int bxl = blockIdx.x; bxl < ntiles; bxl += gridDim.x) {
+    const int bx = bxl / batch;
+    const GemmTriItemT<T> it = items[bxl - bx * batch];
     const int cbi = bx / ppb, pan = bx - cbi * ppb;
-    if (cbi >= it.ncb) return;
+    if (cbi >= it.ncb) continue;
     const int cb = it.cb0 + (it.rev ? it.ncb - 1 - cbi : cbi);
     const int klo = max(0, cb - it.lo_off), khi = min(it.nk, cb - it.hi_off);
     const int row0 = blockIdx.y * kTallM, m = min(kTallM, s - row0);
     const int col0 = cb * s + pan * TN, cend = (cb + 1) * s;
-    if (col0 >= cend) return;
+    if (col0 >= cend) continue;
     const int k = max(0, khi - klo) * s;
     const GlobalPtr<const T> A = (GlobalPtr<const T>)(it.A + (size_t)row0 * lda + (size_t)klo * s);
     const GlobalPtr<const T> B = (GlobalPtr<const T>)(it.B + (size_t)klo * s * ldb);
@@ -537,6 +541,7 @@ __global__ __launch_bounds__(64 * NW) void k_gemm_tri(const GemmTriItemT<T> *__r
                 const int gr = wm + 16 * t + MF::row(lk, v), gc = col0 + 16 * u + li;
                 if (gr < m && gc < cend) C[(size_t)gr * ldc + gc] = (T)alpha * acc[t][u][v];
             }
+    }
 }
 
 // In-place Gauss-Jordan inversion of one s x s block (s <= 192) per 1024-thread
@@ -1105,14 +1110,16 @@ constexpr int kTriPanel = 32;
 
 template <typename T>
 int gemm_tri_launch(const GemmTriItemT<T> *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
-                    double alpha, hipStream_t st) {
+                    double alpha, int max_groups, hipStream_t st) {
     if (batch <= 0 || max_ncb <= 0 || s <= 0) return BIM_OK;
     if (batch > 65535) return fail(BIM_EINVAL, "gemm batch too large");
+    if (max_groups < 0) return fail(BIM_EINVAL, "block-triangular product: negative workgroup cap");
     const int ppb = cdiv(s, kTriPanel);
     if ((long)max_ncb * ppb * batch > 0x7fffffffL) return fail(BIM_EINVAL, "block-triangular product too wide");
-    dim3 grid(max_ncb * ppb * batch, cdiv(s, kTallM), 1);
+    const int ntiles = max_ncb * ppb * batch;
+    dim3 grid(max_groups > 0 ? std::min(ntiles, max_groups) : ntiles, cdiv(s, kTallM), 1);
     hipLaunchKernelGGL((k_gemm_tri<kTriPanel, kTallWaves, T>), grid, dim3(64 * kTallWaves), 0, st, items_dev, batch, s,
-                       ppb, lda, ldb, ldc, alpha);
+                       ppb, lda, ldb, ldc, alpha, ntiles);
     return hip_check(hipGetLastError(), "block-triangular gemm launch");
 }
 
@@ -1131,12 +1138,12 @@ int gemv_tri_launch(const TA *A, long n, int M, int s, int part, const double *x
 }  // namespace
 
 int gemm_tri_enqueue(const GemmTriItem *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
-                     double alpha, hipStream_t st) {
-    return gemm_tri_launch(items_dev, batch, s, max_ncb, lda, ldb, ldc, alpha, st);
+                     double alpha, hipStream_t st, int max_groups) {
+    return gemm_tri_launch(items_dev, batch, s, max_ncb, lda, ldb, ldc, alpha, max_groups, st);
 }
 int gemm_tri_enqueue(const GemmTriItemF *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
-                     double alpha, hipStream_t st) {
-    return gemm_tri_launch(items_dev, batch, s, max_ncb, lda, ldb, ldc, alpha, st);
+                     double alpha, hipStream_t st, int max_groups) {
+    return gemm_tri_launch(items_dev, batch, s, max_ncb, lda, ldb, ldc, alpha, max_groups, st);
 }
 int gemv_tri_enqueue(const double *A, long n, int M, int s, int part, const double *x, const double *c, double *y,
                      double alpha, double beta, hipStream_t st) {

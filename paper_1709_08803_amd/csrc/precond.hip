@@ -215,42 +215,81 @@ static double *band_blk(double *band, int w, int s, int l, int m) {
 
 // FP32 storage: the nine arrays the apply reads are rounded into a new, half-
 // sized allocation (with the apply scratch), and the FP64 allocation is freed.
-static int precond_round_to_fp32(Precond *pc, hipStream_t st) {
-    const int M = pc->M, s = pc->s, h = pc->h;
-    const long n = pc->n;
-    const size_t cnt[9] = {band_elems(M, 0, s), band_elems(M, 0, s), band_elems(M, 0, s), band_elems(M, h, s),
-                           band_elems(M, h, s), band_elems(M, h, s), band_elems(M, h, s), (size_t)n * n,
-                           band_elems(M, 0, s)};
-    double *src[9] = {pc->Dinv11, pc->Dinv22, pc->E, pc->B21, pc->B23, pc->B31, pc->G, pc->Sinv, pc->Uinv};
-    size_t bytes = 0;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    for (size_t c : cnt) bytes += al(sizeof(float) * c);
-    bytes += al(sizeof(double) * 4 * n);
+// In two parts: the allocation (pc->f32 then points into it; FP64 untouched),
+// and the rounding of the FP64 arrays (all nine, or all but S^-1 when that was
+// formed in FP32 already), after which the FP32 allocation is adopted.
+struct Fp32Mem {
     void *mem = nullptr;
-    int rc = hip_check(hipMalloc(&mem, bytes), "hipMalloc(preconditioner, FP32)");
+    size_t bytes = 0;
+    double *scratch = nullptr;
+};
+
+static const int kNumArrays = 9;
+
+static void precond_counts(const Precond *pc, size_t cnt[kNumArrays]) {
+    const int M = pc->M, s = pc->s, h = pc->h;
+    const size_t b0 = band_elems(M, 0, s), bh = band_elems(M, h, s);
+    const size_t c[kNumArrays] = {b0, b0, b0, bh, bh, bh, bh, (size_t)pc->n * pc->n, b0};
+    for (int q = 0; q < kNumArrays; ++q) cnt[q] = c[q];
+}
+
+static int precond_fp32_alloc(Precond *pc, Fp32Mem *f) {
+    size_t cnt[kNumArrays];
+    precond_counts(pc, cnt);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t bytes = 0;
+    for (size_t c : cnt) bytes += al(sizeof(float) * c);
+    bytes += al(sizeof(double) * 4 * pc->n);
+    void *mem = nullptr;
+    const int rc = hip_check(hipMalloc(&mem, bytes), "hipMalloc(preconditioner, FP32)");
     if (rc) return rc;
     DevArena ar{(char *)mem, 0, bytes};
-    float **dst[9] = {&pc->f32.Dinv11, &pc->f32.Dinv22, &pc->f32.E,    &pc->f32.B21, &pc->f32.B23,
-                      &pc->f32.B31,    &pc->f32.G,      &pc->f32.Sinv, &pc->f32.Uinv};
-    for (int q = 0; q < 9 && !rc; ++q) {
-        *dst[q] = ar.take<float>(cnt[q]);
-        rc = to_float_enqueue(src[q], *dst[q], cnt[q], st);
-    }
-    double *scratch = ar.take<double>((size_t)4 * n);
+    float **dst[kNumArrays] = {&pc->f32.Dinv11, &pc->f32.Dinv22, &pc->f32.E,    &pc->f32.B21, &pc->f32.B23,
+                               &pc->f32.B31,    &pc->f32.G,      &pc->f32.Sinv, &pc->f32.Uinv};
+    for (int q = 0; q < kNumArrays; ++q) *dst[q] = ar.take<float>(cnt[q]);
+    f->scratch = ar.take<double>((size_t)4 * pc->n);
+    f->mem = mem;
+    f->bytes = bytes;
+    return BIM_OK;
+}
+
+// Releases an FP32 allocation that was not adopted.
+static void precond_fp32_drop(Precond *pc, Fp32Mem *f) {
+    if (f->mem) (void)hipFree(f->mem);
+    *f = Fp32Mem{};
+    pc->f32 = PrecondArrays<float>{};
+}
+
+static int precond_fp32_finish(Precond *pc, Fp32Mem *f, bool with_sinv, hipStream_t st) {
+    size_t cnt[kNumArrays];
+    precond_counts(pc, cnt);
+    const double *src[kNumArrays] = {pc->Dinv11, pc->Dinv22, pc->E, pc->B21, pc->B23, pc->B31, pc->G, pc->Sinv, pc->Uinv};
+    float *dst[kNumArrays] = {pc->f32.Dinv11, pc->f32.Dinv22, pc->f32.E,    pc->f32.B21, pc->f32.B23,
+                              pc->f32.B31,    pc->f32.G,      pc->f32.Sinv, pc->f32.Uinv};
+    int rc = BIM_OK;
+    for (int q = 0; q < kNumArrays && !rc; ++q)
+        if (q != 7 || with_sinv) rc = to_float_enqueue(src[q], dst[q], cnt[q], st);
     if (!rc) rc = hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
-    if (rc) {
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(mem);
-        pc->f32 = PrecondArrays<float>{};
-        return rc;
-    }
+    if (rc) return rc;  // (the caller releases f once no stream uses it)
     (void)hipFree(pc->mem);
-    pc->mem = mem;
-    pc->bytes = bytes;
-    pc->scratch = scratch;
+    pc->mem = f->mem;
+    pc->bytes = f->bytes;
+    pc->scratch = f->scratch;
+    *f = Fp32Mem{};
     pc->Dinv11 = pc->Dinv22 = pc->E = pc->B21 = pc->B23 = pc->B31 = pc->G = pc->Sinv = pc->Uinv = nullptr;
     pc->storage = BIM_STORE_FP32;
     return BIM_OK;
+}
+
+static int precond_round_to_fp32(Precond *pc, hipStream_t st) {
+    Fp32Mem f;
+    int rc = precond_fp32_alloc(pc, &f);
+    if (!rc) rc = precond_fp32_finish(pc, &f, true, st);
+    if (rc) {
+        (void)hipStreamSynchronize(st);
+        precond_fp32_drop(pc, &f);
+    }
+    return rc;
 }
 
 int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipStream_t st) {
@@ -396,6 +435,7 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
 
     hipStream_t aux = nullptr;  // the second stream (default priority) and its events
     hipEvent_t ev_l = nullptr, ev_f = nullptr;
+    Fp32Mem f32mem;             // the FP32 operator's memory until it is adopted
     rc = [&]() -> int {
     // 1. diagonal blocks and their inverses, E = D11^-1 D12
     hipLaunchKernelGGL(k_diag_blocks, dim3(cdiv((long)s * s, 256)), dim3(256), 0, st, D11, D12, D22, N, p->x1,
@@ -512,37 +552,64 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         // row j needs the L blocks of row j, all formed by step j - 1, and the
         // rows of L^-1 above it, and it touches nothing the LU reads or writes.
         // The pivot inversions leave all but one compute unit idle, and the
-        // forward rows fill them (setup 49.7 -> 47.9 ms at 181 x 61, FP64).  In
-        // FP32 (FP32-stored operator and 128 < s <= 192) both substitutions run
-        // after the LU, on FP32 copies.
+        // forward rows fill them.  In FP32 (FP32-stored operator and
+        // 128 < s <= 192) the second stream first rounds row j of L to FP32 and
+        // the rows of L^-1 are formed in FP32, directly in the FP32 operator.
+        // The forward rows' workgroups (one per compute unit, by their LDS) are
+        // capped so that compute units stay free: a pivot inversion needs a whole
+        // compute unit's registers and would otherwise wait for one to drain.
+        constexpr int kAuxTriGroups = 192;
         const bool bw32 = storage == BIM_STORE_FP32 && s > 128 && s <= 192;
         const int far = 1 << 29;  // an offset that leaves klo at 0 / khi at nk
+        const size_t lrow = (size_t)s * w2 * s;  // elements of one block row of L (or V)
+        float *S32 = nullptr;
         std::vector<GemmTriItem> fwd;
-        if (!bw32) {
-            RUN(identity_enqueue(pc->Sinv, n, st));
-            for (int j = 1; j < M; ++j) {
-                const int lf = j, q0 = std::max(0, lf - w2), nkf = lf - q0;
-                fwd.push_back({Lrow + ((size_t)lf * s) * (w2 * s) + (size_t)(q0 - (lf - w2)) * s,
-                               pc->Sinv + (size_t)q0 * s * n, pc->Sinv + (size_t)lf * s * n, nkf, 0, lf, q0, -far, 0});
-            }
-            if (!fwd.empty())
-                RUN(hip_check(hipMemcpyAsync(tri_dev, fwd.data(), sizeof(GemmTriItem) * fwd.size(), hipMemcpyHostToDevice,
-                                             st), "copy"));
-            RUN(hip_check(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking), "hipStreamCreate"));
-            RUN(hip_check(hipEventCreateWithFlags(&ev_l, hipEventDisableTiming), "hipEventCreate"));
-            RUN(hip_check(hipEventCreateWithFlags(&ev_f, hipEventDisableTiming), "hipEventCreate"));
+        std::vector<GemmTriItemF> fwd32;
+        RUN(identity_enqueue(pc->Sinv, n, st));
+        if (bw32) {
+            // the FP32 operator's memory now, with S^-1 = I rounded into it
+            RUN(precond_fp32_alloc(pc, &f32mem));
+            S32 = pc->f32.Sinv;
+            RUN(to_float_enqueue(pc->Sinv, S32, (size_t)n * n, st));
         }
+        for (int j = 1; j < M; ++j) {
+            const int lf = j, q0 = std::max(0, lf - w2), nkf = lf - q0;
+            const size_t a_off = lf * lrow + (size_t)(q0 - (lf - w2)) * s;
+            if (bw32)
+                fwd32.push_back({L32 + a_off, S32 + (size_t)q0 * s * n, S32 + (size_t)lf * s * n, nkf, 0, lf, q0, -far,
+                                 0});
+            else
+                fwd.push_back({Lrow + a_off, pc->Sinv + (size_t)q0 * s * n, pc->Sinv + (size_t)lf * s * n, nkf, 0, lf,
+                               q0, -far, 0});
+        }
+        if (!fwd.empty())
+            RUN(hip_check(hipMemcpyAsync(tri_dev, fwd.data(), sizeof(GemmTriItem) * fwd.size(), hipMemcpyHostToDevice,
+                                         st),
+                          "copy"));
+        if (!fwd32.empty())
+            RUN(hip_check(hipMemcpyAsync(tri32_dev, fwd32.data(), sizeof(GemmTriItemF) * fwd32.size(),
+                                         hipMemcpyHostToDevice, st),
+                          "copy"));
+        RUN(hip_check(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking), "hipStreamCreate"));
+        RUN(hip_check(hipEventCreateWithFlags(&ev_l, hipEventDisableTiming), "hipEventCreate"));
+        RUN(hip_check(hipEventCreateWithFlags(&ev_f, hipEventDisableTiming), "hipEventCreate"));
         for (int l = 0; l < M; ++l) {
             RUN(invert_range(2 + l, 1));
             if (op_bl[l] >= 0) RUN(run_op(ops[op_bl[l]], st));
-            if (aux && l + 1 < M) {  // row l + 1 of L^-1
+            if (l + 1 < M) {  // row l + 1 of L^-1
                 RUN(hip_check(hipEventRecord(ev_l, st), "hipEventRecord"));
                 RUN(hip_check(hipStreamWaitEvent(aux, ev_l, 0), "hipStreamWaitEvent"));
-                RUN(gemm_tri_enqueue(tri_dev + l, 1, s, l + 1, w2 * s, (int)n, (int)n, -1.0, aux));
+                if (bw32) {
+                    RUN(to_float_enqueue(Lrow + (l + 1) * lrow, L32 + (l + 1) * lrow, lrow, aux));
+                    RUN(gemm_tri_enqueue(tri32_dev + l, 1, s, l + 1, w2 * s, (int)n, (int)n, -1.0, aux,
+                                         kAuxTriGroups));
+                } else {
+                    RUN(gemm_tri_enqueue(tri_dev + l, 1, s, l + 1, w2 * s, (int)n, (int)n, -1.0, aux, kAuxTriGroups));
+                }
             }
             if (op_upd[l] >= 0) RUN(run_op(ops[op_upd[l]], st));
         }
-        if (aux) RUN(hip_check(hipEventRecord(ev_f, aux), "hipEventRecord"));
+        RUN(hip_check(hipEventRecord(ev_f, aux), "hipEventRecord"));
         // U rows: U[l][m] for m = l+1..l+2h packed as [l][s][2h s] (block j = m - l - 1,
         // copied while l + j + 1 < M)
         RUN(copy_blocks_enqueue(S + (size_t)(w2 + 1) * bs, brow, bs, s, Urow, (long)s * w2 * s, s, (long)w2 * s, s, s,
@@ -552,7 +619,6 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         // (the host item arrays stay alive until the closing synchronisation)
         double *Vrow = S;
         std::vector<GemmItem> vi;
-        std::vector<GemmTriItemF> tf;
         {
             for (int l = 0; l < M; ++l)
                 vi.push_back({pc->Uinv + (size_t)l * s * s, Urow + (size_t)l * s * w2 * s, Vrow + (size_t)l * s * w2 * s});
@@ -565,55 +631,44 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         // substitutions and never written:
         //   row block l of L^-1:  X[l][c] = -sum_{q = max(q0, c)}^{l-1} L[l][q] X[q][c],  c < l
         //   row block l of V^-1:  Y[l][c] = -sum_{m = l+1}^{min(c, l+2h)} V[l][m] Y[m][c],  c > l
-        // (q0 = max(0, l - 2h)).  The two touch disjoint triangles.  In FP32, step j
-        // computes row j of L^-1 and row M-1-j of V^-1 in one launch (both j column
-        // blocks wide, at most 2h K blocks deep); otherwise the rows of L^-1 ran
-        // during the LU, and step j computes row M-1-j of V^-1 alone.
-        if (bw32) RUN(identity_enqueue(pc->Sinv, n, st));
-        std::vector<GemmTriItem> tri;
+        // (q0 = max(0, l - 2h)).  The two touch disjoint triangles, so the rows of
+        // V^-1 (step j: row M-1-j, j column blocks wide, at most 2h K blocks deep)
+        // run while the second stream finishes the rows of L^-1.
+        std::vector<GemmTriItem> bwd;
+        std::vector<GemmTriItemF> bwd32;
+        const float *V32 = nullptr;
+        if (bw32) {
+            // V into its FP32 copy (in the memory of the FP64 U rows), then the
+            // other arrays of the operator rounded; the FP64 allocation is freed
+            float *v32 = (float *)Urow;
+            RUN(to_float_enqueue(Vrow, v32, (size_t)M * lrow, st));
+            V32 = v32;
+            RUN(precond_fp32_finish(pc, &f32mem, false, st));
+        }
         for (int j = 1; j < M; ++j) {
-            const int lf = j, q0 = std::max(0, lf - w2), nkf = lf - q0;
-            tri.push_back({Lrow + ((size_t)lf * s) * (w2 * s) + (size_t)(q0 - (lf - w2)) * s, pc->Sinv + (size_t)q0 * s * n,
-                           pc->Sinv + (size_t)lf * s * n, nkf, 0, lf, q0, -far, 0});
             const int lb = M - 1 - j, nkb = std::min(M - 1, lb + w2) - lb;
-            tri.push_back({Vrow + ((size_t)lb * s) * (w2 * s), pc->Sinv + (size_t)(lb + 1) * s * n,
-                           pc->Sinv + (size_t)lb * s * n, nkb, lb + 1, M - 1 - lb, far, lb, 1});
+            if (bw32)
+                bwd32.push_back({V32 + lb * lrow, S32 + (size_t)(lb + 1) * s * n, S32 + (size_t)lb * s * n, nkb, lb + 1,
+                                 M - 1 - lb, far, lb, 1});
+            else
+                bwd.push_back({Vrow + lb * lrow, pc->Sinv + (size_t)(lb + 1) * s * n, pc->Sinv + (size_t)lb * s * n,
+                               nkb, lb + 1, M - 1 - lb, far, lb, 1});
         }
-        if (!bw32) {
-            std::vector<GemmTriItem> bwd;
-            for (size_t i = 1; i < tri.size(); i += 2) bwd.push_back(tri[i]);
-            tri.swap(bwd);
-            if (!tri.empty())
-                RUN(hip_check(hipMemcpyAsync(tri_dev + M, tri.data(), sizeof(GemmTriItem) * tri.size(), hipMemcpyHostToDevice,
-                                             st),
-                              "copy"));
-            for (int j = 1; j < M; ++j)
+        if (!bwd.empty())
+            RUN(hip_check(hipMemcpyAsync(tri_dev + M, bwd.data(), sizeof(GemmTriItem) * bwd.size(),
+                                         hipMemcpyHostToDevice, st),
+                          "copy"));
+        if (!bwd32.empty())
+            RUN(hip_check(hipMemcpyAsync(tri32_dev + M, bwd32.data(), sizeof(GemmTriItemF) * bwd32.size(),
+                                         hipMemcpyHostToDevice, st),
+                          "copy"));
+        for (int j = 1; j < M; ++j) {
+            if (bw32)
+                RUN(gemm_tri_enqueue(tri32_dev + M + (j - 1), 1, s, j, w2 * s, (int)n, (int)n, -1.0, st));
+            else
                 RUN(gemm_tri_enqueue(tri_dev + M + (j - 1), 1, s, j, w2 * s, (int)n, (int)n, -1.0, st));
-            RUN(hip_check(hipStreamWaitEvent(st, ev_f, 0), "hipStreamWaitEvent"));
-        } else {
-            // round the operator (Sinv = I so far) to FP32 now, then L and V into
-            // their FP32 copies (V's into the memory of the FP64 U rows)
-            const double *Sinv64 = pc->Sinv;
-            RUN(precond_round_to_fp32(pc, st));
-            float *S32 = pc->f32.Sinv;
-            float *V32 = (float *)Urow;
-            RUN(to_float_enqueue(Lrow, L32, (size_t)M * s * w2 * s, st));
-            RUN(to_float_enqueue(Vrow, V32, (size_t)M * s * w2 * s, st));
-            for (size_t i = 0; i < tri.size(); ++i) {
-                const GemmTriItem &t = tri[i];
-                const bool fwd = (i % 2) == 0;
-                const float *Ab = fwd ? L32 : V32;
-                const double *Ad = fwd ? Lrow : Vrow;
-                tf.push_back({Ab + (t.A - Ad), S32 + (t.B - Sinv64), S32 + (t.C - Sinv64), t.nk, t.cb0, t.ncb,
-                              t.lo_off, t.hi_off, t.rev});
-            }
-            if (!tf.empty())
-                RUN(hip_check(hipMemcpyAsync(tri32_dev, tf.data(), sizeof(GemmTriItemF) * tf.size(),
-                                             hipMemcpyHostToDevice, st),
-                              "copy"));
-            for (int j = 1; j < M; ++j)
-                RUN(gemm_tri_enqueue(tri32_dev + 2 * (j - 1), 2, s, j, w2 * s, (int)n, (int)n, -1.0, st));
         }
+        RUN(hip_check(hipStreamWaitEvent(st, ev_f, 0), "hipStreamWaitEvent"));
         // a zero pivot in any inverted block makes P singular in this factorisation
         std::vector<int> hinfo(3 * (2 + M), 0);
         RUN(hip_check(hipMemcpyAsync(hinfo.data(), info, sizeof(int) * 3 * (2 + M), hipMemcpyDeviceToHost, st),
@@ -633,6 +688,10 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
     }
     if (ev_l) (void)hipEventDestroy(ev_l);
     if (ev_f) (void)hipEventDestroy(ev_f);
+    if (f32mem.mem) {  // allocated but not adopted: an error came first
+        (void)hipStreamSynchronize(st);
+        precond_fp32_drop(pc, &f32mem);
+    }
     (void)hipFreeAsync(tbase, st);
     if (!rc && storage == BIM_STORE_FP32 && pc->storage != BIM_STORE_FP32) rc = precond_round_to_fp32(pc, st);
     if (rc) {
