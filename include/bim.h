@@ -223,7 +223,7 @@ int precond_setup(const bim_problem *prob, int band_halfwidth, bim_precond **out
  * blocks, the replicated diagonal inverses, the triangular inverses of the
  * Schur complement's block LU and its inverse pivot blocks) are held in FP32,
  * halving the apply's memory traffic and precond_bytes().  The block
- * elimination and the block LU run in FP64; for 128 < N + 1 <= 192 the
+ * elimination and the block LU run in FP64; for 128 < N + 1 <= 384 the
  * substitutions that form the triangular inverses run in FP32 on FP32 copies
  * of the factors, otherwise the FP64 inverses are rounded.  The apply still
  * forms its products and sums in FP64.  The rounding of the elements is

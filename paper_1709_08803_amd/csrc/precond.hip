@@ -553,13 +553,13 @@ int precond_build(const bim_problem *p, int hb, int storage, Precond **out, hipS
         // rows of L^-1 above it, and it touches nothing the LU reads or writes.
         // The pivot inversions leave all but one compute unit idle, and the
         // forward rows fill them.  In FP32 (FP32-stored operator and
-        // 128 < s <= 192) the second stream first rounds row j of L to FP32 and
+        // 128 < s <= 384) the second stream first rounds row j of L to FP32 and
         // the rows of L^-1 are formed in FP32, directly in the FP32 operator.
         // The forward rows' workgroups (one per compute unit, by their LDS) are
         // capped so that compute units stay free: a pivot inversion needs a whole
         // compute unit's registers and would otherwise wait for one to drain.
         constexpr int kAuxTriGroups = 192;
-        const bool bw32 = storage == BIM_STORE_FP32 && s > 128 && s <= 192;
+        const bool bw32 = storage == BIM_STORE_FP32 && s > 128 && s <= 384;
         const int far = 1 << 29;  // an offset that leaves klo at 0 / khi at nk
         const size_t lrow = (size_t)s * w2 * s;  // elements of one block row of L (or V)
         float *S32 = nullptr;

@@ -139,10 +139,14 @@ def test_precond_rejects_unknown_storage(bim):
 @pytest.mark.parametrize("name,mk,hb,tol", [
     ("odd-s-44x9-h2", lambda: W.make_problem(44, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 2, 2e-4),
     ("even-s-45x9-h3", lambda: W.make_problem(45, 9, -12, 12, 0, 6, 0.9, [W.Bump(0.25, 1.3, 0.9)]), 3, 2e-4),
-    # 128 < s <= 192: the substitutions forming S^-1 run in FP32 (odd s)
+    # 128 < s <= 384: the substitutions forming S^-1 run in FP32 (odd s; and
+    # s = 212, whose pivot blocks are inverted as 2 x 2 block matrices and whose
+    # triangular products span two 192-row panels)
     ("fp32-substitutions-150x9-h2", lambda: W.make_problem(150, 9, -20, 20, 0, 4, 1.1, [W.Bump(0.2, 1.0, 1.0)]), 2,
      1e-2),
-], ids=["odd-s", "even-s", "fp32-substitutions-odd-s"])
+    ("fp32-substitutions-211x9-h2", lambda: W.make_problem(211, 9, -40, 30, 0, 4, 1.1, [W.Bump(0.2, 1.0, 1.0)]), 2,
+     1e-2),
+], ids=["odd-s", "even-s", "fp32-substitutions-odd-s", "fp32-substitutions-two-panels"])
 def test_fp32_storage_small_meshes_match_oracle(bim, name, mk, hb, tol):
     # FP32 elements read one per lane (odd s: rows not aligned to two elements)
     # or two per lane (even s): both apply the oracle's P to FP32 rounding
