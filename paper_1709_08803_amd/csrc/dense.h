@@ -53,8 +53,9 @@ int gemm_kblocks_enqueue(const GemmKItem *items_dev, int batch, int m, int n, in
                          long sA, long sB, double alpha, double beta, hipStream_t s);
 // Block-triangular products of `batch` items (FP64 or FP32 matrix cores, any
 // block size s); max_ncb: the largest ncb.  max_groups > 0 caps the workgroups
-// per row panel (they then walk the column tiles with a stride), which leaves
-// compute units free for other streams; 0: one workgroup per tile.
+// of the launch (over all row panels; they then walk the column tiles with a
+// stride), which leaves compute units free for other streams; 0: one
+// workgroup per tile.
 int gemm_tri_enqueue(const GemmTriItem *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,
                      double alpha, hipStream_t st, int max_groups = 0);
 int gemm_tri_enqueue(const GemmTriItemF *items_dev, int batch, int s, int max_ncb, int lda, int ldb, int ldc,

@@ -1116,8 +1116,8 @@ int gemm_tri_launch(const GemmTriItemT<T> *items_dev, int batch, int s, int max_
     if (max_groups < 0) return fail(BIM_EINVAL, "block-triangular product: negative workgroup cap");
     const int ppb = cdiv(s, kTriPanel);
     if ((long)max_ncb * ppb * batch > 0x7fffffffL) return fail(BIM_EINVAL, "block-triangular product too wide");
-    const int ntiles = max_ncb * ppb * batch;
-    dim3 grid(max_groups > 0 ? std::min(ntiles, max_groups) : ntiles, cdiv(s, kTallM), 1);
+    const int ntiles = max_ncb * ppb * batch, panels = cdiv(s, kTallM);
+    dim3 grid(max_groups > 0 ? std::min(ntiles, std::max(1, max_groups / panels)) : ntiles, panels, 1);
     hipLaunchKernelGGL((k_gemm_tri<kTriPanel, kTallWaves, T>), grid, dim3(64 * kTallWaves), 0, st, items_dev, batch, s,
                        ppb, lda, ldb, ldc, alpha, ntiles);
     return hip_check(hipGetLastError(), "block-triangular gemm launch");
