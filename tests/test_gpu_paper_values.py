@@ -95,3 +95,35 @@ def test_supercritical_centreline_heights_on_the_papers_mesh(bim):
     print("maximum centreline heights", heights)
     assert abs(heights[0.1] - (vals["supercritical_max_centreline_height_eps0.1_printed"] - 1.0)) <= 5e-4
     assert abs(heights[2.75] - vals["supercritical_max_centreline_height_eps2.75"]) <= 0.01 * 2.556
+
+
+@pytest.mark.timeout(300)
+def test_subcritical_bump_reaches_the_papers_largest_height(bim):
+    # Section 5.1: F = 0.6, eq. (bottom) with delta = 0.5, on the paper's
+    # 281 x 281 mesh (dx = dy = 0.0857, x in [-7, 17], y in [-12, 12]; here its
+    # half 281 x 141).  The paper computes solutions up to eps = 0.285, its most
+    # nonlinear subcritical one, and bounds the surface by F^2 / 2 (Bernoulli's
+    # equation).  Continuation 0.1, 0.2, 0.25, 0.285 must converge at every step
+    # (||F||_inf <= 1e-10), with the maximum height rising with eps and staying
+    # below F^2 / 2.
+    from oracle import residual as R
+    vals = _paper_values()
+    froude = 0.6
+    w = math.sqrt(2.0) * 0.5
+    u_prev, heights = None, {}
+    for eps in (0.1, 0.2, 0.25, 0.285):
+        p = W.make_problem(281, 141, -7.0, 17.0, 0.0, 12.0, froude, [W.Bump(eps, w, w)])
+        dp = bim.DeviceProblem(p)
+        P = bim.Preconditioner(dp)
+        u = bim.linear_start(dp, P, rtol=1e-8) if u_prev is None else torch.as_tensor(u_prev, device="cuda")
+        rep = bim.solve(dp, u, P, ftol=1e-10, check=False, max_newton=20)
+        P.close()
+        print(f"F = 0.6, eps {eps}: status {rep['status']} Newton {rep['newton_iters']} GMRES {rep['gmres_iters']}",
+              flush=True)
+        assert rep["status"] == 0
+        u_prev = u.cpu().numpy()
+        heights[eps] = float(R.reconstruct(p, u_prev).zeta.max())
+    print("maximum heights", heights, "limit", vals["limiting_height_factor"] * froude ** 2)
+    hs = [heights[e] for e in (0.1, 0.2, 0.25, 0.285)]
+    assert all(b > a for a, b in zip(hs, hs[1:]))
+    assert hs[-1] < vals["limiting_height_factor"] * froude ** 2
