@@ -127,3 +127,59 @@ def test_subcritical_bump_reaches_the_papers_largest_height(bim):
     hs = [heights[e] for e in (0.1, 0.2, 0.25, 0.285)]
     assert all(b > a for a, b in zip(hs, hs[1:]))
     assert hs[-1] < vals["limiting_height_factor"] * froude ** 2
+
+
+def _centreline_crests(x, z, xlo, xhi):
+    # positive local maxima of z on [xlo, xhi], refined by a parabola through
+    # each maximum and its two neighbours
+    m = (x >= xlo) & (x <= xhi)
+    xs, zs = x[m], z[m]
+    h = xs[1] - xs[0]
+    out = []
+    for i in range(1, len(zs) - 1):
+        if zs[i] > 0 and zs[i] > zs[i - 1] and zs[i] >= zs[i + 1]:
+            a, b, c = zs[i - 1], zs[i], zs[i + 1]
+            out.append(xs[i] + 0.5 * (a - c) / (a - 2 * b + c) * h)
+    return np.array(out)
+
+
+@pytest.mark.timeout(300)
+def test_inline_bumps_nonlinear_separations_and_interference(bim):
+    # Section 5.3: two bumps of eq. (bottom) (eps = 0.1, delta = 0.5, F = 0.6) on
+    # the x-axis, the paper's mesh x in [-7, 53], y in [-30, 30], 281 x 281
+    # (dx = dy = 0.2143; here its half 281 x 141).  The paper spaces the
+    # nonlinear pairs 9.92 and 11.16 apart, about 4 and 4.5 wavelengths of the
+    # transverse waves of a single-hump nonlinear solution.  Here: the crest
+    # spacing of that single-hump solution along the centreline times 4 and 4.5
+    # must give the printed separations to 1%, and at those separations the
+    # downstream centreline waves must show the interference the paper shows,
+    # constructive at 9.92 against destructive at 11.16 (amplitude ratio >= 3).
+    from oracle import residual as R
+    vals = _paper_values()
+    w = math.sqrt(2.0) * 0.5
+
+    def solve(bumps):
+        p = W.make_problem(281, 141, -7.0, 53.0, 0.0, 30.0, 0.6, bumps)
+        dp = bim.DeviceProblem(p)
+        P = bim.Preconditioner(dp)
+        u = bim.linear_start(dp, P, rtol=1e-8)
+        rep = bim.solve(dp, u, P, ftol=1e-10, check=False, max_newton=20)
+        P.close()
+        assert rep["status"] == 0
+        return p.x(), R.reconstruct(p, u.cpu().numpy()).zeta[0]  # row j = 0 is y = 0
+
+    x, z = solve([W.Bump(0.1, w, w)])
+    crests = _centreline_crests(x, z, 5.0, 45.0)
+    lam = float(np.mean(np.diff(crests)))
+    print(f"single hump: {crests.size} crests, wavelength {lam:.4f}; 4 and 4.5 wavelengths {4 * lam:.3f}, "
+          f"{4.5 * lam:.3f}", flush=True)
+    assert abs(4.0 * lam - vals["inline_constructive_separation_nonlinear"]) <= 0.01 * 9.92
+    assert abs(4.5 * lam - vals["inline_destructive_separation_nonlinear"]) <= 0.01 * 11.16
+    amp = {}
+    for key in ("inline_constructive_separation_nonlinear", "inline_destructive_separation_nonlinear"):
+        sep = vals[key]
+        x, z = solve([W.Bump(0.1, w, w), W.Bump(0.1, w, w, cx=sep, cy=0.0)])
+        m = (x >= sep + 5.0) & (x <= 45.0)
+        amp[sep] = float(np.abs(z[m]).max())
+    print("downstream centreline amplitudes", amp)
+    assert amp[9.92] >= 3.0 * amp[11.16]
