@@ -64,6 +64,17 @@ def test_crater_maximum_heights_on_the_papers_mesh(bim):
     assert abs(heights[-0.62] - vals["crater_max_height_eps-0.62"]) <= 5e-4
 
 
+def _apparent_wake_angle(x, y, zeta, xlo, xhi):
+    # the ridge: at each x in [xlo, xhi], the y (off the centreline rows) where
+    # zeta(x, .) is largest; the angle of a least-squares line through it
+    xs, ys = [], []
+    for i in np.where((x >= xlo) & (x <= xhi))[0]:
+        xs.append(x[i])
+        ys.append(y[int(np.argmax(zeta[2:, i])) + 2])
+    slope = np.polyfit(np.array(xs), np.array(ys), 1)[0]
+    return math.degrees(math.atan(slope))
+
+
 @pytest.mark.timeout(600)
 def test_supercritical_centreline_heights_on_the_papers_mesh(bim):
     # Section 5.2: F = 3, eq. (bottom) with delta = 3, on the paper's 281 x 281
@@ -75,11 +86,12 @@ def test_supercritical_centreline_heights_on_the_papers_mesh(bim):
     # agrees with 0.091 to the printed precision.  eps = 2.75 is reached by
     # continuation (0.5, 1, 1.5, 2, 2.4, 2.75) and agrees with 2.556 to 1%
     # (measured 2.539, 0.7%: the most nonlinear solution of the paper, where
-    # the two discretisations' small differences weigh most).
+    # the two discretisations' small differences weigh most).  The same
+    # solutions give the apparent wake angle (below).
     from oracle import residual as R
     vals = _paper_values()
     w = math.sqrt(2.0) * 3.0
-    u_prev, heights = None, {}
+    u_prev, heights, angles = None, {}, {}
     for eps in (0.1, 0.5, 1.0, 1.5, 2.0, 2.4, 2.75):
         p = W.make_problem(281, 141, -21.0, 51.0, 0.0, 36.0, 3.0, [W.Bump(eps, w, w)])
         dp = bim.DeviceProblem(p)
@@ -91,10 +103,20 @@ def test_supercritical_centreline_heights_on_the_papers_mesh(bim):
               flush=True)
         assert rep["status"] == 0
         u_prev = u.cpu().numpy()
-        heights[eps] = float(R.reconstruct(p, u_prev).zeta[0].max())  # row j = 0 is y = 0
+        zeta = R.reconstruct(p, u_prev).zeta
+        heights[eps] = float(zeta[0].max())  # row j = 0 is y = 0
+        angles[eps] = _apparent_wake_angle(p.x(), p.y(), zeta, 15.0, 45.0)
     print("maximum centreline heights", heights)
+    print("apparent wake angles (degrees)", angles, "arcsin(1/F)", math.degrees(math.asin(1.0 / 3.0)))
     assert abs(heights[0.1] - (vals["supercritical_max_centreline_height_eps0.1_printed"] - 1.0)) <= 5e-4
     assert abs(heights[2.75] - vals["supercritical_max_centreline_height_eps2.75"]) <= 0.01 * 2.556
+    # Section 5.2 (wake-angle figure): the apparent wake angle, between the
+    # V-shaped ridge and the centreline, grows with eps.  Its small-eps limit is
+    # the linear wedge of supercritical flow, sin(theta) = 1 / F.
+    a = [angles[e] for e in sorted(angles)]
+    assert all(b > c for c, b in zip(a, a[1:]))
+    assert abs(angles[0.1] - math.degrees(math.asin(1.0 / 3.0))) <= 1.0
+    assert angles[2.75] - angles[0.1] >= 3.0
 
 
 @pytest.mark.timeout(300)
