@@ -117,6 +117,19 @@ def test_supercritical_centreline_heights_on_the_papers_mesh(bim):
     assert all(b > c for c, b in zip(a, a[1:]))
     assert abs(angles[0.1] - math.degrees(math.asin(1.0 / 3.0))) <= 1.0
     assert angles[2.75] - angles[0.1] >= 3.0
+    # the figure's second Froude number: at F = 4 the angle is lower, and at
+    # small eps it is the wedge arcsin(1/4)
+    p = W.make_problem(281, 141, -21.0, 51.0, 0.0, 36.0, 4.0, [W.Bump(0.1, w, w)])
+    dp = bim.DeviceProblem(p)
+    P = bim.Preconditioner(dp)
+    u = bim.linear_start(dp, P, rtol=1e-8)
+    rep = bim.solve(dp, u, P, ftol=1e-10, check=False, max_newton=20)
+    P.close()
+    assert rep["status"] == 0
+    a4 = _apparent_wake_angle(p.x(), p.y(), R.reconstruct(p, u.cpu().numpy()).zeta, 15.0, 45.0)
+    print("F = 4, eps = 0.1: apparent wake angle", a4, "arcsin(1/F)", math.degrees(math.asin(0.25)))
+    assert a4 < angles[0.1]
+    assert abs(a4 - math.degrees(math.asin(0.25))) <= 1.0
 
 
 @pytest.mark.timeout(300)
