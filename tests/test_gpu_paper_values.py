@@ -75,6 +75,16 @@ def _apparent_wake_angle(x, y, zeta, xlo, xhi):
     return math.degrees(math.atan(slope))
 
 
+def _outer_steepness(x, y, zeta, xlo, xhi):
+    # the largest outward slope -d zeta / dy beyond the ridge, over x in [xlo, xhi]
+    dzdy = np.gradient(zeta, y, axis=0)
+    best = 0.0
+    for i in np.where((x >= xlo) & (x <= xhi))[0]:
+        j = int(np.argmax(zeta[2:, i])) + 2
+        best = max(best, float(np.max(-dzdy[j:, i])))
+    return best
+
+
 @pytest.mark.timeout(600)
 def test_supercritical_centreline_heights_on_the_papers_mesh(bim):
     # Section 5.2: F = 3, eq. (bottom) with delta = 3, on the paper's 281 x 281
@@ -91,7 +101,7 @@ def test_supercritical_centreline_heights_on_the_papers_mesh(bim):
     from oracle import residual as R
     vals = _paper_values()
     w = math.sqrt(2.0) * 3.0
-    u_prev, heights, angles = None, {}, {}
+    u_prev, heights, angles, steep = None, {}, {}, {}
     for eps in (0.1, 0.5, 1.0, 1.5, 2.0, 2.4, 2.75):
         p = W.make_problem(281, 141, -21.0, 51.0, 0.0, 36.0, 3.0, [W.Bump(eps, w, w)])
         dp = bim.DeviceProblem(p)
@@ -106,6 +116,7 @@ def test_supercritical_centreline_heights_on_the_papers_mesh(bim):
         zeta = R.reconstruct(p, u_prev).zeta
         heights[eps] = float(zeta[0].max())  # row j = 0 is y = 0
         angles[eps] = _apparent_wake_angle(p.x(), p.y(), zeta, 15.0, 45.0)
+        steep[eps] = _outer_steepness(p.x(), p.y(), zeta, 15.0, 45.0)
     print("maximum centreline heights", heights)
     print("apparent wake angles (degrees)", angles, "arcsin(1/F)", math.degrees(math.asin(1.0 / 3.0)))
     assert abs(heights[0.1] - (vals["supercritical_max_centreline_height_eps0.1_printed"] - 1.0)) <= 5e-4
@@ -117,6 +128,13 @@ def test_supercritical_centreline_heights_on_the_papers_mesh(bim):
     assert all(b > c for c, b in zip(a, a[1:]))
     assert abs(angles[0.1] - math.degrees(math.asin(1.0 / 3.0))) <= 1.0
     assert angles[2.75] - angles[0.1] >= 3.0
+    # the same figure's wave steepness, the largest slope on the outside of the
+    # ridge: it grows with eps, and faster than eps (a linear response would
+    # keep steepness / eps fixed)
+    print("outer steepness", steep)
+    st = [steep[e] for e in sorted(steep)]
+    assert all(b > c for c, b in zip(st, st[1:]))
+    assert steep[2.75] / 2.75 >= 1.5 * steep[0.1] / 0.1
     # the figure's second Froude number: at F = 4 the angle is lower, and at
     # small eps it is the wedge arcsin(1/4)
     p = W.make_problem(281, 141, -21.0, 51.0, 0.0, 36.0, 4.0, [W.Bump(0.1, w, w)])
